@@ -1,0 +1,117 @@
+"""Pins of the brute-force allocator against hand-solved grids and closed forms."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import alloc as A
+import workload_gen as G
+
+BIG = 1 << 60
+
+
+def _problem(lat, batches, cu_total, cu_step, qos=BIG, nmax=1, I=48, bw=None, mem=None,
+             bw_budget=BIG, mem_budget=BIG, wait=None):
+    lat = np.asarray(lat, np.int64)
+    S, K, nb = lat.shape
+    return A.Problem(cu_total=cu_total, cu_step=cu_step, max_instances=I,
+                     max_inst_per_stage=nmax, batches=batches, qos_ns=qos,
+                     hbm_bytes_budget=mem_budget, hbm_bw_budget=bw_budget,
+                     lat_ns=lat,
+                     bw_bps=np.zeros_like(lat) if bw is None else np.asarray(bw, np.int64),
+                     mem_bytes=np.zeros((S, nb), np.int64) if mem is None else np.asarray(mem, np.int64),
+                     batch_wait_ns=wait)
+
+
+# Two stages, 16 CUs in steps of 4, batch 2. Solved by hand:
+#   shares (12, 4): T = min(2e9/450, 2e9/500) = 4e6 q/s  <- peak (uses all 16 CUs)
+#   shares ( 8, 4): T = 2e9/600 = 3.33e6 with 12 CUs    <- min CUs for load 3e6
+#   shares ( 4, 4): T = 2e9/1000 = 2e6 with 8 CUs       <- min CUs for load 1e6
+HAND = [[[1000], [600], [450], [400]], [[500], [400], [350], [330]]]
+
+
+def test_hand_solved_peak():
+    a = A.alloc_peak(_problem(HAND, [2], 16, 4))
+    assert a.cu == [12, 4] and a.n == [1, 1]
+    assert (a.thr_num, a.thr_den) == (4000000, 1)
+    assert a.cu_used == 16 and a.lat_ns == 950
+
+
+def test_hand_solved_min():
+    p = _problem(HAND, [2], 16, 4)
+    a = A.alloc_min(p, 3_000_000, 1)
+    assert a.cu == [8, 4] and (a.thr_num, a.thr_den) == (10000000, 3) and a.cu_used == 12
+    a = A.alloc_min(p, 1_000_000, 1)
+    assert a.cu == [4, 4] and a.cu_used == 8
+    assert A.alloc_min(p, 5_000_000, 1) is None
+
+
+def test_hand_solved_qos_and_budgets():
+    assert A.alloc_peak(_problem(HAND, [2], 16, 4, qos=1000)).cu == [12, 4]
+    assert A.alloc_peak(_problem(HAND, [2], 16, 4, qos=900)) is None
+    # memory: each instance needs 10 bytes; budget 20 -> one instance per stage only
+    p = _problem(HAND, [2], 16, 4, nmax=2, mem=[[10], [10]], mem_budget=20)
+    assert A.alloc_peak(p).n == [1, 1]
+    # the batch wait counts against the latency target
+    assert A.alloc_peak(_problem(HAND, [2], 16, 4, qos=1000, wait=[60])) is None
+
+
+def test_instances_can_replicate_slow_stage():
+    # stage 0 is 4x slower than stage 1 at every share: with 2 instances allowed,
+    # two copies of stage 0 on 4 CUs each beat one copy on 8
+    lat = [[[4000]] * 3, [[1000]] * 3]
+    a = A.alloc_peak(_problem(lat, [1], 12, 4, nmax=3))
+    assert a.n == [2, 1] and a.cu == [4, 4] and (a.thr_num, a.thr_den) == (500000, 1)
+
+
+def test_single_stage_takes_all_cus():
+    lat = [[[1000 // (k + 1) + 7] for k in range(8)]]
+    a = A.alloc_peak(_problem(lat, [1], 64, 8))
+    assert a.cu == [64]
+
+
+def test_identical_stages_split_evenly():
+    row = [[int(50000 / (k + 1)) + 100] for k in range(8)]
+    a = A.alloc_peak(_problem([row, row], [1], 64, 8))
+    assert a.cu == [32, 32]
+
+
+def test_proportional_closed_form():
+    c = [3.0, 1.0, 2.0]                  # work per query; L = c * b * 1000 / p ns
+    R, step = 128, 8
+    K = R // step
+    lat = [[[int(np.ceil(ci * 4 * 1000 / ((k + 1) * step)))] for k in range(K)] for ci in c]
+    a = A.alloc_peak(_problem(lat, [4], R, step))
+    t_star = Fraction(R * 10 ** 6) / Fraction(sum(c)).limit_denominator()
+    assert a.thr <= t_star
+    assert a.thr >= t_star - Fraction(step * 10 ** 6, int(min(c)))
+    # shares ordered like the work
+    assert a.cu[0] > a.cu[2] > a.cu[1]
+
+
+def test_even_split_rounding():
+    lat = np.ones((3, 32, 1), np.int64) * 1000
+    a = A.even_split(_problem(lat, [1], 256, 8), 0)
+    assert a.cu == [88, 88, 80]
+
+
+@pytest.mark.parametrize("sub", range(4))
+def test_monotone_in_resources_qos_and_load(sub):
+    lat, bw, mem = G.random_problem_tables(3, 8, [1, 4, 16], seed=1, sub=sub)
+    base = dict(bw=bw, mem=mem, bw_budget=int(bw.max() * 2), mem_budget=int(mem.max() * 3))
+    full = A.alloc_peak(_problem(lat, [1, 4, 16], 64, 8, **base))
+    less = A.alloc_peak(_problem(lat, [1, 4, 16], 48, 8, **base))
+    assert full is not None
+    assert less is None or less.thr <= full.thr
+    q_hi = A.alloc_peak(_problem(lat, [1, 4, 16], 64, 8, qos=int(lat.max() * 3), **base))
+    q_lo = A.alloc_peak(_problem(lat, [1, 4, 16], 64, 8, qos=int(lat.max() * 2), **base))
+    if q_lo is not None:
+        assert q_hi is not None and q_lo.thr <= q_hi.thr
+    p = _problem(lat, [1, 4, 16], 64, 8, **base)
+    prev = 0
+    for frac in (0.1, 0.3, 0.6, 1.0):
+        lam = full.thr * Fraction(frac).limit_denominator()
+        m = A.alloc_min(p, lam.numerator, lam.denominator)
+        assert m is not None and m.thr >= lam
+        assert m.cu_used >= prev
+        prev = m.cu_used

@@ -1,0 +1,150 @@
+"""Pins of the oracle's stage math against facts fixed outside the oracle."""
+import numpy as np
+import pytest
+
+from oracle import stages as O
+import workload_gen as G
+
+
+# ---------------------------------------------------------------- DFT
+def test_dft_matches_library_rfft():
+    x = G.rng("handoff", 11).standard_normal(400)
+    ref = np.fft.rfft(np.concatenate([x, np.zeros(112)]))
+    got = O.dft_direct(x)
+    assert got.shape == (257,)
+    assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_dft_parseval():
+    x = G.rng("handoff", 12).standard_normal(400)
+    X = O.dft_direct(x)
+    p = np.abs(X) ** 2
+    full = p[0] + p[-1] + 2 * p[1:-1].sum()      # conjugate symmetry of a real input
+    assert abs(full - 512 * np.sum(x * x)) < 1e-8 * full
+
+
+def test_dft_bin_centred_tone():
+    k0, A = 37, 0.75
+    n = np.arange(512)
+    X = O.dft_direct(A * np.cos(2 * np.pi * k0 * n / 512))
+    assert abs(abs(X[k0]) - A * 512 / 2) < 1e-9
+    others = np.delete(np.abs(X), k0)
+    assert np.max(others) < 1e-9
+
+
+# ---------------------------------------------------------------- mel
+def test_mel_scale_roundtrip_and_anchor():
+    # HTK: 1000 Hz is ~1000 mel (2595 log10(1 + 1000/700) = 999.985...)
+    assert abs(O.hz_to_mel(1000.0) - 999.9855) < 1e-3
+    f = np.array([0.0, 123.0, 4000.0, 8000.0])
+    assert np.allclose(O.mel_to_hz(O.hz_to_mel(f)), f)
+
+
+def test_mel_filterbank_partition_of_unity():
+    fb = O.mel_filterbank()
+    assert fb.shape == (40, 257)
+    assert np.all(fb >= 0) and np.all(fb <= 1.0 + 1e-12)
+    pts = O.mel_to_hz(np.linspace(0, O.hz_to_mel(8000.0), 42))
+    fk = np.arange(257) * 16000 / 512
+    inner = (fk >= pts[1]) & (fk <= pts[40])
+    s = fb.sum(axis=0)
+    assert np.allclose(s[inner], 1.0, atol=1e-12)
+    # outside the filterbank's span only the outer slopes contribute (< 1)
+    assert np.all(s[~inner] < 1.0)
+    # each filter is supported between its neighbours' centres, peaks in order
+    peaks = fb.argmax(axis=1)
+    assert np.all(np.diff(peaks) >= 0)
+
+
+# ---------------------------------------------------------------- log-mel
+def test_log_mel_impulse_pins_framing_window_and_filters():
+    clip = np.zeros((1, 2000))
+    clip[0, 170] = 1.0                       # lands in frames 0 (pos 170) and 1 (pos 10)
+    feat = O.log_mel(clip).reshape(11, 40)
+    fb = O.mel_filterbank()
+    w = O.hamming()
+    # a windowed impulse has a flat power spectrum w[pos]^2
+    for frame, pos in ((0, 170), (1, 10)):
+        ref = np.log(np.maximum(w[pos] ** 2 * fb.sum(axis=1), 1e-10))
+        assert np.allclose(feat[frame], ref, atol=1e-12)
+    assert np.all(feat[2:] == np.log(1e-10))
+
+
+def test_log_mel_matches_library_fft_path():
+    clip = G.c1_audio(2, seed=3)
+    got = O.log_mel(clip)
+    w = np.hamming(400)                      # library symmetric Hamming window
+    fb = O.mel_filterbank()
+    ref = np.empty_like(got)
+    for b in range(2):
+        for f in range(11):
+            seg = clip[b, f * 160: f * 160 + 400].astype(np.float64) * w
+            p = np.abs(np.fft.rfft(seg, 512)) ** 2
+            ref[b, f * 40:(f + 1) * 40] = np.log(np.maximum(fb @ p, 1e-10))
+    assert np.max(np.abs(got - ref)) < 1e-9
+
+
+def test_log_mel_floor():
+    feat = O.log_mel(np.zeros((1, 2000)))
+    assert np.all(feat == np.log(1e-10))
+
+
+# ---------------------------------------------------------------- GEMM / argmax / top-k
+def test_gemm_relu_identity():
+    x = G.c0_queries(4, seed=1)
+    y = O.gemm_relu(x, np.eye(512, dtype=np.float32))
+    assert np.array_equal(y, np.maximum(x.astype(np.float64), 0))
+
+
+def test_gemm_relu_hand_case():
+    x = np.array([[1.0, -2.0]])
+    w = np.array([[3.0, -1.0, 0.5], [1.0, 1.0, 2.0]])
+    assert np.array_equal(O.gemm_relu(x, w), [[1.0, 0.0, 0.0]])
+
+
+def test_argmax_lowest_index_on_ties():
+    s = np.array([[1.0, 3.0, 3.0, -1.0], [0.0, 0.0, 0.0, 0.0], [-5.0, -4.0, -4.5, -4.0]])
+    assert list(O.argmax_lowest(s)) == [1, 0, 1]
+
+
+def test_topk_against_stable_sort():
+    g = G.rng("handoff", 5)
+    s = np.round(g.standard_normal((6, 300)), 1)      # many exact ties
+    idx, val = O.topk(s, 25)
+    for r in range(6):
+        ref = np.argsort(-s[r], kind="stable")[:25]
+        assert list(idx[r]) == list(ref)
+        assert np.array_equal(val[r], s[r, ref])
+
+
+# ---------------------------------------------------------------- BF16
+def _bf16_from_f32_bits(x32):
+    u = x32.astype(np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_round_matches_bit_rounding_on_fp32_inputs():
+    x = G.rng("handoff", 7).standard_normal(20000).astype(np.float32) * 3
+    assert np.array_equal(O.bf16_round(x.astype(np.float64)), _bf16_from_f32_bits(x))
+
+
+def test_bf16_round_halfway_to_even():
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: rounds to the even significand (1)
+    assert O.bf16_round(np.array([1 + 2 ** -8]))[0] == 1.0
+    # 1 + 3 * 2^-8 is halfway between 1 + 2^-7 (odd) and 1 + 2^-6 (even)
+    assert O.bf16_round(np.array([1 + 3 * 2 ** -8]))[0] == 1 + 2 ** -6
+    for v in (1.0, -2.5, 0.0078125, 3.0 * 2 ** 20):
+        assert O.bf16_round(np.array([v]))[0] == v
+
+
+def test_mlp_bf16_identity_chain():
+    eye = G._to_bf16_bits(np.eye(8, dtype=np.float32))
+    x = G.rng("handoff", 8).standard_normal((3, 8))
+    y = O.mlp_bf16(x, [eye, eye])
+    assert np.array_equal(y, O.bf16_round(np.maximum(O.bf16_round(x), 0)))
+
+
+def test_normwise_err():
+    assert O.normwise_err([1.0, 0.0], [1.0, 0.0]) == 0.0
+    assert O.normwise_err([1.0, 0.5], [2.0, 0.0]) == 0.5

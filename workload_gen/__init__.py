@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/bench and the CPU oracle.
+
+This module only draws random numbers and lays them out. It holds none of the
+pipeline's arithmetic (no transforms, no products, no allocation logic): both the
+oracle and the HIP path receive the same bytes from here and compute on their own.
+
+Workloads (shapes follow the pipeline configurations the method is evaluated on):
+
+* two-stage FP32 pipeline: queries X ~ N(0,1) [n,512]; W1 ~ N(0,1/512) [512,512];
+  W2 ~ N(0,1/512) [512,10]; weights are [in, out] row-major.
+* speech-assistant pipeline: 2000-sample 16 kHz clips = white noise (sigma 0.1) plus
+  three sinusoids (f ~ U(100, 7900) Hz, amplitude ~ U(0.1, 1), phase ~ U(0, 2pi));
+  MLP 440->2048->2048->2048->4096 with weights N(0, 1/fan_in) rounded to BF16 and
+  stored [out, in] (K contiguous).
+* Poisson arrival schedules (exponential gaps, integer nanoseconds) and uneven
+  request sizes U{1..128}.
+* random integer latency / bandwidth / footprint tables for allocator tests.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Keys that separate the random streams of different configurations / purposes.
+_STREAMS = {
+    "c0_weights": 1, "c0_queries": 2, "c1_audio": 3, "c1_weights": 4,
+    "arrivals": 5, "requests": 6, "tables": 7, "predictor": 8, "c4": 9,
+    "handoff": 10,
+}
+
+
+def rng(purpose: str, seed: int = 0, sub: int = 0) -> np.random.Generator:
+    """A numpy Generator for (purpose, seed, sub); streams never overlap."""
+    return np.random.default_rng(np.random.SeedSequence([seed, _STREAMS[purpose], sub]))
+
+
+# ---------------------------------------------------------------- two-stage FP32
+C0_D_IN, C0_D_HID, C0_D_OUT = 512, 512, 10
+
+
+def c0_weights(seed: int = 0):
+    g = rng("c0_weights", seed)
+    w1 = (g.standard_normal((C0_D_IN, C0_D_HID)) / np.sqrt(C0_D_IN)).astype(np.float32)
+    w2 = (g.standard_normal((C0_D_HID, C0_D_OUT)) / np.sqrt(C0_D_HID)).astype(np.float32)
+    return w1, w2
+
+
+def c0_queries(n: int, seed: int = 0, first: int = 0) -> np.ndarray:
+    """Query vectors [n, 512] FP32; row j depends only on (seed, first + j)."""
+    out = np.empty((n, C0_D_IN), np.float32)
+    for j in range(n):
+        out[j] = rng("c0_queries", seed, first + j).standard_normal(C0_D_IN)
+    return out
+
+
+def c0_queries_fast(n: int, seed: int = 0) -> np.ndarray:
+    """Bulk variant (one stream for all rows) for large pools."""
+    return rng("c0_queries", seed, 1 << 30).standard_normal((n, C0_D_IN), dtype=np.float32)
+
+
+# ---------------------------------------------------------------- speech pipeline
+C1_RATE = 16000
+C1_SAMPLES = 2000
+C1_MLP_DIMS = (440, 2048, 2048, 2048, 4096)
+
+
+def c1_audio(n: int, seed: int = 0, first: int = 0, samples: int = C1_SAMPLES) -> np.ndarray:
+    """White noise (sigma 0.1) + 3 random sinusoids per clip, FP32 [n, samples]."""
+    t = np.arange(samples, dtype=np.float64) / C1_RATE
+    out = np.empty((n, samples), np.float32)
+    for j in range(n):
+        g = rng("c1_audio", seed, first + j)
+        x = 0.1 * g.standard_normal(samples)
+        f = g.uniform(100.0, 7900.0, 3)
+        a = g.uniform(0.1, 1.0, 3)
+        ph = g.uniform(0.0, 2 * np.pi, 3)
+        for i in range(3):
+            x += a[i] * np.sin(2 * np.pi * f[i] * t + ph[i])
+        out[j] = x
+    return out
+
+
+def c1_audio_fast(n: int, seed: int = 0, samples: int = C1_SAMPLES) -> np.ndarray:
+    """Vectorised bulk variant for large query pools (one stream for all rows)."""
+    g = rng("c1_audio", seed, 1 << 30)
+    t = np.arange(samples, dtype=np.float64) / C1_RATE
+    x = 0.1 * g.standard_normal((n, samples))
+    f = g.uniform(100.0, 7900.0, (n, 3, 1))
+    a = g.uniform(0.1, 1.0, (n, 3, 1))
+    ph = g.uniform(0.0, 2 * np.pi, (n, 3, 1))
+    x += (a * np.sin(2 * np.pi * f * t[None, None, :] + ph)).sum(axis=1)
+    return x.astype(np.float32)
+
+
+def _to_bf16_bits(x32: np.ndarray) -> np.ndarray:
+    """Round FP32 to BF16 (nearest-even) and return the 16-bit patterns.
+
+    Used only to *store* generated weights in BF16; values are finite N(0, s)."""
+    u = x32.astype(np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return r.astype(np.uint16)
+
+
+def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+def c1_mlp_weights(seed: int = 0, dims=C1_MLP_DIMS):
+    """List of BF16 weight matrices as uint16 bit patterns, each [out, in]."""
+    g = rng("c1_weights", seed)
+    ws = []
+    for din, dout in zip(dims[:-1], dims[1:]):
+        w = (g.standard_normal((dout, din)) / np.sqrt(din)).astype(np.float32)
+        ws.append(_to_bf16_bits(w))
+    return ws
+
+
+# ---------------------------------------------------------------- arrivals
+def poisson_arrivals_ns(n: int, rate_qps: float, seed: int = 0, sub: int = 0) -> np.ndarray:
+    """Arrival times (int64 ns from 0) of a Poisson process with the given rate."""
+    gaps = rng("arrivals", seed, sub).exponential(1e9 / rate_qps, n)
+    return np.floor(np.cumsum(gaps)).astype(np.int64)
+
+
+def request_rows(n: int, seed: int = 0, lo: int = 1, hi: int = 128) -> np.ndarray:
+    """Uneven request sizes U{lo..hi}."""
+    return rng("requests", seed).integers(lo, hi + 1, n).astype(np.int32)
+
+
+# ---------------------------------------------------------------- allocator tables
+def random_problem_tables(n_stages: int, n_shares: int, batches, seed: int = 0,
+                          sub: int = 0):
+    """Integer latency (ns), bandwidth (B/s) and footprint (B) tables shaped like a
+    solo profile: latency falls with CU share and grows with batch, plus noise.
+
+    Returns (lat [S,K,nb] int64, bw [S,K,nb] int64, mem [S,nb] int64)."""
+    g = rng("tables", seed, sub)
+    batches = np.asarray(batches, np.int64)
+    nb = len(batches)
+    lat = np.empty((n_stages, n_shares, nb), np.int64)
+    bw = np.empty((n_stages, n_shares, nb), np.int64)
+    mem = np.empty((n_stages, nb), np.int64)
+    for s in range(n_stages):
+        work = g.uniform(2e3, 2e5)          # ns of work per query on one share step
+        fixed = g.uniform(1e3, 2e4)         # ns fixed cost per batch
+        byt = g.uniform(1e5, 4e7)           # bytes per batch
+        for k in range(n_shares):
+            for j, b in enumerate(batches):
+                base = fixed + work * b / (k + 1) ** g.uniform(0.6, 1.0)
+                lat[s, k, j] = max(1, int(base * g.uniform(0.9, 1.1)))
+                bw[s, k, j] = int(byt * (1 + 0.01 * b) * 1e9 / lat[s, k, j])
+        for j, b in enumerate(batches):
+            mem[s, j] = int(byt + b * g.uniform(1e3, 1e6))
+    return lat, bw, mem
+
+
+# ---------------------------------------------------------------- predictor
+def predictor_init(seed: int = 0, dims=(16, 64, 64, 1)):
+    """He-normal weights ([in, out] row-major) and zero biases, FP32."""
+    g = rng("predictor", seed)
+    params = []
+    for din, dout in zip(dims[:-1], dims[1:]):
+        params.append((g.standard_normal((din, dout)) * np.sqrt(2.0 / din)).astype(np.float32))
+        params.append(np.zeros(dout, np.float32))
+    return params
+
+
+def predictor_batch(m: int, seed: int = 0, sub: int = 0, n_in: int = 16):
+    """A random regression minibatch (features U(0,1), targets N(10, 1))."""
+    g = rng("predictor", seed, 1000 + sub)
+    x = g.uniform(0.0, 1.0, (m, n_in)).astype(np.float32)
+    y = g.normal(10.0, 1.0, m).astype(np.float32)
+    return x, y
