@@ -1,0 +1,352 @@
+/*
+ * camelot.h - C ABI of libcamelot, an MI355X (gfx950) runtime for pipelines of GPU
+ * microservices co-located on one GPU under spatial CU partitioning.
+ *
+ * What the library implements (Zhang et al., "Towards QoS-Aware and
+ * Resource-Efficient GPU Microservices Based on Spatial Multitasking GPUs In
+ * Datacenters", arXiv 2005.02088):
+ *   - global-memory communication between pipeline stages on one GPU (Section IV-B):
+ *     here a device-global ring buffer with doorbell flags between persistent stage
+ *     workers, one copy of the data, no host round trip; the host-staged
+ *     (device->host->device) path of Section IV-A is kept as the baseline;
+ *   - the allocation problems of Section V: maximise the supported peak load under
+ *     the QoS target (Eq. 1) and minimise the computational resources at low load
+ *     (Eq. 3), solved exactly over a measured integer profile table;
+ *   - the query flow of Section III-B: a wait queue, batch formation, per-stage
+ *     processing on the stage's CU share.
+ *
+ * Conventions (every entry point):
+ *   - Return value: CAMELOT_OK (0) or a negative camelot_status. No entry point
+ *     aborts or throws; camelot_last_error() returns a thread-local message
+ *     describing the last failure on the calling thread.
+ *   - Pointers are host pointers unless the parameter says "device". Device
+ *     pointers are plain HIP device allocations (hipMalloc or a PyTorch tensor's
+ *     data pointer) on the current device.
+ *   - The caller owns every buffer it passes; the library never frees them.
+ *     Objects the library creates (pipelines, streams, rings) are released by the
+ *     matching destroy call.
+ *   - Streams are hipStream_t passed as void*; NULL means the library's own stream.
+ *   - Allocation entry points are pure host computations: deterministic, the same
+ *     inputs give the same bytes out, no GPU needed.
+ */
+#ifndef CAMELOT_H
+#define CAMELOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef enum {
+  CAMELOT_OK = 0,
+  CAMELOT_EINVAL = -1,       /* bad argument (message says which)                    */
+  CAMELOT_ENOMEM = -2,       /* device/host allocation failed or footprint > budget  */
+  CAMELOT_EAGAIN = -3,       /* ingest queue full: back-pressure, retry later        */
+  CAMELOT_ETIMEDOUT = -4,    /* a wait ran past its limit (host or device side)      */
+  CAMELOT_EINFEASIBLE = -5,  /* no allocation satisfies the constraints              */
+  CAMELOT_EDEVICE = -6,      /* a HIP call failed or a device worker reported error  */
+  CAMELOT_ESTOPPED = -7      /* pipeline already stopped / workers exited            */
+} camelot_status;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* camelot_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t camelot_version(void);
+
+/* ------------------------------------------------------------------ device info */
+typedef struct {
+  int32_t n_cus;             /* compute units (256 on MI355X)                        */
+  int32_t n_xcds;            /* XCDs (8); CU-mask bit i lands on XCD i % n_xcds      */
+  int64_t wall_clock_hz;     /* rate of the device's constant wall clock             */
+  int64_t hbm_bytes;         /* device memory capacity                               */
+  char arch[32];             /* e.g. "gfx950"                                        */
+} camelot_device_info;
+
+/* Fills *out for the current device. */
+int32_t camelot_device_query(camelot_device_info* out);
+
+/* ------------------------------------------------------------------ allocation
+ * Section V, Eq. 1 and Eq. 3 over an integer profile table.
+ *
+ * Decision variables per stage i: instance count N_i (1..max_inst_per_stage) and
+ * CU share p_i = (k_i + 1) * cu_step (k_i = 0 .. cu_total/cu_step - 1); one batch
+ * size b = batches[j] for the whole pipeline.
+ * Throughput T = min_i N_i * b * 1e9 / lat_ns[i][k_i][j]   (queries/s, exact rational)
+ * Constraints (Eq. 1 / Eq. 3):
+ *   sum N_i p_i <= cu_total; sum N_i <= max_instances;
+ *   sum N_i bw_bps[i][k_i][j] <= hbm_bw_budget; sum N_i mem_bytes[i][j] <= hbm_bytes_budget;
+ *   batch_wait_ns[j] + sum lat_ns[i][k_i][j] <= qos_ns.
+ * A table entry lat_ns <= 0 marks an unmeasured point, never chosen.
+ * Ties: peak -> larger T, fewer CUs, lower latency, then the lexicographically
+ * smallest (j, N_1, k_1, N_2, k_2, ...); min -> fewer CUs, larger T, lower latency,
+ * lexicographic.  Results are exact: integer tables, 128-bit cross-multiplied
+ * rational comparisons.
+ * Table layouts: lat_ns and bw_bps are [n_stages][cu_total/cu_step][n_batches]
+ * row-major int64; mem_bytes is [n_stages][n_batches]; batch_wait_ns is
+ * [n_batches] or NULL (all zero). All owned by the caller, read only.
+ */
+#define CAMELOT_MAX_STAGES 8
+
+typedef struct {
+  int32_t n_stages;            /* 1..CAMELOT_MAX_STAGES                              */
+  int32_t cu_total;            /* R: CUs available (<= 256)                          */
+  int32_t cu_step;             /* share granularity; cu_total % cu_step == 0         */
+  int32_t max_instances;       /* I: cap on sum of N_i (Eq. 1 constraint 2)          */
+  int32_t max_inst_per_stage;  /* search bound on each N_i (<= max_instances)       */
+  int32_t n_batches;           /* >= 1                                               */
+  const int32_t* batches;      /* [n_batches], each >= 1                             */
+  int64_t qos_ns;              /* latency target                                     */
+  int64_t hbm_bytes_budget;    /* F                                                  */
+  int64_t hbm_bw_budget;       /* BW, bytes/s                                        */
+  const int64_t* lat_ns;
+  const int64_t* bw_bps;
+  const int64_t* mem_bytes;
+  const int64_t* batch_wait_ns;
+} camelot_problem;
+
+typedef struct {
+  int32_t n_stages;
+  int32_t batch;               /* chosen b                                           */
+  int32_t batch_index;         /* its index in problem.batches                       */
+  int32_t n[CAMELOT_MAX_STAGES];   /* instances per stage                            */
+  int32_t cu[CAMELOT_MAX_STAGES];  /* CUs per instance                               */
+  int64_t thr_num, thr_den;    /* T = thr_num / thr_den queries/s, gcd-reduced       */
+  int64_t lat_ns;              /* batch_wait + sum of stage latencies                */
+  int64_t cu_used;             /* sum N_i * cu_i                                     */
+} camelot_alloc;
+
+/* Eq. 1: maximise T. CAMELOT_EINFEASIBLE when no point satisfies the constraints. */
+int32_t camelot_alloc_peak(const camelot_problem* problem, camelot_alloc* out);
+
+/* Eq. 3 with the load constraint T >= load_num / load_den (queries/s):
+ * minimise sum N_i p_i. CAMELOT_EINFEASIBLE when no point reaches the load. */
+int32_t camelot_alloc_min(const camelot_problem* problem, int64_t load_num,
+                          int64_t load_den, camelot_alloc* out);
+
+/* Evaluate one given point (instances/shares in *inout, batch_index set): fills
+ * thr/lat/cu_used and returns CAMELOT_OK if it satisfies every constraint,
+ * CAMELOT_EINFEASIBLE otherwise (fields still filled when the table has the point). */
+int32_t camelot_alloc_eval(const camelot_problem* problem, camelot_alloc* inout);
+
+/* ------------------------------------------------------------------ stages
+ * The synthetic microservice stages. Row = one query. All activations are
+ * row-major [rows][dim].
+ *   GEMM_RELU    in f32[in_dim], out f32[out_dim] = max(0, x W); weights[0] = W f32
+ *                [in_dim][out_dim] row-major ([in, out]).
+ *   GEMM_ARGMAX  in f32[in_dim]; s = x W with W f32 [in_dim][out_dim]; output is a
+ *                result of k = 1: (argmax, max score), lowest index on ties.
+ *   LOGMEL       in f32[2000] (16 kHz); 11 frames of 400 (hop 160), Hamming window,
+ *                512-point FFT power, 40 HTK mel bands over 0..8 kHz,
+ *                ln(max(E, 1e-10)); out f32[440] frame-major. No weights.
+ *   MLP_BF16     in f32[dims[0]] rounded to BF16 (nearest-even); layers l = 1..L with
+ *                weights[l-1] BF16 [dims[l]][dims[l-1]] ([out, in]);
+ *                hidden h_l = bf16(max(0, h_{l-1} W_l^T)), FP32 accumulation;
+ *                out f32[dims[L]] = h_{L-1} W_L^T (no rounding). dims[l] % 16 == 0
+ *                for l >= 1 and dims[l] % 8 == 0 for all l.
+ *   TOPK         in f32[in_dim]; output is a result of k entries (index, value) in
+ *                descending value, equal values by ascending index.
+ * GEMM_ARGMAX and TOPK produce results and must be the last stage of a pipeline.
+ */
+typedef enum {
+  CAMELOT_STAGE_GEMM_RELU = 1,
+  CAMELOT_STAGE_GEMM_ARGMAX = 2,
+  CAMELOT_STAGE_LOGMEL = 3,
+  CAMELOT_STAGE_MLP_BF16 = 4,
+  CAMELOT_STAGE_TOPK = 5
+} camelot_stage_kind;
+
+#define CAMELOT_MAX_LAYERS 8
+#define CAMELOT_MAX_K 128
+#define CAMELOT_MAX_BATCH 128
+
+typedef struct {
+  int32_t kind;                          /* camelot_stage_kind                       */
+  int32_t n_layers;                      /* MLP_BF16: L; GEMM_*: 1; others 0          */
+  int32_t dims[CAMELOT_MAX_LAYERS + 1];  /* dims[0] = in_dim, dims[n_layers] = out   */
+  int32_t k;                             /* TOPK: k (1..CAMELOT_MAX_K)                */
+  const void* weights[CAMELOT_MAX_LAYERS]; /* device pointers, borrowed for the
+                                              lifetime of any object using them      */
+} camelot_stage_desc;
+
+/* Bytes of one input row / one output row of a stage (result stages: k entries of
+ * int32 index + f32 value = 8 * k bytes). Returns < 0 on a bad descriptor. */
+int64_t camelot_stage_row_bytes_in(const camelot_stage_desc* stage);
+int64_t camelot_stage_row_bytes_out(const camelot_stage_desc* stage);
+
+/* Run one stage over `rows` rows (0..CAMELOT_MAX_BATCH) on `n_cus` CUs starting
+ * at CU-mask bit `cu_offset` (n_cus and cu_offset multiples of 8; 0 n_cus = all
+ * CUs), `reps` times back to back (the same input each time), as the persistent
+ * worker does inside a pipeline (same kernel, same grid).
+ *   in   device, rows * row_bytes_in
+ *   out  device, rows * row_bytes_out (result stages: [rows][k] int32 indices
+ *        followed by [rows][k] f32 values, i.e. 2 planes)
+ *   ns_per_rep (may be NULL) receives the device-clock time of the reps divided
+ *        by reps, in ns.
+ * Synchronous: returns after the work completed. */
+int32_t camelot_stage_run(const camelot_stage_desc* stage, const void* in, void* out,
+                          int32_t rows, int32_t n_cus, int32_t cu_offset, int32_t reps,
+                          double* ns_per_rep);
+
+/* ------------------------------------------------------------------ pipelines
+ * A pipeline is a chain of stages, each run by one persistent worker kernel on its
+ * own CU-masked stream (stage i on cu[i] CUs). Stage i hands its batch to stage
+ * i+1 through a device-global ring of ring_depth slots with doorbells
+ * (CAMELOT_HANDOFF_DEVICE) or, for the baseline, by a device->pinned host->device
+ * copy per batch driven by a host thread (CAMELOT_HANDOFF_HOST).
+ *
+ * Queries arrive as requests of 1..max_rows_per_request rows. Stage 0 forms a
+ * batch from whole waiting requests in arrival order, at most max_batch rows,
+ * and starts it when at least batch_target rows wait or the oldest waiting request
+ * has waited batch_timeout_ns (batch_target 1 = start as soon as anything waits:
+ * continuous batching). Results come out in submit order, one per row.
+ *
+ * Ingest modes:
+ *   CAMELOT_INGEST_HOST    camelot_pipeline_submit copies each request into a
+ *                          pinned ingest ring; arrival time = submit time.
+ *   CAMELOT_INGEST_REPLAY  the requests (ids, rows, arrival times, payload rows)
+ *                          are resident in device memory before the run starts
+ *                          (camelot_pipeline_replay); stage 0 admits request r
+ *                          once the device clock passes its arrival time.
+ */
+typedef enum { CAMELOT_HANDOFF_DEVICE = 0, CAMELOT_HANDOFF_HOST = 1 } camelot_handoff;
+typedef enum { CAMELOT_INGEST_HOST = 0, CAMELOT_INGEST_REPLAY = 1 } camelot_ingest;
+
+typedef struct {
+  int32_t n_stages;
+  camelot_stage_desc stages[CAMELOT_MAX_STAGES];
+  int32_t cu[CAMELOT_MAX_STAGES];  /* CUs per stage, multiples of 8, sum <= 256 - cu_offset */
+  int32_t cu_offset;           /* first CU-mask bit of this pipeline (multiple of 8) */
+  int32_t max_batch;           /* rows per batch, 1..CAMELOT_MAX_BATCH               */
+  int32_t batch_target;        /* start a batch once this many rows wait (>= 1)     */
+  int64_t batch_timeout_ns;    /* ... or once the oldest waited this long           */
+  int32_t ring_depth;          /* slots per device ring, >= 2                        */
+  int32_t handoff;             /* camelot_handoff                                    */
+  int32_t ingest;              /* camelot_ingest                                     */
+  int32_t max_rows_per_request;/* 1..max_batch                                       */
+  int32_t ingest_capacity;     /* requests the ingest queue holds (host mode)        */
+  int32_t egress_capacity;     /* result rows buffered for drain                     */
+  int64_t idle_timeout_ns;     /* workers exit after this long with nothing to do   */
+  int64_t hbm_budget_bytes;    /* admission: ENOMEM if the footprint exceeds it (0 = no limit) */
+} camelot_pipeline_config;
+
+typedef struct camelot_pipeline camelot_pipeline;
+
+/* Builds rings, streams and workers and launches the workers (HOST ingest) or
+ * prepares them (REPLAY ingest; workers start in camelot_pipeline_replay).
+ * *out receives the handle. ENOMEM when the footprint exceeds hbm_budget_bytes. */
+int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, camelot_pipeline** out);
+
+/* HBM bytes the pipeline holds (rings, scratch, control; weights are borrowed and
+ * not counted). */
+int64_t camelot_pipeline_footprint(const camelot_pipeline* p);
+
+/* Host ingest. Copies `rows` rows of payload (host pointer, rows * row_bytes_in of
+ * stage 0) before returning. query_id must exceed every id submitted before on this
+ * pipeline. EAGAIN when the ingest queue is full; ESTOPPED after destroy/stop. */
+int32_t camelot_pipeline_submit(camelot_pipeline* p, uint64_t query_id,
+                                const void* payload, int32_t rows);
+
+/* One result row. t_ns: [0] arrival, then per stage (start, end) of the batch,
+ * then done; all in ns of the device clock since the pipeline's epoch. */
+typedef struct {
+  uint64_t query_id;
+  int32_t row;                          /* row index within the request            */
+  int32_t n_out;                        /* k                                       */
+  int32_t idx[CAMELOT_MAX_K];
+  float val[CAMELOT_MAX_K];
+  uint64_t t_ns[2 * CAMELOT_MAX_STAGES + 2];
+} camelot_result;
+
+/* Copies up to max finished rows into out[] in submit order; *n_out receives the
+ * count. Waits up to timeout_ns for at least one (0 = poll). ETIMEDOUT when none
+ * arrived in time; EDEVICE if a worker reported a failure. */
+int32_t camelot_pipeline_drain(camelot_pipeline* p, camelot_result* out, int32_t max,
+                               int32_t* n_out, int64_t timeout_ns);
+
+/* Device replay ingest: n_req requests with ids[] (strictly increasing), rows[],
+ * arrival_ns[] (ns after the start, non-decreasing) and payload_row[] (index of
+ * the request's first row in `payload`, a device buffer of payload_rows rows of
+ * row_bytes_in). Host arrays are copied. Starts the workers and returns at once;
+ * results are drained as in host mode. */
+int32_t camelot_pipeline_replay(camelot_pipeline* p, int32_t n_req, const uint64_t* ids,
+                                const int32_t* rows, const int64_t* arrival_ns,
+                                const int64_t* payload_row, const void* payload,
+                                int64_t payload_rows);
+
+/* Counters of the run so far. */
+typedef struct {
+  uint64_t submitted_requests, submitted_rows;
+  uint64_t delivered_rows;
+  uint64_t batches[CAMELOT_MAX_STAGES];          /* batches finished per stage      */
+  uint64_t id_sum[CAMELOT_MAX_STAGES];           /* sum of splitmix64(id) per row
+                                                    leaving stage i (mod 2^64)      */
+  uint64_t id_xor[CAMELOT_MAX_STAGES];           /* xor of the same                 */
+  int32_t worker_status[CAMELOT_MAX_STAGES];     /* 0 running/ok, else error code   */
+} camelot_pipeline_stats;
+
+int32_t camelot_pipeline_stats_get(camelot_pipeline* p, camelot_pipeline_stats* out);
+
+/* Stops the workers (they finish the batch in hand and exit), waits for them and
+ * frees everything. *undelivered (may be NULL) receives the number of submitted
+ * rows never delivered. */
+int32_t camelot_pipeline_destroy(camelot_pipeline* p, uint64_t* undelivered);
+
+/* ------------------------------------------------------------------ handoff benchmark
+ * Section IV-B's claim, measured: a producer worker on cu_producer CUs writes
+ * n_slots_total slots of slot_bytes into a device ring of depth slots; a consumer
+ * worker on the next cu_consumer CUs waits on each slot's doorbell, reads every
+ * word into a checksum and frees the slot. Both run concurrently.
+ * out: [0] seconds of the run (device clock), [1] bytes moved (written + read),
+ *      [2] checksum sum, [3] checksum xor (compare with
+ *      camelot_handoff_expected), [4] handoff GB/s.
+ * mode CAMELOT_HANDOFF_HOST measures the host-staged path instead: per slot a
+ * device->pinned and a pinned->device copy (out[1] counts the bytes of both). */
+int32_t camelot_handoff_bench(int32_t mode, int64_t slot_bytes, int32_t depth,
+                              int64_t n_slots_total, int32_t cu_producer,
+                              int32_t cu_consumer, double* out);
+
+/* Expected (sum, xor) checksum of the handoff pattern (host computation). */
+int32_t camelot_handoff_expected(int64_t slot_bytes, int64_t n_slots_total,
+                                 uint64_t* sum, uint64_t* xr);
+
+/* ------------------------------------------------------------------ predictor
+ * Learned contention predictor (replaces Section V-A's per-microservice model):
+ * MLP 16 -> 64 (ReLU) -> 64 (ReLU) -> 1, FP32, predicting ln(latency ns).
+ * Parameters live in one device buffer of CAMELOT_PRED_NPARAMS floats in the order
+ * W1[16][64], b1[64], W2[64][64], b2[64], W3[64][1], b3[1] (weights [in, out]).
+ * Loss L = mean over the minibatch of (yhat - y)^2.
+ */
+#define CAMELOT_PRED_NIN 16
+#define CAMELOT_PRED_NHID 64
+#define CAMELOT_PRED_NPARAMS (16 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* yhat[m] (device f32) for x (device f32 [m][16]). */
+int32_t camelot_predictor_forward(const float* params, const float* x, int32_t m,
+                                  float* yhat, void* stream);
+
+/* grad (device f32 [NPARAMS]) = dL/dparams over the minibatch x [m][16], y [m];
+ * *loss_out (host, may be NULL) receives L. */
+int32_t camelot_predictor_grad(const float* params, const float* x, const float* y,
+                               int32_t m, float* grad, float* loss_out, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at step t >= 1 on device buffers
+ * params, grad, m1, m2 (each NPARAMS floats; m1 and m2 start at zero). */
+int32_t camelot_predictor_adam(float* params, const float* grad, float* m1, float* m2,
+                               int32_t t, float lr, void* stream);
+
+/* Trains for `epochs` over x [n][16], y [n] (device) with minibatches of `batch`
+ * rows in a fixed order (row permutation `perm` [epochs][n] int32 device, or NULL
+ * for sequential); params/m1/m2 device as above; step counter continues from *t.
+ * Per-epoch mean loss written to epoch_loss (host [epochs], may be NULL). */
+int32_t camelot_predictor_train(float* params, float* m1, float* m2, int32_t* t,
+                                const float* x, const float* y, int32_t n, int32_t batch,
+                                int32_t epochs, const int32_t* perm, float lr,
+                                float* epoch_loss, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAMELOT_H */

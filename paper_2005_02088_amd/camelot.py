@@ -1,0 +1,363 @@
+"""Thin ctypes binding of libcamelot (include/camelot.h): argument marshalling only.
+
+Every computation runs in the library (HIP kernels on the GPU, C++ on the host for
+the allocator). Importing this module raises if libcamelot.so has not been built;
+there is no fallback path. Device buffers are passed as integers (e.g. a torch
+tensor's ``data_ptr()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcamelot.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2005_02088_amd.build`")
+_lib = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
+
+# ------------------------------------------------------------------ constants
+OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EINFEASIBLE, EDEVICE, ESTOPPED = 0, -1, -2, -3, -4, -5, -6, -7
+MAX_STAGES, MAX_LAYERS, MAX_K, MAX_BATCH = 8, 8, 128, 128
+STAGE_GEMM_RELU, STAGE_GEMM_ARGMAX, STAGE_LOGMEL, STAGE_MLP_BF16, STAGE_TOPK = 1, 2, 3, 4, 5
+HANDOFF_DEVICE, HANDOFF_HOST = 0, 1
+INGEST_HOST, INGEST_REPLAY = 0, 1
+PRED_NIN, PRED_NHID = 16, 64
+PRED_NPARAMS = 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EAGAIN: "EAGAIN", ETIMEDOUT: "ETIMEDOUT",
+          EINFEASIBLE: "EINFEASIBLE", EDEVICE: "EDEVICE", ESTOPPED: "ESTOPPED"}
+
+
+class CamelotError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ------------------------------------------------------------------ structs
+class DeviceInfo(C.Structure):
+    _fields_ = [("n_cus", C.c_int32), ("n_xcds", C.c_int32), ("wall_clock_hz", C.c_int64),
+                ("hbm_bytes", C.c_int64), ("arch", C.c_char * 32)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_stages", C.c_int32), ("cu_total", C.c_int32), ("cu_step", C.c_int32),
+                ("max_instances", C.c_int32), ("max_inst_per_stage", C.c_int32),
+                ("n_batches", C.c_int32), ("batches", C.POINTER(C.c_int32)),
+                ("qos_ns", C.c_int64), ("hbm_bytes_budget", C.c_int64), ("hbm_bw_budget", C.c_int64),
+                ("lat_ns", C.POINTER(C.c_int64)), ("bw_bps", C.POINTER(C.c_int64)),
+                ("mem_bytes", C.POINTER(C.c_int64)), ("batch_wait_ns", C.POINTER(C.c_int64))]
+
+
+class Alloc(C.Structure):
+    _fields_ = [("n_stages", C.c_int32), ("batch", C.c_int32), ("batch_index", C.c_int32),
+                ("n", C.c_int32 * MAX_STAGES), ("cu", C.c_int32 * MAX_STAGES),
+                ("thr_num", C.c_int64), ("thr_den", C.c_int64), ("lat_ns", C.c_int64),
+                ("cu_used", C.c_int64)]
+
+    def as_dict(self):
+        S = self.n_stages
+        return {"batch": self.batch, "batch_index": self.batch_index, "n": list(self.n[:S]),
+                "cu": list(self.cu[:S]), "thr_num": self.thr_num, "thr_den": self.thr_den,
+                "lat_ns": self.lat_ns, "cu_used": self.cu_used}
+
+
+class StageDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_layers", C.c_int32), ("dims", C.c_int32 * (MAX_LAYERS + 1)),
+                ("k", C.c_int32), ("weights", C.c_void_p * MAX_LAYERS)]
+
+
+class PipelineConfig(C.Structure):
+    _fields_ = [("n_stages", C.c_int32), ("stages", StageDesc * MAX_STAGES), ("cu", C.c_int32 * MAX_STAGES),
+                ("cu_offset", C.c_int32), ("max_batch", C.c_int32), ("batch_target", C.c_int32),
+                ("batch_timeout_ns", C.c_int64), ("ring_depth", C.c_int32), ("handoff", C.c_int32),
+                ("ingest", C.c_int32), ("max_rows_per_request", C.c_int32), ("ingest_capacity", C.c_int32),
+                ("egress_capacity", C.c_int32), ("idle_timeout_ns", C.c_int64),
+                ("hbm_budget_bytes", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("query_id", C.c_uint64), ("row", C.c_int32), ("n_out", C.c_int32),
+                ("idx", C.c_int32 * MAX_K), ("val", C.c_float * MAX_K),
+                ("t_ns", C.c_uint64 * (2 * MAX_STAGES + 2))]
+
+
+class PipelineStats(C.Structure):
+    _fields_ = [("submitted_requests", C.c_uint64), ("submitted_rows", C.c_uint64),
+                ("delivered_rows", C.c_uint64), ("batches", C.c_uint64 * MAX_STAGES),
+                ("id_sum", C.c_uint64 * MAX_STAGES), ("id_xor", C.c_uint64 * MAX_STAGES),
+                ("worker_status", C.c_int32 * MAX_STAGES)]
+
+
+STRUCTS = {"camelot_device_info": DeviceInfo, "camelot_problem": Problem, "camelot_alloc": Alloc,
+           "camelot_stage_desc": StageDesc, "camelot_pipeline_config": PipelineConfig,
+           "camelot_result": Result, "camelot_pipeline_stats": PipelineStats}
+
+# ------------------------------------------------------------------ prototypes
+_P = C.c_void_p
+_SIGS = {
+    "camelot_last_error": (C.c_char_p, []),
+    "camelot_version": (C.c_int32, []),
+    "camelot_device_query": (C.c_int32, [C.POINTER(DeviceInfo)]),
+    "camelot_alloc_peak": (C.c_int32, [C.POINTER(Problem), C.POINTER(Alloc)]),
+    "camelot_alloc_min": (C.c_int32, [C.POINTER(Problem), C.c_int64, C.c_int64, C.POINTER(Alloc)]),
+    "camelot_alloc_eval": (C.c_int32, [C.POINTER(Problem), C.POINTER(Alloc)]),
+    "camelot_stage_row_bytes_in": (C.c_int64, [C.POINTER(StageDesc)]),
+    "camelot_stage_row_bytes_out": (C.c_int64, [C.POINTER(StageDesc)]),
+    "camelot_stage_run": (C.c_int32, [C.POINTER(StageDesc), _P, _P, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_int32, C.POINTER(C.c_double)]),
+    "camelot_pipeline_create": (C.c_int32, [C.POINTER(PipelineConfig), C.POINTER(_P)]),
+    "camelot_pipeline_footprint": (C.c_int64, [_P]),
+    "camelot_pipeline_submit": (C.c_int32, [_P, C.c_uint64, _P, C.c_int32]),
+    "camelot_pipeline_drain": (C.c_int32, [_P, C.POINTER(Result), C.c_int32, C.POINTER(C.c_int32),
+                                           C.c_int64]),
+    "camelot_pipeline_replay": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, C.c_int64]),
+    "camelot_pipeline_stats_get": (C.c_int32, [_P, C.POINTER(PipelineStats)]),
+    "camelot_pipeline_destroy": (C.c_int32, [_P, C.POINTER(C.c_uint64)]),
+    "camelot_handoff_bench": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
+                                          C.c_int32, C.POINTER(C.c_double)]),
+    "camelot_handoff_expected": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_uint64),
+                                             C.POINTER(C.c_uint64)]),
+    "camelot_predictor_forward": (C.c_int32, [_P, _P, C.c_int32, _P, _P]),
+    "camelot_predictor_grad": (C.c_int32, [_P, _P, _P, C.c_int32, _P, C.POINTER(C.c_float), _P]),
+    "camelot_predictor_adam": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_float, _P]),
+    "camelot_predictor_train": (C.c_int32, [_P, _P, _P, C.POINTER(C.c_int32), _P, _P, C.c_int32,
+                                            C.c_int32, C.c_int32, _P, C.c_float, _P, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+EXPORTS = sorted(_SIGS)
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise CamelotError(rc, _lib.camelot_last_error().decode())
+    return rc
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+# ------------------------------------------------------------------ device / misc
+def camelot_version() -> int:
+    return _lib.camelot_version()
+
+
+def camelot_device_query() -> DeviceInfo:
+    d = DeviceInfo()
+    _check(_lib.camelot_device_query(C.byref(d)))
+    return d
+
+
+# ------------------------------------------------------------------ allocation
+class ProblemArrays:
+    """Keeps the numpy arrays a Problem points at alive."""
+
+    def __init__(self, *, cu_total, cu_step, max_instances, max_inst_per_stage, batches, qos_ns,
+                 hbm_bytes_budget, hbm_bw_budget, lat_ns, bw_bps, mem_bytes, batch_wait_ns=None):
+        self.batches = np.ascontiguousarray(batches, dtype=np.int32)
+        self.lat = _i64(lat_ns)
+        self.bw = _i64(bw_bps)
+        self.mem = _i64(mem_bytes)
+        self.wait = None if batch_wait_ns is None else _i64(batch_wait_ns)
+        self.struct = Problem(
+            n_stages=self.lat.shape[0], cu_total=cu_total, cu_step=cu_step, max_instances=max_instances,
+            max_inst_per_stage=max_inst_per_stage, n_batches=len(self.batches),
+            batches=_ptr(self.batches, C.c_int32), qos_ns=int(qos_ns),
+            hbm_bytes_budget=int(hbm_bytes_budget), hbm_bw_budget=int(hbm_bw_budget),
+            lat_ns=_ptr(self.lat, C.c_int64), bw_bps=_ptr(self.bw, C.c_int64),
+            mem_bytes=_ptr(self.mem, C.c_int64),
+            batch_wait_ns=_ptr(self.wait, C.c_int64) if self.wait is not None else None)
+
+
+def camelot_alloc_peak(problem: ProblemArrays):
+    """Returns the Alloc, or None when infeasible."""
+    a = Alloc()
+    rc = _lib.camelot_alloc_peak(C.byref(problem.struct), C.byref(a))
+    if rc == EINFEASIBLE:
+        return None
+    _check(rc)
+    return a
+
+
+def camelot_alloc_min(problem: ProblemArrays, load_num: int, load_den: int = 1):
+    a = Alloc()
+    rc = _lib.camelot_alloc_min(C.byref(problem.struct), int(load_num), int(load_den), C.byref(a))
+    if rc == EINFEASIBLE:
+        return None
+    _check(rc)
+    return a
+
+
+def camelot_alloc_eval(problem: ProblemArrays, batch_index: int, n, cu):
+    """Returns (feasible, Alloc) for the given point."""
+    a = Alloc()
+    a.batch_index = batch_index
+    for i, (nn, cc) in enumerate(zip(n, cu)):
+        a.n[i] = nn
+        a.cu[i] = cc
+    rc = _lib.camelot_alloc_eval(C.byref(problem.struct), C.byref(a))
+    if rc == EINFEASIBLE:
+        return False, a
+    _check(rc)
+    return True, a
+
+
+# ------------------------------------------------------------------ stages
+def stage_desc(kind: int, dims=(), weights=(), k: int = 0, n_layers: int | None = None) -> StageDesc:
+    d = StageDesc()
+    d.kind = kind
+    dims = list(dims)
+    d.n_layers = n_layers if n_layers is not None else max(len(dims) - 1, 0)
+    for i, v in enumerate(dims):
+        d.dims[i] = v
+    d.k = k
+    for i, w in enumerate(weights):
+        d.weights[i] = int(w)
+    return d
+
+
+def camelot_stage_row_bytes_in(desc: StageDesc) -> int:
+    return _check(_lib.camelot_stage_row_bytes_in(C.byref(desc)))
+
+
+def camelot_stage_row_bytes_out(desc: StageDesc) -> int:
+    return _check(_lib.camelot_stage_row_bytes_out(C.byref(desc)))
+
+
+def camelot_stage_run(desc: StageDesc, in_ptr: int, out_ptr: int, rows: int, n_cus: int = 0,
+                      cu_offset: int = 0, reps: int = 1) -> float:
+    """Runs the stage worker once over `reps` batches; returns ns per batch."""
+    ns = C.c_double(0.0)
+    _check(_lib.camelot_stage_run(C.byref(desc), in_ptr, out_ptr, rows, n_cus, cu_offset, reps, C.byref(ns)))
+    return ns.value
+
+
+# ------------------------------------------------------------------ pipelines
+def pipeline_config(stages, cu, *, cu_offset=0, max_batch=32, batch_target=1, batch_timeout_ns=0,
+                    ring_depth=4, handoff=HANDOFF_DEVICE, ingest=INGEST_HOST, max_rows_per_request=1,
+                    ingest_capacity=4096, egress_capacity=65536, idle_timeout_ns=20_000_000_000,
+                    hbm_budget_bytes=0) -> PipelineConfig:
+    c = PipelineConfig()
+    c.n_stages = len(stages)
+    for i, s in enumerate(stages):
+        c.stages[i] = s
+        c.cu[i] = cu[i]
+    c.cu_offset = cu_offset
+    c.max_batch = max_batch
+    c.batch_target = batch_target
+    c.batch_timeout_ns = batch_timeout_ns
+    c.ring_depth = ring_depth
+    c.handoff = handoff
+    c.ingest = ingest
+    c.max_rows_per_request = max_rows_per_request
+    c.ingest_capacity = ingest_capacity
+    c.egress_capacity = egress_capacity
+    c.idle_timeout_ns = idle_timeout_ns
+    c.hbm_budget_bytes = hbm_budget_bytes
+    return c
+
+
+def camelot_pipeline_create(cfg: PipelineConfig) -> int:
+    h = C.c_void_p()
+    _check(_lib.camelot_pipeline_create(C.byref(cfg), C.byref(h)))
+    return h.value
+
+
+def camelot_pipeline_footprint(p: int) -> int:
+    return _lib.camelot_pipeline_footprint(p)
+
+
+def camelot_pipeline_submit(p: int, query_id: int, payload: np.ndarray, rows: int) -> int:
+    """Returns OK or EAGAIN (queue full); raises on other errors."""
+    buf = np.ascontiguousarray(payload)
+    rc = _lib.camelot_pipeline_submit(p, int(query_id), buf.ctypes.data, int(rows))
+    if rc == EAGAIN:
+        return EAGAIN
+    return _check(rc)
+
+
+def camelot_pipeline_drain(p: int, max_results: int = 4096, timeout_ns: int = 0):
+    """Returns a list of Result structs (possibly empty on timeout)."""
+    out = (Result * max_results)()
+    n = C.c_int32(0)
+    rc = _lib.camelot_pipeline_drain(p, out, max_results, C.byref(n), int(timeout_ns))
+    if rc == ETIMEDOUT:
+        return []
+    _check(rc)
+    return out[: n.value]
+
+
+def camelot_pipeline_replay(p: int, ids, rows, arrival_ns, payload_row, payload_ptr: int, payload_rows: int):
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+    prow = np.ascontiguousarray(payload_row, dtype=np.int64)
+    _check(_lib.camelot_pipeline_replay(p, len(ids), ids.ctypes.data, rows.ctypes.data, arr.ctypes.data,
+                                        prow.ctypes.data, payload_ptr, int(payload_rows)))
+
+
+def camelot_pipeline_stats_get(p: int) -> PipelineStats:
+    s = PipelineStats()
+    _check(_lib.camelot_pipeline_stats_get(p, C.byref(s)))
+    return s
+
+
+def camelot_pipeline_destroy(p: int) -> int:
+    """Returns the number of undelivered rows."""
+    u = C.c_uint64(0)
+    _check(_lib.camelot_pipeline_destroy(p, C.byref(u)))
+    return u.value
+
+
+# ------------------------------------------------------------------ handoff
+def camelot_handoff_bench(mode: int, slot_bytes: int, depth: int, n_slots: int, cu_producer: int = 128,
+                          cu_consumer: int = 128) -> dict:
+    out = (C.c_double * 5)()
+    _check(_lib.camelot_handoff_bench(mode, slot_bytes, depth, n_slots, cu_producer, cu_consumer, out))
+    raw = bytes(out)
+    s = int.from_bytes(raw[16:24], "little")
+    x = int.from_bytes(raw[24:32], "little")
+    return {"seconds": out[0], "bytes": out[1], "sum": s, "xor": x, "gbs": out[4]}
+
+
+def camelot_handoff_expected(slot_bytes: int, n_slots: int):
+    s, x = C.c_uint64(0), C.c_uint64(0)
+    _check(_lib.camelot_handoff_expected(slot_bytes, n_slots, C.byref(s), C.byref(x)))
+    return s.value, x.value
+
+
+# ------------------------------------------------------------------ predictor
+def camelot_predictor_forward(params: int, x: int, m: int, yhat: int, stream: int = 0):
+    _check(_lib.camelot_predictor_forward(params, x, m, yhat, stream or None))
+
+
+def camelot_predictor_grad(params: int, x: int, y: int, m: int, grad: int, stream: int = 0) -> float:
+    loss = C.c_float(0.0)
+    _check(_lib.camelot_predictor_grad(params, x, y, m, grad, C.byref(loss), stream or None))
+    return loss.value
+
+
+def camelot_predictor_adam(params: int, grad: int, m1: int, m2: int, t: int, lr: float, stream: int = 0):
+    _check(_lib.camelot_predictor_adam(params, grad, m1, m2, t, lr, stream or None))
+
+
+def camelot_predictor_train(params: int, m1: int, m2: int, t: int, x: int, y: int, n: int, batch: int,
+                            epochs: int, perm: int = 0, lr: float = 1e-3, stream: int = 0):
+    """Returns (new step counter, per-epoch mean loss array)."""
+    tt = C.c_int32(t)
+    losses = np.zeros(max(epochs, 1), np.float32)
+    _check(_lib.camelot_predictor_train(params, m1, m2, C.byref(tt), x, y, n, batch, epochs, perm or None,
+                                        lr, losses.ctypes.data, stream or None))
+    return tt.value, losses[:epochs]

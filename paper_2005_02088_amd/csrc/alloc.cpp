@@ -1,0 +1,222 @@
+// Exact solver of the allocation problems of Section V over an integer profile
+// table: Eq. 1 (maximise the pipeline throughput under the QoS target and the
+// resource constraints) and Eq. 3 (minimise the computational resources while the
+// throughput reaches a given load).
+//
+// Search: depth-first over (batch index, N_1, k_1, N_2, k_2, ...) in lexicographic
+// order with pruning on the additive constraints (CUs, instances, bandwidth,
+// memory, latency are sums of non-negative terms) and on the objective bound
+// (the throughput of a partial assignment can only fall as stages are added).
+// A candidate replaces the incumbent only when strictly better, so among equal
+// candidates the lexicographically first one is kept. Throughputs are compared
+// as exact rationals with 128-bit cross products.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+
+#include "../../include/camelot.h"
+#include "errors.h"
+
+namespace {
+
+constexpr int64_t kNsPerS = 1000000000LL;
+typedef __int128 i128;
+
+struct Rat {
+  int64_t num = 0, den = 1;   // den > 0
+};
+
+inline int cmp(const Rat& a, const Rat& b) {   // sign of a - b
+  const i128 l = (i128)a.num * b.den, r = (i128)b.num * a.den;
+  return l < r ? -1 : (l > r ? 1 : 0);
+}
+
+struct Search {
+  const camelot_problem* p;
+  int S, K, nmax, bi;
+  int64_t b, wait;
+  bool peak;                  // true: Eq. 1; false: Eq. 3 with load
+  Rat load;
+  int n[CAMELOT_MAX_STAGES], k[CAMELOT_MAX_STAGES];
+  bool have = false;
+  camelot_alloc best;
+  Rat best_thr;
+
+  int64_t lat(int s, int kk) const { return p->lat_ns[((int64_t)s * K + kk) * p->n_batches + bi]; }
+  int64_t bw(int s, int kk) const { return p->bw_bps[((int64_t)s * K + kk) * p->n_batches + bi]; }
+  int64_t mem(int s) const { return p->mem_bytes[(int64_t)s * p->n_batches + bi]; }
+
+  // true when (thr, cu, lat) is strictly better than the incumbent
+  bool better(const Rat& thr, int64_t cu, int64_t latency) const {
+    if (!have) return true;
+    if (peak) {
+      const int c = cmp(thr, best_thr);
+      if (c != 0) return c > 0;
+      if (cu != best.cu_used) return cu < best.cu_used;
+      return latency < best.lat_ns;
+    }
+    if (cu != best.cu_used) return cu < best.cu_used;
+    const int c = cmp(thr, best_thr);
+    if (c != 0) return c > 0;
+    return latency < best.lat_ns;
+  }
+
+  void leaf(const Rat& thr, int64_t cu, int64_t latency) {
+    if (!peak && cmp(thr, load) < 0) return;
+    if (!better(thr, cu, latency)) return;
+    have = true;
+    best_thr = thr;
+    std::memset(&best, 0, sizeof(best));
+    best.n_stages = S;
+    best.batch = (int32_t)b;
+    best.batch_index = bi;
+    for (int s = 0; s < S; ++s) { best.n[s] = n[s]; best.cu[s] = (k[s] + 1) * p->cu_step; }
+    const int64_t g = std::gcd(thr.num, thr.den);
+    best.thr_num = thr.num / g;
+    best.thr_den = thr.den / g;
+    best.lat_ns = latency;
+    best.cu_used = cu;
+  }
+
+  void rec(int s, int64_t cu, int64_t inst, int64_t bwsum, int64_t memsum, int64_t latsum,
+           bool has_thr, Rat thr) {
+    if (s == S) { leaf(thr, cu, latsum); return; }
+    for (int nn = 1; nn <= nmax; ++nn) {
+      const int64_t inst2 = inst + nn;
+      if (inst2 > p->max_instances) break;
+      const int64_t mem2 = memsum + nn * mem(s);
+      if (mem2 > p->hbm_bytes_budget) break;
+      for (int kk = 0; kk < K; ++kk) {
+        const int64_t L = lat(s, kk);
+        if (L <= 0) continue;
+        const int64_t cu2 = cu + (int64_t)nn * (kk + 1) * p->cu_step;
+        if (cu2 > p->cu_total) break;                     // shares only grow with kk
+        const int64_t bw2 = bwsum + nn * bw(s, kk);
+        if (bw2 > p->hbm_bw_budget) continue;
+        const int64_t lat2 = latsum + L;
+        if (lat2 > p->qos_ns) continue;
+        Rat t{(int64_t)nn * b * kNsPerS, L};
+        Rat thr2 = (!has_thr || cmp(t, thr) < 0) ? t : thr;
+        if (have) {
+          if (peak) {
+            const int c = cmp(thr2, best_thr);
+            if (c < 0) continue;
+            if (c == 0 && cu2 > best.cu_used) continue;
+          } else {
+            if (cu2 > best.cu_used) break;                // larger shares cost more CUs
+          }
+        }
+        if (!peak && cmp(thr2, load) < 0) continue;
+        n[s] = nn;
+        k[s] = kk;
+        rec(s + 1, cu2, inst2, bw2, mem2, lat2, true, thr2);
+      }
+    }
+  }
+};
+
+int validate(const camelot_problem* p) {
+  if (!p) return camelot::fail(CAMELOT_EINVAL, "problem is NULL");
+  if (p->n_stages < 1 || p->n_stages > CAMELOT_MAX_STAGES)
+    return camelot::fail(CAMELOT_EINVAL, "n_stages must be in 1..%d", CAMELOT_MAX_STAGES);
+  if (p->cu_total < 1 || p->cu_step < 1 || p->cu_total % p->cu_step != 0)
+    return camelot::fail(CAMELOT_EINVAL, "cu_total must be a positive multiple of cu_step");
+  if (p->max_instances < 1 || p->max_inst_per_stage < 1)
+    return camelot::fail(CAMELOT_EINVAL, "instance caps must be >= 1");
+  if (p->n_batches < 1 || !p->batches)
+    return camelot::fail(CAMELOT_EINVAL, "need at least one batch size");
+  for (int j = 0; j < p->n_batches; ++j)
+    if (p->batches[j] < 1 || p->batches[j] > (1 << 20))
+      return camelot::fail(CAMELOT_EINVAL, "batch sizes must be in 1..2^20");
+  if (p->max_inst_per_stage > 1024 || p->max_instances > (1 << 20))
+    return camelot::fail(CAMELOT_EINVAL, "instance caps too large");
+  if (!p->lat_ns || !p->bw_bps || !p->mem_bytes)
+    return camelot::fail(CAMELOT_EINVAL, "lat_ns, bw_bps and mem_bytes are required");
+  const int64_t K = p->cu_total / p->cu_step;
+  for (int64_t i = 0; i < (int64_t)p->n_stages * K * p->n_batches; ++i)
+    if (p->bw_bps[i] < 0) return camelot::fail(CAMELOT_EINVAL, "bw_bps entries must be >= 0");
+  for (int64_t i = 0; i < (int64_t)p->n_stages * p->n_batches; ++i)
+    if (p->mem_bytes[i] < 0) return camelot::fail(CAMELOT_EINVAL, "mem_bytes entries must be >= 0");
+  return CAMELOT_OK;
+}
+
+int solve(const camelot_problem* p, bool peak, int64_t load_num, int64_t load_den, camelot_alloc* out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return camelot::fail(CAMELOT_EINVAL, "out is NULL");
+  if (!peak && (load_num < 0 || load_den <= 0))
+    return camelot::fail(CAMELOT_EINVAL, "load must be a non-negative rational with den > 0");
+  Search s;
+  s.p = p;
+  s.S = p->n_stages;
+  s.K = p->cu_total / p->cu_step;
+  s.nmax = std::min(p->max_inst_per_stage, p->max_instances);
+  s.peak = peak;
+  s.load = Rat{load_num, load_den};
+  for (int bi = 0; bi < p->n_batches; ++bi) {
+    s.bi = bi;
+    s.b = p->batches[bi];
+    s.wait = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
+    if (s.wait > p->qos_ns) continue;
+    s.rec(0, 0, 0, 0, 0, s.wait, false, Rat{});
+  }
+  if (!s.have) return camelot::fail(CAMELOT_EINFEASIBLE, "no allocation satisfies the constraints");
+  *out = s.best;
+  return CAMELOT_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t camelot_alloc_peak(const camelot_problem* problem, camelot_alloc* out) {
+  camelot::clear_error();
+  return solve(problem, true, 0, 1, out);
+}
+
+extern "C" int32_t camelot_alloc_min(const camelot_problem* problem, int64_t load_num, int64_t load_den,
+                                     camelot_alloc* out) {
+  camelot::clear_error();
+  return solve(problem, false, load_num, load_den, out);
+}
+
+extern "C" int32_t camelot_alloc_eval(const camelot_problem* p, camelot_alloc* a) {
+  camelot::clear_error();
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!a) return camelot::fail(CAMELOT_EINVAL, "alloc is NULL");
+  const int K = p->cu_total / p->cu_step;
+  const int bi = a->batch_index;
+  if (bi < 0 || bi >= p->n_batches) return camelot::fail(CAMELOT_EINVAL, "batch_index out of range");
+  const int64_t b = p->batches[bi];
+  int64_t cu = 0, inst = 0, bw = 0, mem = 0;
+  int64_t lat = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
+  Rat thr{0, 1};
+  bool has = false;
+  for (int s = 0; s < p->n_stages; ++s) {
+    const int nn = a->n[s];
+    if (nn < 1 || a->cu[s] < p->cu_step || a->cu[s] % p->cu_step != 0 || a->cu[s] > p->cu_total)
+      return camelot::fail(CAMELOT_EINVAL, "stage %d: bad instance count or share", s);
+    const int kk = a->cu[s] / p->cu_step - 1;
+    const int64_t L = p->lat_ns[((int64_t)s * K + kk) * p->n_batches + bi];
+    if (L <= 0) return camelot::fail(CAMELOT_EINFEASIBLE, "stage %d: unmeasured table point", s);
+    cu += (int64_t)nn * a->cu[s];
+    inst += nn;
+    bw += nn * p->bw_bps[((int64_t)s * K + kk) * p->n_batches + bi];
+    mem += nn * p->mem_bytes[(int64_t)s * p->n_batches + bi];
+    lat += L;
+    Rat t{(int64_t)nn * b * kNsPerS, L};
+    if (!has || cmp(t, thr) < 0) thr = t;
+    has = true;
+  }
+  a->n_stages = p->n_stages;
+  a->batch = (int32_t)b;
+  const int64_t g = std::gcd(thr.num, thr.den);
+  a->thr_num = thr.num / g;
+  a->thr_den = thr.den / g;
+  a->lat_ns = lat;
+  a->cu_used = cu;
+  if (cu > p->cu_total || inst > p->max_instances || bw > p->hbm_bw_budget ||
+      mem > p->hbm_bytes_budget || lat > p->qos_ns)
+    return camelot::fail(CAMELOT_EINFEASIBLE, "allocation violates a constraint");
+  return CAMELOT_OK;
+}

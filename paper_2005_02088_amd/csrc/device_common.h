@@ -1,0 +1,267 @@
+// Shared host/device definitions of the Camelot runtime: ring slot layout, worker
+// arguments, control blocks, and the device-side synchronisation primitives
+// (grid barrier, bounded doorbell waits) every persistent stage worker uses.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/camelot.h"
+
+namespace camelot {
+
+constexpr int kThreads = 256;          // 4 wave64s per workgroup
+constexpr int kWaves = kThreads / 64;
+constexpr int kWgPerCu = 2;            // worker grid = 2 workgroups per CU of the share
+constexpr int kMaxBatch = CAMELOT_MAX_BATCH;
+constexpr int kMaxStages = CAMELOT_MAX_STAGES;
+constexpr int kSlotHeaderBytes = 4096;
+
+// Status codes a worker reports (0 = ok / running).
+enum WorkerStatus : int32_t {
+  kStatusOk = 0,
+  kStatusIdleExit = 1,     // idle longer than the idle timeout: exited cleanly
+  kStatusTimeout = 2,      // a bounded wait inside a batch expired
+  kStatusAborted = 3,      // another worker of the same grid aborted
+  kStatusStopped = 4,      // host asked to stop
+};
+
+// Header at the start of every ring slot (device memory). Written by the producer
+// stage's workgroup 0 before the slot's doorbell is rung.
+struct SlotHeader {
+  uint64_t seq;
+  uint32_t n_req;
+  uint32_t n_rows;
+  uint64_t t_stage[2 * kMaxStages];     // device ticks: start/end of each stage so far
+  uint64_t req_id[kMaxBatch];
+  uint64_t req_tarr[kMaxBatch];         // arrival, device ticks
+  uint32_t req_rows[kMaxBatch];
+};
+static_assert(sizeof(SlotHeader) <= kSlotHeaderBytes, "slot header too large");
+
+// One request of the ingest table (replay: device memory; host: pinned ring).
+struct IngestRec {
+  uint64_t id;
+  uint64_t t_arr;          // device ticks (absolute)
+  uint64_t payload_off;    // byte offset of the request's first row in the payload base
+  uint32_t rows;
+  uint32_t valid;          // host ring: == lap+1 once written (torn-read guard)
+};
+
+// Result record header in the egress ring (pinned host memory), followed by
+// k int32 indices and k f32 values.
+struct EgressRec {
+  uint64_t id;
+  uint32_t row;
+  uint32_t n_out;
+  uint64_t t_arr;
+  uint64_t t_done;
+  uint64_t t_stage[2 * kMaxStages];
+};
+
+// Host-written, device-read control block (pinned).
+struct HostCtl {
+  uint64_t stop;
+  uint64_t pad0[15];
+  uint64_t ingest_head;    // requests published by the host
+  uint64_t pad1[15];
+  uint64_t egress_tail;    // result rows consumed by the host
+  uint64_t pad2[15];
+};
+
+// Device-written, host-read block (pinned). One writer per field.
+struct DevPub {
+  uint64_t t0;                              // epoch (device ticks)
+  uint64_t egress_head;                     // result rows published
+  uint64_t ingest_tail;                     // requests taken by stage 0
+  uint64_t batches[kMaxStages];
+  uint64_t id_sum[kMaxStages];
+  uint64_t id_xor[kMaxStages];
+  int32_t status[kMaxStages];
+  int32_t started[kMaxStages];
+  uint64_t pad[16];
+};
+
+// Per-worker device control block (device memory, zeroed at creation).
+struct WorkerCtl {
+  uint32_t bar_count;  uint32_t pad0[31];
+  uint32_t bar_gen;    uint32_t pad1[31];
+  uint32_t abort;      uint32_t pad2[31];
+  // batch descriptor broadcast by workgroup 0 through the grid barrier
+  uint64_t d_seq;
+  uint32_t d_stop;
+  uint32_t d_rows;
+  uint32_t d_nreq;
+  uint32_t d_pad;
+  uint8_t* d_out;                 // payload of the output slot (ring output)
+  SlotHeader* d_out_hdr;          // header of the output slot (ring output)
+  const SlotHeader* d_in_hdr;     // header of the input slot (ring input)
+  uint64_t d_t_start;
+  uint64_t d_egress_base;               // egress row index of this batch's first row
+  uint64_t d_t_stage[2 * kMaxStages];   // stage timestamps of the batch so far
+  const uint8_t* d_rowptr[kMaxBatch];   // input row pointers
+  uint64_t d_row_id[kMaxBatch];         // (request id) per row
+  uint32_t d_row_idx[kMaxBatch];        // row index within its request
+  uint64_t d_row_tarr[kMaxBatch];
+  // persistent state
+  uint64_t next_seq;              // next batch sequence number
+  uint64_t ingest_cursor;         // stage 0: next request to take
+  uint64_t egress_head;            // result rows written (terminal stage)
+  uint64_t ticks_bench;           // bench mode: elapsed device ticks
+  uint64_t sum_acc, xor_acc, batches_acc;
+};
+
+// Stage parameters (device pointers borrowed from the caller or owned by the
+// library's stage object).
+struct StageParams {
+  int32_t kind;
+  int32_t n_layers;
+  int32_t dims[CAMELOT_MAX_LAYERS + 1];
+  int32_t k;
+  int32_t in_row_bytes;
+  int32_t out_row_bytes;
+  const void* w[CAMELOT_MAX_LAYERS];
+  uint16_t* scratch;              // MLP: two [kMaxBatch][max_dim] BF16 buffers
+  int32_t scratch_stride;         // elements per scratch row
+  const float* tables;            // LOGMEL: window, twiddles, mel filters
+};
+
+enum InKind : int32_t { kInRing = 0, kInReplay = 1, kInHost = 2, kInBench = 3 };
+enum OutKind : int32_t { kOutRing = 0, kOutEgress = 1, kOutBench = 2 };
+
+struct WorkerArgs {
+  StageParams sp;
+  int32_t stage_index;
+  int32_t n_stages;
+  int32_t max_batch;
+  int32_t batch_target;
+  int64_t batch_timeout_ticks;
+  int64_t idle_ticks;             // exit after this long with nothing to do
+  int64_t spin_ticks;             // limit of any wait inside a batch
+  // input
+  int32_t in_kind;
+  int32_t in_depth;
+  uint8_t* in_ring;               // ring base (slot i at in_ring + i * in_stride)
+  uint64_t* in_state;             // per-slot state words
+  int32_t in_state_sys;           // state words live in pinned host memory
+  int64_t in_stride;
+  const IngestRec* ingest;        // replay table or host ring
+  int64_t n_ingest;               // replay: count; host: ring capacity
+  const uint8_t* ingest_payload;  // payload base
+  // output
+  int32_t out_kind;
+  int32_t out_depth;
+  uint8_t* out_ring;
+  uint64_t* out_state;
+  int32_t out_state_sys;
+  int64_t out_stride;
+  uint8_t* egress;                // pinned host ring of records
+  int64_t egress_cap;
+  int32_t rec_bytes;
+  // control
+  WorkerCtl* ctl;
+  HostCtl* hctl;
+  DevPub* pub;
+  // bench mode
+  const uint8_t* bench_in;
+  uint8_t* bench_out;
+  int32_t bench_rows;
+  int32_t bench_reps;
+};
+
+// Handoff benchmark arguments (handoff.hip).
+struct HandoffArgs {
+  uint8_t* ring;            // depth * slot_bytes
+  uint32_t* full;           // [depth][nwg] : times the chunk was filled
+  uint32_t* freed;          // [depth][nwg] : times the chunk was consumed
+  int64_t slot_bytes;
+  int32_t depth;
+  int64_t n_slots;
+  int64_t chunk_bytes;      // multiple of 16
+  int64_t spin_ticks;
+  uint64_t* result;         // [0] sum, [1] xor, [2] t_first (min), [3] t_last (max), [4] error
+};
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ uint64_t now_ticks() { return (uint64_t)wall_clock64(); }
+
+template <typename T>
+__device__ __forceinline__ T ld_acquire_agent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_release_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_acquire_sys(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ void st_release_sys(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed_sys(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// SplitMix64 output function on id + golden gamma (first output for seed = id).
+__device__ __host__ __forceinline__ uint64_t id_hash(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Grid-wide barrier for a persistent grid of nwg co-resident workgroups.
+// Every thread fences its own writes at agent scope before the workgroup barrier,
+// one thread per workgroup arrives on the counter, the last arrival bumps the
+// generation, and every thread re-acquires after. The wait is bounded: on expiry
+// or when another workgroup aborted, returns false (and sets ctl->abort).
+__device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64_t spin_ticks) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    uint32_t gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == nwg - 1) {
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint64_t t0 = now_ticks();
+      uint32_t polls = 0;
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+        if ((int64_t)(now_ticks() - t0) > spin_ticks) {
+          __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        // short naps while a barrier is expected soon, longer ones once it is idle
+        if (++polls < 256) __builtin_amdgcn_s_sleep(1);
+        else __builtin_amdgcn_s_sleep(32);
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return s_ok != 0;
+}
+
+// Intra-wave LDS hand-off: orders this wave's LDS writes before its later reads
+// by other lanes of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+#endif  // device
+
+}  // namespace camelot

@@ -1,0 +1,102 @@
+// Device-global handoff benchmark (the global-memory communication of Section IV-B
+// measured on its own): a persistent producer grid writes ring slots and rings a
+// doorbell per (slot, workgroup) channel; a persistent consumer grid on other CUs
+// waits on each doorbell, folds every 32-bit word of the chunk into a checksum and
+// frees the slot. Producer workgroup j and consumer workgroup j own the same chunk
+// of every slot, so the channels are independent (no grid barrier). All waits are
+// bounded by spin_ticks.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace camelot {
+
+// Pattern word w of slot s: (s * 0x9E3779B1) xor w (32-bit arithmetic).
+__device__ __forceinline__ uint32_t pattern(uint64_t s, uint32_t w) {
+  return ((uint32_t)s * 0x9E3779B1u) ^ w;
+}
+
+__device__ __forceinline__ bool wait_eq(const uint32_t* p, uint32_t want, int64_t spin_ticks, uint64_t* err) {
+  const uint64_t t0 = now_ticks();
+  while (ld_acquire_agent(p) != want) {
+    if ((int64_t)(now_ticks() - t0) > spin_ticks) {
+      __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_producer(HandoffArgs a) {
+  __shared__ int s_ok;
+  const int j = blockIdx.x, nwg = gridDim.x, tid = threadIdx.x;
+  const int64_t lo = (int64_t)j * a.chunk_bytes;
+  const int64_t hi = min(lo + a.chunk_bytes, a.slot_bytes);
+  if (tid == 0) atomicMin((unsigned long long*)&a.result[2], (unsigned long long)now_ticks());
+  for (int64_t s = 0; s < a.n_slots; ++s) {
+    const int d = (int)(s % a.depth);
+    const uint32_t lap = (uint32_t)(s / a.depth);
+    if (tid == 0) s_ok = wait_eq(&a.freed[(int64_t)d * nwg + j], lap, a.spin_ticks, &a.result[4]);
+    __syncthreads();
+    if (!s_ok) return;
+    uint4* base = (uint4*)(a.ring + (int64_t)d * a.slot_bytes);
+    for (int64_t o = lo + (int64_t)tid * 16; o < hi; o += (int64_t)kThreads * 16) {
+      const uint32_t w = (uint32_t)(o >> 2);
+      uint4 v;
+      v.x = pattern(s, w);
+      v.y = pattern(s, w + 1);
+      v.z = pattern(s, w + 2);
+      v.w = pattern(s, w + 3);
+      base[o >> 4] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) st_release_agent(&a.full[(int64_t)d * nwg + j], lap + 1);
+  }
+  if (tid == 0) atomicMax((unsigned long long*)&a.result[3], (unsigned long long)now_ticks());
+}
+
+extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_consumer(HandoffArgs a) {
+  __shared__ int s_ok;
+  __shared__ uint64_t s_sum[kWaves], s_xor[kWaves];
+  const int j = blockIdx.x, nwg = gridDim.x, tid = threadIdx.x;
+  const int64_t lo = (int64_t)j * a.chunk_bytes;
+  const int64_t hi = min(lo + a.chunk_bytes, a.slot_bytes);
+  uint64_t sum = 0;
+  uint32_t xr = 0;
+  for (int64_t s = 0; s < a.n_slots; ++s) {
+    const int d = (int)(s % a.depth);
+    const uint32_t lap = (uint32_t)(s / a.depth);
+    if (tid == 0) s_ok = wait_eq(&a.full[(int64_t)d * nwg + j], lap + 1, a.spin_ticks, &a.result[4]);
+    __syncthreads();
+    if (!s_ok) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const uint4* base = (const uint4*)(a.ring + (int64_t)d * a.slot_bytes);
+    for (int64_t o = lo + (int64_t)tid * 16; o < hi; o += (int64_t)kThreads * 16) {
+      const uint4 v = base[o >> 4];
+      sum += (uint64_t)v.x + v.y + v.z + v.w;
+      xr ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    __syncthreads();
+    if (tid == 0) st_release_agent(&a.freed[(int64_t)d * nwg + j], lap + 1);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_xor(sum, off, 64);
+    xr ^= __shfl_xor(xr, off, 64);
+  }
+  if ((tid & 63) == 0) { s_sum[tid >> 6] = sum; s_xor[tid >> 6] = xr; }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t ts = 0, tx = 0;
+    for (int w = 0; w < kWaves; ++w) { ts += s_sum[w]; tx ^= s_xor[w]; }
+    atomicAdd((unsigned long long*)&a.result[0], (unsigned long long)ts);
+    atomicXor((unsigned long long*)&a.result[1], (unsigned long long)tx);
+    atomicMax((unsigned long long*)&a.result[3], (unsigned long long)now_ticks());
+  }
+}
+
+}  // namespace camelot

@@ -1,0 +1,722 @@
+// Stage kernels and the persistent stage worker.
+//
+// One worker kernel is launched per stage on the stage's CU-masked stream with a
+// grid of kWgPerCu workgroups per CU of its share; every workgroup stays resident
+// for the life of the pipeline. Workgroup 0 runs the control side (batch
+// formation or doorbell wait, header copy, publication); all workgroups run the
+// stage's compute, separated by grid barriers where a stage has dependent phases.
+// Every wait is bounded (idle limit between batches, spin limit inside a batch),
+// so every wave reaches the kernel's end.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "device_common.h"
+
+namespace camelot {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// LOGMEL table layout (floats), built by the host (stage_tables.cpp)
+constexpr int kTabWin = 0;          // 400 Hamming window values
+constexpr int kTabTw256 = 400;      // 256 complex exp(-2 pi i t / 256)
+constexpr int kTabTw512 = 912;      // 257 complex exp(-2 pi i k / 512)
+constexpr int kTabMelMeta = 1426;   // 40 x (first bin, bin count, weight offset)
+constexpr int kTabMelW = 1546;      // concatenated filter weights
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// ------------------------------------------------------------------ result emit
+// Writes one result row (k indices + k values held in LDS) either into the
+// planar bench output or into the pinned egress ring. Called by a whole wave.
+__device__ __forceinline__ void emit_row(const WorkerArgs& a, WorkerCtl* ctl, int rows, int r,
+                                         int k, const int32_t* idx, const float* val, int lane) {
+  if (a.out_kind == kOutBench) {
+    int32_t* ip = (int32_t*)a.bench_out;
+    float* vp = (float*)(a.bench_out + (int64_t)rows * k * 4);
+    for (int j = lane; j < k; j += 64) {
+      ip[(int64_t)r * k + j] = idx[j];
+      vp[(int64_t)r * k + j] = val[j];
+    }
+    return;
+  }
+  uint64_t slot = (ctl->d_egress_base + (uint64_t)r) % (uint64_t)a.egress_cap;
+  uint8_t* rec = a.egress + slot * (uint64_t)a.rec_bytes;
+  int32_t* ip = (int32_t*)(rec + sizeof(EgressRec));
+  float* vp = (float*)(ip + k);
+  for (int j = lane; j < k; j += 64) {
+    ip[j] = idx[j];
+    vp[j] = val[j];
+  }
+  if (lane < 2 * kMaxStages) {
+    ((EgressRec*)rec)->t_stage[lane] = ctl->d_t_stage[lane];
+  }
+  if (lane == 0) {
+    EgressRec* h = (EgressRec*)rec;
+    h->id = ctl->d_row_id[r];
+    h->row = ctl->d_row_idx[r];
+    h->n_out = (uint32_t)k;
+    h->t_arr = ctl->d_row_tarr[r];
+    h->t_done = now_ticks();
+  }
+}
+
+// ------------------------------------------------------------------ GEMM + ReLU (FP32)
+// Unit = (64 output columns, 8 rows) per workgroup; the 4 waves split K in
+// interleaved 64-wide chunks and their partial sums are added in a fixed order,
+// so every output's arithmetic is independent of the batch and of the grid.
+constexpr int kGemmMaxK = 1024;
+
+__device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  __shared__ float xs[8][kGemmMaxK];
+  __shared__ float part[kWaves][8][64];
+  const int K = a.sp.dims[0], N = a.sp.dims[1];
+  const float* W = (const float*)a.sp.w[0];
+  float* Y = (float*)out;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int n_cb = (N + 63) / 64, n_rb = (rows + 7) / 8;
+  for (int u = blockIdx.x; u < n_cb * n_rb; u += gridDim.x) {
+    const int cb = u % n_cb, rb = u / n_cb;
+    for (int i = tid; i < 8 * K; i += kThreads) {
+      const int r = i / K, kk = i - r * K, row = rb * 8 + r;
+      xs[r][kk] = row < rows ? ((const float*)ctl->d_rowptr[row])[kk] : 0.f;
+    }
+    __syncthreads();
+    const int col = cb * 64 + lane;
+    float acc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = 0.f;
+    if (col < N) {
+      for (int kc = w * 64; kc < K; kc += kWaves * 64) {
+        const int kend = min(kc + 64, K);
+        for (int kk = kc; kk < kend; ++kk) {
+          const float wv = W[(int64_t)kk * N + col];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) acc[r] = fmaf(xs[r][kk], wv, acc[r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) part[w][r][lane] = acc[r];
+    __syncthreads();
+    for (int i = tid; i < 8 * 64; i += kThreads) {
+      const int r = i >> 6, c = i & 63, row = rb * 8 + r, cc = cb * 64 + c;
+      if (row < rows && cc < N) {
+        const float s = ((part[0][r][c] + part[1][r][c]) + part[2][r][c]) + part[3][r][c];
+        Y[(int64_t)row * N + cc] = fmaxf(s, 0.f);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ GEMM + argmax (FP32)
+// One wave per row: lanes stride over K, butterfly sums (lane 0's order is fixed),
+// lane 0 picks the first maximum.
+constexpr int kArgmaxMaxN = 16;
+
+__device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
+  __shared__ int32_t s_idx[kWaves][1];
+  __shared__ float s_val[kWaves][1];
+  const int K = a.sp.dims[0], N = a.sp.dims[1];
+  const float* W = (const float*)a.sp.w[0];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+    const float* x = (const float*)ctl->d_rowptr[r];
+    float acc[kArgmaxMaxN];
+#pragma unroll
+    for (int j = 0; j < kArgmaxMaxN; ++j) acc[j] = 0.f;
+    for (int kk = lane; kk < K; kk += 64) {
+      const float xv = x[kk];
+#pragma unroll
+      for (int j = 0; j < kArgmaxMaxN; ++j)
+        if (j < N) acc[j] = fmaf(xv, W[(int64_t)kk * N + j], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kArgmaxMaxN; ++j) {
+      float v = acc[j];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[j] = v;
+    }
+    if (lane == 0) {
+      int best = 0;
+      float bv = acc[0];
+#pragma unroll
+      for (int j = 1; j < kArgmaxMaxN; ++j)
+        if (j < N && acc[j] > bv) { bv = acc[j]; best = j; }
+      s_idx[w][0] = best;
+      s_val[w][0] = bv;
+    }
+    wave_lds_sync();
+    emit_row(a, ctl, rows, r, 1, s_idx[w], s_val[w], lane);
+    wave_lds_sync();
+  }
+}
+
+// ------------------------------------------------------------------ top-k
+// One wave per row. Each lane keeps its strided slice (element lane + 64 t) in
+// registers; k rounds of a wave-wide arg-max (ties to the smaller index) pick the
+// results in order.
+constexpr int kTopkMaxN = 4096;
+
+__device__ __forceinline__ bool topk_better(float v1, int i1, float v2, int i2) {
+  if (i2 < 0) return i1 >= 0;
+  if (i1 < 0) return false;
+  return v1 > v2 || (v1 == v2 && i1 < i2);
+}
+
+__device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
+  __shared__ int32_t s_idx[kWaves][CAMELOT_MAX_K];
+  __shared__ float s_val[kWaves][CAMELOT_MAX_K];
+  const int N = a.sp.dims[0], k = a.sp.k;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+    const float* s = (const float*)ctl->d_rowptr[r];
+    float v[kTopkMaxN / 64];
+#pragma unroll
+    for (int t = 0; t < kTopkMaxN / 64; ++t) v[t] = (lane + 64 * t < N) ? s[lane + 64 * t] : 0.f;
+    uint64_t removed = 0;
+    for (int j = 0; j < k; ++j) {
+      float bv = 0.f;
+      int bi = -1;
+#pragma unroll
+      for (int t = 0; t < kTopkMaxN / 64; ++t) {
+        const int i = lane + 64 * t;
+        if (i < N && !((removed >> t) & 1ull) && (bi < 0 || v[t] > bv)) { bv = v[t]; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (topk_better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+      }
+      if (bi >= 0 && (bi & 63) == lane) removed |= 1ull << (bi >> 6);
+      if (lane == 0) { s_idx[w][j] = bi; s_val[w][j] = bv; }
+    }
+    wave_lds_sync();
+    emit_row(a, ctl, rows, r, k, s_idx[w], s_val[w], lane);
+    wave_lds_sync();
+  }
+}
+
+// ------------------------------------------------------------------ log-mel front end
+// One wave per (row, frame): window 400 samples, pack into 256 complex points,
+// radix-4 Stockham FFT in LDS (4 passes), split into the 257-bin spectrum of the
+// 512-point real transform, power, sparse mel filters, natural log with floor.
+__device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  __shared__ float2 fbuf[kWaves][2][256];
+  __shared__ float pbuf[kWaves][260];
+  const float* T = a.sp.tables;
+  const float* win = T + kTabWin;
+  const float2* tw256 = (const float2*)(T + kTabTw256);
+  const float2* tw512 = (const float2*)(T + kTabTw512);
+  const float* meta = T + kTabMelMeta;
+  const float* melw = T + kTabMelW;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* Y = (float*)out;
+  const int units = rows * 11;
+  for (int u = blockIdx.x * kWaves + w; u < units; u += gridDim.x * kWaves) {
+    const int r = u / 11, f = u - r * 11;
+    const float* x = (const float*)ctl->d_rowptr[r] + f * 160;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = lane + 64 * q;
+      float2 z = make_float2(0.f, 0.f);
+      if (n < 200) z = make_float2(x[2 * n] * win[2 * n], x[2 * n + 1] * win[2 * n + 1]);
+      fbuf[w][0][n] = z;
+    }
+    wave_lds_sync();
+    int src = 0;
+    for (int ns = 1; ns < 256; ns *= 4) {
+      const int j = lane, jm = j % ns, step = 64 / ns;
+      float2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float2 e = fbuf[w][src][j + 64 * q];
+        const float2 t = tw256[q * jm * step];
+        v[q] = make_float2(e.x * t.x - e.y * t.y, e.x * t.y + e.y * t.x);
+      }
+      // forward radix-4 butterfly (omega = -i)
+      const float2 s02 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+      const float2 d02 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+      const float2 s13 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+      const float2 d13 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+      float2 y[4];
+      y[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
+      y[2] = make_float2(s02.x - s13.x, s02.y - s13.y);
+      y[1] = make_float2(d02.x + d13.y, d02.y - d13.x);   // d02 - i d13
+      y[3] = make_float2(d02.x - d13.y, d02.y + d13.x);   // d02 + i d13
+      const int d = (j / ns) * ns * 4 + jm;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fbuf[w][src ^ 1][d + q * ns] = y[q];
+      wave_lds_sync();
+      src ^= 1;
+    }
+    for (int kk = lane; kk <= 256; kk += 64) {
+      const float2 za = fbuf[w][src][kk & 255];
+      const float2 zb = fbuf[w][src][(256 - kk) & 255];
+      const float er = 0.5f * (za.x + zb.x), ei = 0.5f * (za.y - zb.y);
+      const float dr = za.x - zb.x, di = za.y + zb.y;            // a - conj(b)
+      const float orr = 0.5f * di, oi = -0.5f * dr;               // (a - conj b) / 2i
+      const float2 t = tw512[kk];
+      const float xr = er + (t.x * orr - t.y * oi);
+      const float xi = ei + (t.x * oi + t.y * orr);
+      pbuf[w][kk] = xr * xr + xi * xi;
+    }
+    wave_lds_sync();
+    if (lane < 40) {
+      const int lo = (int)meta[3 * lane], cnt = (int)meta[3 * lane + 1], off = (int)meta[3 * lane + 2];
+      float e = 0.f;
+      for (int t = 0; t < cnt; ++t) e = fmaf(melw[off + t], pbuf[w][lo + t], e);
+      Y[(int64_t)r * 440 + f * 40 + lane] = logf(fmaxf(e, 1e-10f));
+    }
+    wave_lds_sync();
+  }
+}
+
+// ------------------------------------------------------------------ BF16 MLP chain on MFMA
+// Per layer: unit = 16 output columns (one strip) per workgroup; the 4 waves split
+// K in interleaved 32-wide chunks (v_mfma_f32_16x16x32_bf16, up to 8 row blocks of
+// 16 rows each), partial tiles are added in LDS in a fixed order, then ReLU and
+// BF16 rounding (hidden layers) or the FP32 store (last layer). Layers are
+// separated by grid barriers. Weights are [N][K] BF16 (K contiguous).
+__device__ __forceinline__ bf16x8 ld_bf16x8(const uint16_t* p) {
+  const uint4 q = *(const uint4*)p;
+  bf16x8 r;
+  __builtin_memcpy(&r, &q, 16);
+  return r;
+}
+
+__device__ __forceinline__ bf16x8 ld_f32x8_as_bf16(const float* p) {
+  const float4 a = *(const float4*)p;
+  const float4 b = *(const float4*)(p + 4);
+  uint4 q;
+  q.x = (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(a.y) << 16);
+  q.y = (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(a.w) << 16);
+  q.z = (uint32_t)f32_to_bf16_rne(b.x) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
+  q.w = (uint32_t)f32_to_bf16_rne(b.z) | ((uint32_t)f32_to_bf16_rne(b.w) << 16);
+  bf16x8 r;
+  __builtin_memcpy(&r, &q, 16);
+  return r;
+}
+
+__device__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  __shared__ float part[kWaves][8][256];
+  const int L = a.sp.n_layers;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int nrb = (rows + 15) >> 4;
+  const int stride = a.sp.scratch_stride;
+  for (int l = 0; l < L; ++l) {
+    const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
+    const uint16_t* W = (const uint16_t*)a.sp.w[l];
+    const uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
+    uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
+    const bool last = (l == L - 1);
+    const int nchunks = (K + 31) >> 5;
+    const int nstrips = N >> 4;
+    for (int strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
+      f32x4 acc[8];
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb) acc[rb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      const int n = strip * 16 + (lane & 15);
+      const uint16_t* wrow = W + (int64_t)n * K;
+      for (int c = w; c < nchunks; c += kWaves) {
+        const int kb = c * 32 + (lane >> 4) * 8;
+        const bool kin = kb < K;
+        bf16x8 bfrag = kin ? ld_bf16x8(wrow + kb) : (bf16x8){};
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb) {
+          if (rb < nrb) {
+            const int row = rb * 16 + (lane & 15);
+            bf16x8 afrag = (bf16x8){};
+            if (row < rows && kin) {
+              afrag = (l == 0) ? ld_f32x8_as_bf16((const float*)ctl->d_rowptr[row] + kb)
+                               : ld_bf16x8(hin + (int64_t)row * stride + kb);
+            }
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[rb], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb) {
+        if (rb < nrb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) part[w][rb][((lane >> 4) * 4 + i) * 16 + (lane & 15)] = acc[rb][i];
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < nrb * 256; i += kThreads) {
+        const int rb = i >> 8, e = i & 255, row = rb * 16 + (e >> 4), col = strip * 16 + (e & 15);
+        if (row < rows) {
+          const float s = ((part[0][rb][e] + part[1][rb][e]) + part[2][rb][e]) + part[3][rb][e];
+          if (last) ((float*)out)[(int64_t)row * N + col] = s;
+          else hout[(int64_t)row * stride + col] = f32_to_bf16_rne(fmaxf(s, 0.f));
+        }
+      }
+      __syncthreads();
+    }
+    if (!last && !grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ stage dispatch
+template <int KIND>
+__device__ __forceinline__ bool exec_stage(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  if constexpr (KIND == CAMELOT_STAGE_GEMM_RELU) { exec_gemm_relu(a, ctl, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_GEMM_ARGMAX) { exec_gemm_argmax(a, ctl, rows); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_LOGMEL) { exec_logmel(a, ctl, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_MLP_BF16) { return exec_mlp(a, ctl, rows, out); }
+  if constexpr (KIND == CAMELOT_STAGE_TOPK) { exec_topk(a, ctl, rows); return true; }
+  return false;
+}
+
+// ------------------------------------------------------------------ control side
+// Ring slot states: 0 free (never used), 2*seq+1 full with batch seq,
+// 2*seq+2 consumed after batch seq.
+__device__ __forceinline__ uint64_t ring_load(const uint64_t* p, bool sys) {
+  return sys ? ld_acquire_sys(p) : ld_acquire_agent(p);
+}
+__device__ __forceinline__ void ring_store(uint64_t* p, uint64_t v, bool sys) {
+  if (sys) st_release_sys(p, v); else st_release_agent(p, v);
+}
+
+struct Acq {
+  int status;      // 0 ok (batch ready), else a WorkerStatus to exit with
+  int nreq;
+  int rows;
+};
+
+// Polling helper: true when the host asked to stop (checked every 16th call).
+__device__ __forceinline__ bool host_stop(const WorkerArgs& a, uint32_t& polls) {
+  if ((++polls & 15u) != 0) return false;
+  return ld_acquire_sys(&a.hctl->stop) != 0;
+}
+
+// Stage 0: form a batch from the ingest (wave 0 of workgroup 0). Requests are
+// taken whole, in order, while the rows fit in max_batch; the batch starts when
+// batch_target rows wait, when the next waiting request does not fit, or when the
+// oldest waited batch_timeout. Writes the chosen requests into LDS arrays.
+__device__ Acq acquire_ingest(const WorkerArgs& a, WorkerCtl* ctl, uint64_t t0, uint64_t* s_id,
+                              uint64_t* s_tarr, uint32_t* s_rows, const uint8_t** s_ptr) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t c = ctl->ingest_cursor;
+  // replay arrival times are relative to the epoch t0; host ones are absolute
+  const uint64_t base = a.in_kind == kInHost ? 0 : t0;
+  const uint64_t t_wait0 = now_ticks();
+  uint32_t polls = 0;
+  const bool host = a.in_kind == kInHost;
+  for (;;) {
+    uint64_t avail;
+    if (host) {
+      const uint64_t head = ld_acquire_sys(&a.hctl->ingest_head);
+      avail = head > c ? head - c : 0;
+    } else {
+      avail = (uint64_t)a.n_ingest > c ? (uint64_t)a.n_ingest - c : 0;
+    }
+    const uint64_t now = now_ticks();
+    int taken = 0, rows = 0, full = 0;
+    uint64_t first_tarr = 0;
+    // up to two 64-request chunks (a batch holds at most kMaxBatch >= requests)
+    for (int chunk = 0; chunk < 2 && !full; ++chunk) {
+      const uint64_t i = (uint64_t)(chunk * 64 + lane);
+      const bool valid = i < avail && taken == chunk * 64;
+      IngestRec rec = {};
+      if (valid) {
+        const uint64_t r = c + i;
+        rec = a.ingest[host ? (r % (uint64_t)a.n_ingest) : r];
+        rec.t_arr += base;
+      }
+      const bool arrived = valid && (host || rec.t_arr <= now);
+      // prefix of arrived requests
+      const uint64_t nb = __ballot(!arrived);
+      const int first_gap = nb ? __builtin_ctzll(nb) : 64;
+      int v = (arrived && lane < first_gap) ? (int)rec.rows : 0;
+      int cum = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(cum, d, 64);
+        if (lane >= d) cum += t;
+      }
+      const bool fits = arrived && lane < first_gap && rows + cum <= a.max_batch;
+      const uint64_t fm = __ballot(fits);
+      const int nfit = fm ? 64 - __builtin_clzll(fm) : 0;  // fits is a prefix
+      if (fits) {
+        const int q = taken + lane;
+        s_id[q] = rec.id;
+        s_tarr[q] = rec.t_arr;
+        s_rows[q] = rec.rows;
+        s_ptr[q] = a.ingest_payload + rec.payload_off;
+      }
+      if (chunk == 0) first_tarr = __shfl(rec.t_arr, 0, 64);
+      const int add_rows = __shfl(cum, nfit > 0 ? nfit - 1 : 0, 64);
+      if (nfit > 0) rows += add_rows;
+      taken += nfit;
+      // a waiting request that does not fit makes the batch full
+      if (nfit < first_gap) full = 1;
+      if (first_gap < 64) break;
+    }
+    if (taken > 0) {
+      const bool timeout = (int64_t)(now - first_tarr) >= a.batch_timeout_ticks;
+      if (full || rows >= a.batch_target || rows >= a.max_batch || timeout) {
+        return Acq{0, taken, rows};
+      }
+    }
+    if (host_stop(a, polls)) return Acq{kStatusStopped, 0, 0};
+    if ((int64_t)(now - t_wait0) > a.idle_ticks) return Acq{kStatusIdleExit, 0, 0};
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Stages > 0: wait for the doorbell of input slot seq.
+__device__ Acq acquire_ring(const WorkerArgs& a, uint64_t seq) {
+  const uint64_t slot = seq % (uint64_t)a.in_depth;
+  const uint64_t want = 2 * seq + 1;
+  const uint64_t t_wait0 = now_ticks();
+  uint32_t polls = 0;
+  const bool st_sys = a.in_state_sys != 0;
+  for (;;) {
+    if (ring_load(&a.in_state[slot], st_sys) == want) {
+      const SlotHeader* h = (const SlotHeader*)(a.in_ring + slot * (uint64_t)a.in_stride);
+      return Acq{0, (int)h->n_req, (int)h->n_rows};
+    }
+    if (host_stop(a, polls)) return Acq{kStatusStopped, 0, 0};
+    if ((int64_t)(now_ticks() - t_wait0) > a.idle_ticks) return Acq{kStatusIdleExit, 0, 0};
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Wait until the output can take batch seq of `rows` rows.
+__device__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq, int rows) {
+  const uint64_t t_wait0 = now_ticks();
+  uint32_t polls = 0;
+  for (;;) {
+    bool ok;
+    if (a.out_kind == kOutRing) {
+      const uint64_t slot = seq % (uint64_t)a.out_depth;
+      const uint64_t want = seq < (uint64_t)a.out_depth ? 0 : 2 * (seq - a.out_depth) + 2;
+      ok = ring_load(&a.out_state[slot], a.out_state_sys != 0) == want;
+    } else {
+      const uint64_t tail = ld_acquire_sys(&a.hctl->egress_tail);
+      ok = ctl->egress_head + (uint64_t)rows - tail <= (uint64_t)a.egress_cap;
+    }
+    if (ok) return 0;
+    if (host_stop(a, polls)) return kStatusStopped;
+    if ((int64_t)(now_ticks() - t_wait0) > a.idle_ticks) return kStatusIdleExit;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// ------------------------------------------------------------------ worker kernel
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
+  WorkerCtl* ctl = a.ctl;
+  const int tid = threadIdx.x;
+  const bool wg0 = blockIdx.x == 0;
+  const int si = a.stage_index;
+
+  // ---------------- bench mode: fixed input, `reps` back-to-back batches
+  if (a.in_kind == kInBench) {
+    if (wg0)
+      for (int i = tid; i < a.bench_rows; i += kThreads)
+        ctl->d_rowptr[i] = a.bench_in + (int64_t)i * a.sp.in_row_bytes;
+    if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
+    const uint64_t t0 = now_ticks();
+    for (int rep = 0; rep < a.bench_reps; ++rep) {
+      if (!exec_stage<KIND>(a, ctl, a.bench_rows, a.bench_out)) return;
+      if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
+    }
+    if (wg0 && tid == 0) ctl->ticks_bench = now_ticks() - t0;
+    return;
+  }
+
+  // ---------------- pipeline mode
+  __shared__ uint64_t s_id[kMaxBatch];
+  __shared__ uint64_t s_tarr[kMaxBatch];
+  __shared__ uint32_t s_rows[kMaxBatch];
+  __shared__ const uint8_t* s_ptr[kMaxBatch];
+  __shared__ uint32_t s_rbase[kMaxBatch + 1];
+  __shared__ int s_acq[3];
+  __shared__ uint64_t s_red[2][kWaves];
+
+  __shared__ uint64_t s_t0;
+  if (wg0 && tid == 0) {
+    s_t0 = now_ticks();
+    if (si == 0) st_relaxed_sys(&a.pub->t0, s_t0);
+    st_relaxed_sys(&a.pub->started[si], 1);
+  }
+  if (wg0) __syncthreads();
+  uint64_t seq = ctl->next_seq;
+  int exit_status = kStatusOk;
+  for (;;) {
+    // ---------------- control: acquire the next batch (workgroup 0)
+    if (wg0) {
+      if (tid < 64) {
+        Acq q;
+        if (si == 0) {
+          q = acquire_ingest(a, ctl, s_t0, s_id, s_tarr, s_rows, s_ptr);
+        } else {
+          q = (tid == 0) ? acquire_ring(a, seq) : Acq{0, 0, 0};
+          q.status = __shfl(q.status, 0, 64);
+          q.nreq = __shfl(q.nreq, 0, 64);
+          q.rows = __shfl(q.rows, 0, 64);
+        }
+        if (q.status == 0 && tid == 0) q.status = acquire_output(a, ctl, seq, q.rows);
+        if (tid == 0) { s_acq[0] = q.status; s_acq[1] = q.nreq; s_acq[2] = q.rows; }
+      }
+      __syncthreads();
+      const int st = s_acq[0], nreq = s_acq[1], rows = s_acq[2];
+      if (st == 0) {
+        const uint64_t t_start = now_ticks();
+        const SlotHeader* ih = nullptr;
+        if (si > 0) {
+          ih = (const SlotHeader*)(a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride);
+          for (int q = tid; q < nreq; q += kThreads) {
+            s_id[q] = ih->req_id[q];
+            s_tarr[q] = ih->req_tarr[q];
+            s_rows[q] = ih->req_rows[q];
+          }
+        }
+        __syncthreads();
+        if (tid == 0) {
+          uint32_t acc = 0;
+          for (int q = 0; q < nreq; ++q) { s_rbase[q] = acc; acc += s_rows[q]; }
+          s_rbase[nreq] = acc;
+        }
+        __syncthreads();
+        // per-row descriptor
+        const uint8_t* in_payload = ih ? (const uint8_t*)ih + kSlotHeaderBytes : nullptr;
+        for (int q = tid; q < nreq; q += kThreads) {
+          for (uint32_t j = 0; j < s_rows[q]; ++j) {
+            const uint32_t row = s_rbase[q] + j;
+            ctl->d_rowptr[row] = ih ? in_payload + (int64_t)row * a.sp.in_row_bytes
+                                    : s_ptr[q] + (int64_t)j * a.sp.in_row_bytes;
+            ctl->d_row_id[row] = s_id[q];
+            ctl->d_row_idx[row] = j;
+            ctl->d_row_tarr[row] = s_tarr[q];
+          }
+        }
+        if (tid < 2 * kMaxStages) {
+          uint64_t tv = ih ? ih->t_stage[tid] : 0;
+          if (tid == 2 * si) tv = t_start;
+          ctl->d_t_stage[tid] = tv;
+        }
+        if (a.out_kind == kOutRing) {
+          SlotHeader* oh = (SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
+          for (int q = tid; q < nreq; q += kThreads) {
+            oh->req_id[q] = s_id[q];
+            oh->req_tarr[q] = s_tarr[q];
+            oh->req_rows[q] = s_rows[q];
+          }
+          if (tid == 0) {
+            oh->seq = seq;
+            oh->n_req = (uint32_t)nreq;
+            oh->n_rows = (uint32_t)rows;
+          }
+          if (tid < 2 * kMaxStages) {
+            uint64_t tv = ih ? ih->t_stage[tid] : 0;
+            if (tid == 2 * si) tv = t_start;
+            oh->t_stage[tid] = tv;
+          }
+          if (tid == 0) ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
+        } else if (tid == 0) {
+          ctl->d_egress_base = ctl->egress_head;
+          ctl->d_out = nullptr;
+        }
+        // id checksums of the requests of this batch
+        uint64_t hs = 0, hx = 0;
+        for (int q = tid; q < nreq; q += kThreads) {
+          const uint64_t h = id_hash(s_id[q]);
+          hs += h;
+          hx ^= h;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          hs += __shfl_xor(hs, off, 64);
+          hx ^= __shfl_xor(hx, off, 64);
+        }
+        if ((tid & 63) == 0) { s_red[0][tid >> 6] = hs; s_red[1][tid >> 6] = hx; }
+        if (tid == 0) {
+          ctl->d_rows = (uint32_t)rows;
+          ctl->d_nreq = (uint32_t)nreq;
+          ctl->d_seq = seq;
+          ctl->d_t_start = t_start;
+        }
+      }
+      if (tid == 0) ctl->d_stop = (uint32_t)st;
+    }
+    // workgroup 0 may wait for input (up to the idle limit) and then for output space
+    if (!grid_barrier(ctl, gridDim.x, 2 * a.idle_ticks + a.spin_ticks)) { exit_status = kStatusTimeout; break; }
+    // a host-staged input slot was written by a DMA copy: acquire at system scope
+    if (a.in_state_sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    const uint32_t stop = ctl->d_stop;
+    if (stop) { exit_status = (int)stop; break; }
+    const int rows = (int)ctl->d_rows;
+    if (!exec_stage<KIND>(a, ctl, rows, ctl->d_out)) { exit_status = kStatusTimeout; break; }
+    // results go to pinned host memory, a host-staged output slot is read by DMA
+    if (a.out_kind == kOutEgress || a.out_state_sys) __threadfence_system();
+    if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) { exit_status = kStatusTimeout; break; }
+    // ---------------- publish (workgroup 0, thread 0)
+    if (wg0 && tid == 0) {
+      const uint64_t t_end = now_ticks();
+      const int nreq = (int)ctl->d_nreq;
+      if (a.out_kind == kOutRing) {
+        SlotHeader* oh = (SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
+        oh->t_stage[2 * si + 1] = t_end;
+        if (a.out_state_sys) {
+          // host-staged boundary: the relay reads the row count next to the state word
+          st_relaxed_sys(&a.out_state[a.out_depth + seq % (uint64_t)a.out_depth], (uint64_t)rows);
+          __threadfence_system();
+        }
+        ring_store(&a.out_state[seq % (uint64_t)a.out_depth], 2 * seq + 1, a.out_state_sys != 0);
+      } else {
+        ctl->egress_head += (uint64_t)rows;
+        st_release_sys(&a.pub->egress_head, ctl->egress_head);
+      }
+      if (si == 0) {
+        ctl->ingest_cursor += (uint64_t)nreq;
+        st_relaxed_sys(&a.pub->ingest_tail, ctl->ingest_cursor);
+      } else {
+        ring_store(&a.in_state[seq % (uint64_t)a.in_depth], 2 * seq + 2, a.in_state_sys != 0);
+      }
+      uint64_t hs = 0, hx = 0;
+      for (int w = 0; w < kWaves; ++w) { hs += s_red[0][w]; hx ^= s_red[1][w]; }
+      ctl->sum_acc += hs;
+      ctl->xor_acc ^= hx;
+      ctl->batches_acc += 1;
+      st_relaxed_sys(&a.pub->id_sum[si], ctl->sum_acc);
+      st_relaxed_sys(&a.pub->id_xor[si], ctl->xor_acc);
+      st_relaxed_sys(&a.pub->batches[si], ctl->batches_acc);
+    }
+    ++seq;
+  }
+  if (wg0 && tid == 0) {
+    ctl->next_seq = seq;
+    st_release_sys(&a.pub->status[si], (int32_t)exit_status);
+  }
+}
+
+template __global__ void stage_worker<CAMELOT_STAGE_GEMM_RELU>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_GEMM_ARGMAX>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_LOGMEL>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_MLP_BF16>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_TOPK>(WorkerArgs);
+
+// Host-side accessor of the kernel entry for a stage kind.
+const void* worker_kernel(int kind) {
+  switch (kind) {
+    case CAMELOT_STAGE_GEMM_RELU: return (const void*)&stage_worker<CAMELOT_STAGE_GEMM_RELU>;
+    case CAMELOT_STAGE_GEMM_ARGMAX: return (const void*)&stage_worker<CAMELOT_STAGE_GEMM_ARGMAX>;
+    case CAMELOT_STAGE_LOGMEL: return (const void*)&stage_worker<CAMELOT_STAGE_LOGMEL>;
+    case CAMELOT_STAGE_MLP_BF16: return (const void*)&stage_worker<CAMELOT_STAGE_MLP_BF16>;
+    case CAMELOT_STAGE_TOPK: return (const void*)&stage_worker<CAMELOT_STAGE_TOPK>;
+    default: return nullptr;
+  }
+}
+}  // namespace camelot

@@ -1,0 +1,169 @@
+"""Stage kernels on the GPU vs the FP64 oracle (called through the C ABI).
+
+Tolerances (normwise max|y - r| / max|r|): 1e-5 for FP32 stages, 2e-2 for the BF16
+MLP; top-k and argmax are exact on identical inputs."""
+import numpy as np
+import pytest
+
+from oracle import stages as O
+import workload_gen as G
+from tests.gpu_util import c0_stages, c1_stages, log, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_cuda()
+
+
+@pytest.fixture(scope="module")
+def cm():
+    from paper_2005_02088_amd import camelot
+    return camelot
+
+
+def test_device_query(torch, cm):
+    d = cm.camelot_device_query()
+    log(f"device: {d.arch} CUs={d.n_cus} wallclock={d.wall_clock_hz} hbm={d.hbm_bytes >> 30} GiB")
+    assert d.n_cus >= 8 and d.wall_clock_hz > 0
+
+
+@pytest.mark.parametrize("rows", [1, 7, 32, 128])
+def test_gemm_relu_parity(torch, cm, rows):
+    (w1, _), _, (sa, _) = c0_stages(torch)
+    x = G.c0_queries(rows, seed=rows)
+    dx = to_dev(torch, x)
+    dy = torch.empty((rows, 512), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    log(f"gemm_relu rows={rows}")
+    cm.camelot_stage_run(sa, dx.data_ptr(), dy.data_ptr(), rows, 64, 0)
+    y = dy.cpu().numpy()
+    err = O.normwise_err(y, O.gemm_relu(x, w1))
+    log(f"  err={err:.3e}")
+    assert err <= 1e-5
+
+
+def test_gemm_relu_grid_and_batch_invariant(torch, cm):
+    (w1, _), _, (sa, _) = c0_stages(torch)
+    x = G.c0_queries(32, seed=5)
+    dx = to_dev(torch, x)
+    outs = []
+    for n_cus, rows in ((8, 32), (128, 32), (256, 32), (64, 1)):
+        dy = torch.empty((rows, 512), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        cm.camelot_stage_run(sa, dx.data_ptr(), dy.data_ptr(), rows, n_cus, 0)
+        outs.append(dy.cpu().numpy())
+    for o in outs[1:3]:
+        assert np.array_equal(o, outs[0])
+    assert np.array_equal(outs[3][0], outs[0][0])
+
+
+@pytest.mark.parametrize("rows", [1, 9, 64])
+def test_gemm_argmax_parity(torch, cm, rows):
+    (w1, w2), _, (sa, sb) = c0_stages(torch)
+    x = G.c0_queries(rows, seed=100 + rows)
+    dx = to_dev(torch, x)
+    dy = torch.empty((rows, 512), dtype=torch.float32, device="cuda")
+    dout = torch.empty(2 * rows, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    cm.camelot_stage_run(sa, dx.data_ptr(), dy.data_ptr(), rows, 32, 0)
+    cm.camelot_stage_run(sb, dy.data_ptr(), dout.data_ptr(), rows, 32, 0)
+    y = dy.cpu().numpy()
+    raw = dout.cpu().numpy()
+    idx = raw[:rows]
+    val = raw[rows:].view(np.float32)
+    s, ref = O.gemm_argmax(y, w2)        # on the GPU's own stage-A output
+    srt = np.sort(s, axis=1)
+    gap = srt[:, -1] - srt[:, -2]
+    tol = 1e-5 * np.max(np.abs(s))
+    sure = gap > tol
+    assert np.array_equal(idx[sure], ref[sure])
+    assert O.normwise_err(val, s[np.arange(rows), ref]) <= 1e-5
+
+
+def test_topk_parity_with_ties(torch, cm):
+    g = G.rng("handoff", 31)
+    for rows, n, k in ((1, 4096, 10), (13, 4096, 10), (64, 4096, 100), (5, 256, 100), (3, 100, 100)):
+        s = np.round(g.standard_normal((rows, n)), 2).astype(np.float32)   # many exact ties
+        ds = to_dev(torch, s)
+        dout = torch.empty(2 * rows * k, dtype=torch.int32, device="cuda")
+        desc = cm.stage_desc(cm.STAGE_TOPK, dims=(n,), k=k, n_layers=0)
+        torch.cuda.synchronize()
+        log(f"topk rows={rows} n={n} k={k}")
+        cm.camelot_stage_run(desc, ds.data_ptr(), dout.data_ptr(), rows, 16, 0)
+        raw = dout.cpu().numpy()
+        idx = raw[: rows * k].reshape(rows, k)
+        val = raw[rows * k:].view(np.float32).reshape(rows, k)
+        ridx, rval = O.topk(s, k)
+        assert np.array_equal(idx, ridx)
+        assert np.array_equal(val, rval)
+
+
+@pytest.mark.parametrize("rows", [1, 3, 16])
+def test_logmel_parity(torch, cm, rows):
+    audio = G.c1_audio(rows, seed=rows)
+    da = to_dev(torch, audio)
+    dy = torch.empty((rows, 440), dtype=torch.float32, device="cuda")
+    desc = cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0)
+    torch.cuda.synchronize()
+    log(f"logmel rows={rows}")
+    cm.camelot_stage_run(desc, da.data_ptr(), dy.data_ptr(), rows, 32, 0)
+    y = dy.cpu().numpy()
+    err = O.normwise_err(y, O.log_mel(audio))
+    log(f"  err={err:.3e}")
+    assert err <= 1e-5
+
+
+def test_logmel_silence_and_impulse(torch, cm):
+    audio = np.zeros((2, 2000), np.float32)
+    audio[1, 170] = 1.0
+    da = to_dev(torch, audio)
+    dy = torch.empty((2, 440), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    cm.camelot_stage_run(cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0), da.data_ptr(), dy.data_ptr(), 2, 8, 0)
+    y = dy.cpu().numpy()
+    ref = O.log_mel(audio)
+    assert O.normwise_err(y, ref) <= 1e-5
+    assert np.all(np.abs(y[0] - np.log(1e-10)) < 1e-5 * abs(np.log(1e-10)))
+
+
+@pytest.mark.parametrize("rows", [1, 5, 16, 128])
+def test_mlp_bf16_parity(torch, cm, rows):
+    ws, d_ws, (_, mlp, _) = c1_stages(torch)
+    x = O.log_mel(G.c1_audio(min(rows, 4), seed=40 + rows)).astype(np.float32)
+    x = np.tile(x, (rows // len(x) + 1, 1))[:rows]
+    x = x + G.rng("handoff", rows).standard_normal(x.shape).astype(np.float32)
+    dx = to_dev(torch, x)
+    dy = torch.empty((rows, 4096), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    log(f"mlp rows={rows}")
+    ns = cm.camelot_stage_run(mlp, dx.data_ptr(), dy.data_ptr(), rows, 128, 0)
+    y = dy.cpu().numpy()
+    err = O.normwise_err(y, O.mlp_bf16(x, ws))
+    log(f"  err={err:.3e} ns={ns:.0f}")
+    assert err <= 2e-2
+
+
+def test_mlp_batch_and_grid_invariant(torch, cm):
+    ws, d_ws, (_, mlp, _) = c1_stages(torch)
+    x = G.rng("handoff", 77).standard_normal((128, 440)).astype(np.float32)
+    dx = to_dev(torch, x)
+    full = torch.empty((128, 4096), dtype=torch.float32, device="cuda")
+    one = torch.empty((1, 4096), dtype=torch.float32, device="cuda")
+    other = torch.empty((128, 4096), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    cm.camelot_stage_run(mlp, dx.data_ptr(), full.data_ptr(), 128, 128, 0)
+    cm.camelot_stage_run(mlp, dx[37:38].data_ptr(), one.data_ptr(), 1, 64, 64)
+    cm.camelot_stage_run(mlp, dx.data_ptr(), other.data_ptr(), 128, 48, 200 - 48 - 8)
+    f = full.cpu().numpy()
+    assert np.array_equal(one.cpu().numpy()[0], f[37])
+    assert np.array_equal(other.cpu().numpy(), f)
+
+
+def test_stage_run_rejects_bad_shares(torch, cm):
+    desc = cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0)
+    for n_cus, off in ((12, 0), (8, 4), (256, 8)):
+        with pytest.raises(cm.CamelotError) as e:
+            cm.camelot_stage_run(desc, 0, 0, 0, n_cus, off)
+        assert e.value.code == cm.EINVAL
