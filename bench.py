@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Benchmark of the speech-assistant pipeline on one MI355X.
+
+Workload: 3 co-located stages on one GPU, each a persistent worker on its own
+CU-masked stream: (1) 2000-sample 16 kHz clips -> 11 frames -> 512-point FFT ->
+40-bin log-mel (FP32); (2) MLP 440->2048->2048->2048->4096, BF16 weights and
+activations on MFMA with FP32 accumulation; (3) top-10 over 4096 scores. Batches of
+up to 128 queries; p99 QoS target 50 ms.
+
+Steps (all on synthetic, seeded inputs resident in HBM before any timed region):
+ 1. solo profile table: every stage x CU share (8..256 in steps of 8) x batch
+    (1..128, powers of two), measured with the library's one-shot stage kernel;
+ 2. allocation: max-peak problem (Eq. 1) over that table -> CU shares and batch;
+ 3. peak QPS at p99 <= QoS: Poisson-arrival replays (device-side arrival clock,
+    payloads already in HBM), binary search on the rate, for the allocation with
+    device-global handoff and for the baseline (even split 88/88/80 CUs,
+    host-staged handoff, same batching rule);
+ 4. timed steps: K replays at the found peak rate (one step = one trial);
+ 5. CUs at 20% load: min-resource problem (Eq. 3) at 20% of the baseline's peak,
+    checked with a replay;
+ 6. device-global handoff GB/s (1 GiB ring, 128 + 128 CUs) vs the 8 TB/s HBM peak;
+ 7. roofline of the dominant kernel (the BF16 MLP stage at batch 128 on its share);
+ 8. the CPU oracle timed on a bounded sample on this host (1 thread).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+QOS_NS = 50_000_000
+HBM_PEAK = 8.0e12
+MFMA_BF16_PEAK = 2.5e15
+MLP_PARAMS = 440 * 2048 + 2048 * 2048 * 2 + 2048 * 4096
+BATCHES = [1, 2, 4, 8, 16, 32, 64, 128]
+SHARES = list(range(8, 257, 8))
+WORKLOAD = ("3-stage speech pipeline: 2000-sample 16 kHz clips -> 512-pt FFT + 40-bin log-mel (FP32) -> "
+            "MLP 440-2048-2048-2048-4096 (BF16 MFMA, FP32 acc) -> top-10; batch <= 128; p99 QoS 50 ms")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- CPU baseline
+def cpu_baseline(n: int) -> dict:
+    """The oracle (FP64 NumPy) on `n` queries of the same workload, one thread."""
+    import numpy as np  # noqa: F401
+    import workload_gen as G
+    from oracle import stages as O
+    ws = G.c1_mlp_weights(0)
+    audio = G.c1_audio(n, seed=7)
+    t0 = time.perf_counter()
+    for i in range(0, n, 16):
+        x = audio[i:i + 16]
+        O.topk(O.mlp_bf16(O.log_mel(x), ws), 10)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} queries of the speech pipeline (log-mel, BF16-rounded MLP, top-10) in FP64 NumPy, "
+                      f"1 thread, {dt:.1f} s"}
+
+
+def run_cpu_baseline(n: int) -> dict:
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", str(n)],
+                       capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+# ---------------------------------------------------------------- GPU parts
+class Speech:
+    def __init__(self, torch, cm, G, pool_base=16384, tiles=8):
+        import numpy as np
+        self.torch, self.cm, self.np = torch, cm, np
+        self.ws = G.c1_mlp_weights(0)
+        self.d_ws = [torch.from_numpy(w.view(np.int16)).cuda() for w in self.ws]
+        self.stages = (cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0),
+                       cm.stage_desc(cm.STAGE_MLP_BF16, dims=G.C1_MLP_DIMS, weights=[t.data_ptr() for t in self.d_ws]),
+                       cm.stage_desc(cm.STAGE_TOPK, dims=(4096,), k=10, n_layers=0))
+        base = torch.from_numpy(G.c1_audio_fast(pool_base, seed=0)).cuda()
+        # tiled copies at distinct addresses: the pool (1 GiB) does not fit the 256 MB MALL
+        self.pool = torch.empty((pool_base * tiles, 2000), dtype=torch.float32, device="cuda")
+        for t in range(tiles):
+            self.pool[t * pool_base:(t + 1) * pool_base] = base
+        g = G.rng("handoff", 1234)
+        self.in_bufs = [self.pool[:128].contiguous(),
+                        torch.from_numpy(g.standard_normal((128, 440)).astype(np.float32)).cuda(),
+                        torch.from_numpy(g.standard_normal((128, 4096)).astype(np.float32)).cuda()]
+        self.out_bufs = [torch.empty((128, 440), dtype=torch.float32, device="cuda"),
+                         torch.empty((128, 4096), dtype=torch.float32, device="cuda"),
+                         torch.empty((128 * 20,), dtype=torch.float32, device="cuda")]
+        torch.cuda.synchronize()
+
+    # algorithmic bytes moved by one batch of b rows through stage s (inputs,
+    # outputs, weights once per batch)
+    @staticmethod
+    def stage_bytes(s, b):
+        if s == 0:
+            return b * (8000 + 1760)
+        if s == 1:
+            return 2 * MLP_PARAMS + b * (1760 + 16384)
+        return b * (16384 + 80)
+
+    def stage_footprint(self, s, b, depth=4):
+        slot = 4096 + 128 * [1760, 16384, 80][s]
+        w = 2 * MLP_PARAMS if s == 1 else 0
+        scratch = 2 * 128 * 4096 * 2 if s == 1 else 0
+        return w + scratch + depth * slot
+
+    def profile(self, reps=16):
+        import numpy as np
+        S, K, nb = 3, len(SHARES), len(BATCHES)
+        lat = np.zeros((S, K, nb), np.int64)
+        for s in range(S):
+            for k, share in enumerate(SHARES):
+                for j, b in enumerate(BATCHES):
+                    ns = self.cm.camelot_stage_run(self.stages[s], self.in_bufs[s].data_ptr(),
+                                                   self.out_bufs[s].data_ptr(), b, share, 0, reps)
+                    lat[s, k, j] = max(1, int(math.ceil(ns)))
+            log(f"  profiled stage {s}: b=128 {lat[s, 0, -1] / 1e3:.1f} us @8 CUs, "
+                f"{lat[s, -1, -1] / 1e3:.1f} us @256 CUs")
+        bw = np.zeros_like(lat)
+        for s in range(S):
+            for j, b in enumerate(BATCHES):
+                bw[s, :, j] = (self.stage_bytes(s, b) * 1_000_000_000) // lat[s, :, j]
+        mem = np.array([[self.stage_footprint(s, b) for b in BATCHES] for s in range(S)], np.int64)
+        return lat, bw, mem
+
+    def trial(self, cu, rate, duration_s, handoff, batch, batch_timeout_ns, seed=0, cu_offset=0):
+        """One Poisson replay; returns dict(p50, p99, n, wall_s, achieved_qps)."""
+        import numpy as np
+        import workload_gen as G
+        cm = self.cm
+        n = int(min(max(rate * duration_s, 2000), 6_000_000))
+        arr = G.poisson_arrivals_ns(n, rate, seed=seed, sub=int(rate) % 100000)
+        ids = np.arange(1, n + 1, dtype=np.uint64)
+        prow = np.arange(n, dtype=np.int64) % self.pool.shape[0]
+        cfg = cm.pipeline_config(self.stages, cu, cu_offset=cu_offset, max_batch=batch, batch_target=batch,
+                                 batch_timeout_ns=batch_timeout_ns, ring_depth=4, handoff=handoff,
+                                 ingest=cm.INGEST_REPLAY, egress_capacity=1 << 20,
+                                 idle_timeout_ns=5_000_000_000)
+        p = cm.camelot_pipeline_create(cfg)
+        lat = np.empty(n, np.int64)
+        got_ids = np.empty(n, np.uint64)
+        done = 0
+        chunk_ids = np.empty(1 << 16, np.uint64)
+        chunk_lat = np.empty(1 << 16, np.int64)
+        t0 = time.perf_counter()
+        try:
+            cm.camelot_pipeline_replay(p, ids, np.ones(n, np.int32), arr, prow, self.pool.data_ptr(),
+                                       self.pool.shape[0])
+            deadline = t0 + duration_s * 4 + 10
+            while done < n and time.perf_counter() < deadline:
+                k = cm.camelot_pipeline_drain_latency(p, chunk_ids, chunk_lat, 100_000_000)
+                if k:
+                    m = min(k, n - done)
+                    lat[done:done + m] = chunk_lat[:m]
+                    got_ids[done:done + m] = chunk_ids[:m]
+                    done += m
+            wall = time.perf_counter() - t0
+        finally:
+            cm.camelot_pipeline_destroy(p)
+        if done < n:
+            return {"n": n, "done": done, "p50": math.inf, "p99": math.inf, "wall_s": wall, "ok": False}
+        assert np.array_equal(got_ids, ids), "delivery out of order"
+        warm = n // 10                       # discard the warm-up tenth
+        srt = np.sort(lat[warm:])
+        p99 = int(srt[math.ceil(0.99 * len(srt)) - 1])
+        p50 = int(srt[math.ceil(0.50 * len(srt)) - 1])
+        return {"n": n, "done": done, "p50": p50, "p99": p99, "wall_s": wall, "ok": p99 <= QOS_NS,
+                "span_s": float(arr[-1]) / 1e9}
+
+    def peak_search(self, cu, handoff, batch, guess_qps, duration_s, iters, tag):
+        lo, hi = 0.0, guess_qps * 2.0
+        best = None
+        timeout = QOS_NS // 4
+        for it in range(iters):
+            rate = (lo + hi) / 2 if it else guess_qps
+            r = self.trial(cu, rate, duration_s, handoff, batch, timeout, seed=it)
+            log(f"  [{tag}] rate {rate / 1e6:.3f} Mq/s -> p50 {r['p50'] / 1e3:.0f} us p99 {r['p99'] / 1e3:.0f} us "
+                f"ok={r['ok']}")
+            if r["ok"]:
+                lo = rate
+                best = (rate, r)
+            else:
+                hi = rate
+            if best is None and it == iters - 1:
+                break
+        return best
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--trial-s", type=float, default=0.5, help="seconds of arrivals per replay trial")
+    ap.add_argument("--search-iters", type=int, default=8)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-baseline-only", type=int, default=0)
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.cpu_baseline_only)))
+        return 0
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: this build runs on a single GPU only (use --gpus 1).",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import workload_gen as G
+    from paper_2005_02088_amd import camelot as cm
+
+    dev = cm.camelot_device_query()
+    log(f"device {dev.arch.decode()} CUs={dev.n_cus}")
+    sp = Speech(torch, cm, G)
+
+    # 1-2: profile table and allocation (Eq. 1)
+    t0 = time.perf_counter()
+    lat, bw, mem = sp.profile()
+    log(f"profile table: {time.perf_counter() - t0:.1f} s")
+    prob = cm.ProblemArrays(cu_total=256, cu_step=8, max_instances=48, max_inst_per_stage=1, batches=BATCHES,
+                            qos_ns=QOS_NS, hbm_bytes_budget=dev.hbm_bytes, hbm_bw_budget=int(HBM_PEAK),
+                            lat_ns=lat, bw_bps=bw, mem_bytes=mem)
+    t0 = time.perf_counter()
+    alloc = cm.camelot_alloc_peak(prob)
+    alloc_ms = (time.perf_counter() - t0) * 1e3
+    a = alloc.as_dict()
+    pred = a["thr_num"] / a["thr_den"]
+    log(f"allocation {a} predicted {pred / 1e6:.3f} Mq/s ({alloc_ms:.2f} ms)")
+    even = [88, 88, 80]
+    ok_even, ea = cm.camelot_alloc_eval(prob, a["batch_index"], [1, 1, 1], even)
+    pred_even = ea.thr_num / ea.thr_den
+    batch = a["batch"]
+
+    # 3: peak QPS at p99 <= QoS
+    cam = sp.peak_search(a["cu"], cm.HANDOFF_DEVICE, batch, pred, args.trial_s, args.search_iters, "camelot")
+    base = sp.peak_search(even, cm.HANDOFF_HOST, batch, pred_even, args.trial_s, args.search_iters, "baseline")
+    peak = cam[0] if cam else 0.0
+    peak_base = base[0] if base else 0.0
+
+    # 4: timed steps at the found peak
+    for w in range(args.warmup):
+        sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    steps = []
+    for k in range(args.steps):
+        steps.append(sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=200 + k))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    p99s = [s["p99"] for s in steps]
+    log(f"timed steps p99 {p99s}")
+
+    # 5: CUs at 20% load
+    lam20 = 0.2 * peak_base
+    num, den = int(lam20 * 1000), 1000
+    amin = cm.camelot_alloc_min(prob, num, den)
+    cus20 = None
+    p99_20 = None
+    if amin is not None:
+        m = amin.as_dict()
+        cus20 = m["cu_used"]
+        r20 = sp.trial(m["cu"], lam20, args.trial_s, cm.HANDOFF_DEVICE, m["batch"], QOS_NS // 4, seed=300)
+        p99_20 = r20["p99"]
+        log(f"20% load {lam20 / 1e6:.3f} Mq/s: allocation {m} p99 {p99_20 / 1e3:.0f} us")
+
+    # 6: handoff GB/s
+    slot = 64 << 20
+    h = cm.camelot_handoff_bench(cm.HANDOFF_DEVICE, slot, 16, 128, 128, 128)
+    hs, hx = cm.camelot_handoff_expected(slot, 128)
+    handoff_ok = (h["sum"], h["xor"]) == (hs, hx)
+    hh = cm.camelot_handoff_bench(cm.HANDOFF_HOST, slot, 2, 8, 8, 8)
+    log(f"handoff device {h['gbs']:.0f} GB/s (checksum ok={handoff_ok}), host-staged {hh['gbs']:.1f} GB/s")
+
+    # 7: roofline of the dominant kernel (MLP stage, batch 128, on its share)
+    mlp_cus = a["cu"][1]
+    reps = 50
+    ns = cm.camelot_stage_run(sp.stages[1], sp.in_bufs[1].data_ptr(), sp.out_bufs[1].data_ptr(), 128,
+                              mlp_cus, 0, reps)
+    mlp_bytes = Speech.stage_bytes(1, 128)
+    mlp_flops = 2 * MLP_PARAMS * 128
+    achieved = mlp_bytes / (ns * 1e-9)
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": None,
+            "kernel": "stage_bench<MLP_BF16>", "share_cus": mlp_cus, "launch_ns_per_batch": ns,
+            "bytes_per_batch": mlp_bytes, "mfma_tflops": mlp_flops / (ns * 1e-9) / 1e12,
+            "mfma_frac": mlp_flops / (ns * 1e-9) / MFMA_BF16_PEAK}
+    log(f"MLP @128 on {mlp_cus} CUs: {ns / 1e3:.1f} us/batch -> {achieved / 1e9:.0f} GB/s")
+
+    # 8: CPU baseline
+    cpu = None if args.skip_cpu else run_cpu_baseline(args.cpu_sample)
+
+    out = {
+        "metric": "peak QPS at p99<=QoS per GPU; CUs used at 20% load; handoff GB/s vs HBM peak",
+        "value": peak, "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / max(args.steps, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "global_batch": batch, "parallelism": "spatial CU partitions on 1 GPU",
+                   "allocation_cus": a["cu"], "ingest": "device replay of Poisson arrivals, payloads in HBM",
+                   "handoff": "device-global ring + doorbells", "qos_ns": QOS_NS},
+        "timed_steps_p99_ns": p99s, "timed_steps_qos_met": all(s["ok"] for s in steps),
+        "predicted_qps": pred, "alloc_ms": alloc_ms,
+        "baseline": {"kind": "even split 88/88/80 CUs, host-staged handoff", "peak_qps": peak_base,
+                     "predicted_qps": pred_even},
+        "gain_vs_even_split_host_staged": (peak / peak_base) if peak_base else None,
+        "cus_at_20pct_load": {"camelot": cus20, "baseline_even_split": 256, "load_qps": lam20,
+                              "p99_ns": p99_20},
+        "handoff": {"gbs": h["gbs"], "frac_of_hbm_peak": h["gbs"] * 1e9 / HBM_PEAK, "checksum_ok": handoff_ok,
+                    "ring_bytes": slot * 16, "host_staged_gbs": hh["gbs"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -178,13 +178,14 @@ int64_t camelot_stage_row_bytes_out(const camelot_stage_desc* stage);
 
 /* Run one stage over `rows` rows (0..CAMELOT_MAX_BATCH) on `n_cus` CUs starting
  * at CU-mask bit `cu_offset` (n_cus and cu_offset multiples of 8; 0 n_cus = all
- * CUs), `reps` times back to back (the same input each time), as the persistent
- * worker does inside a pipeline (same kernel, same grid).
+ * CUs), `reps` times back to back (the same input each time), with the compute
+ * code and grid of the persistent worker (one kernel launch, grid barriers
+ * between reps).
  *   in   device, rows * row_bytes_in
  *   out  device, rows * row_bytes_out (result stages: [rows][k] int32 indices
  *        followed by [rows][k] f32 values, i.e. 2 planes)
- *   ns_per_rep (may be NULL) receives the device-clock time of the reps divided
- *        by reps, in ns.
+ *   ns_per_rep (may be NULL) receives the launch's duration measured with HIP
+ *        events on the stream it ran on, divided by reps, in ns.
  * Synchronous: returns after the work completed. */
 int32_t camelot_stage_run(const camelot_stage_desc* stage, const void* in, void* out,
                           int32_t rows, int32_t n_cus, int32_t cu_offset, int32_t reps,
@@ -265,6 +266,13 @@ typedef struct {
  * arrived in time; EDEVICE if a worker reported a failure. */
 int32_t camelot_pipeline_drain(camelot_pipeline* p, camelot_result* out, int32_t max,
                                int32_t* n_out, int64_t timeout_ns);
+
+/* Bulk drain for load tests: for up to max finished rows, in the same order as
+ * camelot_pipeline_drain, the request id and the latency done - arrival in ns.
+ * ids and lat_ns are host arrays of max entries. Same waiting and errors as
+ * camelot_pipeline_drain. */
+int32_t camelot_pipeline_drain_latency(camelot_pipeline* p, uint64_t* ids, int64_t* lat_ns,
+                                       int32_t max, int32_t* n_out, int64_t timeout_ns);
 
 /* Device replay ingest: n_req requests with ids[] (strictly increasing), rows[],
  * arrival_ns[] (ns after the start, non-decreasing) and payload_row[] (index of

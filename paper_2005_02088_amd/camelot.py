@@ -115,6 +115,7 @@ _SIGS = {
     "camelot_pipeline_submit": (C.c_int32, [_P, C.c_uint64, _P, C.c_int32]),
     "camelot_pipeline_drain": (C.c_int32, [_P, C.POINTER(Result), C.c_int32, C.POINTER(C.c_int32),
                                            C.c_int64]),
+    "camelot_pipeline_drain_latency": (C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(C.c_int32), C.c_int64]),
     "camelot_pipeline_replay": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, C.c_int64]),
     "camelot_pipeline_stats_get": (C.c_int32, [_P, C.POINTER(PipelineStats)]),
     "camelot_pipeline_destroy": (C.c_int32, [_P, C.POINTER(C.c_uint64)]),
@@ -297,6 +298,17 @@ def camelot_pipeline_drain(p: int, max_results: int = 4096, timeout_ns: int = 0)
         return []
     _check(rc)
     return out[: n.value]
+
+
+def camelot_pipeline_drain_latency(p: int, ids: np.ndarray, lat_ns: np.ndarray, timeout_ns: int = 0) -> int:
+    """Fills ids (uint64) and lat_ns (int64) arrays from the front; returns the count."""
+    n = C.c_int32(0)
+    rc = _lib.camelot_pipeline_drain_latency(p, ids.ctypes.data, lat_ns.ctypes.data, min(len(ids), len(lat_ns)),
+                                             C.byref(n), int(timeout_ns))
+    if rc == ETIMEDOUT:
+        return 0
+    _check(rc)
+    return n.value
 
 
 def camelot_pipeline_replay(p: int, ids, rows, arrival_ns, payload_row, payload_ptr: int, payload_rows: int):

@@ -43,7 +43,7 @@ void clear_error() { g_err.clear(); }
     if (e_ != hipSuccess) return fail(CAMELOT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-const void* worker_kernel(int kind);   // stages.hip
+const void* worker_kernel(int kind, bool bench);   // stages.hip
 
 // All library allocations, fills and frees go through one non-blocking stream with
 // stream-ordered allocation: the CU-masked streams of live pipelines are blocking
@@ -323,7 +323,7 @@ static int32_t check_share(int n_cus, int offset, int total) {
 }
 
 static int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
-  const void* fn = worker_kernel(kind);
+  const void* fn = worker_kernel(kind, a.in_kind == kInBench);
   if (!fn) return fail(CAMELOT_EINVAL, "no worker for stage kind %d", kind);
   void* args[] = {(void*)&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(kWgPerCu * n_cus), dim3(kThreads), args, 0, s));
@@ -400,14 +400,23 @@ extern "C" int32_t camelot_stage_run(const camelot_stage_desc* stage, const void
   a.bench_out = (uint8_t*)out;
   a.bench_rows = rows;
   a.bench_reps = reps;
-  if ((rc = launch_worker(stage->kind, a, n_cus, s))) return rc;
+  hipEvent_t ev0, ev1;
+  HIP_TRY(hipEventCreate(&ev0));
+  HIP_TRY(hipEventCreate(&ev1));
+  HIP_TRY(hipEventRecord(ev0, s));
+  rc = launch_worker(stage->kind, a, n_cus, s);
+  if (!rc) HIP_TRY(hipEventRecord(ev1, s));
   HIP_TRY(hipStreamSynchronize(s));
-  uint64_t ticks = 0;
+  float ms = 0.f;
+  if (!rc) HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (rc) return rc;
   uint32_t abort_flag = 0;
-  if ((rc = d2h(&ticks, &ctl->ticks_bench, 8))) return rc;
   if ((rc = d2h(&abort_flag, &ctl->abort, 4))) return rc;
   if (abort_flag) return fail(CAMELOT_ETIMEDOUT, "stage worker grid barrier timed out");
-  if (ns_per_rep) *ns_per_rep = (double)ticks * 1e9 / (double)dev.wclk_hz / reps;
+  // HIP events on the stream the kernel ran on: the whole launch, divided by reps
+  if (ns_per_rep) *ns_per_rep = (double)ms * 1e6 / reps;
   return CAMELOT_OK;
 }
 
@@ -896,6 +905,38 @@ extern "C" int32_t camelot_pipeline_drain(camelot_pipeline* p, camelot_result* o
     }
     r.t_ns[2 * S] = ticks_to_ns((int64_t)h.t_done - epoch, hz);   // last stage ends when its row is done
     r.t_ns[2 * S + 1] = ticks_to_ns((int64_t)h.t_done - epoch, hz);
+  }
+  p->egress_tail += n;
+  __atomic_store_n(&p->hctl->egress_tail, p->egress_tail, __ATOMIC_RELEASE);
+  *n_out = (int32_t)n;
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_pipeline_drain_latency(camelot_pipeline* p, uint64_t* ids, int64_t* lat_ns,
+                                                  int32_t max, int32_t* n_out, int64_t timeout_ns) {
+  clear_error();
+  if (!p || !ids || !lat_ns || !n_out || max < 0) return fail(CAMELOT_EINVAL, "bad drain arguments");
+  *n_out = 0;
+  const int64_t t_end = host_ns() + std::max<int64_t>(timeout_ns, 0);
+  uint64_t head;
+  for (;;) {
+    head = __atomic_load_n(&p->pub->egress_head, __ATOMIC_ACQUIRE);
+    if (head > p->egress_tail || max == 0) break;
+    int32_t rc = worker_error(p);
+    if (rc && rc != CAMELOT_ESTOPPED) return rc;
+    if (host_ns() >= t_end) {
+      if (rc == CAMELOT_ESTOPPED) return rc;
+      return fail(CAMELOT_ETIMEDOUT, "no result within the timeout");
+    }
+    std::this_thread::yield();
+  }
+  const uint64_t n = std::min<uint64_t>(head - p->egress_tail, (uint64_t)max);
+  const int64_t hz = p->dev.wclk_hz;
+  for (uint64_t j = 0; j < n; ++j) {
+    const uint64_t slot = (p->egress_tail + j) % (uint64_t)p->cfg.egress_capacity;
+    const EgressRec* h = (const EgressRec*)(p->egress + slot * p->rec_bytes);
+    ids[j] = h->id;
+    lat_ns[j] = (int64_t)ticks_to_ns((int64_t)h->t_done - (int64_t)h->t_arr, hz);
   }
   p->egress_tail += n;
   __atomic_store_n(&p->hctl->egress_tail, p->egress_tail, __ATOMIC_RELEASE);

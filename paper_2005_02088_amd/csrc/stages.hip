@@ -513,6 +513,26 @@ __device__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq,
   }
 }
 
+// ------------------------------------------------------------------ one-shot / profiling kernel
+// Runs the stage's compute `reps` times back to back on a fixed input with the
+// same grid and the same code as the persistent worker (used for parity checks
+// and for the solo profiling table).
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void stage_bench(WorkerArgs a) {
+  WorkerCtl* ctl = a.ctl;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0)
+    for (int i = tid; i < a.bench_rows; i += kThreads)
+      ctl->d_rowptr[i] = a.bench_in + (int64_t)i * a.sp.in_row_bytes;
+  if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
+  const uint64_t t0 = now_ticks();
+  for (int rep = 0; rep < a.bench_reps; ++rep) {
+    if (!exec_stage<KIND>(a, ctl, a.bench_rows, a.bench_out)) return;
+    if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
+  }
+  if (blockIdx.x == 0 && tid == 0) ctl->ticks_bench = now_ticks() - t0;
+}
+
 // ------------------------------------------------------------------ worker kernel
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
@@ -520,21 +540,6 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
   const int tid = threadIdx.x;
   const bool wg0 = blockIdx.x == 0;
   const int si = a.stage_index;
-
-  // ---------------- bench mode: fixed input, `reps` back-to-back batches
-  if (a.in_kind == kInBench) {
-    if (wg0)
-      for (int i = tid; i < a.bench_rows; i += kThreads)
-        ctl->d_rowptr[i] = a.bench_in + (int64_t)i * a.sp.in_row_bytes;
-    if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
-    const uint64_t t0 = now_ticks();
-    for (int rep = 0; rep < a.bench_reps; ++rep) {
-      if (!exec_stage<KIND>(a, ctl, a.bench_rows, a.bench_out)) return;
-      if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
-    }
-    if (wg0 && tid == 0) ctl->ticks_bench = now_ticks() - t0;
-    return;
-  }
 
   // ---------------- pipeline mode
   __shared__ uint64_t s_id[kMaxBatch];
@@ -707,9 +712,24 @@ template __global__ void stage_worker<CAMELOT_STAGE_GEMM_ARGMAX>(WorkerArgs);
 template __global__ void stage_worker<CAMELOT_STAGE_LOGMEL>(WorkerArgs);
 template __global__ void stage_worker<CAMELOT_STAGE_MLP_BF16>(WorkerArgs);
 template __global__ void stage_worker<CAMELOT_STAGE_TOPK>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_GEMM_RELU>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_GEMM_ARGMAX>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_LOGMEL>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_MLP_BF16>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_TOPK>(WorkerArgs);
 
-// Host-side accessor of the kernel entry for a stage kind.
-const void* worker_kernel(int kind) {
+// Host-side accessor of the kernel entry for a stage kind (bench: one-shot kernel).
+const void* worker_kernel(int kind, bool bench) {
+  if (bench) {
+    switch (kind) {
+      case CAMELOT_STAGE_GEMM_RELU: return (const void*)&stage_bench<CAMELOT_STAGE_GEMM_RELU>;
+      case CAMELOT_STAGE_GEMM_ARGMAX: return (const void*)&stage_bench<CAMELOT_STAGE_GEMM_ARGMAX>;
+      case CAMELOT_STAGE_LOGMEL: return (const void*)&stage_bench<CAMELOT_STAGE_LOGMEL>;
+      case CAMELOT_STAGE_MLP_BF16: return (const void*)&stage_bench<CAMELOT_STAGE_MLP_BF16>;
+      case CAMELOT_STAGE_TOPK: return (const void*)&stage_bench<CAMELOT_STAGE_TOPK>;
+      default: return nullptr;
+    }
+  }
   switch (kind) {
     case CAMELOT_STAGE_GEMM_RELU: return (const void*)&stage_worker<CAMELOT_STAGE_GEMM_RELU>;
     case CAMELOT_STAGE_GEMM_ARGMAX: return (const void*)&stage_worker<CAMELOT_STAGE_GEMM_ARGMAX>;

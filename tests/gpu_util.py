@@ -1,4 +1,5 @@
 """Helpers shared by the GPU tests (device buffers via torch, library calls via the binding)."""
+import functools
 import sys
 
 import numpy as np
@@ -32,11 +33,17 @@ def c0_stages(torch, seed=0):
     return (w1, w2), (d_w1, d_w2), (a, b)
 
 
+@functools.lru_cache(maxsize=4)
+def c1_weights(seed=0):
+    import workload_gen as G
+    return G.c1_mlp_weights(seed)
+
+
 def c1_stages(torch, seed=0, k=10):
     """Device weights and stage descriptors of the speech-assistant pipeline."""
     import workload_gen as G
     from paper_2005_02088_amd import camelot as cm
-    ws = G.c1_mlp_weights(seed)
+    ws = c1_weights(seed)
     d_ws = [to_dev(torch, w.view(np.int16)) for w in ws]
     mel = cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0)
     mlp = cm.stage_desc(cm.STAGE_MLP_BF16, dims=G.C1_MLP_DIMS, weights=[t.data_ptr() for t in d_ws])

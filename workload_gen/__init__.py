@@ -95,9 +95,12 @@ def _to_bf16_bits(x32: np.ndarray) -> np.ndarray:
     """Round FP32 to BF16 (nearest-even) and return the 16-bit patterns.
 
     Used only to *store* generated weights in BF16; values are finite N(0, s)."""
-    u = x32.astype(np.float32).view(np.uint32).astype(np.uint64)
-    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-    return r.astype(np.uint16)
+    u = np.array(x32, dtype=np.float32).view(np.uint32)   # a copy we can work in place on
+    lsb = (u >> 16) & np.uint32(1)
+    u += np.uint32(0x7FFF)          # finite inputs: no 32-bit overflow
+    u += lsb
+    u >>= 16
+    return u.astype(np.uint16)
 
 
 def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
@@ -109,7 +112,8 @@ def c1_mlp_weights(seed: int = 0, dims=C1_MLP_DIMS):
     g = rng("c1_weights", seed)
     ws = []
     for din, dout in zip(dims[:-1], dims[1:]):
-        w = (g.standard_normal((dout, din)) / np.sqrt(din)).astype(np.float32)
+        w = g.standard_normal((dout, din), dtype=np.float32)
+        w *= np.float32(1.0 / np.sqrt(din))
         ws.append(_to_bf16_bits(w))
     return ws
 
