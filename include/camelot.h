@@ -354,6 +354,76 @@ int32_t camelot_predictor_train(float* params, float* m1, float* m2, int32_t* t,
                                 int32_t epochs, const int32_t* perm, float lr,
                                 float* epoch_loss, void* stream);
 
+/* ------------------------------------------------------------------ contention profiles
+ * The paper profiles each microservice alone and observes that co-located stages
+ * run slower than their solo profiles (Section III-A, the balanced deployment
+ * policy). These calls measure that contention.
+ *
+ * camelot_stage_corun: runs n stages at once, stage j on n_cus[j] CUs from mask bit
+ * cu_offset[j] (shares disjoint, multiples of 8), each repeating batches of rows[j]
+ * rows of in[j] into out[j] (as camelot_stage_run) for duration_ns of device time,
+ * and writes each stage's mean time per batch while the others ran. */
+int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stages, const void* const* in,
+                            void* const* out, const int32_t* rows, const int32_t* n_cus,
+                            const int32_t* cu_offset, int64_t duration_ns, double* ns_per_batch);
+
+typedef struct {
+  int32_t m;                   /* stages in this run, 1..3                            */
+  int32_t kinds[3];            /* which of the n_kinds stages                         */
+  int32_t cu[3];               /* CUs of each                                         */
+  int32_t bi[3];               /* batch index of each                                 */
+  double ns[3];                /* measured time per batch of each                    */
+} camelot_corun_record;
+
+/* Random co-location profiles: n_runs runs, each of m = 1, 2 or 3 distinct stage
+ * kinds (probabilities 0.1, 0.3, 0.6, capped at n_kinds), shares drawn uniformly in
+ * cu_step steps with total <= cu_total and placed side by side from bit 0, batch
+ * indices equal for all stages with probability 1/2 and independent otherwise;
+ * the draws come from a SplitMix64 stream seeded with `seed`. in[k]/out[k] are
+ * kind k's device buffers for max(batches) rows. */
+int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_desc* stages, const void* const* in,
+                               void* const* out, int32_t cu_total, int32_t cu_step, int32_t n_batches,
+                               const int32_t* batches, int32_t n_runs, uint64_t seed,
+                               int64_t duration_ns, camelot_corun_record* records);
+
+/* ------------------------------------------------------------------ learned predictor features
+ * Solo summaries the features use, per stage kind, CU share index k ((k + 1) * cu_step
+ * CUs) and batch index: hbm = solo algorithmic HBM bytes/s / HBM peak, mfma = solo
+ * flop rate / MFMA peak of the whole GPU; both [n_kinds][n_shares][n_batches] host
+ * float arrays. */
+typedef struct {
+  int32_t n_kinds, cu_step, n_shares, n_batches;
+  const int32_t* batches;
+  const float* hbm;
+  const float* mfma;
+} camelot_solo_tables;
+
+#define CAMELOT_PRED_FEATURES 16
+
+/* Features of one co-location of m <= 3 stages: stage j has kind kinds[j] (< 3),
+ * share cu[j] and batch index bi[j]. Row j (16 floats) of feat (host) is:
+ * own share / 256, log2(own batch) / 7, own solo hbm, own solo mfma, one-hot kind (3),
+ * then for each other stage in order (2 slots, zeros if absent): share / 256,
+ * log2(batch) / 7, solo hbm, solo mfma; last, the CUs of all m stages / 256. */
+int32_t camelot_predictor_features(const camelot_solo_tables* t, int32_t m, const int32_t* kinds,
+                                   const int32_t* cu, const int32_t* bi, float* feat);
+
+/* Standardisation fitted on n rows of host features x [n][16]: mean and std (host
+ * [16], std floored at 1e-6); camelot_predictor_standardize applies it in place. */
+int32_t camelot_predictor_fit_norm(const float* x, int32_t n, float* mean, float* std);
+int32_t camelot_predictor_standardize(float* x, int32_t n, const float* mean, const float* std);
+
+/* Contention-aware Eq. 1: as camelot_alloc_peak with one instance per stage (n_stages
+ * <= 3, stage i of kind i), but every stage's latency comes from the learned predictor
+ * for the co-location the candidate forms (exp of its output, rounded up to ns), not
+ * from the solo table. params: device [CAMELOT_PRED_NPARAMS]; mean/std: host [16].
+ * The problem's lat_ns only marks unmeasured points (<= 0); bw_bps, mem_bytes and the
+ * tie rules are the same. lat_pred_ns (host [n_stages], may be NULL) receives the
+ * predicted latencies of the chosen point. */
+int32_t camelot_alloc_peak_learned(const camelot_problem* problem, const camelot_solo_tables* t,
+                                   const float* params, const float* mean, const float* std,
+                                   camelot_alloc* out, int64_t* lat_pred_ns);
+
 #ifdef __cplusplus
 }
 #endif

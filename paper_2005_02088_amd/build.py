@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["stages.hip", "handoff.hip", "predictor.hip", "runtime.cpp", "alloc.cpp"]
+SOURCES = ["stages.hip", "handoff.hip", "predictor.hip", "runtime.cpp", "learned.cpp", "alloc.cpp"]
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable"]
@@ -27,7 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    lang = ["-x", "hip"] if src.endswith((".hip", "runtime.cpp")) else []
+    lang = ["-x", "hip"] if src.endswith((".hip", "runtime.cpp", "learned.cpp")) else []
     cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"

@@ -93,7 +93,19 @@ class PipelineStats(C.Structure):
                 ("worker_status", C.c_int32 * MAX_STAGES)]
 
 
-STRUCTS = {"camelot_device_info": DeviceInfo, "camelot_problem": Problem, "camelot_alloc": Alloc,
+class CorunRecord(C.Structure):
+    _fields_ = [("m", C.c_int32), ("kinds", C.c_int32 * 3), ("cu", C.c_int32 * 3), ("bi", C.c_int32 * 3),
+                ("ns", C.c_double * 3)]
+
+
+class SoloTables(C.Structure):
+    _fields_ = [("n_kinds", C.c_int32), ("cu_step", C.c_int32), ("n_shares", C.c_int32),
+                ("n_batches", C.c_int32), ("batches", C.POINTER(C.c_int32)), ("hbm", C.POINTER(C.c_float)),
+                ("mfma", C.POINTER(C.c_float))]
+
+
+STRUCTS = {"camelot_corun_record": CorunRecord, "camelot_solo_tables": SoloTables,
+           "camelot_device_info": DeviceInfo, "camelot_problem": Problem, "camelot_alloc": Alloc,
            "camelot_stage_desc": StageDesc, "camelot_pipeline_config": PipelineConfig,
            "camelot_result": Result, "camelot_pipeline_stats": PipelineStats}
 
@@ -123,6 +135,15 @@ _SIGS = {
                                           C.c_int32, C.POINTER(C.c_double)]),
     "camelot_handoff_expected": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_uint64),
                                              C.POINTER(C.c_uint64)]),
+    "camelot_stage_corun": (C.c_int32, [C.c_int32, C.POINTER(StageDesc), _P, _P, _P, _P, _P, C.c_int64, _P]),
+    "camelot_profile_coruns": (C.c_int32, [C.c_int32, C.POINTER(StageDesc), _P, _P, C.c_int32, C.c_int32,
+                                           C.c_int32, _P, C.c_int32, C.c_uint64, C.c_int64,
+                                           C.POINTER(CorunRecord)]),
+    "camelot_predictor_features": (C.c_int32, [C.POINTER(SoloTables), C.c_int32, _P, _P, _P, _P]),
+    "camelot_predictor_fit_norm": (C.c_int32, [_P, C.c_int32, _P, _P]),
+    "camelot_predictor_standardize": (C.c_int32, [_P, C.c_int32, _P, _P]),
+    "camelot_alloc_peak_learned": (C.c_int32, [C.POINTER(Problem), C.POINTER(SoloTables), _P, _P, _P,
+                                               C.POINTER(Alloc), _P]),
     "camelot_predictor_forward": (C.c_int32, [_P, _P, C.c_int32, _P, _P]),
     "camelot_predictor_grad": (C.c_int32, [_P, _P, _P, C.c_int32, _P, C.POINTER(C.c_float), _P]),
     "camelot_predictor_adam": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_float, _P]),
@@ -373,3 +394,95 @@ def camelot_predictor_train(params: int, m1: int, m2: int, t: int, x: int, y: in
     _check(_lib.camelot_predictor_train(params, m1, m2, C.byref(tt), x, y, n, batch, epochs, perm or None,
                                         lr, losses.ctypes.data, stream or None))
     return tt.value, losses[:epochs]
+
+
+# ------------------------------------------------------------------ contention profiles
+def _descs(stages):
+    arr = (StageDesc * len(stages))()
+    for i, s in enumerate(stages):
+        arr[i] = s
+    return arr
+
+
+def _ptrs(vals):
+    return np.ascontiguousarray([int(v) for v in vals], dtype=np.uint64)
+
+
+def camelot_stage_corun(stages, ins, outs, rows, n_cus, cu_offset, duration_ns: int):
+    """Runs the stages at once on disjoint shares; returns ns per batch of each."""
+    n = len(stages)
+    d = _descs(stages)
+    pin, pout = _ptrs(ins), _ptrs(outs)
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    c = np.ascontiguousarray(n_cus, dtype=np.int32)
+    o = np.ascontiguousarray(cu_offset, dtype=np.int32)
+    ns = np.zeros(n, np.float64)
+    _check(_lib.camelot_stage_corun(n, d, pin.ctypes.data, pout.ctypes.data, r.ctypes.data, c.ctypes.data,
+                                    o.ctypes.data, int(duration_ns), ns.ctypes.data))
+    return ns
+
+
+def camelot_profile_coruns(stages, ins, outs, cu_total, cu_step, batches, n_runs, seed, duration_ns):
+    """Random co-location profiles; returns a list of CorunRecord."""
+    d = _descs(stages)
+    pin, pout = _ptrs(ins), _ptrs(outs)
+    b = np.ascontiguousarray(batches, dtype=np.int32)
+    recs = (CorunRecord * max(n_runs, 1))()
+    _check(_lib.camelot_profile_coruns(len(stages), d, pin.ctypes.data, pout.ctypes.data, cu_total, cu_step,
+                                       len(b), b.ctypes.data, n_runs, seed, int(duration_ns), recs))
+    return list(recs[:n_runs])
+
+
+class SoloTablesArrays:
+    """Keeps the arrays a SoloTables points at alive. hbm/mfma: [kinds][shares][batches]."""
+
+    def __init__(self, cu_step, batches, hbm, mfma):
+        self.batches = np.ascontiguousarray(batches, dtype=np.int32)
+        self.hbm = np.ascontiguousarray(hbm, dtype=np.float32)
+        self.mfma = np.ascontiguousarray(mfma, dtype=np.float32)
+        k, s, b = self.hbm.shape
+        self.struct = SoloTables(n_kinds=k, cu_step=cu_step, n_shares=s, n_batches=b,
+                                 batches=_ptr(self.batches, C.c_int32),
+                                 hbm=_ptr(self.hbm, C.c_float), mfma=_ptr(self.mfma, C.c_float))
+
+
+def camelot_predictor_features(tables: SoloTablesArrays, kinds, cu, bi) -> np.ndarray:
+    m = len(kinds)
+    k = np.ascontiguousarray(kinds, dtype=np.int32)
+    c = np.ascontiguousarray(cu, dtype=np.int32)
+    b = np.ascontiguousarray(bi, dtype=np.int32)
+    out = np.zeros((m, 16), np.float32)
+    _check(_lib.camelot_predictor_features(C.byref(tables.struct), m, k.ctypes.data, c.ctypes.data,
+                                           b.ctypes.data, out.ctypes.data))
+    return out
+
+
+def camelot_predictor_fit_norm(x: np.ndarray):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    mean = np.zeros(16, np.float32)
+    std = np.zeros(16, np.float32)
+    _check(_lib.camelot_predictor_fit_norm(x.ctypes.data, x.shape[0], mean.ctypes.data, std.ctypes.data))
+    return mean, std
+
+
+def camelot_predictor_standardize(x: np.ndarray, mean, std) -> np.ndarray:
+    """Returns a standardised copy."""
+    x = np.array(x, dtype=np.float32, order="C", copy=True)
+    mean = np.ascontiguousarray(mean, dtype=np.float32)
+    std = np.ascontiguousarray(std, dtype=np.float32)
+    _check(_lib.camelot_predictor_standardize(x.ctypes.data, x.shape[0], mean.ctypes.data, std.ctypes.data))
+    return x
+
+
+def camelot_alloc_peak_learned(problem: ProblemArrays, tables: SoloTablesArrays, params_ptr: int, mean, std):
+    """Returns (Alloc or None, predicted stage latencies in ns)."""
+    mean = np.ascontiguousarray(mean, dtype=np.float32)
+    std = np.ascontiguousarray(std, dtype=np.float32)
+    a = Alloc()
+    lat = np.zeros(MAX_STAGES, np.int64)
+    rc = _lib.camelot_alloc_peak_learned(C.byref(problem.struct), C.byref(tables.struct), params_ptr,
+                                         mean.ctypes.data, std.ctypes.data, C.byref(a), lat.ctypes.data)
+    if rc == EINFEASIBLE:
+        return None, None
+    _check(rc)
+    return a, lat[: problem.struct.n_stages]

@@ -11,7 +11,11 @@ namespace camelot {
 
 constexpr int kThreads = 256;          // 4 wave64s per workgroup
 constexpr int kWaves = kThreads / 64;
-constexpr int kWgPerCu = 2;            // worker grid = 2 workgroups per CU of the share
+// Worker grid = one workgroup per CU of the share. The dispatcher spreads a grid's
+// workgroups evenly over the shader engines of each XCD whatever the number of CUs
+// each engine has in the mask, so a CU can receive up to twice the average; every
+// stage kernel fits at least 2 workgroups per CU, which keeps the grid co-resident.
+constexpr int kWgPerCu = 1;
 constexpr int kMaxBatch = CAMELOT_MAX_BATCH;
 constexpr int kMaxStages = CAMELOT_MAX_STAGES;
 constexpr int kSlotHeaderBytes = 4096;
@@ -83,9 +87,14 @@ struct DevPub {
 
 // Per-worker device control block (device memory, zeroed at creation).
 struct WorkerCtl {
-  uint32_t bar_count;  uint32_t pad0[31];
-  uint32_t bar_gen;    uint32_t pad1[31];
+  // hierarchical grid barrier: workgroup g arrives on group counter g % 8, the last
+  // arrival of each group on the top counter; release words per group
+  uint32_t bar_group[8][32];      // one 128-byte line per group
+  uint32_t bar_top;    uint32_t pad0[31];
+  uint32_t bar_gen[8][32];        // release generation, one line per group
   uint32_t abort;      uint32_t pad2[31];
+  uint32_t diag_arrived, diag_nwg, diag_group;   // filled on a barrier timeout
+  uint32_t diag_pad;
   // batch descriptor broadcast by workgroup 0 through the grid barrier
   uint64_t d_seq;
   uint32_t d_stop;
@@ -107,6 +116,8 @@ struct WorkerCtl {
   uint64_t ingest_cursor;         // stage 0: next request to take
   uint64_t egress_head;            // result rows written (terminal stage)
   uint64_t ticks_bench;           // bench mode: elapsed device ticks
+  uint64_t reps_bench;            // bench mode: batches run
+  uint32_t bench_stop[2];         // bench mode: workgroup 0's decision to stop, by rep parity
   uint64_t sum_acc, xor_acc, batches_acc;
 };
 
@@ -165,7 +176,8 @@ struct WorkerArgs {
   const uint8_t* bench_in;
   uint8_t* bench_out;
   int32_t bench_rows;
-  int32_t bench_reps;
+  int32_t bench_reps;             // upper bound on batches
+  int64_t bench_ticks;            // > 0: stop after this much device time
 };
 
 // Handoff benchmark arguments (handoff.hip).
@@ -216,28 +228,63 @@ __device__ __host__ __forceinline__ uint64_t id_hash(uint64_t x) {
 }
 
 // Grid-wide barrier for a persistent grid of nwg co-resident workgroups.
-// Every thread fences its own writes at agent scope before the workgroup barrier,
-// one thread per workgroup arrives on the counter, the last arrival bumps the
-// generation, and every thread re-acquires after. The wait is bounded: on expiry
-// or when another workgroup aborted, returns false (and sets ctl->abort).
-__device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64_t spin_ticks) {
-  __shared__ int s_ok;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+// Two levels: workgroups arrive on one of 8 group counters (group = block index
+// mod 8, the XCD a workgroup lands on under round-robin dispatch), the last
+// arrival of a group arrives on the top counter, and the last group releases every
+// group's generation word. Memory ordering costs one agent-scope release fence
+// (L2 write-back) and one acquire fence (invalidate) per workgroup, issued by
+// thread 0 after the workgroup barrier has made every wave's stores complete;
+// polling uses relaxed loads. Counter resets are waited on (s_waitcnt) before the
+// next arrival can depend on them. The wait is bounded: on expiry, or when another
+// workgroup aborted, returns false (and sets ctl->abort).
+// Workgroup barrier after which every wave's global stores have completed (reached
+// the L2), so that one agent-scope write-back by thread 0 publishes all of them.
+__device__ __forceinline__ void wg_barrier_stores_done() {
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+}
+
+// sys_release: publish the workgroup's writes at system scope (results written to
+// pinned host memory, or slots a DMA copy reads) instead of agent scope.
+__device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64_t spin_ticks,
+                                             bool sys_release = false) {
+  __shared__ int s_ok;
+  wg_barrier_stores_done();
   if (threadIdx.x == 0) {
     int ok = 1;
-    uint32_t gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == nwg - 1) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      uint64_t t0 = now_ticks();
+    const uint32_t g = blockIdx.x & 7u;
+    const uint32_t ngroups = nwg < 8u ? nwg : 8u;
+    const uint32_t members = (nwg - g + 7u) >> 3;
+    uint32_t* genp = &ctl->bar_gen[g][0];
+    if (sys_release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t gen = __hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool wait = true;
+    const uint32_t prev = __hip_atomic_fetch_add(&ctl->bar_group[g][0], 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == members - 1) {
+      __hip_atomic_store(&ctl->bar_group[g][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      const uint32_t top = __hip_atomic_fetch_add(&ctl->bar_top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (top == ngroups - 1) {
+        __hip_atomic_store(&ctl->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        for (uint32_t q = 0; q < ngroups; ++q)
+          __hip_atomic_store(&ctl->bar_gen[q][0], gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait = false;
+      }
+    }
+    if (wait) {
+      const uint64_t t0 = now_ticks();
       uint32_t polls = 0;
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
         if ((int64_t)(now_ticks() - t0) > spin_ticks) {
+          // record who was missing: arrivals on this group and on the top counter
+          ctl->diag_arrived = __hip_atomic_load(&ctl->bar_group[g][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+                              (__hip_atomic_load(&ctl->bar_top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 16);
+          ctl->diag_nwg = nwg;
+          ctl->diag_group = g;
           __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
@@ -247,10 +294,10 @@ __device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64
         else __builtin_amdgcn_s_sleep(32);
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return s_ok != 0;
 }
 

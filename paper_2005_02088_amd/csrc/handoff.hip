@@ -19,7 +19,7 @@ __device__ __forceinline__ uint32_t pattern(uint64_t s, uint32_t w) {
 
 __device__ __forceinline__ bool wait_eq(const uint32_t* p, uint32_t want, int64_t spin_ticks, uint64_t* err) {
   const uint64_t t0 = now_ticks();
-  while (ld_acquire_agent(p) != want) {
+  while (__hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
     if ((int64_t)(now_ticks() - t0) > spin_ticks) {
       __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
@@ -27,6 +27,7 @@ __device__ __forceinline__ bool wait_eq(const uint32_t* p, uint32_t want, int64_
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
     __builtin_amdgcn_s_sleep(1);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
@@ -52,8 +53,7 @@ extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_producer(
       v.w = pattern(s, w + 3);
       base[o >> 4] = v;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
+    wg_barrier_stores_done();
     if (tid == 0) st_release_agent(&a.full[(int64_t)d * nwg + j], lap + 1);
   }
   if (tid == 0) atomicMax((unsigned long long*)&a.result[3], (unsigned long long)now_ticks());
@@ -73,7 +73,6 @@ extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_consumer(
     if (tid == 0) s_ok = wait_eq(&a.full[(int64_t)d * nwg + j], lap + 1, a.spin_ticks, &a.result[4]);
     __syncthreads();
     if (!s_ok) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint4* base = (const uint4*)(a.ring + (int64_t)d * a.slot_bytes);
     for (int64_t o = lo + (int64_t)tid * 16; o < hi; o += (int64_t)kThreads * 16) {
       const uint4 v = base[o >> 4];

@@ -1,0 +1,353 @@
+// Contention profiles and the learned contention predictor's host side:
+// concurrent co-location runs, random co-location profiling, the 16 features,
+// their standardisation, and the contention-aware allocator (Eq. 1 with predicted
+// latencies).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+extern "C" __global__ void camelot_pred_forward(const float*, const float*, int, float*);
+
+namespace {
+
+using namespace camelot;
+
+struct CtlBuf {
+  WorkerCtl* p = nullptr;
+  ~CtlBuf() { dfree(p); }
+};
+
+bool overlaps(int a0, int an, int b0, int bn) { return a0 < b0 + bn && b0 < a0 + an; }
+
+uint64_t splitmix_next(uint64_t& s) {
+  s += 0x9E3779B97F4A7C15ull;
+  uint64_t z = s;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// uniform integer in [0, n)
+int uniform(uint64_t& s, int n) { return (int)(splitmix_next(s) % (uint64_t)n); }
+
+}  // namespace
+
+extern "C" int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stages, const void* const* in,
+                                       void* const* out, const int32_t* rows, const int32_t* n_cus,
+                                       const int32_t* cu_offset, int64_t duration_ns, double* ns_per_batch) {
+  clear_error();
+  if (n < 1 || n > kMaxStages || !stages || !in || !out || !rows || !n_cus || !cu_offset || !ns_per_batch)
+    return fail(CAMELOT_EINVAL, "bad co-run arguments");
+  if (duration_ns <= 0 || duration_ns > 10LL * 1000000000LL)
+    return fail(CAMELOT_EINVAL, "duration_ns must be in (0, 10 s]");
+  DevInfo dev;
+  int32_t rc = dev_info(&dev);
+  if (rc) return rc;
+  for (int j = 0; j < n; ++j) {
+    if ((rc = check_share(n_cus[j], cu_offset[j], dev.n_cus))) return rc;
+    if (rows[j] < 0 || rows[j] > kMaxBatch) return fail(CAMELOT_EINVAL, "rows must be in 0..%d", kMaxBatch);
+    for (int q = 0; q < j; ++q)
+      if (overlaps(cu_offset[j], n_cus[j], cu_offset[q], n_cus[q]))
+        return fail(CAMELOT_EINVAL, "co-run shares %d and %d overlap", q, j);
+  }
+  std::vector<StageRes> res(n);
+  std::vector<CtlBuf> ctl(n);
+  std::vector<WorkerArgs> args(n);
+  std::vector<hipStream_t> streams(n);
+  for (int j = 0; j < n; ++j) {
+    WorkerArgs& a = args[j];
+    std::memset(&a, 0, sizeof a);
+    if ((rc = fill_params(&stages[j], &res[j], &a.sp))) return rc;
+    if ((rc = dmalloc(&ctl[j].p, sizeof(WorkerCtl))) || (rc = dzero(ctl[j].p, sizeof(WorkerCtl)))) return rc;
+    if ((rc = cached_stream(cu_offset[j], n_cus[j], &streams[j]))) return rc;
+    a.n_stages = 1;
+    a.max_batch = kMaxBatch;
+    a.spin_ticks = 2 * dev.wclk_hz;
+    a.idle_ticks = 2 * dev.wclk_hz;
+    a.in_kind = kInBench;
+    a.out_kind = is_result_stage(stages[j].kind) ? kOutBench : kOutRing;
+    a.ctl = ctl[j].p;
+    a.bench_in = (const uint8_t*)in[j];
+    a.bench_out = (uint8_t*)out[j];
+    a.bench_rows = rows[j];
+    a.bench_reps = 1 << 30;
+    a.bench_ticks = ns_to_ticks(duration_ns, dev.wclk_hz);
+  }
+  for (int j = 0; j < n && !rc; ++j) rc = launch_worker(stages[j].kind, args[j], n_cus[j], streams[j]);
+  for (int j = 0; j < n; ++j) (void)hipStreamSynchronize(streams[j]);
+  if (rc) return rc;
+  for (int j = 0; j < n; ++j) {
+    uint64_t tr[2] = {0, 0};
+    uint32_t abort_flag = 0;
+    if ((rc = d2h(tr, &ctl[j].p->ticks_bench, sizeof tr)) || (rc = d2h(&abort_flag, &ctl[j].p->abort, 4)))
+      return rc;
+    if (abort_flag) return fail(CAMELOT_ETIMEDOUT, "co-run stage %d: grid barrier timed out", j);
+    ns_per_batch[j] = tr[1] ? (double)tr[0] * 1e9 / (double)dev.wclk_hz / (double)tr[1] : 0.0;
+  }
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_desc* stages, const void* const* in,
+                                          void* const* out, int32_t cu_total, int32_t cu_step, int32_t n_batches,
+                                          const int32_t* batches, int32_t n_runs, uint64_t seed,
+                                          int64_t duration_ns, camelot_corun_record* records) {
+  clear_error();
+  if (n_kinds < 1 || n_kinds > 3 || !stages || !in || !out || !batches || n_batches < 1 || n_runs < 0 ||
+      !records || cu_step < 8 || cu_step % 8 != 0 || cu_total < cu_step * n_kinds)
+    return fail(CAMELOT_EINVAL, "bad co-run profiling arguments");
+  uint64_t st = seed;
+  for (int r = 0; r < n_runs; ++r) {
+    camelot_corun_record& rec = records[r];
+    std::memset(&rec, 0, sizeof rec);
+    const int u = uniform(st, 10);
+    int m = u < 1 ? 1 : (u < 4 ? 2 : 3);
+    m = std::min(m, n_kinds);
+    // distinct kinds: partial Fisher-Yates over 0..n_kinds-1
+    int perm[3] = {0, 1, 2};
+    for (int i = 0; i < m; ++i) std::swap(perm[i], perm[i + uniform(st, n_kinds - i)]);
+    const int steps = cu_total / cu_step;
+    int sh[3];
+    for (;;) {
+      int tot = 0;
+      for (int i = 0; i < m; ++i) { sh[i] = 1 + uniform(st, steps - (m - 1)); tot += sh[i]; }
+      if (tot <= steps) break;
+    }
+    const bool same = uniform(st, 2) == 0;
+    const int b0 = uniform(st, n_batches);
+    camelot_stage_desc d[3];
+    const void* ins[3];
+    void* outs[3];
+    int32_t rows[3], cus[3], offs[3];
+    int off = 0;
+    rec.m = m;
+    for (int i = 0; i < m; ++i) {
+      const int k = perm[i];
+      rec.kinds[i] = k;
+      rec.cu[i] = sh[i] * cu_step;
+      rec.bi[i] = same ? b0 : uniform(st, n_batches);
+      d[i] = stages[k];
+      ins[i] = in[k];
+      outs[i] = out[k];
+      rows[i] = batches[rec.bi[i]];
+      cus[i] = rec.cu[i];
+      offs[i] = off;
+      off += rec.cu[i];
+    }
+    int32_t rc = camelot_stage_corun(m, d, ins, outs, rows, cus, offs, duration_ns, rec.ns);
+    if (rc) return rc;
+  }
+  return CAMELOT_OK;
+}
+
+// ------------------------------------------------------------------ features
+namespace {
+int32_t check_tables(const camelot_solo_tables* t) {
+  if (!t || t->n_kinds < 1 || t->n_kinds > 3 || t->cu_step < 1 || t->n_shares < 1 || t->n_batches < 1 ||
+      !t->batches || !t->hbm || !t->mfma)
+    return fail(CAMELOT_EINVAL, "bad solo tables");
+  return CAMELOT_OK;
+}
+
+inline float log2b(int b) { return std::log2((float)std::max(b, 1)) / 7.f; }
+
+// one row of 16 features for stage j of a co-location (no validation)
+void feature_row(const camelot_solo_tables* t, int m, const int32_t* kinds, const int32_t* cu,
+                 const int32_t* bi, int j, float* f) {
+  auto at = [&](const float* tab, int k, int share_cus, int b) {
+    const int ks = share_cus / t->cu_step - 1;
+    return tab[((int64_t)k * t->n_shares + ks) * t->n_batches + b];
+  };
+  std::memset(f, 0, CAMELOT_PRED_FEATURES * sizeof(float));
+  f[0] = cu[j] / 256.f;
+  f[1] = log2b(t->batches[bi[j]]);
+  f[2] = at(t->hbm, kinds[j], cu[j], bi[j]);
+  f[3] = at(t->mfma, kinds[j], cu[j], bi[j]);
+  f[4 + kinds[j]] = 1.f;
+  int slot = 0, total = 0;
+  for (int q = 0; q < m; ++q) {
+    total += cu[q];
+    if (q == j || slot >= 2) continue;
+    float* g = f + 7 + 4 * slot;
+    g[0] = cu[q] / 256.f;
+    g[1] = log2b(t->batches[bi[q]]);
+    g[2] = at(t->hbm, kinds[q], cu[q], bi[q]);
+    g[3] = at(t->mfma, kinds[q], cu[q], bi[q]);
+    ++slot;
+  }
+  f[15] = total / 256.f;
+}
+}  // namespace
+
+extern "C" int32_t camelot_predictor_features(const camelot_solo_tables* t, int32_t m, const int32_t* kinds,
+                                              const int32_t* cu, const int32_t* bi, float* feat) {
+  clear_error();
+  int32_t rc = check_tables(t);
+  if (rc) return rc;
+  if (m < 1 || m > 3 || !kinds || !cu || !bi || !feat) return fail(CAMELOT_EINVAL, "bad feature arguments");
+  for (int j = 0; j < m; ++j) {
+    if (kinds[j] < 0 || kinds[j] >= t->n_kinds) return fail(CAMELOT_EINVAL, "kind out of range");
+    if (cu[j] < t->cu_step || cu[j] % t->cu_step != 0 || cu[j] / t->cu_step > t->n_shares)
+      return fail(CAMELOT_EINVAL, "share out of range");
+    if (bi[j] < 0 || bi[j] >= t->n_batches) return fail(CAMELOT_EINVAL, "batch index out of range");
+  }
+  for (int j = 0; j < m; ++j) feature_row(t, m, kinds, cu, bi, j, feat + (int64_t)j * CAMELOT_PRED_FEATURES);
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_predictor_fit_norm(const float* x, int32_t n, float* mean, float* std) {
+  clear_error();
+  if (!x || n < 1 || !mean || !std) return fail(CAMELOT_EINVAL, "bad normalisation arguments");
+  for (int c = 0; c < CAMELOT_PRED_FEATURES; ++c) {
+    double s = 0, s2 = 0;
+    for (int i = 0; i < n; ++i) s += x[(int64_t)i * CAMELOT_PRED_FEATURES + c];
+    const double mu = s / n;
+    for (int i = 0; i < n; ++i) {
+      const double d = x[(int64_t)i * CAMELOT_PRED_FEATURES + c] - mu;
+      s2 += d * d;
+    }
+    mean[c] = (float)mu;
+    std[c] = (float)std::max(std::sqrt(s2 / n), 1e-6);
+  }
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_predictor_standardize(float* x, int32_t n, const float* mean, const float* std) {
+  clear_error();
+  if (!x || n < 0 || !mean || !std) return fail(CAMELOT_EINVAL, "bad normalisation arguments");
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < CAMELOT_PRED_FEATURES; ++c) {
+      float& v = x[(int64_t)i * CAMELOT_PRED_FEATURES + c];
+      v = (v - mean[c]) / std[c];
+    }
+  return CAMELOT_OK;
+}
+
+// ------------------------------------------------------------------ learned allocator
+namespace {
+typedef __int128 i128;
+struct Cand {
+  int bi;
+  int k[3];
+};
+inline int cmp_rat(int64_t an, int64_t ad, int64_t bn, int64_t bd) {
+  const i128 l = (i128)an * bd, r = (i128)bn * ad;
+  return l < r ? -1 : (l > r ? 1 : 0);
+}
+}  // namespace
+
+extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const camelot_solo_tables* t,
+                                              const float* params, const float* mean, const float* std,
+                                              camelot_alloc* out, int64_t* lat_pred_ns) {
+  clear_error();
+  int32_t rc = check_tables(t);
+  if (rc) return rc;
+  if (!p || !params || !mean || !std || !out) return fail(CAMELOT_EINVAL, "bad learned allocation arguments");
+  const int S = p->n_stages;
+  if (S < 1 || S > 3 || t->n_kinds != S) return fail(CAMELOT_EINVAL, "learned allocation needs 1..3 stages matching the tables");
+  if (p->cu_step != t->cu_step || p->cu_total / p->cu_step > t->n_shares || p->n_batches != t->n_batches)
+    return fail(CAMELOT_EINVAL, "solo tables do not cover the problem's shares and batches");
+  if (!p->lat_ns || !p->bw_bps || !p->mem_bytes || !p->batches) return fail(CAMELOT_EINVAL, "incomplete problem");
+  const int K = p->cu_total / p->cu_step;
+  // candidates in lexicographic order (batch index, k_0, k_1, ...), shares fitting the GPU
+  std::vector<Cand> cands;
+  for (int bi = 0; bi < p->n_batches; ++bi) {
+    const int64_t wait = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
+    if (wait > p->qos_ns) continue;
+    int k[3] = {0, 0, 0};
+    const int total = (int)std::pow((double)K, S);
+    for (int c = 0; c < total; ++c) {
+      int rem = c, used = 0;
+      bool ok = true;
+      for (int s = S - 1; s >= 0; --s) { k[s] = rem % K; rem /= K; }
+      for (int s = 0; s < S; ++s) {
+        used += (k[s] + 1) * p->cu_step;
+        if (p->lat_ns[((int64_t)s * K + k[s]) * p->n_batches + bi] <= 0) ok = false;
+      }
+      if (ok && used <= p->cu_total) cands.push_back(Cand{bi, {k[0], k[1], k[2]}});
+    }
+  }
+  if (cands.empty()) return fail(CAMELOT_EINFEASIBLE, "no candidate allocation");
+  const int64_t nrows = (int64_t)cands.size() * S;
+  std::vector<float> x((size_t)nrows * CAMELOT_PRED_FEATURES);
+  for (size_t c = 0; c < cands.size(); ++c) {
+    int32_t kinds[3], cu[3], bis[3];
+    for (int s = 0; s < S; ++s) { kinds[s] = s; cu[s] = (cands[c].k[s] + 1) * p->cu_step; bis[s] = cands[c].bi; }
+    for (int s = 0; s < S; ++s)
+      feature_row(t, S, kinds, cu, bis, s, x.data() + ((int64_t)c * S + s) * CAMELOT_PRED_FEATURES);
+  }
+  camelot_predictor_standardize(x.data(), (int32_t)nrows, mean, std);
+  float *dx = nullptr, *dy = nullptr;
+  if ((rc = dmalloc(&dx, x.size() * sizeof(float))) || (rc = dmalloc(&dy, nrows * sizeof(float)))) {
+    dfree(dx);
+    return rc;
+  }
+  std::vector<float> yhat((size_t)nrows);
+  rc = h2d(dx, x.data(), x.size() * sizeof(float));
+  if (!rc) {
+    hipStream_t s = mem_stream();
+    hipLaunchKernelGGL(camelot_pred_forward, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, params,
+                       (const float*)dx, (int)nrows, dy);
+    if (hipGetLastError() != hipSuccess) rc = fail(CAMELOT_EDEVICE, "predictor forward launch failed");
+    if (!rc) rc = d2h(yhat.data(), dy, nrows * sizeof(float));
+  }
+  dfree(dx);
+  dfree(dy);
+  if (rc) return rc;
+  // exact search with the predicted integer latencies (same rules as camelot_alloc_peak)
+  bool have = false;
+  camelot_alloc best;
+  int64_t best_lat[3] = {0, 0, 0};
+  for (size_t c = 0; c < cands.size(); ++c) {
+    const Cand& cd = cands[c];
+    const int bi = cd.bi;
+    const int64_t b = p->batches[bi];
+    int64_t cu = 0, bw = 0, mem = 0, lat = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
+    int64_t tn = 0, td = 1;
+    bool has = false;
+    int64_t L[3];
+    for (int s = 0; s < S; ++s) {
+      const double y = std::min<double>(yhat[c * S + s], 40.0);
+      L[s] = std::max<int64_t>(1, (int64_t)std::ceil(std::exp(y)));
+      const int kk = cd.k[s];
+      cu += (int64_t)(kk + 1) * p->cu_step;
+      bw += p->bw_bps[((int64_t)s * K + kk) * p->n_batches + bi];
+      mem += p->mem_bytes[(int64_t)s * p->n_batches + bi];
+      lat += L[s];
+      const int64_t n1 = b * 1000000000LL;
+      if (!has || cmp_rat(n1, L[s], tn, td) < 0) { tn = n1; td = L[s]; }
+      has = true;
+    }
+    if (cu > p->cu_total || S > p->max_instances || bw > p->hbm_bw_budget || mem > p->hbm_bytes_budget ||
+        lat > p->qos_ns)
+      continue;
+    bool better = !have;
+    if (have) {
+      const int c1 = cmp_rat(tn, td, best.thr_num, best.thr_den);
+      better = c1 > 0 || (c1 == 0 && (cu < best.cu_used || (cu == best.cu_used && lat < best.lat_ns)));
+    }
+    if (!better) continue;
+    have = true;
+    std::memset(&best, 0, sizeof best);
+    best.n_stages = S;
+    best.batch = (int32_t)b;
+    best.batch_index = bi;
+    for (int s = 0; s < S; ++s) { best.n[s] = 1; best.cu[s] = (cd.k[s] + 1) * p->cu_step; best_lat[s] = L[s]; }
+    const int64_t g = std::gcd(tn, td);
+    best.thr_num = tn / g;
+    best.thr_den = td / g;
+    best.lat_ns = lat;
+    best.cu_used = cu;
+  }
+  if (!have) return fail(CAMELOT_EINFEASIBLE, "no allocation satisfies the constraints");
+  *out = best;
+  if (lat_pred_ns)
+    for (int s = 0; s < S; ++s) lat_pred_ns[s] = best_lat[s];
+  return CAMELOT_OK;
+}

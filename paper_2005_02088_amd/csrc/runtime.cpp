@@ -20,6 +20,7 @@
 #include "../../include/camelot.h"
 #include "device_common.h"
 #include "errors.h"
+#include "internal.h"
 
 namespace camelot {
 
@@ -37,11 +38,6 @@ int32_t fail(int32_t code, const char* fmt, ...) {
 }
 void clear_error() { g_err.clear(); }
 
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
-    if (e_ != hipSuccess) return fail(CAMELOT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
 
 const void* worker_kernel(int kind, bool bench);   // stages.hip
 
@@ -51,35 +47,33 @@ const void* worker_kernel(int kind, bool bench);   // stages.hip
 // (null-stream copies, hipFree, hipDeviceSynchronize) would wait for those workers.
 static hipStream_t g_mem_stream = nullptr;
 static std::mutex g_mem_mu;
-static hipStream_t mem_stream() {
+hipStream_t mem_stream() {
   std::lock_guard<std::mutex> lk(g_mem_mu);
   if (!g_mem_stream) (void)hipStreamCreateWithFlags(&g_mem_stream, hipStreamNonBlocking);
   return g_mem_stream;
 }
-static int32_t dmalloc(void** ptr, size_t bytes) {
+int32_t dmalloc(void** ptr, size_t bytes) {
   hipStream_t s = mem_stream();
   HIP_TRY(hipMallocAsync(ptr, bytes, s));
   HIP_TRY(hipStreamSynchronize(s));
   return CAMELOT_OK;
 }
-template <typename T>
-static int32_t dmalloc(T** ptr, size_t bytes) { return dmalloc((void**)ptr, bytes); }
-static void dfree(void* ptr) {
+void dfree(void* ptr) {
   if (ptr) (void)hipFreeAsync(ptr, mem_stream());
 }
-static int32_t dzero(void* ptr, size_t bytes) {
+int32_t dzero(void* ptr, size_t bytes) {
   hipStream_t s = mem_stream();
   HIP_TRY(hipMemsetAsync(ptr, 0, bytes, s));
   HIP_TRY(hipStreamSynchronize(s));
   return CAMELOT_OK;
 }
-static int32_t d2h(void* dst, const void* src, size_t bytes) {
+int32_t d2h(void* dst, const void* src, size_t bytes) {
   hipStream_t s = mem_stream();
   HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return CAMELOT_OK;
 }
-static int32_t h2d(void* dst, const void* src, size_t bytes) {
+int32_t h2d(void* dst, const void* src, size_t bytes) {
   hipStream_t s = mem_stream();
   HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -90,17 +84,10 @@ extern "C" __global__ void camelot_handoff_producer(HandoffArgs);
 extern "C" __global__ void camelot_handoff_consumer(HandoffArgs);
 
 // ------------------------------------------------------------------ device info
-struct DevInfo {
-  bool ok = false;
-  int n_cus = 0;
-  int64_t wclk_hz = 100000000;
-  int64_t mem = 0;
-  char arch[32] = {0};
-};
 static std::mutex g_mu;
 static DevInfo g_dev;
 
-static int32_t dev_info(DevInfo* out) {
+int32_t dev_info(DevInfo* out) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_dev.ok) {
     int dev = 0;
@@ -119,7 +106,7 @@ static int32_t dev_info(DevInfo* out) {
   return CAMELOT_OK;
 }
 
-static int64_t ns_to_ticks(int64_t ns, int64_t hz) { return (int64_t)((long double)ns * hz / 1e9L); }
+int64_t ns_to_ticks(int64_t ns, int64_t hz) { return (int64_t)((long double)ns * hz / 1e9L); }
 static uint64_t ticks_to_ns(int64_t ticks, int64_t hz) {
   return ticks <= 0 ? 0 : (uint64_t)((long double)ticks * 1e9L / hz);
 }
@@ -145,7 +132,7 @@ static int32_t make_masked_stream(int offset, int n, hipStream_t* s) {
 
 // Cache of masked streams used by the one-shot stage runs (profiling).
 static std::map<std::pair<int, int>, hipStream_t> g_streams;
-static int32_t cached_stream(int offset, int n, hipStream_t* s) {
+int32_t cached_stream(int offset, int n, hipStream_t* s) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_streams.find({offset, n});
   if (it != g_streams.end()) { *s = it->second; return CAMELOT_OK; }
@@ -196,6 +183,8 @@ static std::vector<float> logmel_tables() {
     for (int k = first; k <= last; ++k) w.push_back((float)wk[k]);
   }
   t.insert(t.end(), w.begin(), w.end());
+  if (t.size() > 2304) t.clear();   // cannot happen for 40 bands over 257 bins; caught by the caller
+  else t.resize(2304, 0.f);         // the kernel stages a fixed-size table in LDS
   return t;
 }
 
@@ -204,6 +193,7 @@ static int32_t logmel_device_tables(const float** out) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_logmel_dev) {
     std::vector<float> t = logmel_tables();
+    if (t.empty()) return fail(CAMELOT_EINVAL, "log-mel tables exceed the kernel's LDS table");
     float* d = nullptr;
     int32_t rc = dmalloc(&d, t.size() * sizeof(float));
     if (!rc) rc = h2d(d, t.data(), t.size() * sizeof(float));
@@ -215,7 +205,7 @@ static int32_t logmel_device_tables(const float** out) {
 }
 
 // ------------------------------------------------------------------ stages
-static bool is_result_stage(int kind) {
+bool is_result_stage(int kind) {
   return kind == CAMELOT_STAGE_GEMM_ARGMAX || kind == CAMELOT_STAGE_TOPK;
 }
 
@@ -270,14 +260,6 @@ static int result_k(const camelot_stage_desc* d) {
   return d->kind == CAMELOT_STAGE_TOPK ? d->k : 1;
 }
 
-// Device resources one stage worker needs (scratch, tables). Owned by a pipeline or
-// by a one-shot run.
-struct StageRes {
-  uint16_t* scratch = nullptr;
-  int64_t scratch_bytes = 0;
-  ~StageRes() { dfree(scratch); }
-};
-
 static int64_t stage_scratch_bytes(const camelot_stage_desc* d, int* stride) {
   *stride = 0;
   if (d->kind != CAMELOT_STAGE_MLP_BF16) return 0;
@@ -287,7 +269,9 @@ static int64_t stage_scratch_bytes(const camelot_stage_desc* d, int* stride) {
   return 2LL * kMaxBatch * mx * 2;
 }
 
-static int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp) {
+StageRes::~StageRes() { dfree(scratch); }
+
+int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp) {
   int64_t in_b = 0, out_b = 0;
   int32_t rc = check_stage(d, &in_b, &out_b);
   if (rc) return rc;
@@ -315,14 +299,14 @@ static int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StagePara
   return CAMELOT_OK;
 }
 
-static int32_t check_share(int n_cus, int offset, int total) {
+int32_t check_share(int n_cus, int offset, int total) {
   if (n_cus < 8 || n_cus % 8 != 0 || offset < 0 || offset % 8 != 0 || offset + n_cus > total)
     return fail(CAMELOT_EINVAL, "CU share %d at offset %d: need multiples of 8 within %d CUs", n_cus,
                 offset, total);
   return CAMELOT_OK;
 }
 
-static int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
+int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
   const void* fn = worker_kernel(kind, a.in_kind == kInBench);
   if (!fn) return fail(CAMELOT_EINVAL, "no worker for stage kind %d", kind);
   void* args[] = {(void*)&a};
@@ -414,7 +398,14 @@ extern "C" int32_t camelot_stage_run(const camelot_stage_desc* stage, const void
   if (rc) return rc;
   uint32_t abort_flag = 0;
   if ((rc = d2h(&abort_flag, &ctl->abort, 4))) return rc;
-  if (abort_flag) return fail(CAMELOT_ETIMEDOUT, "stage worker grid barrier timed out");
+  if (abort_flag) {
+    uint32_t diag[3] = {0, 0, 0};
+    (void)d2h(diag, &ctl->diag_arrived, sizeof diag);
+    return fail(CAMELOT_ETIMEDOUT,
+                "grid barrier timed out (stage kind %d, %d rows, %d CUs at %d, %d workgroups): group %u had "
+                "%u arrivals, top counter %u",
+                stage->kind, rows, n_cus, cu_offset, kWgPerCu * n_cus, diag[2], diag[0] & 0xffff, diag[0] >> 16);
+  }
   // HIP events on the stream the kernel ran on: the whole launch, divided by reps
   if (ns_per_rep) *ns_per_rep = (double)ms * 1e6 / reps;
   return CAMELOT_OK;

@@ -209,26 +209,34 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
 // One wave per (row, frame): window 400 samples, pack into 256 complex points,
 // radix-4 Stockham FFT in LDS (4 passes), split into the 257-bin spectrum of the
 // 512-point real transform, power, sparse mel filters, natural log with floor.
+constexpr int kTabFloats = 2304;     // room for the window, twiddles and filters
+
 __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
   __shared__ float2 fbuf[kWaves][2][256];
   __shared__ float pbuf[kWaves][260];
-  const float* T = a.sp.tables;
-  const float* win = T + kTabWin;
-  const float2* tw256 = (const float2*)(T + kTabTw256);
-  const float2* tw512 = (const float2*)(T + kTabTw512);
-  const float* meta = T + kTabMelMeta;
-  const float* melw = T + kTabMelW;
+  __shared__ float tab[kTabFloats];
+  // stage the small tables in LDS once per batch
+  for (int i = threadIdx.x; i < kTabFloats; i += kThreads) tab[i] = a.sp.tables[i];
+  __syncthreads();
+  const float* win = tab + kTabWin;
+  const float2* tw256 = (const float2*)(tab + kTabTw256);
+  const float2* tw512 = (const float2*)(tab + kTabTw512);
+  const float* meta = tab + kTabMelMeta;
+  const float* melw = tab + kTabMelW;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* Y = (float*)out;
   const int units = rows * 11;
   for (int u = blockIdx.x * kWaves + w; u < units; u += gridDim.x * kWaves) {
     const int r = u / 11, f = u - r * 11;
-    const float* x = (const float*)ctl->d_rowptr[r] + f * 160;
+    const float2* x2 = (const float2*)((const float*)ctl->d_rowptr[r] + f * 160);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int n = lane + 64 * q;
       float2 z = make_float2(0.f, 0.f);
-      if (n < 200) z = make_float2(x[2 * n] * win[2 * n], x[2 * n + 1] * win[2 * n + 1]);
+      if (n < 200) {
+        const float2 v = x2[n];
+        z = make_float2(v.x * win[2 * n], v.y * win[2 * n + 1]);
+      }
       fbuf[w][0][n] = z;
     }
     wave_lds_sync();
@@ -306,40 +314,53 @@ __device__ __forceinline__ bf16x8 ld_f32x8_as_bf16(const float* p) {
   return r;
 }
 
+constexpr int kMlpChunksPerWave = 16;   // K chunks of 32 a wave keeps in flight per segment
+constexpr int kMlpSegK = kMlpChunksPerWave * kWaves * 32;   // K covered per segment (2048)
+
 __device__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
   __shared__ float part[kWaves][8][256];
   const int L = a.sp.n_layers;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int nrb = (rows + 15) >> 4;
   const int stride = a.sp.scratch_stride;
+  const int krow = (lane >> 4) * 8;          // this lane's 8-element K offset within a chunk
   for (int l = 0; l < L; ++l) {
     const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
     const uint16_t* W = (const uint16_t*)a.sp.w[l];
     const uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
     uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
     const bool last = (l == L - 1);
-    const int nchunks = (K + 31) >> 5;
     const int nstrips = N >> 4;
     for (int strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
       f32x4 acc[8];
 #pragma unroll
       for (int rb = 0; rb < 8; ++rb) acc[rb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      const int n = strip * 16 + (lane & 15);
-      const uint16_t* wrow = W + (int64_t)n * K;
-      for (int c = w; c < nchunks; c += kWaves) {
-        const int kb = c * 32 + (lane >> 4) * 8;
-        const bool kin = kb < K;
-        bf16x8 bfrag = kin ? ld_bf16x8(wrow + kb) : (bf16x8){};
+      const uint16_t* wrow = W + (int64_t)(strip * 16 + (lane & 15)) * K;
+      // K in segments: wave w owns chunks seg/32 + w + 4 i, i < 16
+      for (int seg = 0; seg < K; seg += kMlpSegK) {
+        // weight fragments of the whole segment first: 16 independent loads in flight
+        bf16x8 bq[kMlpChunksPerWave];
+#pragma unroll
+        for (int i = 0; i < kMlpChunksPerWave; ++i) {
+          const int kb = seg + (w + kWaves * i) * 32 + krow;
+          bq[i] = kb < K ? ld_bf16x8(wrow + kb) : (bf16x8){};
+        }
 #pragma unroll
         for (int rb = 0; rb < 8; ++rb) {
           if (rb < nrb) {
             const int row = rb * 16 + (lane & 15);
-            bf16x8 afrag = (bf16x8){};
-            if (row < rows && kin) {
-              afrag = (l == 0) ? ld_f32x8_as_bf16((const float*)ctl->d_rowptr[row] + kb)
-                               : ld_bf16x8(hin + (int64_t)row * stride + kb);
+            const bool rin = row < rows;
+            const uint16_t* hrow = hin + (int64_t)row * stride;
+            const float* xrow = rin && l == 0 ? (const float*)ctl->d_rowptr[row] : nullptr;
+#pragma unroll
+            for (int i = 0; i < kMlpChunksPerWave; ++i) {
+              const int kb = seg + (w + kWaves * i) * 32 + krow;
+              if (seg + (w + kWaves * i) * 32 < K) {
+                bf16x8 af = (bf16x8){};
+                if (rin && kb < K) af = (l == 0) ? ld_f32x8_as_bf16(xrow + kb) : ld_bf16x8(hrow + kb);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bq[i], acc[rb], 0, 0, 0);
+              }
             }
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[rb], 0, 0, 0);
           }
         }
       }
@@ -380,8 +401,15 @@ __device__ __forceinline__ bool exec_stage(const WorkerArgs& a, WorkerCtl* ctl, 
 // ------------------------------------------------------------------ control side
 // Ring slot states: 0 free (never used), 2*seq+1 full with batch seq,
 // 2*seq+2 consumed after batch seq.
+// Doorbell polling: relaxed loads (no cache invalidation per poll); the caller
+// issues one acquire fence once the awaited value is seen.
 __device__ __forceinline__ uint64_t ring_load(const uint64_t* p, bool sys) {
-  return sys ? ld_acquire_sys(p) : ld_acquire_agent(p);
+  return sys ? __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)
+             : __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ring_acquire(bool sys) {
+  if (sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+  else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 __device__ __forceinline__ void ring_store(uint64_t* p, uint64_t v, bool sys) {
   if (sys) st_release_sys(p, v); else st_release_agent(p, v);
@@ -396,7 +424,7 @@ struct Acq {
 // Polling helper: true when the host asked to stop (checked every 16th call).
 __device__ __forceinline__ bool host_stop(const WorkerArgs& a, uint32_t& polls) {
   if ((++polls & 15u) != 0) return false;
-  return ld_acquire_sys(&a.hctl->stop) != 0;
+  return __hip_atomic_load(&a.hctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
 }
 
 // Stage 0: form a batch from the ingest (wave 0 of workgroup 0). Requests are
@@ -415,7 +443,7 @@ __device__ Acq acquire_ingest(const WorkerArgs& a, WorkerCtl* ctl, uint64_t t0, 
   for (;;) {
     uint64_t avail;
     if (host) {
-      const uint64_t head = ld_acquire_sys(&a.hctl->ingest_head);
+      const uint64_t head = ld_acquire_sys(&a.hctl->ingest_head);   // one PCIe read per poll
       avail = head > c ? head - c : 0;
     } else {
       avail = (uint64_t)a.n_ingest > c ? (uint64_t)a.n_ingest - c : 0;
@@ -483,6 +511,7 @@ __device__ Acq acquire_ring(const WorkerArgs& a, uint64_t seq) {
   const bool st_sys = a.in_state_sys != 0;
   for (;;) {
     if (ring_load(&a.in_state[slot], st_sys) == want) {
+      ring_acquire(st_sys);
       const SlotHeader* h = (const SlotHeader*)(a.in_ring + slot * (uint64_t)a.in_stride);
       return Acq{0, (int)h->n_req, (int)h->n_rows};
     }
@@ -503,10 +532,13 @@ __device__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq,
       const uint64_t want = seq < (uint64_t)a.out_depth ? 0 : 2 * (seq - a.out_depth) + 2;
       ok = ring_load(&a.out_state[slot], a.out_state_sys != 0) == want;
     } else {
-      const uint64_t tail = ld_acquire_sys(&a.hctl->egress_tail);
+      const uint64_t tail = __hip_atomic_load(&a.hctl->egress_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       ok = ctl->egress_head + (uint64_t)rows - tail <= (uint64_t)a.egress_cap;
     }
-    if (ok) return 0;
+    if (ok) {
+      ring_acquire(a.out_kind != kOutRing || a.out_state_sys != 0);
+      return 0;
+    }
     if (host_stop(a, polls)) return kStatusStopped;
     if ((int64_t)(now_ticks() - t_wait0) > a.idle_ticks) return kStatusIdleExit;
     __builtin_amdgcn_s_sleep(1);
@@ -526,11 +558,22 @@ __global__ __launch_bounds__(kThreads) void stage_bench(WorkerArgs a) {
       ctl->d_rowptr[i] = a.bench_in + (int64_t)i * a.sp.in_row_bytes;
   if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
   const uint64_t t0 = now_ticks();
-  for (int rep = 0; rep < a.bench_reps; ++rep) {
+  int rep = 0;
+  while (rep < a.bench_reps) {
     if (!exec_stage<KIND>(a, ctl, a.bench_rows, a.bench_out)) return;
+    ++rep;
+    // duration mode: workgroup 0 decides for the whole grid, published by the barrier;
+    // two slots by parity so a fast workgroup 0 never overwrites a decision that a
+    // slow workgroup has not read yet
+    if (blockIdx.x == 0 && tid == 0)
+      ctl->bench_stop[rep & 1] = (a.bench_ticks > 0 && (int64_t)(now_ticks() - t0) >= a.bench_ticks) ? 1u : 0u;
     if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
+    if (ctl->bench_stop[rep & 1]) break;
   }
-  if (blockIdx.x == 0 && tid == 0) ctl->ticks_bench = now_ticks() - t0;
+  if (blockIdx.x == 0 && tid == 0) {
+    ctl->ticks_bench = now_ticks() - t0;
+    ctl->reps_bench = (uint64_t)rep;
+  }
 }
 
 // ------------------------------------------------------------------ worker kernel
@@ -664,9 +707,12 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
     if (stop) { exit_status = (int)stop; break; }
     const int rows = (int)ctl->d_rows;
     if (!exec_stage<KIND>(a, ctl, rows, ctl->d_out)) { exit_status = kStatusTimeout; break; }
-    // results go to pinned host memory, a host-staged output slot is read by DMA
-    if (a.out_kind == kOutEgress || a.out_state_sys) __threadfence_system();
-    if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) { exit_status = kStatusTimeout; break; }
+    // results go to pinned host memory, a host-staged output slot is read by DMA:
+    // those are published at system scope
+    if (!grid_barrier(ctl, gridDim.x, a.spin_ticks, a.out_kind == kOutEgress || a.out_state_sys != 0)) {
+      exit_status = kStatusTimeout;
+      break;
+    }
     // ---------------- publish (workgroup 0, thread 0)
     if (wg0 && tid == 0) {
       const uint64_t t_end = now_ticks();
