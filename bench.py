@@ -121,7 +121,7 @@ class Speech:
         scratch = 2 * 128 * 4096 * 2 if s == 1 else 0
         return w + scratch + depth * slot
 
-    def profile(self, reps=16):
+    def profile(self, reps=8):
         import numpy as np
         S, K, nb = 3, len(SHARES), len(BATCHES)
         lat = np.zeros((S, K, nb), np.int64)
@@ -130,7 +130,8 @@ class Speech:
                 for j, b in enumerate(BATCHES):
                     try:
                         ns = self.cm.camelot_stage_run(self.stages[s], self.in_bufs[s].data_ptr(),
-                                                       self.out_bufs[s].data_ptr(), b, share, 0, reps)
+                                                       self.out_bufs[s].data_ptr(), b, share, 0, reps,
+                                                       device=True)
                     except self.cm.CamelotError as e:     # unmeasured point: never chosen
                         log(f"  stage {s} share {share} batch {b}: {e}")
                         self.failures.append(str(e))
@@ -223,6 +224,8 @@ def mlp_roofline(cm, sp, mlp_cus):
     MLP's CU share, ROOF_LAUNCHES launches of ROOF_REPS batches each, timed with HIP
     events on the stream the kernel runs on."""
     per = []
+    # one untimed launch first: the first launch of a kernel includes loading its code
+    cm.camelot_stage_run(sp.stages[1], sp.in_bufs[1].data_ptr(), sp.out_bufs[1].data_ptr(), 128, mlp_cus, 0, 1)
     for _ in range(ROOF_LAUNCHES):
         per.append(cm.camelot_stage_run(sp.stages[1], sp.in_bufs[1].data_ptr(), sp.out_bufs[1].data_ptr(), 128,
                                         mlp_cus, 0, ROOF_REPS))

@@ -148,6 +148,18 @@ int32_t camelot_alloc_eval(const camelot_problem* problem, camelot_alloc* inout)
  *                for l >= 1 and dims[l] % 8 == 0 for all l.
  *   TOPK         in f32[in_dim]; output is a result of k entries (index, value) in
  *                descending value, equal values by ascending index.
+ *   GATHER       in int32[dims[0]] row ids; weights[0] = FP16 table [k][dims[1]] (k rows,
+ *                dims[1] <= 1024, a multiple of 64); out f32[dims[1]] = mean over the
+ *                ids of table[id] (FP32 sums in id order). Ids outside [0, k) add zero.
+ *   CONV_POOL    in BF16 feature map [dims[0]=H][dims[1]=W][dims[2]=C] (NHWC, C = 64);
+ *                weights[0] = BF16 [dims[3]=Cout=64][3][3][C] ([out][ky][kx][in]);
+ *                out f32[Cout] = mean over the H*W pixels of max(0, 3x3 convolution,
+ *                stride 1, zero padding 1), FP32 accumulation on MFMA.
+ *   GATHER_SCORE in f32[dims[0] = heads * dims[1]] query vectors; the row's side bytes
+ *                (camelot_pipeline_config.side_bytes, or the input row's tail in
+ *                camelot_stage_run) hold int32 ids[dims[2]]; weights[0] = FP16 table
+ *                [k][dims[1]]; out f32[heads * dims[2]], score[h * dims[2] + j] =
+ *                sum_d q[h * dims[1] + d] * table[id_j][d]; ids outside [0, k) score 0.
  * GEMM_ARGMAX and TOPK produce results and must be the last stage of a pipeline.
  */
 typedef enum {
@@ -155,7 +167,10 @@ typedef enum {
   CAMELOT_STAGE_GEMM_ARGMAX = 2,
   CAMELOT_STAGE_LOGMEL = 3,
   CAMELOT_STAGE_MLP_BF16 = 4,
-  CAMELOT_STAGE_TOPK = 5
+  CAMELOT_STAGE_TOPK = 5,
+  CAMELOT_STAGE_GATHER = 6,
+  CAMELOT_STAGE_CONV_POOL = 7,
+  CAMELOT_STAGE_GATHER_SCORE = 8
 } camelot_stage_kind;
 
 #define CAMELOT_MAX_LAYERS 8
@@ -166,7 +181,7 @@ typedef struct {
   int32_t kind;                          /* camelot_stage_kind                       */
   int32_t n_layers;                      /* MLP_BF16: L; GEMM_*: 1; others 0          */
   int32_t dims[CAMELOT_MAX_LAYERS + 1];  /* dims[0] = in_dim, dims[n_layers] = out   */
-  int32_t k;                             /* TOPK: k (1..CAMELOT_MAX_K)                */
+  int32_t k;                             /* TOPK: k (1..CAMELOT_MAX_K); GATHER: table rows */
   const void* weights[CAMELOT_MAX_LAYERS]; /* device pointers, borrowed for the
                                               lifetime of any object using them      */
 } camelot_stage_desc;
@@ -176,6 +191,8 @@ typedef struct {
 int64_t camelot_stage_row_bytes_in(const camelot_stage_desc* stage);
 int64_t camelot_stage_row_bytes_out(const camelot_stage_desc* stage);
 
+/* GATHER_SCORE reads its ids from the side bytes: in camelot_stage_run each input row
+ * is row_bytes_in + 4 * dims[2] bytes (the ids follow the query vectors). */
 /* Run one stage over `rows` rows (0..CAMELOT_MAX_BATCH) on `n_cus` CUs starting
  * at CU-mask bit `cu_offset` (n_cus and cu_offset multiples of 8; 0 n_cus = all
  * CUs), `reps` times back to back (the same input each time), with the compute
@@ -186,10 +203,12 @@ int64_t camelot_stage_row_bytes_out(const camelot_stage_desc* stage);
  *        followed by [rows][k] f32 values, i.e. 2 planes)
  *   ns_per_rep (may be NULL) receives the launch's duration measured with HIP
  *        events on the stream it ran on, divided by reps, in ns.
+ *   device_ns_per_rep (may be NULL) receives the device-clock time of the reps
+ *        alone (after the grid has started, excluding the launch), divided by reps.
  * Synchronous: returns after the work completed. */
 int32_t camelot_stage_run(const camelot_stage_desc* stage, const void* in, void* out,
                           int32_t rows, int32_t n_cus, int32_t cu_offset, int32_t reps,
-                          double* ns_per_rep);
+                          double* ns_per_rep, double* device_ns_per_rep);
 
 /* ------------------------------------------------------------------ pipelines
  * A pipeline is a chain of stages, each run by one persistent worker kernel on its
@@ -231,6 +250,11 @@ typedef struct {
   int32_t egress_capacity;     /* result rows buffered for drain                     */
   int64_t idle_timeout_ns;     /* workers exit after this long with nothing to do   */
   int64_t hbm_budget_bytes;    /* admission: ENOMEM if the footprint exceeds it (0 = no limit) */
+  int32_t side_bytes;          /* per-row bytes carried unchanged from the end of each
+                                  payload row through every stage (0..4096, multiple of
+                                  16): e.g. a query's item ids for a GATHER_SCORE stage.
+                                  Payload rows are row_bytes_in(stage 0) + side_bytes. */
+  int32_t pad_;
 } camelot_pipeline_config;
 
 typedef struct camelot_pipeline camelot_pipeline;
@@ -301,6 +325,31 @@ int32_t camelot_pipeline_stats_get(camelot_pipeline* p, camelot_pipeline_stats* 
  * frees everything. *undelivered (may be NULL) receives the number of submitted
  * rows never delivered. */
 int32_t camelot_pipeline_destroy(camelot_pipeline* p, uint64_t* undelivered);
+
+/* ------------------------------------------------------------------ serving: admission
+ * A server is a set of pipelines co-located on one GPU under one HBM budget (F of
+ * Eq. 1 / Eq. 3; global memory capacity is the binding resource for co-location,
+ * Section III-C). A pipeline is admitted only if its footprint - the library's
+ * rings, scratch and control (camelot_pipeline_footprint) plus every weight buffer
+ * not already held by an admitted pipeline - fits what is left. Weight buffers are
+ * identified by pointer, so instances sharing a model count it once (Section V-D).
+ * Admission does not place CUs: the configs' cu_offset/cu ranges must not overlap
+ * those of admitted pipelines (EINVAL otherwise). */
+typedef struct camelot_server camelot_server;
+
+int32_t camelot_server_create(int64_t hbm_budget_bytes, camelot_server** out);
+/* ENOMEM (and nothing created) when the pipeline does not fit the budget. */
+int32_t camelot_server_admit(camelot_server* s, const camelot_pipeline_config* cfg,
+                             camelot_pipeline** out);
+/* Destroys an admitted pipeline (as camelot_pipeline_destroy) and returns its bytes. */
+int32_t camelot_server_release(camelot_server* s, camelot_pipeline* p, uint64_t* undelivered);
+/* HBM bytes held by admitted pipelines (shared weights once). */
+int64_t camelot_server_used_bytes(const camelot_server* s);
+/* Releases every admitted pipeline and frees the server. */
+int32_t camelot_server_destroy(camelot_server* s);
+
+/* Bytes of the weight buffers a stage reads (0 for stages without weights). */
+int64_t camelot_stage_weight_bytes(const camelot_stage_desc* stage);
 
 /* ------------------------------------------------------------------ handoff benchmark
  * Section IV-B's claim, measured: a producer worker on cu_producer CUs writes
@@ -414,12 +463,12 @@ int32_t camelot_predictor_fit_norm(const float* x, int32_t n, float* mean, float
 int32_t camelot_predictor_standardize(float* x, int32_t n, const float* mean, const float* std);
 
 /* Contention-aware Eq. 1: as camelot_alloc_peak with one instance per stage (n_stages
- * <= 3, stage i of kind i), but every stage's latency comes from the learned predictor
- * for the co-location the candidate forms (exp of its output, rounded up to ns), not
- * from the solo table. params: device [CAMELOT_PRED_NPARAMS]; mean/std: host [16].
- * The problem's lat_ns only marks unmeasured points (<= 0); bw_bps, mem_bytes and the
- * tie rules are the same. lat_pred_ns (host [n_stages], may be NULL) receives the
- * predicted latencies of the chosen point. */
+ * <= 3, stage i of kind i), but every stage's latency is its solo latency (lat_ns)
+ * times exp(y), y = the learned predictor's output for the co-location the candidate
+ * forms (the network predicts the log slowdown over the solo profile), rounded up to
+ * ns. params: device [CAMELOT_PRED_NPARAMS]; mean/std: host [16]. bw_bps, mem_bytes
+ * and the tie rules are those of camelot_alloc_peak. lat_pred_ns (host [n_stages], may
+ * be NULL) receives the predicted latencies of the chosen point. */
 int32_t camelot_alloc_peak_learned(const camelot_problem* problem, const camelot_solo_tables* t,
                                    const float* params, const float* mean, const float* std,
                                    camelot_alloc* out, int64_t* lat_pred_ns);

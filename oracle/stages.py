@@ -184,6 +184,63 @@ def log_mel(audio: np.ndarray) -> np.ndarray:
     return out
 
 
+# ----------------------------------------------------------------- embedding gather
+
+
+def gather_mean(ids: np.ndarray, table: np.ndarray) -> np.ndarray:
+    """Per row: the mean over its ids of table[id] (FP64); ids outside the table
+    contribute zero but still count in the mean's denominator."""
+    ids = np.asarray(ids)
+    t = np.asarray(table, np.float64)
+    out = np.zeros((ids.shape[0], t.shape[1]))
+    for r in range(ids.shape[0]):
+        for i in ids[r]:
+            if 0 <= i < t.shape[0]:
+                out[r] += t[i]
+        out[r] /= ids.shape[1]
+    return out
+
+
+def gather_score(q: np.ndarray, ids: np.ndarray, table: np.ndarray, dim: int) -> np.ndarray:
+    """Per row: q is heads x dim query vectors (flattened), ids its item rows;
+    score[h * n_ids + j] = <q_h, table[id_j]> (FP64), zero for ids outside the table."""
+    q = np.asarray(q, np.float64)
+    t = np.asarray(table, np.float64)
+    B = q.shape[0]
+    heads = q.shape[1] // dim
+    n_ids = ids.shape[1]
+    out = np.zeros((B, heads * n_ids))
+    for r in range(B):
+        for h in range(heads):
+            qh = q[r, h * dim:(h + 1) * dim]
+            for j, i in enumerate(ids[r]):
+                if 0 <= i < t.shape[0]:
+                    out[r, h * n_ids + j] = qh @ t[i]
+    return out
+
+
+# ----------------------------------------------------------------- 3x3 convolution + pool
+
+
+def conv3x3_relu_pool(x_bf16_bits: np.ndarray, w_bf16_bits: np.ndarray) -> np.ndarray:
+    """Per row: x is a BF16 feature map [H][W][C] (NHWC), w BF16 [Cout][3][3][C];
+    out[co] = mean over pixels (y, x) of max(0, sum_{ky,kx,ci} w[co,ky,kx,ci] *
+    x[y+ky-1, x+kx-1, ci]) with zero padding, in FP64."""
+    x = bf16_bits_to_f64(x_bf16_bits)
+    w = bf16_bits_to_f64(w_bf16_bits)
+    B, H, W, C = x.shape
+    out = np.zeros((B, w.shape[0]))
+    for b in range(B):
+        pad = np.zeros((H + 2, W + 2, C))
+        pad[1:H + 1, 1:W + 1] = x[b]
+        y = np.zeros((H, W, w.shape[0]))
+        for ky in range(3):
+            for kx in range(3):
+                y += pad[ky:ky + H, kx:kx + W, :] @ w[:, ky, kx, :].T
+        out[b] = np.maximum(y, 0.0).mean(axis=(0, 1))
+    return out
+
+
 # ----------------------------------------------------------------- error metric
 
 

@@ -22,7 +22,8 @@ _lib = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
 # ------------------------------------------------------------------ constants
 OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EINFEASIBLE, EDEVICE, ESTOPPED = 0, -1, -2, -3, -4, -5, -6, -7
 MAX_STAGES, MAX_LAYERS, MAX_K, MAX_BATCH = 8, 8, 128, 128
-STAGE_GEMM_RELU, STAGE_GEMM_ARGMAX, STAGE_LOGMEL, STAGE_MLP_BF16, STAGE_TOPK = 1, 2, 3, 4, 5
+(STAGE_GEMM_RELU, STAGE_GEMM_ARGMAX, STAGE_LOGMEL, STAGE_MLP_BF16, STAGE_TOPK, STAGE_GATHER, STAGE_CONV_POOL,
+ STAGE_GATHER_SCORE) = 1, 2, 3, 4, 5, 6, 7, 8
 HANDOFF_DEVICE, HANDOFF_HOST = 0, 1
 INGEST_HOST, INGEST_REPLAY = 0, 1
 PRED_NIN, PRED_NHID = 16, 64
@@ -77,7 +78,7 @@ class PipelineConfig(C.Structure):
                 ("batch_timeout_ns", C.c_int64), ("ring_depth", C.c_int32), ("handoff", C.c_int32),
                 ("ingest", C.c_int32), ("max_rows_per_request", C.c_int32), ("ingest_capacity", C.c_int32),
                 ("egress_capacity", C.c_int32), ("idle_timeout_ns", C.c_int64),
-                ("hbm_budget_bytes", C.c_int64)]
+                ("hbm_budget_bytes", C.c_int64), ("side_bytes", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -121,7 +122,7 @@ _SIGS = {
     "camelot_stage_row_bytes_in": (C.c_int64, [C.POINTER(StageDesc)]),
     "camelot_stage_row_bytes_out": (C.c_int64, [C.POINTER(StageDesc)]),
     "camelot_stage_run": (C.c_int32, [C.POINTER(StageDesc), _P, _P, C.c_int32, C.c_int32, C.c_int32,
-                                      C.c_int32, C.POINTER(C.c_double)]),
+                                      C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "camelot_pipeline_create": (C.c_int32, [C.POINTER(PipelineConfig), C.POINTER(_P)]),
     "camelot_pipeline_footprint": (C.c_int64, [_P]),
     "camelot_pipeline_submit": (C.c_int32, [_P, C.c_uint64, _P, C.c_int32]),
@@ -131,6 +132,12 @@ _SIGS = {
     "camelot_pipeline_replay": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, C.c_int64]),
     "camelot_pipeline_stats_get": (C.c_int32, [_P, C.POINTER(PipelineStats)]),
     "camelot_pipeline_destroy": (C.c_int32, [_P, C.POINTER(C.c_uint64)]),
+    "camelot_server_create": (C.c_int32, [C.c_int64, C.POINTER(_P)]),
+    "camelot_server_admit": (C.c_int32, [_P, C.POINTER(PipelineConfig), C.POINTER(_P)]),
+    "camelot_server_release": (C.c_int32, [_P, _P, C.POINTER(C.c_uint64)]),
+    "camelot_server_used_bytes": (C.c_int64, [_P]),
+    "camelot_server_destroy": (C.c_int32, [_P]),
+    "camelot_stage_weight_bytes": (C.c_int64, [C.POINTER(StageDesc)]),
     "camelot_handoff_bench": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
                                           C.c_int32, C.POINTER(C.c_double)]),
     "camelot_handoff_expected": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_uint64),
@@ -259,18 +266,21 @@ def camelot_stage_row_bytes_out(desc: StageDesc) -> int:
 
 
 def camelot_stage_run(desc: StageDesc, in_ptr: int, out_ptr: int, rows: int, n_cus: int = 0,
-                      cu_offset: int = 0, reps: int = 1) -> float:
-    """Runs the stage worker once over `reps` batches; returns ns per batch."""
+                      cu_offset: int = 0, reps: int = 1, device: bool = False) -> float:
+    """Runs the stage's one-shot kernel over `reps` batches; returns ns per batch from
+    HIP events on its stream (device=True: from the device clock, launch excluded)."""
     ns = C.c_double(0.0)
-    _check(_lib.camelot_stage_run(C.byref(desc), in_ptr, out_ptr, rows, n_cus, cu_offset, reps, C.byref(ns)))
-    return ns.value
+    dns = C.c_double(0.0)
+    _check(_lib.camelot_stage_run(C.byref(desc), in_ptr, out_ptr, rows, n_cus, cu_offset, reps, C.byref(ns),
+                                  C.byref(dns)))
+    return dns.value if device else ns.value
 
 
 # ------------------------------------------------------------------ pipelines
 def pipeline_config(stages, cu, *, cu_offset=0, max_batch=32, batch_target=1, batch_timeout_ns=0,
                     ring_depth=4, handoff=HANDOFF_DEVICE, ingest=INGEST_HOST, max_rows_per_request=1,
                     ingest_capacity=4096, egress_capacity=65536, idle_timeout_ns=20_000_000_000,
-                    hbm_budget_bytes=0) -> PipelineConfig:
+                    hbm_budget_bytes=0, side_bytes=0) -> PipelineConfig:
     c = PipelineConfig()
     c.n_stages = len(stages)
     for i, s in enumerate(stages):
@@ -288,6 +298,7 @@ def pipeline_config(stages, cu, *, cu_offset=0, max_batch=32, batch_target=1, ba
     c.egress_capacity = egress_capacity
     c.idle_timeout_ns = idle_timeout_ns
     c.hbm_budget_bytes = hbm_budget_bytes
+    c.side_bytes = side_bytes
     return c
 
 
@@ -486,3 +497,38 @@ def camelot_alloc_peak_learned(problem: ProblemArrays, tables: SoloTablesArrays,
         return None, None
     _check(rc)
     return a, lat[: problem.struct.n_stages]
+
+
+# ------------------------------------------------------------------ serving
+def camelot_server_create(hbm_budget_bytes: int) -> int:
+    h = C.c_void_p()
+    _check(_lib.camelot_server_create(int(hbm_budget_bytes), C.byref(h)))
+    return h.value
+
+
+def camelot_server_admit(server: int, cfg: PipelineConfig):
+    """Returns the pipeline handle, or None when it does not fit the HBM budget."""
+    h = C.c_void_p()
+    rc = _lib.camelot_server_admit(server, C.byref(cfg), C.byref(h))
+    if rc == ENOMEM:
+        return None
+    _check(rc)
+    return h.value
+
+
+def camelot_server_release(server: int, p: int) -> int:
+    u = C.c_uint64(0)
+    _check(_lib.camelot_server_release(server, p, C.byref(u)))
+    return u.value
+
+
+def camelot_server_used_bytes(server: int) -> int:
+    return _lib.camelot_server_used_bytes(server)
+
+
+def camelot_server_destroy(server: int):
+    _check(_lib.camelot_server_destroy(server))
+
+
+def camelot_stage_weight_bytes(desc: StageDesc) -> int:
+    return _check(_lib.camelot_stage_weight_bytes(C.byref(desc)))

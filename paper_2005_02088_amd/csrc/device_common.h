@@ -108,6 +108,7 @@ struct WorkerCtl {
   uint64_t d_egress_base;               // egress row index of this batch's first row
   uint64_t d_t_stage[2 * kMaxStages];   // stage timestamps of the batch so far
   const uint8_t* d_rowptr[kMaxBatch];   // input row pointers
+  const uint8_t* d_rowside[kMaxBatch];  // input side bytes of each row (side_bytes > 0)
   uint64_t d_row_id[kMaxBatch];         // (request id) per row
   uint32_t d_row_idx[kMaxBatch];        // row index within its request
   uint64_t d_row_tarr[kMaxBatch];
@@ -134,6 +135,7 @@ struct StageParams {
   uint16_t* scratch;              // MLP: two [kMaxBatch][max_dim] BF16 buffers
   int32_t scratch_stride;         // elements per scratch row
   const float* tables;            // LOGMEL: window, twiddles, mel filters
+  float* partial;                 // CONV_POOL: per-tile channel sums [kMaxBatch][tiles][Cout]
 };
 
 enum InKind : int32_t { kInRing = 0, kInReplay = 1, kInHost = 2, kInBench = 3 };
@@ -144,6 +146,10 @@ struct WorkerArgs {
   int32_t stage_index;
   int32_t n_stages;
   int32_t max_batch;
+  int32_t side_bytes;             // per-row bytes carried through the stages
+  int32_t in_row_stride;          // stage 0: bytes between payload rows (row + side)
+  int64_t in_side_off;            // ring input: offset of the side plane in a slot
+  int64_t out_side_off;           // ring output: same for the output slot
   int32_t batch_target;
   int64_t batch_timeout_ticks;
   int64_t idle_ticks;             // exit after this long with nothing to do

@@ -77,6 +77,8 @@ extern "C" int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stag
     a.bench_in = (const uint8_t*)in[j];
     a.bench_out = (uint8_t*)out[j];
     a.bench_rows = rows[j];
+    a.side_bytes = stages[j].kind == CAMELOT_STAGE_GATHER_SCORE ? 4 * stages[j].dims[2] : 0;
+    a.in_row_stride = a.sp.in_row_bytes + a.side_bytes;
     a.bench_reps = 1 << 30;
     a.bench_ticks = ns_to_ticks(duration_ns, dev.wclk_hz);
   }
@@ -313,9 +315,11 @@ extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const ca
     bool has = false;
     int64_t L[3];
     for (int s = 0; s < S; ++s) {
-      const double y = std::min<double>(yhat[c * S + s], 40.0);
-      L[s] = std::max<int64_t>(1, (int64_t)std::ceil(std::exp(y)));
       const int kk = cd.k[s];
+      // the network predicts the log of the co-location slowdown over the solo latency
+      const double y = std::max(-10.0, std::min<double>(yhat[c * S + s], 10.0));
+      const double solo = (double)p->lat_ns[((int64_t)s * K + kk) * p->n_batches + bi];
+      L[s] = std::max<int64_t>(1, (int64_t)std::ceil(solo * std::exp(y)));
       cu += (int64_t)(kk + 1) * p->cu_step;
       bw += p->bw_bps[((int64_t)s * K + kk) * p->n_batches + bi];
       mem += p->mem_bytes[(int64_t)s * p->n_batches + bi];

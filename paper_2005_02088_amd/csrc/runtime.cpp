@@ -251,9 +251,39 @@ static int32_t check_stage(const camelot_stage_desc* d, int64_t* in_b, int64_t* 
       *in_b = 4LL * d->dims[0];
       *out_b = 8LL * d->k;
       return CAMELOT_OK;
+    case CAMELOT_STAGE_GATHER:
+      if (d->dims[0] < 1 || d->dims[0] > 4096) return fail(CAMELOT_EINVAL, "GATHER needs 1..4096 ids per row");
+      if (d->dims[1] < 64 || d->dims[1] > 1024 || d->dims[1] % 64 != 0)
+        return fail(CAMELOT_EINVAL, "GATHER needs dim in 64..1024, a multiple of 64");
+      if (d->k < 1) return fail(CAMELOT_EINVAL, "GATHER needs the table row count in k");
+      if (!d->weights[0]) return fail(CAMELOT_EINVAL, "GATHER needs weights[0] (the table)");
+      *in_b = 4LL * d->dims[0];
+      *out_b = 4LL * d->dims[1];
+      return CAMELOT_OK;
+    case CAMELOT_STAGE_CONV_POOL:
+      if (d->dims[0] < 1 || d->dims[1] < 1 || d->dims[0] * d->dims[1] > (1 << 20) || d->dims[2] != 64 ||
+          d->dims[3] != 64)
+        return fail(CAMELOT_EINVAL, "CONV_POOL needs H, W >= 1 (H*W <= 2^20) and 64 input and output channels");
+      if (!d->weights[0]) return fail(CAMELOT_EINVAL, "CONV_POOL needs weights[0]");
+      *in_b = 2LL * d->dims[0] * d->dims[1] * d->dims[2];
+      *out_b = 4LL * d->dims[3];
+      return CAMELOT_OK;
+    case CAMELOT_STAGE_GATHER_SCORE:
+      if (d->dims[1] < 1 || d->dims[0] < d->dims[1] || d->dims[0] % d->dims[1] != 0 || d->dims[0] > 1024)
+        return fail(CAMELOT_EINVAL, "GATHER_SCORE needs dims[0] = heads * dims[1] <= 1024");
+      if (d->dims[2] < 1 || d->dims[2] > 1024) return fail(CAMELOT_EINVAL, "GATHER_SCORE needs 1..1024 ids");
+      if (d->k < 1 || !d->weights[0]) return fail(CAMELOT_EINVAL, "GATHER_SCORE needs the table and its rows in k");
+      *in_b = 4LL * d->dims[0];
+      *out_b = 4LL * (d->dims[0] / d->dims[1]) * d->dims[2];
+      return CAMELOT_OK;
     default:
       return fail(CAMELOT_EINVAL, "unknown stage kind %d", d->kind);
   }
+}
+
+// side bytes a stage needs in a one-shot run (ids following each input row)
+static int64_t stage_side_bytes(const camelot_stage_desc* d) {
+  return d->kind == CAMELOT_STAGE_GATHER_SCORE ? 4LL * d->dims[2] : 0;
 }
 
 static int result_k(const camelot_stage_desc* d) {
@@ -262,6 +292,10 @@ static int result_k(const camelot_stage_desc* d) {
 
 static int64_t stage_scratch_bytes(const camelot_stage_desc* d, int* stride) {
   *stride = 0;
+  if (d->kind == CAMELOT_STAGE_CONV_POOL) {
+    const int64_t tiles = ((int64_t)d->dims[0] * d->dims[1] + 63) / 64;
+    return (int64_t)kMaxBatch * tiles * d->dims[3] * 4;
+  }
   if (d->kind != CAMELOT_STAGE_MLP_BF16) return 0;
   int mx = 0;
   for (int l = 0; l <= d->n_layers; ++l) mx = std::max(mx, d->dims[l]);
@@ -292,6 +326,7 @@ int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp)
   }
   sp->scratch = res->scratch;
   sp->scratch_stride = stride;
+  if (d->kind == CAMELOT_STAGE_CONV_POOL) sp->partial = (float*)res->scratch;
   if (d->kind == CAMELOT_STAGE_LOGMEL) {
     rc = logmel_device_tables(&sp->tables);
     if (rc) return rc;
@@ -352,7 +387,8 @@ extern "C" int64_t camelot_stage_row_bytes_out(const camelot_stage_desc* stage) 
 }
 
 extern "C" int32_t camelot_stage_run(const camelot_stage_desc* stage, const void* in, void* out, int32_t rows,
-                                     int32_t n_cus, int32_t cu_offset, int32_t reps, double* ns_per_rep) {
+                                     int32_t n_cus, int32_t cu_offset, int32_t reps, double* ns_per_rep,
+                                     double* device_ns_per_rep) {
   clear_error();
   DevInfo dev;
   int32_t rc = dev_info(&dev);
@@ -384,6 +420,8 @@ extern "C" int32_t camelot_stage_run(const camelot_stage_desc* stage, const void
   a.bench_out = (uint8_t*)out;
   a.bench_rows = rows;
   a.bench_reps = reps;
+  a.side_bytes = (int32_t)stage_side_bytes(stage);
+  a.in_row_stride = a.sp.in_row_bytes + a.side_bytes;
   hipEvent_t ev0, ev1;
   HIP_TRY(hipEventCreate(&ev0));
   HIP_TRY(hipEventCreate(&ev1));
@@ -408,6 +446,11 @@ extern "C" int32_t camelot_stage_run(const camelot_stage_desc* stage, const void
   }
   // HIP events on the stream the kernel ran on: the whole launch, divided by reps
   if (ns_per_rep) *ns_per_rep = (double)ms * 1e6 / reps;
+  if (device_ns_per_rep) {
+    uint64_t tr[2] = {0, 0};
+    if ((rc = d2h(tr, &ctl->ticks_bench, sizeof tr))) return rc;
+    *device_ns_per_rep = tr[1] ? (double)tr[0] * 1e9 / (double)dev.wclk_hz / (double)tr[1] : 0.0;
+  }
   return CAMELOT_OK;
 }
 
@@ -595,6 +638,11 @@ static int32_t validate_config(const camelot_pipeline_config* c, const DevInfo& 
   if (c->egress_capacity < c->max_batch || c->egress_capacity > (1 << 24))
     return fail(CAMELOT_EINVAL, "egress_capacity must be in max_batch..2^24");
   if (c->idle_timeout_ns <= 0) return fail(CAMELOT_EINVAL, "idle_timeout_ns must be > 0");
+  if (c->side_bytes < 0 || c->side_bytes > 4096 || c->side_bytes % 16 != 0)
+    return fail(CAMELOT_EINVAL, "side_bytes must be a multiple of 16 in 0..4096");
+  for (int i = 0; i < c->n_stages; ++i)
+    if (c->stages[i].kind == CAMELOT_STAGE_GATHER_SCORE && c->side_bytes < 4 * c->stages[i].dims[2])
+      return fail(CAMELOT_EINVAL, "stage %d reads %d ids from the side bytes", i, c->stages[i].dims[2]);
   return CAMELOT_OK;
 }
 
@@ -617,8 +665,11 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
   // ---- footprint (HBM held by the library) and admission
   int64_t fp = 0;
   int64_t stride[kMaxStages] = {0};
+  const int64_t side = cfg->side_bytes;
+  int64_t side_off[kMaxStages] = {0};
   for (int i = 0; i + 1 < S; ++i) {
-    stride[i] = kSlotHeaderBytes + round_up((int64_t)cfg->max_batch * p->out_b[i], 256);
+    side_off[i] = kSlotHeaderBytes + round_up((int64_t)cfg->max_batch * p->out_b[i], 256);
+    stride[i] = side_off[i] + round_up((int64_t)cfg->max_batch * side, 256);
     fp += (host_handoff ? 2 : 1) * (D * stride[i] + (host_handoff ? 0 : round_up(8LL * D, 256)));
   }
   for (int i = 0; i < S; ++i) {
@@ -658,7 +709,7 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
   P_CHECK(p->egress, "pinned egress allocation failed");
   if (cfg->ingest == CAMELOT_INGEST_HOST) {
     p->ingest = (IngestRec*)pinned((size_t)cfg->ingest_capacity * sizeof(IngestRec));
-    p->ingest_slot_bytes = round_up((int64_t)cfg->max_rows_per_request * p->in_b[0], 64);
+    p->ingest_slot_bytes = round_up((int64_t)cfg->max_rows_per_request * (p->in_b[0] + cfg->side_bytes), 64);
     p->ingest_payload = (uint8_t*)pinned((size_t)cfg->ingest_capacity * p->ingest_slot_bytes);
     P_CHECK(p->ingest && p->ingest_payload, "pinned ingest allocation failed");
   }
@@ -709,6 +760,10 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     a.stage_index = i;
     a.n_stages = S;
     a.max_batch = cfg->max_batch;
+    a.side_bytes = cfg->side_bytes;
+    a.in_row_stride = (int32_t)(p->in_b[i] + cfg->side_bytes);
+    a.in_side_off = i > 0 ? side_off[i - 1] : 0;
+    a.out_side_off = i + 1 < S ? side_off[i] : 0;
     a.batch_target = std::min(cfg->batch_target, cfg->max_batch);
     a.batch_timeout_ticks = ns_to_ticks(cfg->batch_timeout_ns, p->dev.wclk_hz);
     a.idle_ticks = ns_to_ticks(cfg->idle_timeout_ns, p->dev.wclk_hz);
@@ -794,7 +849,8 @@ extern "C" int32_t camelot_pipeline_submit(camelot_pipeline* p, uint64_t query_i
   const uint64_t tail = __atomic_load_n(&p->pub->ingest_tail, __ATOMIC_ACQUIRE);
   if (p->head - tail >= (uint64_t)p->cfg.ingest_capacity) return fail(CAMELOT_EAGAIN, "ingest queue full");
   const uint64_t slot = p->head % (uint64_t)p->cfg.ingest_capacity;
-  std::memcpy(p->ingest_payload + slot * p->ingest_slot_bytes, payload, (size_t)rows * p->in_b[0]);
+  std::memcpy(p->ingest_payload + slot * p->ingest_slot_bytes, payload,
+              (size_t)rows * (p->in_b[0] + p->cfg.side_bytes));
   IngestRec rec;
   rec.id = query_id;
   rec.t_arr = (uint64_t)host_now_ticks(p);
@@ -832,7 +888,7 @@ extern "C" int32_t camelot_pipeline_replay(camelot_pipeline* p, int32_t n_req, c
       return fail(CAMELOT_EINVAL, "request %d: payload rows out of range", r);
     tab[r].id = ids[r];
     tab[r].t_arr = (uint64_t)ns_to_ticks(arrival_ns[r], p->dev.wclk_hz);
-    tab[r].payload_off = (uint64_t)payload_row[r] * (uint64_t)p->in_b[0];
+    tab[r].payload_off = (uint64_t)payload_row[r] * (uint64_t)(p->in_b[0] + p->cfg.side_bytes);
     tab[r].rows = (uint32_t)rows[r];
     tab[r].valid = 1;
     p->submitted_rows += rows[r];

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <math.h>
+#include <hip/hip_fp16.h>
 
 #include "device_common.h"
 
@@ -387,6 +388,164 @@ __device__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t*
   return true;
 }
 
+// ------------------------------------------------------------------ embedding gather
+// One wave per row: the row's ids are read once (lanes < n_ids) and broadcast; every
+// lane owns dim/64 columns and adds the FP16 table rows in id order in FP32, so a
+// row's result does not depend on the batch. Ids outside [0, table rows) add zero.
+constexpr int kGatherMaxDim = 1024;
+
+__device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  const int n_ids = a.sp.dims[0], dim = a.sp.dims[1];
+  const int64_t trows = a.sp.k;
+  const __half* T = (const __half*)a.sp.w[0];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int per = dim >> 6;                  // columns per lane (dim is a multiple of 64)
+  float* Y = (float*)out;
+  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+    const int32_t* ids = (const int32_t*)ctl->d_rowptr[r];
+    float acc[kGatherMaxDim / 64];
+#pragma unroll
+    for (int c = 0; c < kGatherMaxDim / 64; ++c) acc[c] = 0.f;
+    for (int j0 = 0; j0 < n_ids; j0 += 64) {
+      const int my = j0 + lane < n_ids ? ids[j0 + lane] : -1;
+      const int nj = min(64, n_ids - j0);
+      for (int j = 0; j < nj; ++j) {
+        const int id = __shfl(my, j, 64);
+        if (id < 0 || id >= trows) continue;          // uniform across the wave
+        const __half* src = T + (int64_t)id * dim;
+#pragma unroll
+        for (int c = 0; c < kGatherMaxDim / 64; ++c)
+          if (c < per) acc[c] += __half2float(src[c * 64 + lane]);
+      }
+    }
+    const float inv = 1.f / (float)n_ids;
+#pragma unroll
+    for (int c = 0; c < kGatherMaxDim / 64; ++c)
+      if (c < per) Y[(int64_t)r * dim + c * 64 + lane] = acc[c] * inv;
+  }
+}
+
+// ------------------------------------------------------------------ 3x3 convolution + global pool
+// Implicit GEMM on v_mfma_f32_16x16x32_bf16: per query, M = H*W output pixels,
+// N = 64 output channels, K = 9 positions x 64 input channels (chunks of 32 input
+// channels at one (ky, kx)). A workgroup computes a 64-pixel tile (16 per wave) for
+// all 64 channels, applies ReLU and sums its pixels per channel in a fixed order
+// (within a wave: rows, then the 4 lane groups; then the 4 waves); phase 2, after a
+// grid barrier, adds the tiles of each query in tile order and divides by H*W.
+constexpr int kConvC = 64, kConvCout = 64, kConvTile = 64;
+
+__device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  __shared__ float wsum[kWaves][kConvCout];
+  const int H = a.sp.dims[0], Wd = a.sp.dims[1];
+  const int npix = H * Wd, ntiles = (npix + kConvTile - 1) / kConvTile;
+  const uint16_t* Wc = (const uint16_t*)a.sp.w[0];          // [64][9][64]
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int cin0 = (lane >> 4) * 8;                          // this lane's 8 channels in a chunk
+  const int units = rows * ntiles;
+  for (int u = blockIdx.x; u < units; u += gridDim.x) {
+    const int r = u / ntiles, tile = u - r * ntiles;
+    const uint16_t* X = (const uint16_t*)ctl->d_rowptr[r];
+    const int p = tile * kConvTile + w * 16 + (lane & 15);   // A-operand pixel of this lane
+    const int py = p / Wd, px = p - py * Wd;
+    const bool pin = p < npix;
+    f32x4 acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int pos = 0; pos < 9; ++pos) {
+      const int ky = pos / 3, kx = pos - ky * 3;
+      const int yy = py + ky - 1, xx = px + kx - 1;
+      const bool in = pin && yy >= 0 && yy < H && xx >= 0 && xx < Wd;
+      const uint16_t* xs = X + ((int64_t)yy * Wd + xx) * kConvC;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bf16x8 af = in ? ld_bf16x8(xs + h * 32 + cin0) : (bf16x8){};
+        const int kb = pos * kConvC + h * 32 + cin0;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const bf16x8 bf = ld_bf16x8(Wc + (int64_t)(nb * 16 + (lane & 15)) * (9 * kConvC) + kb);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[nb], 0, 0, 0);
+        }
+      }
+    }
+    // ReLU and the sum over this wave's 16 pixels per channel
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      float v = 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pr = tile * kConvTile + w * 16 + (lane >> 4) * 4 + i;
+        if (pr < npix) v += fmaxf(acc[nb][i], 0.f);
+      }
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (lane < 16) wsum[w][nb * 16 + lane] = v;
+    }
+    __syncthreads();
+    if (tid < kConvCout) {
+      const float t = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
+      a.sp.partial[((int64_t)r * ntiles + tile) * kConvCout + tid] = t;
+    }
+    __syncthreads();
+  }
+  if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
+  const float inv = 1.f / (float)npix;
+  for (int i = blockIdx.x * kThreads + tid; i < rows * kConvCout; i += gridDim.x * kThreads) {
+    const int r = i / kConvCout, c = i - r * kConvCout;
+    const float* pp = a.sp.partial + (int64_t)r * ntiles * kConvCout + c;
+    float t = 0.f;
+    for (int q = 0; q < ntiles; ++q) t += pp[(int64_t)q * kConvCout];
+    ((float*)out)[(int64_t)r * kConvCout + c] = t * inv;
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ gather + score
+// One wave per row: the row's query vectors are staged in LDS; each lane computes
+// whole dot products (fixed order over d) for the (head, id) outputs lane, lane + 64,
+// ...; lanes of the same id read the same table row, which stays in L1.
+constexpr int kScoreMaxQ = 1024;
+
+__device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  __shared__ float q_s[kWaves][kScoreMaxQ];
+  const int qdim = a.sp.dims[0], dim = a.sp.dims[1], n_ids = a.sp.dims[2];
+  const int heads = qdim / dim;
+  const int64_t trows = a.sp.k;
+  const __half* T = (const __half*)a.sp.w[0];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* Y = (float*)out;
+  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+    const float* q = (const float*)ctl->d_rowptr[r];
+    const int32_t* ids = (const int32_t*)ctl->d_rowside[r];
+    for (int i = lane; i < qdim; i += 64) q_s[w][i] = q[i];
+    wave_lds_sync();
+    for (int o = lane; o < heads * n_ids; o += 64) {
+      const int h = o / n_ids, j = o - h * n_ids;
+      const int id = ids[j];
+      float acc = 0.f;
+      if (id >= 0 && id < trows) {
+        const __half* tr = T + (int64_t)id * dim;
+        const float* qh = q_s[w] + h * dim;
+        for (int d = 0; d < dim; ++d) acc = fmaf(qh[d], __half2float(tr[d]), acc);
+      }
+      Y[(int64_t)r * heads * n_ids + o] = acc;
+    }
+    wave_lds_sync();
+  }
+}
+
+// ------------------------------------------------------------------ side bytes
+// Copies every row's side bytes from the input to the output slot's side plane.
+__device__ void copy_side(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
+  if (a.side_bytes <= 0 || a.out_kind != kOutRing) return;
+  uint8_t* dst = (uint8_t*)ctl->d_out_hdr + a.out_side_off;
+  const int words = a.side_bytes >> 2;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < rows * words; i += gridDim.x * kThreads) {
+    const int r = i / words, wd = i - r * words;
+    ((uint32_t*)(dst + (int64_t)r * a.side_bytes))[wd] = ((const uint32_t*)ctl->d_rowside[r])[wd];
+  }
+}
+
 // ------------------------------------------------------------------ stage dispatch
 template <int KIND>
 __device__ __forceinline__ bool exec_stage(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
@@ -395,6 +554,9 @@ __device__ __forceinline__ bool exec_stage(const WorkerArgs& a, WorkerCtl* ctl, 
   if constexpr (KIND == CAMELOT_STAGE_LOGMEL) { exec_logmel(a, ctl, rows, out); return true; }
   if constexpr (KIND == CAMELOT_STAGE_MLP_BF16) { return exec_mlp(a, ctl, rows, out); }
   if constexpr (KIND == CAMELOT_STAGE_TOPK) { exec_topk(a, ctl, rows); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_GATHER) { exec_gather(a, ctl, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_CONV_POOL) { return exec_conv_pool(a, ctl, rows, out); }
+  if constexpr (KIND == CAMELOT_STAGE_GATHER_SCORE) { exec_gather_score(a, ctl, rows, out); return true; }
   return false;
 }
 
@@ -554,8 +716,10 @@ __global__ __launch_bounds__(kThreads) void stage_bench(WorkerArgs a) {
   WorkerCtl* ctl = a.ctl;
   const int tid = threadIdx.x;
   if (blockIdx.x == 0)
-    for (int i = tid; i < a.bench_rows; i += kThreads)
-      ctl->d_rowptr[i] = a.bench_in + (int64_t)i * a.sp.in_row_bytes;
+    for (int i = tid; i < a.bench_rows; i += kThreads) {
+      ctl->d_rowptr[i] = a.bench_in + (int64_t)i * a.in_row_stride;
+      ctl->d_rowside[i] = ctl->d_rowptr[i] + a.sp.in_row_bytes;
+    }
   if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
   const uint64_t t0 = now_ticks();
   int rep = 0;
@@ -643,8 +807,11 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
         for (int q = tid; q < nreq; q += kThreads) {
           for (uint32_t j = 0; j < s_rows[q]; ++j) {
             const uint32_t row = s_rbase[q] + j;
-            ctl->d_rowptr[row] = ih ? in_payload + (int64_t)row * a.sp.in_row_bytes
-                                    : s_ptr[q] + (int64_t)j * a.sp.in_row_bytes;
+            const uint8_t* rp = ih ? in_payload + (int64_t)row * a.sp.in_row_bytes
+                                   : s_ptr[q] + (int64_t)j * a.in_row_stride;
+            ctl->d_rowptr[row] = rp;
+            ctl->d_rowside[row] = ih ? (const uint8_t*)ih + a.in_side_off + (int64_t)row * a.side_bytes
+                                     : rp + a.sp.in_row_bytes;
             ctl->d_row_id[row] = s_id[q];
             ctl->d_row_idx[row] = j;
             ctl->d_row_tarr[row] = s_tarr[q];
@@ -672,7 +839,10 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
             if (tid == 2 * si) tv = t_start;
             oh->t_stage[tid] = tv;
           }
-          if (tid == 0) ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
+          if (tid == 0) {
+            ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
+            ctl->d_out_hdr = oh;
+          }
         } else if (tid == 0) {
           ctl->d_egress_base = ctl->egress_head;
           ctl->d_out = nullptr;
@@ -707,6 +877,7 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
     if (stop) { exit_status = (int)stop; break; }
     const int rows = (int)ctl->d_rows;
     if (!exec_stage<KIND>(a, ctl, rows, ctl->d_out)) { exit_status = kStatusTimeout; break; }
+    copy_side(a, ctl, rows);
     // results go to pinned host memory, a host-staged output slot is read by DMA:
     // those are published at system scope
     if (!grid_barrier(ctl, gridDim.x, a.spin_ticks, a.out_kind == kOutEgress || a.out_state_sys != 0)) {
@@ -758,6 +929,12 @@ template __global__ void stage_worker<CAMELOT_STAGE_GEMM_ARGMAX>(WorkerArgs);
 template __global__ void stage_worker<CAMELOT_STAGE_LOGMEL>(WorkerArgs);
 template __global__ void stage_worker<CAMELOT_STAGE_MLP_BF16>(WorkerArgs);
 template __global__ void stage_worker<CAMELOT_STAGE_TOPK>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_GATHER>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_GATHER>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_GATHER_SCORE>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_GATHER_SCORE>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_CONV_POOL>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_CONV_POOL>(WorkerArgs);
 template __global__ void stage_bench<CAMELOT_STAGE_GEMM_RELU>(WorkerArgs);
 template __global__ void stage_bench<CAMELOT_STAGE_GEMM_ARGMAX>(WorkerArgs);
 template __global__ void stage_bench<CAMELOT_STAGE_LOGMEL>(WorkerArgs);
@@ -773,6 +950,9 @@ const void* worker_kernel(int kind, bool bench) {
       case CAMELOT_STAGE_LOGMEL: return (const void*)&stage_bench<CAMELOT_STAGE_LOGMEL>;
       case CAMELOT_STAGE_MLP_BF16: return (const void*)&stage_bench<CAMELOT_STAGE_MLP_BF16>;
       case CAMELOT_STAGE_TOPK: return (const void*)&stage_bench<CAMELOT_STAGE_TOPK>;
+      case CAMELOT_STAGE_GATHER: return (const void*)&stage_bench<CAMELOT_STAGE_GATHER>;
+      case CAMELOT_STAGE_GATHER_SCORE: return (const void*)&stage_bench<CAMELOT_STAGE_GATHER_SCORE>;
+      case CAMELOT_STAGE_CONV_POOL: return (const void*)&stage_bench<CAMELOT_STAGE_CONV_POOL>;
       default: return nullptr;
     }
   }
@@ -782,6 +962,9 @@ const void* worker_kernel(int kind, bool bench) {
     case CAMELOT_STAGE_LOGMEL: return (const void*)&stage_worker<CAMELOT_STAGE_LOGMEL>;
     case CAMELOT_STAGE_MLP_BF16: return (const void*)&stage_worker<CAMELOT_STAGE_MLP_BF16>;
     case CAMELOT_STAGE_TOPK: return (const void*)&stage_worker<CAMELOT_STAGE_TOPK>;
+    case CAMELOT_STAGE_GATHER: return (const void*)&stage_worker<CAMELOT_STAGE_GATHER>;
+    case CAMELOT_STAGE_GATHER_SCORE: return (const void*)&stage_worker<CAMELOT_STAGE_GATHER_SCORE>;
+    case CAMELOT_STAGE_CONV_POOL: return (const void*)&stage_worker<CAMELOT_STAGE_CONV_POOL>;
     default: return nullptr;
   }
 }

@@ -148,3 +148,62 @@ def test_mlp_bf16_identity_chain():
 def test_normwise_err():
     assert O.normwise_err([1.0, 0.0], [1.0, 0.0]) == 0.0
     assert O.normwise_err([1.0, 0.5], [2.0, 0.0]) == 0.5
+
+
+# ---------------------------------------------------------------- gather
+def test_gather_mean_hand_case_and_out_of_range():
+    t = np.array([[1.0, 2.0], [10.0, 20.0], [100.0, 200.0]])
+    got = O.gather_mean(np.array([[0, 2, 2, 99], [1, 1, -1, 0]]), t)
+    assert np.array_equal(got, [[(1 + 200) / 4, (2 + 400) / 4], [(20 + 1) / 4, (40 + 2) / 4]])
+
+
+def test_gather_mean_matches_fancy_indexing():
+    t = G.fp16_table(1000, 64, seed=2)
+    ids = G.zipf_ids(7, 32, 1000, seed=2)
+    ref = t.astype(np.float64)[ids].mean(axis=1)
+    assert np.allclose(O.gather_mean(ids, t), ref, rtol=0, atol=1e-12)
+
+
+def test_zipf_ids_are_skewed_and_in_range():
+    ids = G.zipf_ids(2000, 32, 10000, seed=1)
+    assert ids.min() >= 0 and ids.max() < 10000
+    _, counts = np.unique(ids, return_counts=True)
+    top = np.sort(counts)[::-1]
+    assert top[0] > 20 * np.median(counts)     # a heavy head
+
+
+# ---------------------------------------------------------------- conv / score
+def test_conv_centre_delta_is_relu_mean_of_channel():
+    x = G.c4_feature_maps(2, seed=3, h=5, w=7)
+    w = np.zeros((64, 3, 3, 64), np.float32)
+    for co in range(64):
+        w[co, 1, 1, co] = 1.0                       # centre tap: identity
+    got = O.conv3x3_relu_pool(x, G._to_bf16_bits(w))
+    xf = O.bf16_bits_to_f64(x)
+    assert np.allclose(got, np.maximum(xf, 0).mean(axis=(1, 2)), atol=1e-12)
+
+
+def test_conv_matches_direct_sum_and_pads_with_zero():
+    x = G.c4_feature_maps(1, seed=4, h=4, w=3)
+    w = G.c4_conv_weights(seed=4)
+    xf, wf = O.bf16_bits_to_f64(x)[0], O.bf16_bits_to_f64(w)
+    H, W = 4, 3
+    ref = np.zeros(64)
+    for y in range(H):
+        for xx in range(W):
+            for co in range(64):
+                acc = 0.0
+                for ky in range(3):
+                    for kx in range(3):
+                        yy, xs = y + ky - 1, xx + kx - 1
+                        if 0 <= yy < H and 0 <= xs < W:
+                            acc += float(wf[co, ky, kx] @ xf[yy, xs])
+                ref[co] += max(acc, 0.0)
+    assert np.allclose(O.conv3x3_relu_pool(x, w)[0], ref / (H * W), rtol=1e-12, atol=1e-12)
+
+
+def test_gather_score_hand_case():
+    t = np.array([[1.0, 0.0], [0.0, 2.0], [1.0, 1.0]])
+    q = np.array([[1.0, 1.0, 2.0, -1.0]])           # two heads of dim 2
+    got = O.gather_score(q, np.array([[0, 2, 7]]), t, 2)
+    assert np.array_equal(got, [[1.0, 2.0, 0.0, 2.0, 1.0, 0.0]])

@@ -130,6 +130,49 @@ def request_rows(n: int, seed: int = 0, lo: int = 1, hi: int = 128) -> np.ndarra
     return rng("requests", seed).integers(lo, hi + 1, n).astype(np.int32)
 
 
+# ---------------------------------------------------------------- embedding tables
+def fp16_table(rows: int, dim: int, seed: int = 0) -> np.ndarray:
+    """Embedding table N(0,1) stored as FP16 [rows, dim]."""
+    g = rng("c4", seed, 1)
+    out = np.empty((rows, dim), np.float16)
+    step = 1 << 20
+    for i in range(0, rows, step):
+        out[i:i + step] = g.standard_normal((min(step, rows - i), dim), dtype=np.float32)
+    return out
+
+
+def zipf_ids(n: int, per_row: int, n_items: int, s: float = 1.1, seed: int = 0) -> np.ndarray:
+    """[n, per_row] int32 ids with Zipf(s) popularity over n_items: ranks drawn by
+    inverse CDF of p(r) ~ r^-s on 1..n_items, mapped to rows by a seeded
+    permutation so popular rows are scattered."""
+    g = rng("c4", seed, 2)
+    ranks = np.arange(1, n_items + 1, dtype=np.float64)
+    cdf = np.cumsum(ranks ** -s)
+    cdf /= cdf[-1]
+    r = np.searchsorted(cdf, g.random(n * per_row), side="right")
+    perm = g.permutation(n_items)
+    return perm[np.minimum(r, n_items - 1)].astype(np.int32).reshape(n, per_row)
+
+
+# ---------------------------------------------------------------- 5-stage (vision + retrieval) pipeline
+C4_H, C4_W, C4_C = 56, 56, 64
+C4_MLP_DIMS = (64, 1024, 1024)
+
+
+def c4_feature_maps(n: int, seed: int = 0, h: int = C4_H, w: int = C4_W, c: int = C4_C) -> np.ndarray:
+    """N(0,1) feature maps rounded to BF16, bit patterns [n, h, w, c] (NHWC)."""
+    g = rng("c4", seed, 10)
+    x = g.standard_normal((n, h, w, c), dtype=np.float32)
+    return _to_bf16_bits(x)
+
+
+def c4_conv_weights(seed: int = 0, c: int = C4_C, cout: int = 64) -> np.ndarray:
+    """3x3 conv weights N(0, 2/(9 c)) rounded to BF16, bit patterns [cout, 3, 3, c]."""
+    g = rng("c4", seed, 11)
+    w = g.standard_normal((cout, 3, 3, c), dtype=np.float32) * np.float32(np.sqrt(2.0 / (9 * c)))
+    return _to_bf16_bits(w)
+
+
 # ---------------------------------------------------------------- allocator tables
 def random_problem_tables(n_stages: int, n_shares: int, batches, seed: int = 0,
                           sub: int = 0):
