@@ -17,7 +17,9 @@ Steps (all on synthetic, seeded inputs resident in HBM before any timed region):
     host-staged handoff, same batching rule);
  4. timed steps: K replays at the found peak rate (one step = one trial);
  5. CUs at 20% load: min-resource problem (Eq. 3) at 20% of the baseline's peak,
-    checked with a replay;
+    checked with a replay; then the contention-aware allocation: co-location
+    profiles, the learned predictor trained on them, Eq. 1 over its predictions,
+    and that allocation's measured peak next to the table allocation's;
  6. device-global handoff GB/s (1 GiB ring, 128 + 128 CUs) vs the 8 TB/s HBM peak;
  7. roofline of the dominant kernel (the BF16 MLP stage at batch 128 on its share);
  8. the CPU oracle timed on a bounded sample on this host (1 thread).
@@ -185,17 +187,23 @@ class Speech:
             st = cm.camelot_pipeline_stats_get(p)
         finally:
             cm.camelot_pipeline_destroy(p)
+        S = len(cu)
+        nb = [max(int(st.batches[i]), 1) for i in range(S)]
+        stage = {"busy_us": [round(st.busy_ns[i] / nb[i] / 1e3, 1) for i in range(S)],
+                 "wait_us": [round(st.wait_ns[i] / nb[i] / 1e3, 1) for i in range(S)],
+                 "rows_per_batch": [round(st.rows[i] / nb[i], 1) for i in range(S)]}
         if done < n:
-            log(f"    trial incomplete: {done}/{n} rows in {wall:.2f} s, batches {list(st.batches[:3])}, "
-                f"worker status {list(st.worker_status[:3])}")
-            return {"n": n, "done": done, "p50": math.inf, "p99": math.inf, "wall_s": wall, "ok": False}
+            log(f"    trial incomplete: {done}/{n} rows in {wall:.2f} s, batches {list(st.batches[:S])}, "
+                f"worker status {list(st.worker_status[:S])}, per batch {stage}")
+            return {"n": n, "done": done, "p50": math.inf, "p99": math.inf, "wall_s": wall, "ok": False,
+                    "stage": stage}
         assert np.array_equal(got_ids, ids), "delivery out of order"
         warm = n // 10                       # discard the warm-up tenth
         srt = np.sort(lat[warm:])
         p99 = int(srt[math.ceil(0.99 * len(srt)) - 1])
         p50 = int(srt[math.ceil(0.50 * len(srt)) - 1])
         return {"n": n, "done": done, "p50": p50, "p99": p99, "wall_s": wall, "ok": p99 <= QOS_NS,
-                "span_s": float(arr[-1]) / 1e9}
+                "span_s": float(arr[-1]) / 1e9, "stage": stage}
 
     def peak_search(self, cu, handoff, batch, guess_qps, duration_s, iters, tag):
         lo, hi = 0.0, guess_qps * 2.0
@@ -205,7 +213,7 @@ class Speech:
             rate = (lo + hi) / 2 if it else guess_qps
             r = self.trial(cu, rate, duration_s, handoff, batch, timeout, seed=it)
             log(f"  [{tag}] rate {rate / 1e6:.3f} Mq/s -> p50 {r['p50'] / 1e3:.0f} us p99 {r['p99'] / 1e3:.0f} us "
-                f"ok={r['ok']}")
+                f"ok={r['ok']} per batch {r['stage']}")
             if r["ok"]:
                 lo = rate
                 best = (rate, r)
@@ -214,6 +222,65 @@ class Speech:
             if best is None and it == iters - 1:
                 break
         return best
+
+
+def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1500, epochs=300):
+    """The contention-aware allocator: co-location profiles of the three stages at
+    random shares and batches, the 16-64-64-1 predictor trained on them with the
+    library's kernels (target: log slowdown over the solo profile), then Eq. 1 over
+    the predicted co-located latencies. Returns the allocation and the held-out
+    error of the predictor vs the solo table at predicting co-located latency."""
+    import numpy as np
+    step = SHARES[0]
+    nb = len(BATCHES)
+    flops = np.array([[0.0] * nb, [2.0 * MLP_PARAMS * b for b in BATCHES], [0.0] * nb])
+    bytes_ = np.array([[Speech.stage_bytes(s, b) for b in BATCHES] for s in range(3)], np.float64)
+    latf = np.maximum(lat.astype(np.float64), 1.0)
+    tabs = cm.SoloTablesArrays(step, BATCHES, bytes_[:, None, :] / (latf * 1e-9) / HBM_PEAK,
+                               flops[:, None, :] / (latf * 1e-9) / MFMA_BF16_PEAK)
+    t0 = time.perf_counter()
+    recs = cm.camelot_profile_coruns(sp.stages, [t.data_ptr() for t in sp.in_bufs],
+                                     [t.data_ptr() for t in sp.out_bufs], 256, step, BATCHES, n_runs, 12345, 400_000)
+    t_prof = time.perf_counter() - t0
+    X, y, solo, multi = [], [], [], []
+    for r in recs:
+        f = cm.camelot_predictor_features(tabs, list(r.kinds[:r.m]), list(r.cu[:r.m]), list(r.bi[:r.m]))
+        for j in range(r.m):
+            sp_ns = latf[r.kinds[j], r.cu[j] // step - 1, r.bi[j]]
+            X.append(f[j])
+            y.append(np.log(r.ns[j] / sp_ns))
+            solo.append(sp_ns)
+            multi.append(r.m > 1)
+    X, y, solo, multi = np.array(X, np.float32), np.array(y, np.float32), np.array(solo), np.array(multi)
+    perm = G.rng("predictor", 5).permutation(len(y))
+    tr, te = perm[: int(0.7 * len(y))], perm[int(0.7 * len(y)):]
+    mean, std = cm.camelot_predictor_fit_norm(X[tr])
+    Z = cm.camelot_predictor_standardize(X, mean, std)
+    dp = torch.from_numpy(np.concatenate([p.reshape(-1) for p in G.predictor_init(seed=0)]).astype(np.float32)).cuda()
+    dm1, dm2 = torch.zeros_like(dp), torch.zeros_like(dp)
+    dx, dy = torch.from_numpy(Z[tr]).cuda(), torch.from_numpy(y[tr]).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, losses = cm.camelot_predictor_train(dp.data_ptr(), dm1.data_ptr(), dm2.data_ptr(), 0, dx.data_ptr(),
+                                           dy.data_ptr(), len(tr), 64, epochs, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    dxe = torch.from_numpy(Z[te]).cuda()
+    yh = torch.empty(len(te), device="cuda")
+    torch.cuda.synchronize()
+    cm.camelot_predictor_forward(dp.data_ptr(), dxe.data_ptr(), len(te), yh.data_ptr())
+    pred = solo[te] * np.exp(yh.cpu().numpy().astype(np.float64))
+    meas = solo[te] * np.exp(y[te].astype(np.float64))
+    co = multi[te]
+    mape_l = float(np.mean(np.abs(pred[co] - meas[co]) / meas[co]))
+    mape_s = float(np.mean(np.abs(solo[te][co] - meas[co]) / meas[co]))
+    t0 = time.perf_counter()
+    a, lp = cm.camelot_alloc_peak_learned(prob, tabs, dp.data_ptr(), mean, std)
+    t_alloc = time.perf_counter() - t0
+    info = {"samples": int(len(y)), "profile_s": t_prof, "train_s": t_train, "epochs": epochs,
+            "loss_first_last": [float(losses[0]), float(losses[-1])], "mape_colocated_learned": mape_l,
+            "mape_colocated_solo_table": mape_s, "alloc_ms": t_alloc * 1e3}
+    log(f"learned predictor: {info}")
+    return (a.as_dict() if a is not None else None), [int(v) for v in lp[:3]], info
 
 
 ROOF_LAUNCHES, ROOF_REPS = 10, 50
@@ -254,6 +321,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--cpu-baseline-only", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-learned", action="store_true", help="skip the learned-allocator comparison")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the MLP roofline launches of step 7 (for rocprofv3 runs)")
     ap.add_argument("--mlp-cus", type=int, default=0, help="MLP share for --roofline-only")
@@ -326,18 +394,24 @@ def main():
 
     if peak <= 0:
         raise SystemExit("no rate met the QoS target; see the trial log above")
-    # 4: timed steps at the found peak
-    for w in range(args.warmup):
-        sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    steps = []
-    for k in range(args.steps):
-        steps.append(sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=200 + k))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    p99s = [s["p99"] for s in steps]
-    log(f"timed steps p99 {p99s}")
+    # 4: timed steps at the found peak; the reported rate is one at which every timed
+    # step met the QoS target (the search's last good rate, lowered by 3% per retry)
+    for attempt in range(6):
+        for w in range(args.warmup):
+            sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        steps = []
+        for k in range(args.steps):
+            steps.append(sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4,
+                                  seed=200 + k))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        p99s = [s["p99"] for s in steps]
+        log(f"timed steps at {peak / 1e6:.3f} Mq/s: p99 {p99s}")
+        if all(s["ok"] for s in steps):
+            break
+        peak *= 0.97
 
     # 5: CUs at 20% load
     lam20 = 0.2 * peak_base
@@ -351,6 +425,20 @@ def main():
         r20 = sp.trial(m["cu"], lam20, args.trial_s, cm.HANDOFF_DEVICE, m["batch"], QOS_NS // 4, seed=300)
         p99_20 = r20["p99"]
         log(f"20% load {lam20 / 1e6:.3f} Mq/s: allocation {m} p99 {p99_20 / 1e3:.0f} us")
+
+    # 5b: contention-aware (learned) allocation, measured the same way
+    learned = None
+    if not args.skip_learned:
+        la, lpred, linfo = learned_allocation(cm, G, torch, sp, lat, prob)
+        if la is not None:
+            lbest = sp.peak_search(la["cu"], cm.HANDOFF_DEVICE, la["batch"], la["thr_num"] / la["thr_den"],
+                                   args.trial_s, args.search_iters, "learned")
+            lpeak = lbest[0] if lbest else 0.0
+            learned = {"allocation_cus": la["cu"], "batch": la["batch"], "predicted_qps": la["thr_num"] / la["thr_den"],
+                       "predicted_stage_ns": lpred, "measured_peak_qps": lpeak,
+                       "ratio_vs_table_allocation": lpeak / peak if peak else None, **linfo}
+            log(f"learned allocation {la['cu']} b={la['batch']}: measured peak {lpeak / 1e6:.3f} Mq/s "
+                f"({learned['ratio_vs_table_allocation']:.3f} of the table allocation's)")
 
     # 6: handoff GB/s
     slot = 64 << 20
@@ -375,6 +463,7 @@ def main():
                    "allocation_cus": a["cu"], "ingest": "device replay of Poisson arrivals, payloads in HBM",
                    "handoff": "device-global ring + doorbells", "qos_ns": QOS_NS},
         "timed_steps_p99_ns": p99s, "timed_steps_qos_met": all(s["ok"] for s in steps),
+        "timed_step_per_batch": steps[0].get("stage"),
         "predicted_qps": pred, "alloc_ms": alloc_ms, "profile_failures": sp.failures,
         "baseline": {"kind": "even split 88/88/80 CUs, host-staged handoff", "peak_qps": peak_base,
                      "predicted_qps": pred_even},
@@ -383,6 +472,7 @@ def main():
                               "p99_ns": p99_20},
         "handoff": {"gbs": h["gbs"], "frac_of_hbm_peak": h["gbs"] * 1e9 / HBM_PEAK, "checksum_ok": handoff_ok,
                     "ring_bytes": slot * 16, "host_staged_gbs": hh["gbs"]},
+        "learned_allocator": learned,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -317,6 +317,12 @@ typedef struct {
                                                     leaving stage i (mod 2^64)      */
   uint64_t id_xor[CAMELOT_MAX_STAGES];           /* xor of the same                 */
   int32_t worker_status[CAMELOT_MAX_STAGES];     /* 0 running/ok, else error code   */
+  uint64_t rows[CAMELOT_MAX_STAGES];             /* rows finished per stage         */
+  int64_t busy_ns[CAMELOT_MAX_STAGES];           /* sum over batches of the time from
+                                                    batch start (input and output
+                                                    slots held) to publish          */
+  int64_t wait_ns[CAMELOT_MAX_STAGES];           /* sum of the waits for input and
+                                                    output space before each batch  */
 } camelot_pipeline_stats;
 
 int32_t camelot_pipeline_stats_get(camelot_pipeline* p, camelot_pipeline_stats* out);

@@ -91,7 +91,9 @@ class PipelineStats(C.Structure):
     _fields_ = [("submitted_requests", C.c_uint64), ("submitted_rows", C.c_uint64),
                 ("delivered_rows", C.c_uint64), ("batches", C.c_uint64 * MAX_STAGES),
                 ("id_sum", C.c_uint64 * MAX_STAGES), ("id_xor", C.c_uint64 * MAX_STAGES),
-                ("worker_status", C.c_int32 * MAX_STAGES)]
+                ("worker_status", C.c_int32 * MAX_STAGES),
+                ("rows", C.c_uint64 * MAX_STAGES), ("busy_ns", C.c_int64 * MAX_STAGES),
+                ("wait_ns", C.c_int64 * MAX_STAGES)]
 
 
 class CorunRecord(C.Structure):

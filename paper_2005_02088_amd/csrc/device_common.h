@@ -16,6 +16,7 @@ constexpr int kWaves = kThreads / 64;
 // each engine has in the mask, so a CU can receive up to twice the average; every
 // stage kernel fits at least 2 workgroups per CU, which keeps the grid co-resident.
 constexpr int kWgPerCu = 1;
+constexpr int kMinWgPerCuResident = 2;  // residency a worker kernel must allow (dispatch slack)
 constexpr int kMaxBatch = CAMELOT_MAX_BATCH;
 constexpr int kMaxStages = CAMELOT_MAX_STAGES;
 constexpr int kSlotHeaderBytes = 4096;
@@ -80,6 +81,9 @@ struct DevPub {
   uint64_t batches[kMaxStages];
   uint64_t id_sum[kMaxStages];
   uint64_t id_xor[kMaxStages];
+  uint64_t rows[kMaxStages];                // rows finished per stage
+  uint64_t busy_ticks[kMaxStages];          // sum over batches of (publish - batch start)
+  uint64_t wait_ticks[kMaxStages];          // sum of the waits for input and output space
   int32_t status[kMaxStages];
   int32_t started[kMaxStages];
   uint64_t pad[16];
@@ -120,6 +124,8 @@ struct WorkerCtl {
   uint64_t reps_bench;            // bench mode: batches run
   uint32_t bench_stop[2];         // bench mode: workgroup 0's decision to stop, by rep parity
   uint64_t sum_acc, xor_acc, batches_acc;
+  uint64_t rows_acc, busy_acc, wait_acc;
+  alignas(128) uint32_t go[32];   // workgroup 0's batch broadcast: seq + 1 (own 128-byte line)
 };
 
 // Stage parameters (device pointers borrowed from the caller or owned by the
@@ -250,22 +256,28 @@ __device__ __forceinline__ void wg_barrier_stores_done() {
   __syncthreads();
 }
 
+// The barrier in two halves: arrive publishes this workgroup's writes and counts
+// it in; wait returns once every workgroup has arrived. Work that reads nothing
+// the other workgroups write (loading constant weights) may run in between.
 // sys_release: publish the workgroup's writes at system scope (results written to
 // pinned host memory, or slots a DMA copy reads) instead of agent scope.
-__device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64_t spin_ticks,
-                                             bool sys_release = false) {
-  __shared__ int s_ok;
+struct BarTicket {
+  uint32_t gen;    // generation word seen at arrival (thread 0)
+  bool wait;       // false for the workgroup that released the barrier
+};
+
+__device__ __forceinline__ BarTicket grid_arrive(WorkerCtl* ctl, uint32_t nwg, bool sys_release = false) {
+  BarTicket t{0u, false};
   wg_barrier_stores_done();
   if (threadIdx.x == 0) {
-    int ok = 1;
     const uint32_t g = blockIdx.x & 7u;
     const uint32_t ngroups = nwg < 8u ? nwg : 8u;
     const uint32_t members = (nwg - g + 7u) >> 3;
     uint32_t* genp = &ctl->bar_gen[g][0];
     if (sys_release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
     else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t gen = __hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool wait = true;
+    t.gen = __hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t.wait = true;
     const uint32_t prev = __hip_atomic_fetch_add(&ctl->bar_group[g][0], 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     if (prev == members - 1) {
@@ -276,14 +288,24 @@ __device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64
         __hip_atomic_store(&ctl->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
         for (uint32_t q = 0; q < ngroups; ++q)
-          __hip_atomic_store(&ctl->bar_gen[q][0], gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wait = false;
+          __hip_atomic_store(&ctl->bar_gen[q][0], t.gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t.wait = false;
       }
     }
-    if (wait) {
+  }
+  return t;
+}
+
+__device__ __forceinline__ bool grid_wait(WorkerCtl* ctl, uint32_t nwg, BarTicket t, int64_t spin_ticks) {
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint32_t g = blockIdx.x & 7u;
+    uint32_t* genp = &ctl->bar_gen[g][0];
+    if (t.wait) {
       const uint64_t t0 = now_ticks();
       uint32_t polls = 0;
-      while (__hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t.gen) {
         if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
         if ((int64_t)(now_ticks() - t0) > spin_ticks) {
           // record who was missing: arrivals on this group and on the top counter
@@ -305,6 +327,11 @@ __device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64
   }
   __syncthreads();
   return s_ok != 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64_t spin_ticks,
+                                             bool sys_release = false) {
+  return grid_wait(ctl, nwg, grid_arrive(ctl, nwg, sys_release), spin_ticks);
 }
 
 // Intra-wave LDS hand-off: orders this wave's LDS writes before its later reads

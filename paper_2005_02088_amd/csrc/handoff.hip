@@ -17,6 +17,14 @@ __device__ __forceinline__ uint32_t pattern(uint64_t s, uint32_t w) {
   return ((uint32_t)s * 0x9E3779B1u) ^ w;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kUnroll = 8;
+constexpr int64_t kStep = (int64_t)kThreads * 16;
+
+__device__ __forceinline__ u32x4 pattern4(uint64_t s, uint32_t w) {
+  return (u32x4){pattern(s, w), pattern(s, w + 1), pattern(s, w + 2), pattern(s, w + 3)};
+}
+
 __device__ __forceinline__ bool wait_eq(const uint32_t* p, uint32_t want, int64_t spin_ticks, uint64_t* err) {
   const uint64_t t0 = now_ticks();
   while (__hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
@@ -31,7 +39,7 @@ __device__ __forceinline__ bool wait_eq(const uint32_t* p, uint32_t want, int64_
   return true;
 }
 
-extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_producer(HandoffArgs a) {
+extern "C" __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void camelot_handoff_producer(HandoffArgs a) {
   __shared__ int s_ok;
   const int j = blockIdx.x, nwg = gridDim.x, tid = threadIdx.x;
   const int64_t lo = (int64_t)j * a.chunk_bytes;
@@ -43,23 +51,24 @@ extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_producer(
     if (tid == 0) s_ok = wait_eq(&a.freed[(int64_t)d * nwg + j], lap, a.spin_ticks, &a.result[4]);
     __syncthreads();
     if (!s_ok) return;
-    uint4* base = (uint4*)(a.ring + (int64_t)d * a.slot_bytes);
-    for (int64_t o = lo + (int64_t)tid * 16; o < hi; o += (int64_t)kThreads * 16) {
-      const uint32_t w = (uint32_t)(o >> 2);
-      uint4 v;
-      v.x = pattern(s, w);
-      v.y = pattern(s, w + 1);
-      v.z = pattern(s, w + 2);
-      v.w = pattern(s, w + 3);
-      base[o >> 4] = v;
+    u32x4* base = (u32x4*)(a.ring + (int64_t)d * a.slot_bytes);
+    int64_t o = lo + (int64_t)tid * 16;
+    // kUnroll independent 16-byte stores per thread per step (streaming, non-temporal)
+    for (; o + (kUnroll - 1) * kStep < hi; o += kUnroll * kStep) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t ou = o + u * kStep;
+        __builtin_nontemporal_store(pattern4(s, (uint32_t)(ou >> 2)), base + (ou >> 4));
+      }
     }
+    for (; o < hi; o += kStep) __builtin_nontemporal_store(pattern4(s, (uint32_t)(o >> 2)), base + (o >> 4));
     wg_barrier_stores_done();
     if (tid == 0) st_release_agent(&a.full[(int64_t)d * nwg + j], lap + 1);
   }
   if (tid == 0) atomicMax((unsigned long long*)&a.result[3], (unsigned long long)now_ticks());
 }
 
-extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_consumer(HandoffArgs a) {
+extern "C" __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void camelot_handoff_consumer(HandoffArgs a) {
   __shared__ int s_ok;
   __shared__ uint64_t s_sum[kWaves], s_xor[kWaves];
   const int j = blockIdx.x, nwg = gridDim.x, tid = threadIdx.x;
@@ -73,9 +82,21 @@ extern "C" __global__ __launch_bounds__(kThreads) void camelot_handoff_consumer(
     if (tid == 0) s_ok = wait_eq(&a.full[(int64_t)d * nwg + j], lap + 1, a.spin_ticks, &a.result[4]);
     __syncthreads();
     if (!s_ok) return;
-    const uint4* base = (const uint4*)(a.ring + (int64_t)d * a.slot_bytes);
-    for (int64_t o = lo + (int64_t)tid * 16; o < hi; o += (int64_t)kThreads * 16) {
-      const uint4 v = base[o >> 4];
+    const u32x4* base = (const u32x4*)(a.ring + (int64_t)d * a.slot_bytes);
+    int64_t o = lo + (int64_t)tid * 16;
+    // kUnroll independent 16-byte loads in flight per thread
+    for (; o + (kUnroll - 1) * kStep < hi; o += kUnroll * kStep) {
+      u32x4 v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(base + ((o + u * kStep) >> 4));
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        sum += (uint64_t)v[u].x + v[u].y + v[u].z + v[u].w;
+        xr ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+      }
+    }
+    for (; o < hi; o += kStep) {
+      const u32x4 v = __builtin_nontemporal_load(base + (o >> 4));
       sum += (uint64_t)v.x + v.y + v.z + v.w;
       xr ^= v.x ^ v.y ^ v.z ^ v.w;
     }

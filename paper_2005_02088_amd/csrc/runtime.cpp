@@ -344,6 +344,15 @@ int32_t check_share(int n_cus, int offset, int total) {
 int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
   const void* fn = worker_kernel(kind, a.in_kind == kInBench);
   if (!fn) return fail(CAMELOT_EINVAL, "no worker for stage kind %d", kind);
+  // One workgroup per CU is launched, but the dispatcher may place two on one CU of
+  // the share (it balances workgroups over shader engines, not over the masked
+  // CUs): a kernel that fits only once per CU could leave a workgroup unplaced and
+  // its grid barriers could never complete. Refuse such a kernel instead.
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0));
+  if (per_cu < kMinWgPerCuResident)
+    return fail(CAMELOT_EDEVICE, "stage kind %d: only %d workgroup(s) fit on a CU, %d needed", kind, per_cu,
+                kMinWgPerCuResident);
   void* args[] = {(void*)&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(kWgPerCu * n_cus), dim3(kThreads), args, 0, s));
   return CAMELOT_OK;
@@ -1003,6 +1012,9 @@ extern "C" int32_t camelot_pipeline_stats_get(camelot_pipeline* p, camelot_pipel
     out->id_sum[i] = __atomic_load_n(&p->pub->id_sum[i], __ATOMIC_ACQUIRE);
     out->id_xor[i] = __atomic_load_n(&p->pub->id_xor[i], __ATOMIC_ACQUIRE);
     out->worker_status[i] = __atomic_load_n(&p->pub->status[i], __ATOMIC_ACQUIRE);
+    out->rows[i] = __atomic_load_n(&p->pub->rows[i], __ATOMIC_ACQUIRE);
+    out->busy_ns[i] = ticks_to_ns((int64_t)__atomic_load_n(&p->pub->busy_ticks[i], __ATOMIC_ACQUIRE), p->dev.wclk_hz);
+    out->wait_ns[i] = ticks_to_ns((int64_t)__atomic_load_n(&p->pub->wait_ticks[i], __ATOMIC_ACQUIRE), p->dev.wclk_hz);
   }
   return CAMELOT_OK;
 }

@@ -161,10 +161,18 @@ __device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, int rows) 
 }
 
 // ------------------------------------------------------------------ top-k
-// One wave per row. Each lane keeps its strided slice (element lane + 64 t) in
-// registers; k rounds of a wave-wide arg-max (ties to the smaller index) pick the
-// results in order.
+// One wave per row; each lane reads its strided slice (element lane + 64 t), a few
+// passes over a row that stays in cache. Order: larger value first, ties to the
+// smaller index.
+//
+// Candidate filter: the k-th largest of the 64 lane maxima is a lower bound tau of
+// the row's k-th largest value (those k maxima are k distinct elements), so every
+// top-k element is >= tau. The elements >= tau (at least k) are compacted into LDS
+// and each one's rank among them is counted directly; ranks below k are the
+// result. When k > 64, or when more than kTopkCand elements pass the filter (heavy
+// ties), k rounds of a wave-wide arg-max give the same result.
 constexpr int kTopkMaxN = 4096;
+constexpr int kTopkCand = 256;
 
 __device__ __forceinline__ bool topk_better(float v1, int i1, float v2, int i2) {
   if (i2 < 0) return i1 >= 0;
@@ -172,33 +180,101 @@ __device__ __forceinline__ bool topk_better(float v1, int i1, float v2, int i2) 
   return v1 > v2 || (v1 == v2 && i1 < i2);
 }
 
+// k rounds of a wave-wide arg-max over the lane slices (values re-read from the
+// row, which stays in cache; removed elements are tracked per lane in a bit mask).
+__device__ __forceinline__ void topk_rounds(const float* s, int N, int k, int lane, int32_t* out_idx,
+                                            float* out_val) {
+  uint64_t removed = 0;
+  for (int j = 0; j < k; ++j) {
+    float bv = 0.f;
+    int bi = -1;
+    for (int t = 0; t < kTopkMaxN / 64; ++t) {
+      const int i = lane + 64 * t;
+      if (i >= N) break;
+      const float v = s[i];
+      if (!((removed >> t) & 1ull) && (bi < 0 || v > bv)) { bv = v; bi = i; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (topk_better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+    }
+    if (bi >= 0 && (bi & 63) == lane) removed |= 1ull << (bi >> 6);
+    if (lane == 0) { out_idx[j] = bi; out_val[j] = bv; }
+  }
+}
+
 __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
   __shared__ int32_t s_idx[kWaves][CAMELOT_MAX_K];
   __shared__ float s_val[kWaves][CAMELOT_MAX_K];
+  __shared__ float c_val[kWaves][kTopkCand];
+  __shared__ int32_t c_idx[kWaves][kTopkCand];
+  __shared__ float m_val[kWaves][64];
+  __shared__ float s_tau[kWaves];
   const int N = a.sp.dims[0], k = a.sp.k;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nt = (N - lane + 63) >> 6;         // elements in this lane's slice
+  const bool filter = k <= 64 && min(N, 64) >= k;
   for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
     const float* s = (const float*)ctl->d_rowptr[r];
-    float v[kTopkMaxN / 64];
+    // threshold tau (all elements are candidates without the filter)
+    float tau = -__builtin_inff();
+    if (filter) {
+      float m = -__builtin_inff();
+#pragma unroll 8
+      for (int t = 0; t < nt; ++t) {
+        const float v = s[lane + 64 * t];
+        m = v > m ? v : m;
+      }
+      m_val[w][lane] = m;
+      wave_lds_sync();
+      int rank = 0;
+      for (int j = 0; j < 64; ++j) {
+        const float o = m_val[w][j];
+        rank += (o > m || (o == m && j < lane)) ? 1 : 0;
+      }
+      if (rank == k - 1) s_tau[w] = m;
+      wave_lds_sync();
+      tau = s_tau[w];
+    }
+    int cnt = nt;
+    if (filter) {
+      cnt = 0;
+#pragma unroll 8
+      for (int t = 0; t < nt; ++t) cnt += s[lane + 64 * t] >= tau ? 1 : 0;
+    }
+    int incl = cnt;
 #pragma unroll
-    for (int t = 0; t < kTopkMaxN / 64; ++t) v[t] = (lane + 64 * t < N) ? s[lane + 64 * t] : 0.f;
-    uint64_t removed = 0;
-    for (int j = 0; j < k; ++j) {
-      float bv = 0.f;
-      int bi = -1;
-#pragma unroll
-      for (int t = 0; t < kTopkMaxN / 64; ++t) {
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    const int C = __shfl(incl, 63, 64);
+    if (C <= kTopkCand) {
+      int pos = incl - cnt;
+      for (int t = 0; t < nt; ++t) {
         const int i = lane + 64 * t;
-        if (i < N && !((removed >> t) & 1ull) && (bi < 0 || v[t] > bv)) { bv = v[t]; bi = i; }
+        const float v = s[i];
+        if (!filter || v >= tau) {
+          c_val[w][pos] = v;
+          c_idx[w][pos] = i;
+          ++pos;
+        }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const float ov = __shfl_xor(bv, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (topk_better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+      wave_lds_sync();
+      for (int c = lane; c < C; c += 64) {
+        const float vc = c_val[w][c];
+        const int ic = c_idx[w][c];
+        int rank = 0;
+        for (int j = 0; j < C; ++j) {
+          const float o = c_val[w][j];
+          rank += (o > vc || (o == vc && c_idx[w][j] < ic)) ? 1 : 0;
+        }
+        if (rank < k) { s_idx[w][rank] = ic; s_val[w][rank] = vc; }
       }
-      if (bi >= 0 && (bi & 63) == lane) removed |= 1ull << (bi >> 6);
-      if (lane == 0) { s_idx[w][j] = bi; s_val[w][j] = bv; }
+    } else {
+      topk_rounds(s, N, k, lane, s_idx[w], s_val[w]);
     }
     wave_lds_sync();
     emit_row(a, ctl, rows, r, k, s_idx[w], s_val[w], lane);
@@ -315,56 +391,97 @@ __device__ __forceinline__ bf16x8 ld_f32x8_as_bf16(const float* p) {
   return r;
 }
 
-constexpr int kMlpChunksPerWave = 16;   // K chunks of 32 a wave keeps in flight per segment
-constexpr int kMlpSegK = kMlpChunksPerWave * kWaves * 32;   // K covered per segment (2048)
+constexpr int kMlpChunksPerWave = 8;    // K chunks of 32 a wave keeps in flight per segment
+constexpr int kMlpSegK = kMlpChunksPerWave * kWaves * 32;   // K covered per segment (1024)
 
+// Weight fragments of one segment of a strip: wave w owns chunks seg/32 + w + 4 i.
+__device__ __forceinline__ void mlp_load_w(bf16x8 (&bq)[kMlpChunksPerWave], const uint16_t* W, int K, int strip,
+                                           int seg, int w, int lane) {
+  const uint16_t* wrow = W + (int64_t)(strip * 16 + (lane & 15)) * K;
+  const int krow = (lane >> 4) * 8;
+#pragma unroll
+  for (int i = 0; i < kMlpChunksPerWave; ++i) {
+    const int kb = seg + (w + kWaves * i) * 32 + krow;
+    bq[i] = kb < K ? ld_bf16x8(wrow + kb) : (bf16x8){};
+  }
+}
+
+// Activation fragments of row block rb for the same chunks (layer 0 reads the FP32
+// input rows and rounds them to BF16; later layers read the BF16 hidden state).
+__device__ __forceinline__ void mlp_load_a(bf16x8 (&aq)[kMlpChunksPerWave], const uint8_t* const* rowptr,
+                                           const uint16_t* hin, int stride, bool first, int K, int rows, int rb,
+                                           int seg, int w, int lane) {
+  const int row = rb * 16 + (lane & 15);
+  const bool rin = row < rows;
+  const int krow = (lane >> 4) * 8;
+  if (first) {
+    const float* xrow = rin ? (const float*)rowptr[row] : nullptr;
+#pragma unroll
+    for (int i = 0; i < kMlpChunksPerWave; ++i) {
+      const int kb = seg + (w + kWaves * i) * 32 + krow;
+      aq[i] = (rin && kb < K) ? ld_f32x8_as_bf16(xrow + kb) : (bf16x8){};
+    }
+  } else {
+    const uint16_t* hrow = hin + (int64_t)row * stride;
+#pragma unroll
+    for (int i = 0; i < kMlpChunksPerWave; ++i) {
+      const int kb = seg + (w + kWaves * i) * 32 + krow;
+      aq[i] = (rin && kb < K) ? ld_bf16x8(hrow + kb) : (bf16x8){};
+    }
+  }
+}
+
+__device__ __forceinline__ void mlp_mfma(f32x4& acc, const bf16x8 (&aq)[kMlpChunksPerWave],
+                                         const bf16x8 (&bq)[kMlpChunksPerWave], int K, int seg, int w) {
+#pragma unroll
+  for (int i = 0; i < kMlpChunksPerWave; ++i)
+    if (seg + (w + kWaves * i) * 32 < K) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[i], bq[i], acc, 0, 0, 0);
+}
+
+// Per layer and strip the order of every sum is fixed: each wave adds its chunks in
+// increasing K order on the matrix cores, then the 4 wave partials are added in LDS
+// as ((p0 + p1) + p2) + p3. Row blocks are software-pipelined (the next block's
+// activation loads are in flight while the current block's MFMAs run), and the
+// next layer's first weight segment is loaded while the workgroup waits at the
+// layer barrier (weights are constant; only the activations need the barrier).
 __device__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
   __shared__ float part[kWaves][8][256];
   const int L = a.sp.n_layers;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int nrb = (rows + 15) >> 4;
   const int stride = a.sp.scratch_stride;
-  const int krow = (lane >> 4) * 8;          // this lane's 8-element K offset within a chunk
+  const uint8_t* const* rowptr = ctl->d_rowptr;
+  bf16x8 bq[kMlpChunksPerWave];
+  bool pref = false;                         // bq holds this layer's first segment already
   for (int l = 0; l < L; ++l) {
     const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
     const uint16_t* W = (const uint16_t*)a.sp.w[l];
     const uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
     uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
     const bool last = (l == L - 1);
+    const bool first = (l == 0);
     const int nstrips = N >> 4;
     for (int strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
       f32x4 acc[8];
 #pragma unroll
       for (int rb = 0; rb < 8; ++rb) acc[rb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      const uint16_t* wrow = W + (int64_t)(strip * 16 + (lane & 15)) * K;
-      // K in segments: wave w owns chunks seg/32 + w + 4 i, i < 16
       for (int seg = 0; seg < K; seg += kMlpSegK) {
-        // weight fragments of the whole segment first: 16 independent loads in flight
-        bf16x8 bq[kMlpChunksPerWave];
+        if (!(pref && seg == 0)) mlp_load_w(bq, W, K, strip, seg, w, lane);
+        bf16x8 a0[kMlpChunksPerWave], a1[kMlpChunksPerWave];
+        if (nrb > 0) mlp_load_a(a0, rowptr, hin, stride, first, K, rows, 0, seg, w, lane);
 #pragma unroll
-        for (int i = 0; i < kMlpChunksPerWave; ++i) {
-          const int kb = seg + (w + kWaves * i) * 32 + krow;
-          bq[i] = kb < K ? ld_bf16x8(wrow + kb) : (bf16x8){};
-        }
-#pragma unroll
-        for (int rb = 0; rb < 8; ++rb) {
+        for (int rb = 0; rb < 8; rb += 2) {
           if (rb < nrb) {
-            const int row = rb * 16 + (lane & 15);
-            const bool rin = row < rows;
-            const uint16_t* hrow = hin + (int64_t)row * stride;
-            const float* xrow = rin && l == 0 ? (const float*)ctl->d_rowptr[row] : nullptr;
-#pragma unroll
-            for (int i = 0; i < kMlpChunksPerWave; ++i) {
-              const int kb = seg + (w + kWaves * i) * 32 + krow;
-              if (seg + (w + kWaves * i) * 32 < K) {
-                bf16x8 af = (bf16x8){};
-                if (rin && kb < K) af = (l == 0) ? ld_f32x8_as_bf16(xrow + kb) : ld_bf16x8(hrow + kb);
-                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bq[i], acc[rb], 0, 0, 0);
-              }
+            if (rb + 1 < nrb) mlp_load_a(a1, rowptr, hin, stride, first, K, rows, rb + 1, seg, w, lane);
+            mlp_mfma(acc[rb], a0, bq, K, seg, w);
+            if (rb + 1 < nrb) {
+              if (rb + 2 < nrb) mlp_load_a(a0, rowptr, hin, stride, first, K, rows, rb + 2, seg, w, lane);
+              mlp_mfma(acc[rb + 1], a1, bq, K, seg, w);
             }
           }
         }
       }
+      pref = false;
 #pragma unroll
       for (int rb = 0; rb < 8; ++rb) {
         if (rb < nrb) {
@@ -383,7 +500,13 @@ __device__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t*
       }
       __syncthreads();
     }
-    if (!last && !grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
+    if (!last) {
+      const BarTicket t = grid_arrive(ctl, gridDim.x);
+      const int nnext = a.sp.dims[l + 2];
+      pref = (int)blockIdx.x < (nnext >> 4);
+      if (pref) mlp_load_w(bq, (const uint16_t*)a.sp.w[l + 1], N, blockIdx.x, 0, w, lane);
+      if (!grid_wait(ctl, gridDim.x, t, a.spin_ticks)) return false;
+    }
   }
   return true;
 }
@@ -712,7 +835,7 @@ __device__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq,
 // same grid and the same code as the persistent worker (used for parity checks
 // and for the solo profiling table).
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void stage_bench(WorkerArgs a) {
+__global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_bench(WorkerArgs a) {
   WorkerCtl* ctl = a.ctl;
   const int tid = threadIdx.x;
   if (blockIdx.x == 0)
@@ -741,8 +864,33 @@ __global__ __launch_bounds__(kThreads) void stage_bench(WorkerArgs a) {
 }
 
 // ------------------------------------------------------------------ worker kernel
+// Workgroups other than 0 wait here for workgroup 0's broadcast of batch `want`
+// (bounded; an abort raised anywhere ends the wait).
+__device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t spin_ticks) {
+  __shared__ int s_go;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint64_t t0 = now_ticks();
+    uint32_t polls = 0;
+    while (__hip_atomic_load(&ctl->go[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+      if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+      if ((int64_t)(now_ticks() - t0) > spin_ticks) {
+        __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      if (++polls < 256) __builtin_amdgcn_s_sleep(1);
+      else __builtin_amdgcn_s_sleep(32);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_go = ok;
+  }
+  __syncthreads();
+  return s_go != 0;
+}
+
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
+__global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(WorkerArgs a) {
   WorkerCtl* ctl = a.ctl;
   const int tid = threadIdx.x;
   const bool wg0 = blockIdx.x == 0;
@@ -767,6 +915,7 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
   uint64_t seq = ctl->next_seq;
   int exit_status = kStatusOk;
   for (;;) {
+    const uint64_t t_top = now_ticks();
     // ---------------- control: acquire the next batch (workgroup 0)
     if (wg0) {
       if (tid < 64) {
@@ -868,9 +1017,18 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
         }
       }
       if (tid == 0) ctl->d_stop = (uint32_t)st;
+      // broadcast: the batch descriptor (or the stop) is in place
+      wg_barrier_stores_done();
+      if (tid == 0) {
+        st_release_agent(&ctl->go[0], (uint32_t)(seq + 1));
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+    } else if (!wait_go(ctl, (uint32_t)(seq + 1), 2 * a.idle_ticks + a.spin_ticks)) {
+      // workgroup 0 may wait for input (up to the idle limit) and then for output space
+      exit_status = kStatusTimeout;
+      break;
     }
-    // workgroup 0 may wait for input (up to the idle limit) and then for output space
-    if (!grid_barrier(ctl, gridDim.x, 2 * a.idle_ticks + a.spin_ticks)) { exit_status = kStatusTimeout; break; }
     // a host-staged input slot was written by a DMA copy: acquire at system scope
     if (a.in_state_sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     const uint32_t stop = ctl->d_stop;
@@ -878,9 +1036,12 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
     const int rows = (int)ctl->d_rows;
     if (!exec_stage<KIND>(a, ctl, rows, ctl->d_out)) { exit_status = kStatusTimeout; break; }
     copy_side(a, ctl, rows);
-    // results go to pinned host memory, a host-staged output slot is read by DMA:
-    // those are published at system scope
-    if (!grid_barrier(ctl, gridDim.x, a.spin_ticks, a.out_kind == kOutEgress || a.out_state_sys != 0)) {
+    // batch done: every workgroup arrives, only workgroup 0 waits (it publishes and
+    // then forms the next batch; the others go on to wait for its broadcast).
+    // Results go to pinned host memory, a host-staged output slot is read by DMA:
+    // those are published at system scope.
+    const BarTicket done = grid_arrive(ctl, gridDim.x, a.out_kind == kOutEgress || a.out_state_sys != 0);
+    if (wg0 && !grid_wait(ctl, gridDim.x, done, a.spin_ticks)) {
       exit_status = kStatusTimeout;
       break;
     }
@@ -912,8 +1073,14 @@ __global__ __launch_bounds__(kThreads) void stage_worker(WorkerArgs a) {
       ctl->sum_acc += hs;
       ctl->xor_acc ^= hx;
       ctl->batches_acc += 1;
+      ctl->rows_acc += (uint64_t)rows;
+      ctl->busy_acc += t_end - ctl->d_t_start;
+      ctl->wait_acc += ctl->d_t_start - t_top;
       st_relaxed_sys(&a.pub->id_sum[si], ctl->sum_acc);
       st_relaxed_sys(&a.pub->id_xor[si], ctl->xor_acc);
+      st_relaxed_sys(&a.pub->rows[si], ctl->rows_acc);
+      st_relaxed_sys(&a.pub->busy_ticks[si], ctl->busy_acc);
+      st_relaxed_sys(&a.pub->wait_ticks[si], ctl->wait_acc);
       st_relaxed_sys(&a.pub->batches[si], ctl->batches_acc);
     }
     ++seq;

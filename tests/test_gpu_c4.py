@@ -1,0 +1,164 @@
+"""Image-retrieval stages on the GPU vs the FP64 oracle: 3x3 convolution + ReLU +
+global mean pool on matrix cores, gather + score against an FP16 table, and the
+four-stage pipeline conv+pool -> BF16 MLP -> gather+score -> top-100 whose item ids
+ride with each query in the slot side plane.
+
+Tolerances (normwise): 1e-5 for the convolution (BF16 products are exact in FP32,
+only the FP32 summation order differs) and for gather+score (FP32 dots of FP16 rows);
+2e-2 end to end (the MLP rounds activations to BF16)."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import delivery as OD
+from oracle import stages as O
+import workload_gen as G
+from tests.gpu_util import log, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TABLE_ROWS = 1 << 20
+N_IDS = 32
+HEADS = 8
+DIM = 128
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_cuda()
+
+
+@pytest.fixture(scope="module")
+def cm():
+    from paper_2005_02088_amd import camelot
+    return camelot
+
+
+def _conv_desc(cm, wdev, h=G.C4_H, w=G.C4_W):
+    return cm.stage_desc(cm.STAGE_CONV_POOL, dims=(h, w, 64, 64), weights=(wdev.data_ptr(),), n_layers=0)
+
+
+def _run_conv(torch, cm, x, wc, rows, n_cus, h, w):
+    dw = to_dev(torch, wc.view(np.int16))
+    dx = to_dev(torch, x.view(np.int16))
+    dy = torch.full((rows, 64), float("nan"), device="cuda")
+    torch.cuda.synchronize()
+    cm.camelot_stage_run(_conv_desc(cm, dw, h, w), dx.data_ptr(), dy.data_ptr(), rows, n_cus, 0)
+    return dy.cpu().numpy()
+
+
+@pytest.mark.parametrize("rows", [1, 3])
+def test_conv_pool_parity(torch, cm, rows):
+    x = G.c4_feature_maps(rows, seed=rows)
+    wc = G.c4_conv_weights(0)
+    log(f"conv_pool rows={rows} 56x56x64")
+    y = _run_conv(torch, cm, x, wc, rows, 64, G.C4_H, G.C4_W)
+    err = O.normwise_err(y, O.conv3x3_relu_pool(x, wc))
+    log(f"  err={err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("hw", [(7, 9), (9, 15), (1, 1)])
+def test_conv_pool_ragged_tiles(torch, cm, hw):
+    h, w = hw
+    x = G.c4_feature_maps(5, seed=h * 100 + w, h=h, w=w)
+    wc = G.c4_conv_weights(1)
+    log(f"conv_pool ragged {h}x{w} (pixels {h * w}, tiles of 64)")
+    y = _run_conv(torch, cm, x, wc, 5, 16, h, w)
+    err = O.normwise_err(y, O.conv3x3_relu_pool(x, wc))
+    log(f"  err={err:.3e}")
+    assert err <= 1e-5
+
+
+def test_conv_pool_grid_and_batch_invariant(torch, cm):
+    x = G.c4_feature_maps(4, seed=77)
+    wc = G.c4_conv_weights(0)
+    log("conv_pool invariance: 8 vs 256 CUs, row alone vs in a batch")
+    a = _run_conv(torch, cm, x, wc, 4, 8, G.C4_H, G.C4_W)
+    b = _run_conv(torch, cm, x, wc, 4, 256, G.C4_H, G.C4_W)
+    c = _run_conv(torch, cm, x[2:3], wc, 1, 32, G.C4_H, G.C4_W)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a[2], c[0])
+
+
+def test_gather_score_parity_and_out_of_range_ids(torch, cm):
+    rows, trows = 7, 4096
+    table = G.fp16_table(trows, DIM, seed=3)
+    g = G.rng("c4", 3, 20)
+    q = g.standard_normal((rows, HEADS * DIM), dtype=np.float32)
+    ids = g.integers(0, trows, (rows, N_IDS)).astype(np.int32)
+    ids[0, 0], ids[1, 5], ids[2, 31] = -1, trows, 2 ** 31 - 1       # outside the table: score 0
+    buf = np.concatenate([q.view(np.uint8).reshape(rows, -1), ids.view(np.uint8).reshape(rows, -1)], axis=1)
+    dt = to_dev(torch, table.view(np.int16))
+    desc = cm.stage_desc(cm.STAGE_GATHER_SCORE, dims=(HEADS * DIM, DIM, N_IDS), weights=(dt.data_ptr(),), k=trows)
+    din = to_dev(torch, buf)
+    dy = torch.full((rows, HEADS * N_IDS), float("nan"), device="cuda")
+    torch.cuda.synchronize()
+    log("gather_score rows=7 heads=8 dim=128 ids=32")
+    cm.camelot_stage_run(desc, din.data_ptr(), dy.data_ptr(), rows, 16, 0)
+    y = dy.cpu().numpy()
+    ref = O.gather_score(q, ids, table, DIM)
+    err = O.normwise_err(y, ref)
+    log(f"  err={err:.3e}")
+    assert err <= 1e-5
+    assert y[0, 0] == 0 and y[1, 5] == 0 and y[2, 31] == 0
+    assert y[0, N_IDS] == 0                                            # same id, head 1
+
+
+@pytest.fixture(scope="module")
+def c4(torch, cm):
+    wc = G.c4_conv_weights(0)
+    wm = G.c1_mlp_weights(4, dims=G.C4_MLP_DIMS)
+    table = G.fp16_table(TABLE_ROWS, DIM, seed=4)
+    n = 24
+    x = G.c4_feature_maps(n, seed=9)
+    ids = G.zipf_ids(n, N_IDS, TABLE_ROWS, seed=9)
+    pool = np.concatenate([x.reshape(n, -1).view(np.uint8), ids.view(np.uint8)], axis=1)
+    d = dict(wc=to_dev(torch, wc.view(np.int16)), wm=[to_dev(torch, w.view(np.int16)) for w in wm],
+             table=to_dev(torch, table.view(np.int16)), pool=to_dev(torch, pool))
+    stages = (_conv_desc(cm, d["wc"]),
+              cm.stage_desc(cm.STAGE_MLP_BF16, dims=G.C4_MLP_DIMS, weights=[t.data_ptr() for t in d["wm"]]),
+              cm.stage_desc(cm.STAGE_GATHER_SCORE, dims=(HEADS * DIM, DIM, N_IDS), weights=(d["table"].data_ptr(),),
+                            k=TABLE_ROWS),
+              cm.stage_desc(cm.STAGE_TOPK, dims=(HEADS * N_IDS,), k=100, n_layers=0))
+    torch.cuda.synchronize()
+    return dict(stages=stages, dev=d, wc=wc, wm=wm, table=table, x=x, ids=ids, n=n)
+
+
+def test_c4_pipeline_replay(torch, cm, c4):
+    cfg = cm.pipeline_config(c4["stages"], (128, 64, 32, 32), max_batch=16, ring_depth=4, ingest=cm.INGEST_REPLAY,
+                             max_rows_per_request=4, side_bytes=4 * N_IDS, idle_timeout_ns=5_000_000_000)
+    rows = np.array([1, 3, 2, 4, 1, 1, 2, 3], np.int32)
+    prow = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)
+    ids = np.arange(1, len(rows) + 1, dtype=np.uint64)
+    arr = G.poisson_arrivals_ns(len(rows), 2000, seed=3)
+    log("c4 pipeline: conv+pool(128 CUs) -> mlp(64) -> gather+score(32) -> top-100(32), 8 requests, 17 rows")
+    p = cm.camelot_pipeline_create(cfg)
+    try:
+        cm.camelot_pipeline_replay(p, ids, rows, arr, prow, c4["dev"]["pool"].data_ptr(), c4["n"])
+        res = []
+        t_end = time.monotonic() + 30
+        while len(res) < int(rows.sum()) and time.monotonic() < t_end:
+            res += cm.camelot_pipeline_drain(p, 4096, 100_000_000)
+    finally:
+        undelivered = cm.camelot_pipeline_destroy(p)
+    assert undelivered == 0 and len(res) == int(rows.sum())
+    assert OD.check_delivery([int(i) for i in ids], list(dict.fromkeys(r.query_id for r in res))) == []
+    n = int(rows.sum())
+    conv = O.conv3x3_relu_pool(c4["x"][:n], c4["wc"])
+    q = O.mlp_bf16(conv, c4["wm"])
+    scores = O.gather_score(q, c4["ids"][:n], c4["table"], DIM)
+    ridx, rval = O.topk(scores, 100)
+    got = {(r.query_id, r.row): r for r in res}
+    gv = np.zeros((n, 100))
+    exact_idx = 0
+    for qi, (i0, nr) in enumerate(zip(prow, rows)):
+        for j in range(nr):
+            r = got[(int(ids[qi]), j)]
+            assert r.n_out == 100
+            gv[i0 + j] = r.val[:100]
+            exact_idx += int(list(r.idx[:100]) == list(ridx[i0 + j]))
+    err = O.normwise_err(gv, rval)
+    log(f"  top-100 values err={err:.3e}; rows with identical index lists {exact_idx}/{n}")
+    assert err <= 2e-2

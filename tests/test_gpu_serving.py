@@ -92,10 +92,11 @@ def test_admission_by_hbm_footprint(torch, cm, world):
         assert cm.camelot_server_admit(s, _cfg(cm, world, 2)) is None          # does not fit
         cm.camelot_server_release(s, p1)
         assert cm.camelot_server_admit(s, _cfg(cm, world, 2)) is not None      # fits once freed
-        # a second instance sharing pipeline 0's weights only adds its own rings
+        # a second instance sharing pipeline 0's weights only adds its own rings; it
+        # takes CUs 32..63, left free by pipeline 1 (pipeline 2 now holds 128..175)
         before = cm.camelot_server_used_bytes(s)
         cfg = _cfg(cm, world, 0)
-        cfg.cu_offset = 224
+        cfg.cu_offset = 32
         assert cm.camelot_server_admit(s, cfg) is not None
         assert cm.camelot_server_used_bytes(s) - before < 10e6
         with pytest.raises(cm.CamelotError):                                   # overlapping CUs

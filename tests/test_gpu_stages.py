@@ -84,13 +84,19 @@ def test_gemm_argmax_parity(torch, cm, rows):
 
 def test_topk_parity_with_ties(torch, cm):
     g = G.rng("handoff", 31)
-    for rows, n, k in ((1, 4096, 10), (13, 4096, 10), (64, 4096, 100), (5, 256, 100), (3, 100, 100)):
+    # the candidate filter (k <= 64), direct ranking (N <= 256) and the k-round path
+    # (k > 64 with N > 256, or rows of equal values: every element passes the filter)
+    for rows, n, k, zero in ((1, 4096, 10, False), (13, 4096, 10, False), (64, 4096, 100, False),
+                             (5, 256, 100, False), (3, 100, 100, False), (4, 37, 5, False),
+                             (2, 4096, 10, True), (2, 200, 64, True), (3, 4096, 64, False)):
         s = np.round(g.standard_normal((rows, n)), 2).astype(np.float32)   # many exact ties
+        if zero:
+            s[:] = 0.0
         ds = to_dev(torch, s)
         dout = torch.empty(2 * rows * k, dtype=torch.int32, device="cuda")
         desc = cm.stage_desc(cm.STAGE_TOPK, dims=(n,), k=k, n_layers=0)
         torch.cuda.synchronize()
-        log(f"topk rows={rows} n={n} k={k}")
+        log(f"topk rows={rows} n={n} k={k} zero={zero}")
         cm.camelot_stage_run(desc, ds.data_ptr(), dout.data_ptr(), rows, 16, 0)
         raw = dout.cpu().numpy()
         idx = raw[: rows * k].reshape(rows, k)
