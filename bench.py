@@ -224,7 +224,7 @@ class Speech:
         return best
 
 
-def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1500, epochs=300):
+def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=2500, epochs=150):
     """The contention-aware allocator: co-location profiles of the three stages at
     random shares and batches, the 16-64-64-1 predictor trained on them with the
     library's kernels (target: log slowdown over the solo profile), then Eq. 1 over

@@ -23,7 +23,9 @@ def to_dev(torch, a):
 
 
 def c0_stages(torch, seed=0):
-    """Device weights and stage descriptors of the two-stage FP32 pipeline."""
+    """Device weights and stage descriptors of the two-stage FP32 pipeline. The
+    descriptors hold raw pointers: the caller keeps the returned device tensors
+    alive for as long as it uses them."""
     import workload_gen as G
     from paper_2005_02088_amd import camelot as cm
     w1, w2 = G.c0_weights(seed)
@@ -40,7 +42,8 @@ def c1_weights(seed=0):
 
 
 def c1_stages(torch, seed=0, k=10):
-    """Device weights and stage descriptors of the speech-assistant pipeline."""
+    """Device weights and stage descriptors of the speech-assistant pipeline (keep
+    the returned device tensors alive while the descriptors are in use)."""
     import workload_gen as G
     from paper_2005_02088_amd import camelot as cm
     ws = c1_weights(seed)

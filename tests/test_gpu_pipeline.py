@@ -217,7 +217,7 @@ def test_backpressure_and_destroy_in_flight(torch, cm):
 
 
 def test_idle_timeout_stops_workers(torch, cm):
-    _, _, stages = c0_stages(torch)
+    _, dws, stages = c0_stages(torch)             # dws: keeps the device weights alive
     torch.cuda.synchronize()
     cfg = cm.pipeline_config(stages, (8, 8), idle_timeout_ns=200_000_000)
     p = cm.camelot_pipeline_create(cfg)
@@ -231,7 +231,7 @@ def test_idle_timeout_stops_workers(torch, cm):
 
 
 def test_create_rejects_bad_configs(torch, cm):
-    _, _, (sa, sb) = c0_stages(torch)
+    _, dws, (sa, sb) = c0_stages(torch)           # dws: keeps the device weights alive
     mel = cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0)
     bad = [
         cm.pipeline_config((sa, sb), (12, 8)),                 # share not a multiple of 8

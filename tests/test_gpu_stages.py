@@ -31,7 +31,7 @@ def test_device_query(torch, cm):
 
 @pytest.mark.parametrize("rows", [1, 7, 32, 128])
 def test_gemm_relu_parity(torch, cm, rows):
-    (w1, _), _, (sa, _) = c0_stages(torch)
+    (w1, _), dws, (sa, _) = c0_stages(torch)      # dws: keeps the device weights alive
     x = G.c0_queries(rows, seed=rows)
     dx = to_dev(torch, x)
     dy = torch.empty((rows, 512), dtype=torch.float32, device="cuda")
@@ -45,7 +45,7 @@ def test_gemm_relu_parity(torch, cm, rows):
 
 
 def test_gemm_relu_grid_and_batch_invariant(torch, cm):
-    (w1, _), _, (sa, _) = c0_stages(torch)
+    (w1, _), dws, (sa, _) = c0_stages(torch)      # dws: keeps the device weights alive
     x = G.c0_queries(32, seed=5)
     dx = to_dev(torch, x)
     outs = []
@@ -61,7 +61,7 @@ def test_gemm_relu_grid_and_batch_invariant(torch, cm):
 
 @pytest.mark.parametrize("rows", [1, 9, 64])
 def test_gemm_argmax_parity(torch, cm, rows):
-    (w1, w2), _, (sa, sb) = c0_stages(torch)
+    (w1, w2), dws, (sa, sb) = c0_stages(torch)    # dws: keeps the device weights alive
     x = G.c0_queries(rows, seed=100 + rows)
     dx = to_dev(torch, x)
     dy = torch.empty((rows, 512), dtype=torch.float32, device="cuda")
