@@ -357,6 +357,13 @@ int32_t camelot_server_destroy(camelot_server* s);
 /* Bytes of the weight buffers a stage reads (0 for stages without weights). */
 int64_t camelot_stage_weight_bytes(const camelot_stage_desc* stage);
 
+/* Resources of the kernel that runs a stage kind: one_shot != 0 for the kernel of
+ * camelot_stage_run, else the pipeline worker. *regs: registers per lane;
+ * *lds_bytes: static LDS per workgroup; *fits: 1 when two workgroups fit on a CU
+ * (what launching a worker requires), else 0. EINVAL for an unknown kind. */
+int32_t camelot_stage_kernel_info(int32_t kind, int32_t one_shot, int32_t* regs, int64_t* lds_bytes,
+                                  int32_t* fits);
+
 /* ------------------------------------------------------------------ handoff benchmark
  * Section IV-B's claim, measured: a producer worker on cu_producer CUs writes
  * n_slots_total slots of slot_bytes into a device ring of depth slots; a consumer

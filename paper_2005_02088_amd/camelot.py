@@ -140,6 +140,8 @@ _SIGS = {
     "camelot_server_used_bytes": (C.c_int64, [_P]),
     "camelot_server_destroy": (C.c_int32, [_P]),
     "camelot_stage_weight_bytes": (C.c_int64, [C.POINTER(StageDesc)]),
+    "camelot_stage_kernel_info": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int32)]),
     "camelot_handoff_bench": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
                                           C.c_int32, C.POINTER(C.c_double)]),
     "camelot_handoff_expected": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_uint64),
@@ -534,3 +536,9 @@ def camelot_server_destroy(server: int):
 
 def camelot_stage_weight_bytes(desc: StageDesc) -> int:
     return _check(_lib.camelot_stage_weight_bytes(C.byref(desc)))
+
+
+def camelot_stage_kernel_info(kind: int, one_shot: bool) -> dict:
+    regs, lds, fits = C.c_int32(0), C.c_int64(0), C.c_int32(0)
+    _check(_lib.camelot_stage_kernel_info(kind, int(one_shot), C.byref(regs), C.byref(lds), C.byref(fits)))
+    return {"regs": regs.value, "lds_bytes": lds.value, "fits": bool(fits.value)}

@@ -17,6 +17,8 @@ constexpr int kWaves = kThreads / 64;
 // stage kernel fits at least 2 workgroups per CU, which keeps the grid co-resident.
 constexpr int kWgPerCu = 1;
 constexpr int kMinWgPerCuResident = 2;  // residency a worker kernel must allow (dispatch slack)
+constexpr int kMaxRegsResident = 512 / kMinWgPerCuResident;          // registers per lane
+constexpr size_t kMaxLdsResident = 160 * 1024 / kMinWgPerCuResident; // LDS bytes per workgroup
 constexpr int kMaxBatch = CAMELOT_MAX_BATCH;
 constexpr int kMaxStages = CAMELOT_MAX_STAGES;
 constexpr int kSlotHeaderBytes = 4096;

@@ -347,12 +347,14 @@ int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
   // One workgroup per CU is launched, but the dispatcher may place two on one CU of
   // the share (it balances workgroups over shader engines, not over the masked
   // CUs): a kernel that fits only once per CU could leave a workgroup unplaced and
-  // its grid barriers could never complete. Refuse such a kernel instead.
-  int per_cu = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0));
-  if (per_cu < kMinWgPerCuResident)
-    return fail(CAMELOT_EDEVICE, "stage kind %d: only %d workgroup(s) fit on a CU, %d needed", kind, per_cu,
-                kMinWgPerCuResident);
+  // its grid barriers could never complete. Refuse such a kernel instead: two
+  // workgroups of 4 wave64s fit on a CU when each wave needs at most 256 of the
+  // SIMD's 512 registers per lane and each workgroup at most half of the LDS.
+  hipFuncAttributes fa;
+  HIP_TRY(hipFuncGetAttributes(&fa, fn));
+  if (fa.numRegs > kMaxRegsResident || fa.sharedSizeBytes > kMaxLdsResident)
+    return fail(CAMELOT_EDEVICE, "stage kind %d: %d registers and %zu LDS bytes per workgroup leave fewer than %d "
+                "workgroups per CU", kind, fa.numRegs, (size_t)fa.sharedSizeBytes, kMinWgPerCuResident);
   void* args[] = {(void*)&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(kWgPerCu * n_cus), dim3(kThreads), args, 0, s));
   return CAMELOT_OK;
@@ -361,6 +363,20 @@ int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
 }  // namespace camelot
 
 using namespace camelot;
+
+extern "C" int32_t camelot_stage_kernel_info(int32_t kind, int32_t one_shot, int32_t* regs, int64_t* lds_bytes,
+                                             int32_t* fits) {
+  clear_error();
+  if (!regs || !lds_bytes || !fits) return fail(CAMELOT_EINVAL, "NULL output");
+  const void* fn = worker_kernel(kind, one_shot != 0);
+  if (!fn) return fail(CAMELOT_EINVAL, "no kernel for stage kind %d", kind);
+  hipFuncAttributes fa;
+  HIP_TRY(hipFuncGetAttributes(&fa, fn));
+  *regs = fa.numRegs;
+  *lds_bytes = (int64_t)fa.sharedSizeBytes;
+  *fits = (fa.numRegs <= kMaxRegsResident && fa.sharedSizeBytes <= kMaxLdsResident) ? 1 : 0;
+  return CAMELOT_OK;
+}
 
 // ==================================================================== C ABI
 extern "C" const char* camelot_last_error(void) { return g_err.c_str(); }

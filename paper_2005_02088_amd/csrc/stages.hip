@@ -367,121 +367,298 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
 
 // ------------------------------------------------------------------ BF16 MLP chain on MFMA
 // Per layer: unit = 16 output columns (one strip) per workgroup; the 4 waves split
-// K in interleaved 32-wide chunks (v_mfma_f32_16x16x32_bf16, up to 8 row blocks of
-// 16 rows each), partial tiles are added in LDS in a fixed order, then ReLU and
-// BF16 rounding (hidden layers) or the FP32 store (last layer). Layers are
-// separated by grid barriers. Weights are [N][K] BF16 (K contiguous).
+// K in interleaved 32-wide chunks (wave w owns chunks w, w + 4, w + 8, ...) on
+// v_mfma_f32_16x16x32_bf16 for up to 8 row blocks of 16 rows; the 4 partial tiles
+// are added in LDS as ((p0 + p1) + p2) + p3, then ReLU and BF16 rounding (hidden
+// layers) or the FP32 store (last layer). Layers are separated by grid barriers.
+// Weights are [N][K] BF16 (K contiguous). Every output element's sum therefore has
+// one fixed order, whatever the batch, the row's position or the grid.
+//
+// Data movement: each wave keeps its weight fragments of a 2048-wide K segment in
+// registers (64 KB per strip and workgroup, loaded once; the next layer's first
+// segment is loaded while the workgroup waits at the layer barrier). Activations
+// go through LDS in tiles of (row blocks x K chunks) = 32 chunk-blocks (32 KB): all
+// 256 threads load a tile with 16-byte loads, two tiles ahead in registers, while
+// the waves run the MFMAs of the tile in LDS, so an L2 round trip is hidden behind
+// two tiles of MFMAs. With NP2 row blocks (1, 2, 4 or 8; the batch rounded up) a
+// tile spans 32 / NP2 chunks.
+// 16-byte load from global memory (explicitly in the global address space, so it
+// is a global load counted by vmcnt only, never a flat load that also holds up
+// every LDS wait).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef const u32x4_t __attribute__((address_space(1)))* gptr_u32x4;
+__device__ __forceinline__ uint4 gld16(const void* p) {
+  const u32x4_t v = *(gptr_u32x4)p;
+  uint4 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
 __device__ __forceinline__ bf16x8 ld_bf16x8(const uint16_t* p) {
-  const uint4 q = *(const uint4*)p;
+  const uint4 q = gld16(p);
   bf16x8 r;
   __builtin_memcpy(&r, &q, 16);
   return r;
 }
 
-__device__ __forceinline__ bf16x8 ld_f32x8_as_bf16(const float* p) {
-  const float4 a = *(const float4*)p;
-  const float4 b = *(const float4*)(p + 4);
+__device__ __forceinline__ float4 u4_as_f4(uint4 u) {
+  float4 f;
+  __builtin_memcpy(&f, &u, 16);
+  return f;
+}
+
+__device__ __forceinline__ uint4 f32x8_to_bf16x8_bits(const float4 a, const float4 b) {
   uint4 q;
   q.x = (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(a.y) << 16);
   q.y = (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(a.w) << 16);
   q.z = (uint32_t)f32_to_bf16_rne(b.x) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
   q.w = (uint32_t)f32_to_bf16_rne(b.z) | ((uint32_t)f32_to_bf16_rne(b.w) << 16);
-  bf16x8 r;
-  __builtin_memcpy(&r, &q, 16);
-  return r;
+  return q;
 }
 
-constexpr int kMlpChunksPerWave = 8;    // K chunks of 32 a wave keeps in flight per segment
-constexpr int kMlpSegK = kMlpChunksPerWave * kWaves * 32;   // K covered per segment (1024)
+constexpr int kMlpTilePieces = 1024;    // 16-byte pieces per activation tile (16 KB)
+constexpr int kMlpPiecesPerThread = kMlpTilePieces / kThreads;
+constexpr int kMlpTileBytes = 64 * (4 * 64 + 16);    // largest tile with its row padding
+static_assert(kMlpTilePieces % kThreads == 0, "tile pieces per thread");
 
-// Weight fragments of one segment of a strip: wave w owns chunks seg/32 + w + 4 i.
-__device__ __forceinline__ void mlp_load_w(bf16x8 (&bq)[kMlpChunksPerWave], const uint16_t* W, int K, int strip,
-                                           int seg, int w, int lane) {
+// Geometry of an activation tile in LDS: RB row blocks of 16 rows x TKC chunks of
+// 32, elements BF16 (hidden layers) or FP32 (the first layer's input rows, rounded
+// to BF16 when read for the MFMA). Every tile is 1024 pieces of 16 bytes, 4 per
+// thread; a thread's piece j lies in row block j * RB / 4 of the tile. Each wave
+// takes Q = TKC / 4 of a tile's chunks (wave w: chunks w, w + 4, ...). A batch of
+// more than 16 RB rows is done in passes of 16 RB rows over the strip's K.
+template <int RB_, int TKC_, bool F32_>
+struct MlpGeo {
+  static constexpr int RB = RB_, TKC = TKC_;
+  static constexpr bool F32 = F32_;
+  static constexpr int ESZ = F32 ? 4 : 2;
+  static constexpr int EPP = 16 / ESZ;                 // elements per piece
+  static constexpr int PPR = TKC * 32 / EPP;           // pieces per tile row
+  static constexpr int PITCH = TKC * 32 * ESZ + 16;    // padded row: rows fall on different banks
+  static constexpr int Q = TKC / 4;
+  static_assert(RB * 16 * PPR == kMlpTilePieces, "tile size");
+  static_assert(RB * 16 * PITCH <= kMlpTileBytes, "tile bytes");
+};
+using MlpGeoWide = MlpGeo<4, 4, false>;    // BF16, batches of 17..128 rows, 64 rows per pass
+using MlpGeoOne = MlpGeo<1, 16, false>;    // BF16, up to 16 rows
+using MlpGeoF32 = MlpGeo<2, 4, true>;      // FP32 first layer, 32 rows per pass
+
+struct MlpIn {
+  const uint8_t* const* rowptr;   // FP32 input rows (first layer)
+  const uint16_t* hin;            // BF16 hidden state [rows][stride] (later layers)
+  const uint16_t* W;              // weights [N][K]
+  int stride, K, rows;
+};
+
+// A tile in flight: its activation pieces and this wave's weight fragments.
+template <class G>
+struct MlpTileRegs {
+  uint4 a[kMlpPiecesPerThread];
+  bf16x8 b[G::Q];
+};
+
+// Activation pieces of tile g (chunks g * TKC ..) for rows row0 .. row0 + 16 RB - 1.
+// Rows past the batch read row 0 and K past the end reads column 0: those values
+// only meet zero weights or feed output rows that are never stored. The loads of
+// the tile pipeline are never inside a branch: the compiler then knows exactly
+// which loads are still in flight and waits only for the ones a step needs.
+template <class G>
+__device__ __forceinline__ void mlp_issue_a(MlpTileRegs<G>& r, const MlpIn& in, int row0, int g, int tid) {
+#pragma unroll
+  for (int j = 0; j < kMlpPiecesPerThread; ++j) {
+    const int p = tid + kThreads * j;
+    const int row = row0 + p / G::PPR, cp = p % G::PPR;
+    const int r0 = row < in.rows ? row : 0;
+    const int k = g * G::TKC * 32 + cp * G::EPP;
+    const int kc = k < in.K ? k : 0;
+    if constexpr (G::F32) r.a[j] = gld16((const float*)in.rowptr[r0] + kc);
+    else r.a[j] = gld16(in.hin + (int64_t)r0 * in.stride + kc);
+  }
+}
+
+// This wave's weight fragments of tile g of a strip (clamped past K; a K tail that
+// is not a multiple of 32 is zeroed at use).
+template <class G>
+__device__ __forceinline__ void mlp_issue_b(MlpTileRegs<G>& r, const uint16_t* W, int K, int strip, int g, int w,
+                                            int lane) {
   const uint16_t* wrow = W + (int64_t)(strip * 16 + (lane & 15)) * K;
-  const int krow = (lane >> 4) * 8;
 #pragma unroll
-  for (int i = 0; i < kMlpChunksPerWave; ++i) {
-    const int kb = seg + (w + kWaves * i) * 32 + krow;
-    bq[i] = kb < K ? ld_bf16x8(wrow + kb) : (bf16x8){};
+  for (int q = 0; q < G::Q; ++q) {
+    const int kb = (g * G::TKC + w + 4 * q) * 32 + (lane >> 4) * 8;
+    r.b[q] = ld_bf16x8(wrow + (kb < K ? kb : 0));
   }
 }
 
-// Activation fragments of row block rb for the same chunks (layer 0 reads the FP32
-// input rows and rounds them to BF16; later layers read the BF16 hidden state).
-__device__ __forceinline__ void mlp_load_a(bf16x8 (&aq)[kMlpChunksPerWave], const uint8_t* const* rowptr,
-                                           const uint16_t* hin, int stride, bool first, int K, int rows, int rb,
-                                           int seg, int w, int lane) {
-  const int row = rb * 16 + (lane & 15);
-  const bool rin = row < rows;
-  const int krow = (lane >> 4) * 8;
-  if (first) {
-    const float* xrow = rin ? (const float*)rowptr[row] : nullptr;
+template <class G>
+__device__ __forceinline__ void mlp_store_a(const MlpTileRegs<G>& r, uint8_t* lds, int tid) {
 #pragma unroll
-    for (int i = 0; i < kMlpChunksPerWave; ++i) {
-      const int kb = seg + (w + kWaves * i) * 32 + krow;
-      aq[i] = (rin && kb < K) ? ld_f32x8_as_bf16(xrow + kb) : (bf16x8){};
-    }
+  for (int j = 0; j < kMlpPiecesPerThread; ++j) {
+    const int p = tid + kThreads * j;
+    *(uint4*)(lds + (p / G::PPR) * G::PITCH + (p % G::PPR) * 16) = r.a[j];
+  }
+}
+
+// A fragment (16 rows x 32 of chunk c) of row block rb from the tile in LDS.
+template <class G>
+__device__ __forceinline__ bf16x8 mlp_lds_frag(const uint8_t* lds, int rb, int c, int lane) {
+  const uint8_t* p = lds + (rb * 16 + (lane & 15)) * G::PITCH + (c * 32 + (lane >> 4) * 8) * G::ESZ;
+  if constexpr (G::F32) {
+    const uint4 q = f32x8_to_bf16x8_bits(*(const float4*)p, *(const float4*)(p + 16));
+    bf16x8 r;
+    __builtin_memcpy(&r, &q, 16);
+    return r;
   } else {
-    const uint16_t* hrow = hin + (int64_t)row * stride;
+    return *(const bf16x8*)p;
+  }
+}
+
+// MFMAs of tile g (in LDS) for this wave's chunks; row block rb of the tile
+// accumulates into acc[AB + rb].
+template <class G, int AB>
+__device__ __forceinline__ void mlp_mfma_tile(f32x4 (&acc)[8], const MlpTileRegs<G>& r, const uint8_t* lds,
+                                              int g, int K, int nrb, int w, int lane) {
 #pragma unroll
-    for (int i = 0; i < kMlpChunksPerWave; ++i) {
-      const int kb = seg + (w + kWaves * i) * 32 + krow;
-      aq[i] = (rin && kb < K) ? ld_bf16x8(hrow + kb) : (bf16x8){};
+  for (int q = 0; q < G::Q; ++q) {
+    const int c = w + 4 * q;
+    const int k0 = (g * G::TKC + c) * 32;
+    if (k0 < K) {
+      bf16x8 bf = r.b[q];
+      if (k0 + 32 > K && k0 + (lane >> 4) * 8 >= K) bf = (bf16x8){};
+#pragma unroll
+      for (int rb = 0; rb < G::RB; ++rb) {
+        if (rb < nrb) acc[AB + rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mlp_lds_frag<G>(lds, rb, c, lane), bf,
+                                                                             acc[AB + rb], 0, 0, 0);
+      }
     }
   }
 }
 
-__device__ __forceinline__ void mlp_mfma(f32x4& acc, const bf16x8 (&aq)[kMlpChunksPerWave],
-                                         const bf16x8 (&bq)[kMlpChunksPerWave], int K, int seg, int w) {
-#pragma unroll
-  for (int i = 0; i < kMlpChunksPerWave; ++i)
-    if (seg + (w + kWaves * i) * 32 < K) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[i], bq[i], acc, 0, 0, 0);
+// One step of the tile pipeline: tile g from registers to LDS buffer BUF, the
+// loads of tile g + 2 into the same registers (the last tile again near the end:
+// unused, but it keeps the loads out of branches), the MFMAs of tile g.
+template <class G, int AB, int BUF>
+__device__ __forceinline__ void mlp_step(f32x4 (&acc)[8], MlpTileRegs<G>& cur, uint8_t* lds, const MlpIn& in,
+                                         int row0, int nrb, int strip, int g, int ntiles, int w, int lane, int tid) {
+  uint8_t* buf = lds + BUF * kMlpTileBytes;
+  const int gn = min(g + 2, ntiles - 1);
+  mlp_store_a<G>(cur, buf, tid);
+  __syncthreads();
+  mlp_issue_a<G>(cur, in, row0, gn, tid);
+  mlp_mfma_tile<G, AB>(acc, cur, buf, g, in.K, nrb, w, lane);
+  mlp_issue_b<G>(cur, in.W, in.K, strip, gn, w, lane);
 }
 
-// Per layer and strip the order of every sum is fixed: each wave adds its chunks in
-// increasing K order on the matrix cores, then the 4 wave partials are added in LDS
-// as ((p0 + p1) + p2) + p3. Row blocks are software-pipelined (the next block's
-// activation loads are in flight while the current block's MFMAs run), and the
-// next layer's first weight segment is loaded while the workgroup waits at the
-// layer barrier (weights are constant; only the activations need the barrier).
-__device__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
-  __shared__ float part[kWaves][8][256];
-  const int L = a.sp.n_layers;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int nrb = (rows + 15) >> 4;
-  const int stride = a.sp.scratch_stride;
-  const uint8_t* const* rowptr = ctl->d_rowptr;
-  bf16x8 bq[kMlpChunksPerWave];
-  bool pref = false;                         // bq holds this layer's first segment already
-  for (int l = 0; l < L; ++l) {
+// One pass over the K of a strip for rows row0 .. row0 + 16 RB - 1 (nrb row blocks
+// of them in the batch). Two tiles are in flight in registers while the tile in
+// LDS (double-buffered, one workgroup barrier per tile) feeds the MFMAs; every
+// wave adds its chunks in increasing K order. have_b: the weight fragments of
+// tiles 0 and 1 are already in ra / rb_ (loaded across the layer barrier).
+template <class G, int AB>
+__device__ __forceinline__ void mlp_pass(f32x4 (&acc)[8], MlpTileRegs<G>& ra, MlpTileRegs<G>& rb_, bool have_b,
+                                         uint8_t* lds, const MlpIn& in, int row0, int nrb, int strip, int w,
+                                         int lane, int tid) {
+  // an even number of tiles (a padding tile past K does no MFMAs)
+  const int ntiles = ((in.K + G::TKC * 32 - 1) / (G::TKC * 32) + 1) & ~1;
+  // same load order as the steady state (pieces, then weights, per register set)
+  mlp_issue_a<G>(ra, in, row0, 0, tid);
+  mlp_issue_b<G>(ra, in.W, in.K, strip, 0, w, lane);
+  mlp_issue_a<G>(rb_, in, row0, 1, tid);
+  mlp_issue_b<G>(rb_, in.W, in.K, strip, 1, w, lane);
+  for (int g = 0; g < ntiles; g += 2) {
+    mlp_step<G, AB, 0>(acc, ra, lds, in, row0, nrb, strip, g, ntiles, w, lane, tid);
+    mlp_step<G, AB, 1>(acc, rb_, lds, in, row0, nrb, strip, g + 1, ntiles, w, lane, tid);
+  }
+  __syncthreads();                           // tile buffers free for the next pass or the reduction
+}
+
+// The passes of a strip: rows 16 RB H .. 16 RB (H + 1) - 1 in pass H (only the
+// first pass can use weight registers loaded across the layer barrier).
+template <class G, int H>
+__device__ __forceinline__ void mlp_passes(f32x4 (&acc)[8], MlpTileRegs<G>& ra, MlpTileRegs<G>& rb_, bool have_b,
+                                           uint8_t* lds, const MlpIn& in, int nrb, int strip, int w, int lane,
+                                           int tid) {
+  if constexpr (H * G::RB < 8) {
+    if (H * G::RB < nrb) {
+      mlp_pass<G, H * G::RB>(acc, ra, rb_, have_b, lds, in, H * G::RB * 16, min(nrb - H * G::RB, G::RB), strip, w,
+                             lane, tid);
+      mlp_passes<G, H + 1>(acc, ra, rb_, false, lds, in, nrb, strip, w, lane, tid);
+    }
+  }
+}
+
+// One layer: every strip of this workgroup, then ReLU + BF16 (hidden layers) or the
+// FP32 store (last layer).
+template <class G>
+__device__ __forceinline__ void mlp_layer(bool have_b, uint8_t* lds, const MlpIn& in, int N, bool last,
+                                          uint16_t* hout, uint8_t* out, int nrb, int w, int lane, int tid) {
+  float (*part)[8][256] = (float (*)[8][256])lds;      // the reduction reuses the tile buffers
+  MlpTileRegs<G> ra, rb_;
+  for (int strip = blockIdx.x; strip < (N >> 4); strip += gridDim.x) {
+    f32x4 acc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    mlp_passes<G, 0>(acc, ra, rb_, have_b, lds, in, nrb, strip, w, lane, tid);
+    have_b = false;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      if (rb < nrb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[w][rb][((lane >> 4) * 4 + i) * 16 + (lane & 15)] = acc[rb][i];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nrb * 256; i += kThreads) {
+      const int rb = i >> 8, e = i & 255, row = rb * 16 + (e >> 4), col = strip * 16 + (e & 15);
+      if (row < in.rows) {
+        const float s = ((part[0][rb][e] + part[1][rb][e]) + part[2][rb][e]) + part[3][rb][e];
+        if (last) ((float*)out)[(int64_t)row * N + col] = s;
+        else hout[(int64_t)row * in.stride + col] = f32_to_bf16_rne(fmaxf(s, 0.f));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Layer l + 1's first two weight tiles for this workgroup's first strip, loaded
+// while waiting at the layer barrier (weights are constant; only the activations
+// need the barrier); the registers are handed to that layer's first pass.
+template <class G>
+__device__ __forceinline__ bool mlp_barrier_prefetch(WorkerCtl* ctl, const WorkerArgs& a, int l, int nrb_unused,
+                                                     MlpTileRegs<G>& ra, MlpTileRegs<G>& rb_, int w, int lane,
+                                                     bool* have_b) {
+  const BarTicket t = grid_arrive(ctl, gridDim.x);
+  const int K = a.sp.dims[l + 1], N = a.sp.dims[l + 2];
+  *have_b = (int)blockIdx.x < (N >> 4);
+  if (*have_b) {
+    const uint16_t* W = (const uint16_t*)a.sp.w[l + 1];
+    mlp_issue_b<G>(ra, W, K, blockIdx.x, 0, w, lane);
+    mlp_issue_b<G>(rb_, W, K, blockIdx.x, 1, w, lane);
+  }
+  return grid_wait(ctl, gridDim.x, t, a.spin_ticks);
+}
+
+// Hidden and last layers (l >= 1) with geometry G; the first layer is run by the
+// caller. The registers of the first two weight tiles cross the layer barriers.
+template <class G>
+__device__ __forceinline__ bool mlp_rest(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out, uint8_t* lds,
+                                         int w, int lane, int tid) {
+  const int L = a.sp.n_layers, nrb = (rows + 15) >> 4, stride = a.sp.scratch_stride;
+  MlpTileRegs<G> ra, rb_;
+  bool have_b = false;
+  if (!mlp_barrier_prefetch<G>(ctl, a, 0, nrb, ra, rb_, w, lane, &have_b)) return false;
+  for (int l = 1; l < L; ++l) {
     const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
-    const uint16_t* W = (const uint16_t*)a.sp.w[l];
-    const uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
     uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
+    const MlpIn in{ctl->d_rowptr, a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride,
+                   (const uint16_t*)a.sp.w[l], stride, K, rows};
     const bool last = (l == L - 1);
-    const bool first = (l == 0);
-    const int nstrips = N >> 4;
-    for (int strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
+    // the first strip takes over the prefetched weight registers
+    float (*part)[8][256] = (float (*)[8][256])lds;
+    for (int strip = blockIdx.x; strip < (N >> 4); strip += gridDim.x) {
       f32x4 acc[8];
 #pragma unroll
-      for (int rb = 0; rb < 8; ++rb) acc[rb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      for (int seg = 0; seg < K; seg += kMlpSegK) {
-        if (!(pref && seg == 0)) mlp_load_w(bq, W, K, strip, seg, w, lane);
-        bf16x8 a0[kMlpChunksPerWave], a1[kMlpChunksPerWave];
-        if (nrb > 0) mlp_load_a(a0, rowptr, hin, stride, first, K, rows, 0, seg, w, lane);
-#pragma unroll
-        for (int rb = 0; rb < 8; rb += 2) {
-          if (rb < nrb) {
-            if (rb + 1 < nrb) mlp_load_a(a1, rowptr, hin, stride, first, K, rows, rb + 1, seg, w, lane);
-            mlp_mfma(acc[rb], a0, bq, K, seg, w);
-            if (rb + 1 < nrb) {
-              if (rb + 2 < nrb) mlp_load_a(a0, rowptr, hin, stride, first, K, rows, rb + 2, seg, w, lane);
-              mlp_mfma(acc[rb + 1], a1, bq, K, seg, w);
-            }
-          }
-        }
-      }
-      pref = false;
+      for (int r = 0; r < 8; ++r) acc[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      mlp_passes<G, 0>(acc, ra, rb_, have_b && strip == (int)blockIdx.x, lds, in, nrb, strip, w, lane, tid);
 #pragma unroll
       for (int rb = 0; rb < 8; ++rb) {
         if (rb < nrb) {
@@ -500,15 +677,26 @@ __device__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t*
       }
       __syncthreads();
     }
-    if (!last) {
-      const BarTicket t = grid_arrive(ctl, gridDim.x);
-      const int nnext = a.sp.dims[l + 2];
-      pref = (int)blockIdx.x < (nnext >> 4);
-      if (pref) mlp_load_w(bq, (const uint16_t*)a.sp.w[l + 1], N, blockIdx.x, 0, w, lane);
-      if (!grid_wait(ctl, gridDim.x, t, a.spin_ticks)) return false;
-    }
+    if (!last && !mlp_barrier_prefetch<G>(ctl, a, l, nrb, ra, rb_, w, lane, &have_b)) return false;
   }
   return true;
+}
+
+__device__ __forceinline__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kMlpTileBytes];
+  // the wave index is uniform across the wave: in a scalar register the per-chunk
+  // conditions become scalar branches instead of exec-mask regions
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int nrb = (rows + 15) >> 4;
+  const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
+  {
+    // first layer: FP32 input rows
+    const MlpIn in{ctl->d_rowptr, nullptr, (const uint16_t*)a.sp.w[0], stride, a.sp.dims[0], rows};
+    mlp_layer<MlpGeoF32>(false, lds, in, a.sp.dims[1], L == 1, a.sp.scratch, out, nrb, w, lane, tid);
+  }
+  if (L == 1) return true;
+  if (nrb <= 1) return mlp_rest<MlpGeoOne>(a, ctl, rows, out, lds, w, lane, tid);
+  return mlp_rest<MlpGeoWide>(a, ctl, rows, out, lds, w, lane, tid);
 }
 
 // ------------------------------------------------------------------ embedding gather

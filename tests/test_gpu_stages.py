@@ -23,6 +23,18 @@ def cm():
     return camelot
 
 
+def test_every_stage_kernel_fits_twice_per_cu(torch, cm):
+    """Workers launch one workgroup per CU of a share but need room for two (the
+    dispatcher may double up on a CU); every stage kernel stays within that."""
+    kinds = (cm.STAGE_GEMM_RELU, cm.STAGE_GEMM_ARGMAX, cm.STAGE_LOGMEL, cm.STAGE_MLP_BF16, cm.STAGE_TOPK,
+             cm.STAGE_GATHER, cm.STAGE_CONV_POOL, cm.STAGE_GATHER_SCORE)
+    for kind in kinds:
+        for one_shot in (True, False):
+            info = cm.camelot_stage_kernel_info(kind, one_shot)
+            log(f"  kind {kind} one_shot={one_shot}: {info}")
+            assert info["fits"] and info["regs"] <= 256 and info["lds_bytes"] <= 80 * 1024
+
+
 def test_device_query(torch, cm):
     d = cm.camelot_device_query()
     log(f"device: {d.arch} CUs={d.n_cus} wallclock={d.wall_clock_hz} hbm={d.hbm_bytes >> 30} GiB")
