@@ -127,7 +127,9 @@ struct WorkerCtl {
   uint32_t bench_stop[2];         // bench mode: workgroup 0's decision to stop, by rep parity
   uint64_t sum_acc, xor_acc, batches_acc;
   uint64_t rows_acc, busy_acc, wait_acc;
-  alignas(128) uint32_t go[32];   // workgroup 0's batch broadcast: seq + 1 (own 128-byte line)
+  // workgroup 0's batch broadcast (seq + 1), one 128-byte line per barrier group so
+  // that the idle workgroups' polls spread over 8 lines instead of one
+  alignas(128) uint32_t go[8][32];
 };
 
 // Stage parameters (device pointers borrowed from the caller or owned by the
@@ -258,6 +260,15 @@ __device__ __forceinline__ void wg_barrier_stores_done() {
   __syncthreads();
 }
 
+// Pause between two polls of a flag other workgroups will write: short naps while
+// the flag is expected soon, longer ones once the wait is long (an idle worker),
+// so idle pollers do not keep a memory channel busy.
+__device__ __forceinline__ void poll_backoff(uint32_t polls) {
+  if (polls < 64) __builtin_amdgcn_s_sleep(1);
+  else if (polls < 1024) __builtin_amdgcn_s_sleep(4);
+  else __builtin_amdgcn_s_sleep(32);
+}
+
 // The barrier in two halves: arrive publishes this workgroup's writes and counts
 // it in; wait returns once every workgroup has arrived. Work that reads nothing
 // the other workgroups write (loading constant weights) may run in between.
@@ -308,7 +319,11 @@ __device__ __forceinline__ bool grid_wait(WorkerCtl* ctl, uint32_t nwg, BarTicke
       const uint64_t t0 = now_ticks();
       uint32_t polls = 0;
       while (__hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t.gen) {
-        if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+        ++polls;
+        if ((polls & 15u) == 0 && __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
         if ((int64_t)(now_ticks() - t0) > spin_ticks) {
           // record who was missing: arrivals on this group and on the top counter
           ctl->diag_arrived = __hip_atomic_load(&ctl->bar_group[g][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
@@ -319,9 +334,7 @@ __device__ __forceinline__ bool grid_wait(WorkerCtl* ctl, uint32_t nwg, BarTicke
           ok = 0;
           break;
         }
-        // short naps while a barrier is expected soon, longer ones once it is idle
-        if (++polls < 256) __builtin_amdgcn_s_sleep(1);
-        else __builtin_amdgcn_s_sleep(32);
+        poll_backoff(polls);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

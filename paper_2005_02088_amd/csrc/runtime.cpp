@@ -130,15 +130,38 @@ static int32_t make_masked_stream(int offset, int n, hipStream_t* s) {
   return CAMELOT_OK;
 }
 
-// Cache of masked streams used by the one-shot stage runs (profiling).
-static std::map<std::pair<int, int>, hipStream_t> g_streams;
+// Cache of masked streams used by the one-shot stage runs (profiling, co-location
+// runs, the handoff benchmark). Every CU-masked stream holds a hardware queue of its
+// own, so the cache is bounded: past kMaxCachedStreams the least recently used one
+// is drained and destroyed. The calls that use these streams synchronize them
+// before returning, so an evicted stream is idle (they are not meant to run
+// concurrently from several host threads).
+constexpr size_t kMaxCachedStreams = 32;
+struct CachedStream {
+  hipStream_t s;
+  uint64_t last_use;
+};
+static std::map<std::pair<int, int>, CachedStream> g_streams;
+static uint64_t g_stream_clock = 0;
 int32_t cached_stream(int offset, int n, hipStream_t* s) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_streams.find({offset, n});
-  if (it != g_streams.end()) { *s = it->second; return CAMELOT_OK; }
+  if (it != g_streams.end()) {
+    it->second.last_use = ++g_stream_clock;
+    *s = it->second.s;
+    return CAMELOT_OK;
+  }
+  if (g_streams.size() >= kMaxCachedStreams) {
+    auto lru = g_streams.begin();
+    for (auto jt = g_streams.begin(); jt != g_streams.end(); ++jt)
+      if (jt->second.last_use < lru->second.last_use) lru = jt;
+    (void)hipStreamSynchronize(lru->second.s);
+    (void)hipStreamDestroy(lru->second.s);
+    g_streams.erase(lru);
+  }
   int32_t rc = make_masked_stream(offset, n, s);
   if (rc) return rc;
-  g_streams[{offset, n}] = *s;
+  g_streams[{offset, n}] = CachedStream{*s, ++g_stream_clock};
   return CAMELOT_OK;
 }
 

@@ -1060,15 +1060,19 @@ __device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t s
     int ok = 1;
     const uint64_t t0 = now_ticks();
     uint32_t polls = 0;
-    while (__hip_atomic_load(&ctl->go[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
-      if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+    const uint32_t* gp = &ctl->go[blockIdx.x & 7u][0];
+    while (__hip_atomic_load(const_cast<uint32_t*>(gp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+      ++polls;
+      if ((polls & 15u) == 0 && __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
       if ((int64_t)(now_ticks() - t0) > spin_ticks) {
         __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
-      if (++polls < 256) __builtin_amdgcn_s_sleep(1);
-      else __builtin_amdgcn_s_sleep(32);
+      poll_backoff(polls);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_go = ok;
@@ -1208,7 +1212,9 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
       // broadcast: the batch descriptor (or the stop) is in place
       wg_barrier_stores_done();
       if (tid == 0) {
-        st_release_agent(&ctl->go[0], (uint32_t)(seq + 1));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (int g = 0; g < 8; ++g)
+          __hip_atomic_store(&ctl->go[g][0], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
