@@ -224,7 +224,7 @@ class Speech:
         return best
 
 
-def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=2500, epochs=150):
+def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=800, epochs=150):
     """The contention-aware allocator: co-location profiles of the three stages at
     random shares and batches, the 16-64-64-1 predictor trained on them with the
     library's kernels (target: log slowdown over the solo profile), then Eq. 1 over
@@ -286,17 +286,20 @@ def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=2500, epochs=150):
 ROOF_LAUNCHES, ROOF_REPS = 10, 50
 
 
-def mlp_roofline(cm, sp, mlp_cus):
+ROOFLINE_EXE = os.path.join(ROOT, "paper_2005_02088_amd", "camelot_mlp_roofline")
+
+
+def mlp_roofline(mlp_cus):
     """The dominant kernel: the BF16 MLP stage's one-shot kernel at batch 128 on the
     MLP's CU share, ROOF_LAUNCHES launches of ROOF_REPS batches each, timed with HIP
-    events on the stream the kernel runs on."""
-    per = []
-    # one untimed launch first: the first launch of a kernel includes loading its code
-    cm.camelot_stage_run(sp.stages[1], sp.in_bufs[1].data_ptr(), sp.out_bufs[1].data_ptr(), 128, mlp_cus, 0, 1)
-    for _ in range(ROOF_LAUNCHES):
-        per.append(cm.camelot_stage_run(sp.stages[1], sp.in_bufs[1].data_ptr(), sp.out_bufs[1].data_ptr(), 128,
-                                        mlp_cus, 0, ROOF_REPS))
-    ns = sum(per) / len(per)
+    events on the stream the kernel runs on, by the library's standalone driver (a
+    plain executable, the same command a profiler wraps)."""
+    cmd = [ROOFLINE_EXE, str(mlp_cus), str(ROOF_LAUNCHES), str(ROOF_REPS)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        raise SystemExit(f"roofline driver failed ({r.returncode}): {r.stderr.strip()}")
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    ns = out["ns_per_batch"]
     mlp_bytes = Speech.stage_bytes(1, 128)
     mlp_flops = 2 * MLP_PARAMS * 128
     achieved = mlp_bytes / (ns * 1e-9)
@@ -306,9 +309,11 @@ def mlp_roofline(cm, sp, mlp_cus):
             "frac": achieved / HBM_PEAK, "traffic": None,
             "kernel": "stage_bench<MLP_BF16> (camelot::stage_bench<4>)", "share_cus": mlp_cus,
             "batches_per_launch": ROOF_REPS, "launches": ROOF_LAUNCHES,
-            "avg_launch_us": ns * ROOF_REPS / 1e3, "ns_per_batch": ns,
+            "avg_launch_us": sum(out["launch_us"]) / len(out["launch_us"]), "ns_per_batch": ns,
             "bytes_per_batch": mlp_bytes, "bytes_per_launch": mlp_bytes * ROOF_REPS,
-            "mfma_tflops": mlp_flops / (ns * 1e-9) / 1e12, "mfma_frac": mlp_flops / (ns * 1e-9) / MFMA_BF16_PEAK}
+            "mfma_tflops": mlp_flops / (ns * 1e-9) / 1e12,
+            "mfma_frac": mlp_flops / (ns * 1e-9) / MFMA_BF16_PEAK,
+            "command": " ".join(["paper_2005_02088_amd/camelot_mlp_roofline"] + cmd[1:])}
 
 
 def main():
@@ -322,12 +327,6 @@ def main():
     ap.add_argument("--cpu-baseline-only", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-learned", action="store_true", help="skip the learned-allocator comparison")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="only the MLP roofline launches of step 7 (for rocprofv3 runs)")
-    ap.add_argument("--mlp-cus", type=int, default=0, help="MLP share for --roofline-only")
-    ap.add_argument("--mlp-cus-from", default="", help="read the MLP share from a bench JSON line")
-    ap.add_argument("--copy-calib", type=int, default=0,
-                    help="run a plain device copy of this many MiB (counter calibration) and exit")
     ap.add_argument("--dump", default="", help="write the profile table and trials to this JSON file")
     args = ap.parse_args()
 
@@ -344,29 +343,9 @@ def main():
     import workload_gen as G
     from paper_2005_02088_amd import camelot as cm
 
-    if args.copy_calib:
-        n = args.copy_calib << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copied {args.copy_calib} MiB x3")
-        return 0
-
     dev = cm.camelot_device_query()
     log(f"device {dev.arch.decode()} CUs={dev.n_cus}")
     sp = Speech(torch, cm, G)
-
-    if args.roofline_only:
-        mlp_cus = args.mlp_cus
-        if args.mlp_cus_from:
-            with open(args.mlp_cus_from) as f:
-                mlp_cus = json.loads(f.read().strip().splitlines()[-1])["roofline"]["share_cus"]
-        roof = mlp_roofline(cm, sp, mlp_cus)
-        print(json.dumps({"roofline": roof}))
-        return 0
 
     # 1-2: profile table and allocation (Eq. 1)
     t0 = time.perf_counter()
@@ -449,7 +428,7 @@ def main():
     log(f"handoff device {h['gbs']:.0f} GB/s (checksum ok={handoff_ok}), host-staged {hh['gbs']:.1f} GB/s")
 
     # 7: roofline of the dominant kernel (MLP stage, batch 128, on its share)
-    roof = mlp_roofline(cm, sp, a["cu"][1])
+    roof = mlp_roofline(a["cu"][1])
 
     # 8: CPU baseline
     cpu = None if args.skip_cpu else run_cpu_baseline(args.cpu_sample)

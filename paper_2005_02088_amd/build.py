@@ -15,6 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcamelot.so")
+ROOFLINE_EXE = os.path.join(HERE, "camelot_mlp_roofline")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -49,8 +50,16 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the standalone roofline driver of the MLP stage (links the library in place)
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    cmd = [HIPCC, "-O2", "-std=c++17", f"--offload-arch={ARCH}", f"-I{inc}", os.path.join(CSRC, "mlp_roofline.cpp"),
+           "-o", ROOFLINE_EXE + ".tmp", f"-L{HERE}", "-lcamelot", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"roofline driver build failed:\n{r.stderr}")
+    os.replace(ROOFLINE_EXE + ".tmp", ROOFLINE_EXE)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {ROOFLINE_EXE}")
     return LIB
 
 

@@ -132,11 +132,15 @@ static int32_t make_masked_stream(int offset, int n, hipStream_t* s) {
 
 // Cache of masked streams used by the one-shot stage runs (profiling, co-location
 // runs, the handoff benchmark). Every CU-masked stream holds a hardware queue of its
-// own, so the cache is bounded: past kMaxCachedStreams the least recently used one
-// is drained and destroyed. The calls that use these streams synchronize them
-// before returning, so an evicted stream is idle (they are not meant to run
-// concurrently from several host threads).
-constexpr size_t kMaxCachedStreams = 32;
+// own, and a process that holds more queues than the device has queue slots gets
+// them time-sliced, which stalls persistent workers (measured: the MLP stage at
+// batch 128 on 136 CUs took 94 us with up to 16 extra idle masked streams alive,
+// 113 us with 32 and 217 us with 48). So the cache is small: past
+// kMaxCachedStreams the least recently used stream is drained and destroyed.
+// The calls that use these streams synchronize them before returning, so an
+// evicted stream is idle (they are not meant to run concurrently from several
+// host threads).
+constexpr size_t kMaxCachedStreams = 4;
 struct CachedStream {
   hipStream_t s;
   uint64_t last_use;
