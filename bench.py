@@ -289,6 +289,25 @@ ROOF_LAUNCHES, ROOF_REPS = 10, 50
 ROOFLINE_EXE = os.path.join(ROOT, "paper_2005_02088_amd", "camelot_mlp_roofline")
 
 
+def profiled_traffic(mlp_cus):
+    """HBM bytes per roofline launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE of the same driver command, scaled by a plain copy kernel), or None
+    when there is none for this CU share or the kernel source changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"mlp_bf16_b128_{mlp_cus}cu_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_t = re.search(r"traffic_bytes_per_launch = (\d+)", text)
+    m_s = re.search(r"source_sha256 = ([0-9a-f]+)", text)
+    src = os.path.join(ROOT, "paper_2005_02088_amd", "csrc", "stages.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if not m_t or not m_s or m_s.group(1) != sha:
+        return None
+    return int(m_t.group(1))
+
+
 def mlp_roofline(mlp_cus):
     """The dominant kernel: the BF16 MLP stage's one-shot kernel at batch 128 on the
     MLP's CU share, ROOF_LAUNCHES launches of ROOF_REPS batches each, timed with HIP
@@ -306,7 +325,8 @@ def mlp_roofline(mlp_cus):
     log(f"MLP @128 on {mlp_cus} CUs: {ns / 1e3:.1f} us/batch -> {achieved / 1e9:.0f} GB/s, "
         f"{mlp_flops / (ns * 1e-9) / 1e12:.0f} TFLOP/s")
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK, "traffic": None,
+            "frac": achieved / HBM_PEAK, "traffic": profiled_traffic(mlp_cus),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
             "kernel": "stage_bench<MLP_BF16> (camelot::stage_bench<4>)", "share_cus": mlp_cus,
             "batches_per_launch": ROOF_REPS, "launches": ROOF_LAUNCHES,
             "avg_launch_us": sum(out["launch_us"]) / len(out["launch_us"]), "ns_per_batch": ns,
