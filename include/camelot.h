@@ -71,7 +71,8 @@ int32_t camelot_device_query(camelot_device_info* out);
 /* ------------------------------------------------------------------ allocation
  * Section V, Eq. 1 and Eq. 3 over an integer profile table.
  *
- * Decision variables per stage i: instance count N_i (1..max_inst_per_stage) and
+ * Decision variables per stage i: instance count N_i (1..max_inst_per_stage, or
+ * 1..inst_max[i] when inst_max is given) and
  * CU share p_i = (k_i + 1) * cu_step (k_i = 0 .. cu_total/cu_step - 1); one batch
  * size b = batches[j] for the whole pipeline.
  * Throughput T = min_i N_i * b * 1e9 / lat_ns[i][k_i][j]   (queries/s, exact rational)
@@ -86,7 +87,8 @@ int32_t camelot_device_query(camelot_device_info* out);
  * rational comparisons.
  * Table layouts: lat_ns and bw_bps are [n_stages][cu_total/cu_step][n_batches]
  * row-major int64; mem_bytes is [n_stages][n_batches]; batch_wait_ns is
- * [n_batches] or NULL (all zero). All owned by the caller, read only.
+ * [n_batches] or NULL (all zero); inst_max is [n_stages] or NULL (every stage
+ * bounded by max_inst_per_stage alone). All owned by the caller, read only.
  */
 #define CAMELOT_MAX_STAGES 8
 
@@ -105,6 +107,7 @@ typedef struct {
   const int64_t* bw_bps;
   const int64_t* mem_bytes;
   const int64_t* batch_wait_ns;
+  const int32_t* inst_max;     /* per-stage bound on N_i, each >= 1, or NULL         */
 } camelot_problem;
 
 typedef struct {

@@ -5,7 +5,9 @@ and a CU share p_i per stage to maximise the pipeline throughput
     T = min_i N_i * b / L_i(p_i, b)          (queries/s, L_i in seconds)
 subject to
     sum_i N_i p_i <= R                        (computational resources)
-    sum_i N_i <= I,  1 <= N_i <= I            (instance cap)
+    sum_i N_i <= I,  1 <= N_i <= I            (instance cap; optionally a lower
+                                              bound per stage, e.g. 1 for a stage
+                                              that must stay single)
     sum_i N_i bw_i(p_i, b) <= BW              (global-memory bandwidth)
     sum_i N_i M(i, b) <= F                    (global-memory capacity)
     W(b) + sum_i L_i(p_i, b) <= QoS           (latency target)
@@ -56,6 +58,7 @@ class Problem:
     bw_bps: np.ndarray                 # [S, K, nb] int64
     mem_bytes: np.ndarray              # [S, nb] int64
     batch_wait_ns: Optional[Sequence[int]] = None   # W(b) per batch index
+    inst_max: Optional[Sequence[int]] = None        # per-stage bound on N_i (default: max_inst_per_stage)
 
     @property
     def n_stages(self) -> int:
@@ -83,11 +86,14 @@ class Alloc:
         return Fraction(self.thr_num, self.thr_den)
 
 
-def _stage_options(p: Problem):
+def _stage_options(p: Problem, s: int):
+    """(N_i, k_i) choices of stage s: 1 <= N_i <= its instance bound, every share."""
     K = p.n_shares
     if p.lat_ns.shape[1] < K or p.bw_bps.shape[1] < K:
         raise ValueError("tables hold fewer CU shares than cu_total / cu_step")
     nmax = min(p.max_inst_per_stage, p.max_instances)
+    if p.inst_max is not None:
+        nmax = min(nmax, int(p.inst_max[s]))
     return [(n, k) for n in range(1, nmax + 1) for k in range(K)]
 
 
@@ -129,9 +135,9 @@ def evaluate(p: Problem, bi: int, choice) -> Optional[Alloc]:
 
 
 def all_feasible(p: Problem):
-    opts = _stage_options(p)
+    opts = [_stage_options(p, s) for s in range(p.n_stages)]
     for bi in range(len(p.batches)):
-        for choice in itertools.product(opts, repeat=p.n_stages):
+        for choice in itertools.product(*opts):
             a = evaluate(p, bi, choice)
             if a is not None:
                 yield a

@@ -51,7 +51,8 @@ class Problem(C.Structure):
                 ("n_batches", C.c_int32), ("batches", C.POINTER(C.c_int32)),
                 ("qos_ns", C.c_int64), ("hbm_bytes_budget", C.c_int64), ("hbm_bw_budget", C.c_int64),
                 ("lat_ns", C.POINTER(C.c_int64)), ("bw_bps", C.POINTER(C.c_int64)),
-                ("mem_bytes", C.POINTER(C.c_int64)), ("batch_wait_ns", C.POINTER(C.c_int64))]
+                ("mem_bytes", C.POINTER(C.c_int64)), ("batch_wait_ns", C.POINTER(C.c_int64)),
+                ("inst_max", C.POINTER(C.c_int32))]
 
 
 class Alloc(C.Structure):
@@ -198,12 +199,13 @@ class ProblemArrays:
     """Keeps the numpy arrays a Problem points at alive."""
 
     def __init__(self, *, cu_total, cu_step, max_instances, max_inst_per_stage, batches, qos_ns,
-                 hbm_bytes_budget, hbm_bw_budget, lat_ns, bw_bps, mem_bytes, batch_wait_ns=None):
+                 hbm_bytes_budget, hbm_bw_budget, lat_ns, bw_bps, mem_bytes, batch_wait_ns=None, inst_max=None):
         self.batches = np.ascontiguousarray(batches, dtype=np.int32)
         self.lat = _i64(lat_ns)
         self.bw = _i64(bw_bps)
         self.mem = _i64(mem_bytes)
         self.wait = None if batch_wait_ns is None else _i64(batch_wait_ns)
+        self.inst_max = None if inst_max is None else np.ascontiguousarray(inst_max, dtype=np.int32)
         self.struct = Problem(
             n_stages=self.lat.shape[0], cu_total=cu_total, cu_step=cu_step, max_instances=max_instances,
             max_inst_per_stage=max_inst_per_stage, n_batches=len(self.batches),
@@ -211,7 +213,8 @@ class ProblemArrays:
             hbm_bytes_budget=int(hbm_bytes_budget), hbm_bw_budget=int(hbm_bw_budget),
             lat_ns=_ptr(self.lat, C.c_int64), bw_bps=_ptr(self.bw, C.c_int64),
             mem_bytes=_ptr(self.mem, C.c_int64),
-            batch_wait_ns=_ptr(self.wait, C.c_int64) if self.wait is not None else None)
+            batch_wait_ns=_ptr(self.wait, C.c_int64) if self.wait is not None else None,
+            inst_max=_ptr(self.inst_max, C.c_int32) if self.inst_max is not None else None)
 
 
 def camelot_alloc_peak(problem: ProblemArrays):

@@ -35,6 +35,7 @@ inline int cmp(const Rat& a, const Rat& b) {   // sign of a - b
 struct Search {
   const camelot_problem* p;
   int S, K, nmax, bi;
+  int nmax_s[CAMELOT_MAX_STAGES];
   int64_t b, wait;
   bool peak;                  // true: Eq. 1; false: Eq. 3 with load
   Rat load;
@@ -82,7 +83,7 @@ struct Search {
   void rec(int s, int64_t cu, int64_t inst, int64_t bwsum, int64_t memsum, int64_t latsum,
            bool has_thr, Rat thr) {
     if (s == S) { leaf(thr, cu, latsum); return; }
-    for (int nn = 1; nn <= nmax; ++nn) {
+    for (int nn = 1; nn <= nmax_s[s]; ++nn) {
       const int64_t inst2 = inst + nn;
       if (inst2 > p->max_instances) break;
       const int64_t mem2 = memsum + nn * mem(s);
@@ -124,6 +125,9 @@ int validate(const camelot_problem* p) {
     return camelot::fail(CAMELOT_EINVAL, "cu_total must be a positive multiple of cu_step");
   if (p->max_instances < 1 || p->max_inst_per_stage < 1)
     return camelot::fail(CAMELOT_EINVAL, "instance caps must be >= 1");
+  if (p->inst_max)
+    for (int i = 0; i < p->n_stages; ++i)
+      if (p->inst_max[i] < 1) return camelot::fail(CAMELOT_EINVAL, "inst_max[%d] must be >= 1", i);
   if (p->n_batches < 1 || !p->batches)
     return camelot::fail(CAMELOT_EINVAL, "need at least one batch size");
   for (int j = 0; j < p->n_batches; ++j)
@@ -152,6 +156,7 @@ int solve(const camelot_problem* p, bool peak, int64_t load_num, int64_t load_de
   s.S = p->n_stages;
   s.K = p->cu_total / p->cu_step;
   s.nmax = std::min(p->max_inst_per_stage, p->max_instances);
+  for (int i = 0; i < s.S; ++i) s.nmax_s[i] = p->inst_max ? std::min(s.nmax, p->inst_max[i]) : s.nmax;
   s.peak = peak;
   s.load = Rat{load_num, load_den};
   for (int bi = 0; bi < p->n_batches; ++bi) {

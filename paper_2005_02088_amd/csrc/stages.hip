@@ -541,11 +541,19 @@ __device__ __forceinline__ void mlp_step(f32x4 (&acc)[8], MlpTileRegs<G>& cur, u
                                          int row0, int nrb, int strip, int g, int ntiles, int w, int lane, int tid) {
   uint8_t* buf = lds + BUF * kMlpTileBytes;
   const int gn = min(g + 2, ntiles - 1);
+  // scheduling barriers keep the load groups in program order, so that the wait
+  // before a tile's store only covers that tile's loads (the other register set's,
+  // issued later, stay in flight)
+  __builtin_amdgcn_sched_barrier(0);
   mlp_store_a<G>(cur, buf, tid);
   __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
   mlp_issue_a<G>(cur, in, row0, gn, tid);
+  __builtin_amdgcn_sched_barrier(0);
   mlp_mfma_tile<G, AB>(acc, cur, buf, g, in.K, nrb, w, lane);
+  __builtin_amdgcn_sched_barrier(0);
   mlp_issue_b<G>(cur, in.W, in.K, strip, gn, w, lane);
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // One pass over the K of a strip for rows row0 .. row0 + 16 RB - 1 (nrb row blocks
@@ -560,10 +568,15 @@ __device__ __forceinline__ void mlp_pass(f32x4 (&acc)[8], MlpTileRegs<G>& ra, Ml
   // an even number of tiles (a padding tile past K does no MFMAs)
   const int ntiles = ((in.K + G::TKC * 32 - 1) / (G::TKC * 32) + 1) & ~1;
   // same load order as the steady state (pieces, then weights, per register set)
+  __builtin_amdgcn_sched_barrier(0);
   mlp_issue_a<G>(ra, in, row0, 0, tid);
+  __builtin_amdgcn_sched_barrier(0);
   mlp_issue_b<G>(ra, in.W, in.K, strip, 0, w, lane);
+  __builtin_amdgcn_sched_barrier(0);
   mlp_issue_a<G>(rb_, in, row0, 1, tid);
+  __builtin_amdgcn_sched_barrier(0);
   mlp_issue_b<G>(rb_, in.W, in.K, strip, 1, w, lane);
+  __builtin_amdgcn_sched_barrier(0);
   for (int g = 0; g < ntiles; g += 2) {
     mlp_step<G, AB, 0>(acc, ra, lds, in, row0, nrb, strip, g, ntiles, w, lane, tid);
     mlp_step<G, AB, 1>(acc, rb_, lds, in, row0, nrb, strip, g + 1, ntiles, w, lane, tid);

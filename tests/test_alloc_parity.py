@@ -11,16 +11,16 @@ BIG = (1 << 62)
 
 
 def _both(lat, bw, mem, batches, cu_total, cu_step, *, qos=BIG, nmax=1, I=48, bw_budget=BIG,
-          mem_budget=BIG, wait=None):
+          mem_budget=BIG, wait=None, inst_max=None):
     lat = np.asarray(lat, np.int64)
     bw = np.asarray(bw, np.int64)
     mem = np.asarray(mem, np.int64)
     po = OA.Problem(cu_total=cu_total, cu_step=cu_step, max_instances=I, max_inst_per_stage=nmax,
                     batches=list(batches), qos_ns=qos, hbm_bytes_budget=mem_budget, hbm_bw_budget=bw_budget,
-                    lat_ns=lat, bw_bps=bw, mem_bytes=mem, batch_wait_ns=wait)
+                    lat_ns=lat, bw_bps=bw, mem_bytes=mem, batch_wait_ns=wait, inst_max=inst_max)
     pc = cm.ProblemArrays(cu_total=cu_total, cu_step=cu_step, max_instances=I, max_inst_per_stage=nmax,
                           batches=batches, qos_ns=qos, hbm_bytes_budget=mem_budget, hbm_bw_budget=bw_budget,
-                          lat_ns=lat, bw_bps=bw, mem_bytes=mem, batch_wait_ns=wait)
+                          lat_ns=lat, bw_bps=bw, mem_bytes=mem, batch_wait_ns=wait, inst_max=inst_max)
     return po, pc
 
 
@@ -110,3 +110,19 @@ def test_invalid_problems_rejected():
                          mem_bytes=np.zeros((1, 1)))
     with pytest.raises(cm.CamelotError):
         cm.camelot_alloc_peak(p)
+
+
+@pytest.mark.parametrize("sub", range(6))
+def test_per_stage_instance_bounds_match_brute_force(sub):
+    g = G.rng("tables", 77, sub)
+    S = int(g.integers(2, 4))
+    K = int(g.integers(2, 6))
+    lat, bw, mem = G.random_problem_tables(S, K, [1, 4], seed=11, sub=sub)
+    inst_max = [int(v) for v in g.integers(1, 4, S)]
+    po, pc = _both(lat, bw, mem, [1, 4], K * 8, 8, nmax=3, I=3 * S, inst_max=inst_max)
+    o = OA.alloc_peak(po)
+    _same(o, cm.camelot_alloc_peak(pc))
+    if o is not None:
+        assert all(n <= m for n, m in zip(o.n, inst_max))
+        lam = o.thr_num // (2 * o.thr_den) + 1
+        _same(OA.alloc_min(po, lam, 1), cm.camelot_alloc_min(pc, lam, 1))

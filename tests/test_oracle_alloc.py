@@ -64,6 +64,20 @@ def test_instances_can_replicate_slow_stage():
     assert a.n == [2, 1] and a.cu == [4, 4] and (a.thr_num, a.thr_den) == (500000, 1)
 
 
+def test_per_stage_instance_bound():
+    # the same grid with stage 0 held to one instance: every share of stage 0 gives
+    # 1e9 / 4000 = 250,000 q/s, reached with the fewest CUs (4 + 4)
+    lat = [[[4000]] * 3, [[1000]] * 3]
+    p = _problem(lat, [1], 12, 4, nmax=3)
+    p.inst_max = [1, 3]
+    a = A.alloc_peak(p)
+    assert a.n == [1, 1] and a.cu == [4, 4] and (a.thr_num, a.thr_den) == (250000, 1)
+    # a bound that does not bind changes nothing
+    p.inst_max = [3, 1]
+    b = A.alloc_peak(p)
+    assert b.n == [2, 1] and b.cu == [4, 4]
+
+
 def test_single_stage_takes_all_cus():
     lat = [[[1000 // (k + 1) + 7] for k in range(8)]]
     a = A.alloc_peak(_problem(lat, [1], 64, 8))
