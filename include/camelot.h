@@ -91,6 +91,8 @@ int32_t camelot_device_query(camelot_device_info* out);
  * bounded by max_inst_per_stage alone). All owned by the caller, read only.
  */
 #define CAMELOT_MAX_STAGES 8
+#define CAMELOT_MAX_INSTANCES 4     /* instances of one pipeline stage              */
+#define CAMELOT_MAX_WORKERS 16      /* stage instances of one pipeline in total     */
 
 typedef struct {
   int32_t n_stages;            /* 1..CAMELOT_MAX_STAGES                              */
@@ -240,7 +242,15 @@ typedef enum { CAMELOT_INGEST_HOST = 0, CAMELOT_INGEST_REPLAY = 1 } camelot_inge
 typedef struct {
   int32_t n_stages;
   camelot_stage_desc stages[CAMELOT_MAX_STAGES];
-  int32_t cu[CAMELOT_MAX_STAGES];  /* CUs per stage, multiples of 8, sum <= 256 - cu_offset */
+  int32_t cu[CAMELOT_MAX_STAGES];  /* CUs per stage instance, multiples of 8           */
+  int32_t n_inst[CAMELOT_MAX_STAGES]; /* instances per stage (N_i of Eq. 1; 0 means 1).
+                                  Only stages between the first and the last may have
+                                  more than one (up to CAMELOT_MAX_INSTANCES): instance j
+                                  of stage i takes batches j, j + N_i, j + 2 N_i, ... on
+                                  its own cu[i] CUs, and the next stage still consumes
+                                  batches in order. Stages are laid out from cu_offset,
+                                  instance after instance: sum_i N_i cu[i] <= 256 -
+                                  cu_offset. ring_depth must be >= 2 max_i N_i.       */
   int32_t cu_offset;           /* first CU-mask bit of this pipeline (multiple of 8) */
   int32_t max_batch;           /* rows per batch, 1..CAMELOT_MAX_BATCH               */
   int32_t batch_target;        /* start a batch once this many rows wait (>= 1)     */
@@ -315,11 +325,14 @@ int32_t camelot_pipeline_replay(camelot_pipeline* p, int32_t n_req, const uint64
 typedef struct {
   uint64_t submitted_requests, submitted_rows;
   uint64_t delivered_rows;
-  uint64_t batches[CAMELOT_MAX_STAGES];          /* batches finished per stage      */
+  uint64_t batches[CAMELOT_MAX_STAGES];          /* batches finished per stage (all
+                                                    its instances; so are the sums
+                                                    below)                          */
   uint64_t id_sum[CAMELOT_MAX_STAGES];           /* sum of splitmix64(id) per row
                                                     leaving stage i (mod 2^64)      */
   uint64_t id_xor[CAMELOT_MAX_STAGES];           /* xor of the same                 */
-  int32_t worker_status[CAMELOT_MAX_STAGES];     /* 0 running/ok, else error code   */
+  int32_t worker_status[CAMELOT_MAX_STAGES];     /* 0 running/ok, else the first
+                                                    instance's error code           */
   uint64_t rows[CAMELOT_MAX_STAGES];             /* rows finished per stage         */
   int64_t busy_ns[CAMELOT_MAX_STAGES];           /* sum over batches of the time from
                                                     batch start (input and output

@@ -75,7 +75,7 @@ class StageDesc(C.Structure):
 
 class PipelineConfig(C.Structure):
     _fields_ = [("n_stages", C.c_int32), ("stages", StageDesc * MAX_STAGES), ("cu", C.c_int32 * MAX_STAGES),
-                ("cu_offset", C.c_int32), ("max_batch", C.c_int32), ("batch_target", C.c_int32),
+                ("n_inst", C.c_int32 * MAX_STAGES), ("cu_offset", C.c_int32), ("max_batch", C.c_int32), ("batch_target", C.c_int32),
                 ("batch_timeout_ns", C.c_int64), ("ring_depth", C.c_int32), ("handoff", C.c_int32),
                 ("ingest", C.c_int32), ("max_rows_per_request", C.c_int32), ("ingest_capacity", C.c_int32),
                 ("egress_capacity", C.c_int32), ("idle_timeout_ns", C.c_int64),
@@ -287,12 +287,13 @@ def camelot_stage_run(desc: StageDesc, in_ptr: int, out_ptr: int, rows: int, n_c
 def pipeline_config(stages, cu, *, cu_offset=0, max_batch=32, batch_target=1, batch_timeout_ns=0,
                     ring_depth=4, handoff=HANDOFF_DEVICE, ingest=INGEST_HOST, max_rows_per_request=1,
                     ingest_capacity=4096, egress_capacity=65536, idle_timeout_ns=20_000_000_000,
-                    hbm_budget_bytes=0, side_bytes=0) -> PipelineConfig:
+                    hbm_budget_bytes=0, side_bytes=0, n_inst=None) -> PipelineConfig:
     c = PipelineConfig()
     c.n_stages = len(stages)
     for i, s in enumerate(stages):
         c.stages[i] = s
         c.cu[i] = cu[i]
+        c.n_inst[i] = 1 if n_inst is None else int(n_inst[i])
     c.cu_offset = cu_offset
     c.max_batch = max_batch
     c.batch_target = batch_target

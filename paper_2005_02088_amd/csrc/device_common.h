@@ -21,6 +21,7 @@ constexpr int kMaxRegsResident = 512 / kMinWgPerCuResident;          // register
 constexpr size_t kMaxLdsResident = 160 * 1024 / kMinWgPerCuResident; // LDS bytes per workgroup
 constexpr int kMaxBatch = CAMELOT_MAX_BATCH;
 constexpr int kMaxStages = CAMELOT_MAX_STAGES;
+constexpr int kMaxWorkers = CAMELOT_MAX_WORKERS;    // stage instances of one pipeline
 constexpr int kSlotHeaderBytes = 4096;
 
 // Status codes a worker reports (0 = ok / running).
@@ -80,14 +81,14 @@ struct DevPub {
   uint64_t t0;                              // epoch (device ticks)
   uint64_t egress_head;                     // result rows published
   uint64_t ingest_tail;                     // requests taken by stage 0
-  uint64_t batches[kMaxStages];
-  uint64_t id_sum[kMaxStages];
-  uint64_t id_xor[kMaxStages];
-  uint64_t rows[kMaxStages];                // rows finished per stage
-  uint64_t busy_ticks[kMaxStages];          // sum over batches of (publish - batch start)
-  uint64_t wait_ticks[kMaxStages];          // sum of the waits for input and output space
-  int32_t status[kMaxStages];
-  int32_t started[kMaxStages];
+  uint64_t batches[kMaxWorkers];   // per worker (stage instance) below
+  uint64_t id_sum[kMaxWorkers];
+  uint64_t id_xor[kMaxWorkers];
+  uint64_t rows[kMaxWorkers];               // rows finished
+  uint64_t busy_ticks[kMaxWorkers];          // sum over batches of (publish - batch start)
+  uint64_t wait_ticks[kMaxWorkers];          // sum of the waits for input and output space
+  int32_t status[kMaxWorkers];
+  int32_t started[kMaxWorkers];
   uint64_t pad[16];
 };
 
@@ -155,6 +156,8 @@ struct WorkerArgs {
   StageParams sp;
   int32_t stage_index;
   int32_t n_stages;
+  int32_t worker_index;           // slot of this stage instance in the published counters
+  int32_t n_inst;                 // instances of this stage: this one takes every n_inst-th batch
   int32_t max_batch;
   int32_t side_bytes;             // per-row bytes carried through the stages
   int32_t in_row_stride;          // stage 0: bytes between payload rows (row + side)

@@ -521,10 +521,14 @@ struct camelot_pipeline {
   int S = 0;
   int64_t in_b[kMaxStages] = {0}, out_b[kMaxStages] = {0};
   int k_out = 1;
-  StageRes res[kMaxStages];
-  hipStream_t streams[kMaxStages] = {nullptr};
-  WorkerArgs args[kMaxStages];
-  WorkerCtl* ctl[kMaxStages] = {nullptr};
+  // workers: the instances of every stage, stage by stage (worker w runs stage
+  // w_stage[w]; stage i's instances are workers first_w[i] .. first_w[i] + n_inst[i] - 1)
+  int NW = 0;
+  int n_inst[kMaxStages] = {0}, first_w[kMaxStages] = {0}, w_stage[kMaxWorkers] = {0};
+  StageRes res[kMaxWorkers];
+  hipStream_t streams[kMaxWorkers] = {nullptr};
+  WorkerArgs args[kMaxWorkers];
+  WorkerCtl* ctl[kMaxWorkers] = {nullptr};
   // device-global rings (DEVICE handoff: one per boundary; HOST: producer + consumer side)
   Ring out_ring[kMaxStages];       // written by stage i
   Ring in_ring[kMaxStages];        // read by stage i (== out_ring[i-1] in DEVICE mode)
@@ -633,10 +637,12 @@ static void relay_loop(camelot_pipeline* p, int i) {
 static void free_pipeline(camelot_pipeline* p) {
   p->relay_stop.store(true);
   for (auto& t : p->relays) if (t.joinable()) t.join();
+  for (int w = 0; w < p->NW; ++w) {
+    if (p->streams[w]) (void)hipStreamDestroy(p->streams[w]);
+    dfree(p->ctl[w]);
+  }
   for (int i = 0; i < p->S; ++i) {
-    if (p->streams[i]) (void)hipStreamDestroy(p->streams[i]);
     if (p->relay_stream[i]) (void)hipStreamDestroy(p->relay_stream[i]);
-    dfree(p->ctl[i]);
     if (p->staging[i]) (void)hipHostFree(p->staging[i]);
     Ring* rs[2] = {&p->out_ring[i], &p->in_ring[i]};
     for (Ring* r : rs) {
@@ -672,9 +678,21 @@ static int32_t validate_config(const camelot_pipeline_config* c, const DevInfo& 
     if (i > 0 && p->out_b[i - 1] != p->in_b[i])
       return fail(CAMELOT_EINVAL, "stage %d consumes %lld-byte rows but stage %d produces %lld", i,
                   (long long)p->in_b[i], i - 1, (long long)p->out_b[i - 1]);
-    if ((rc = check_share(c->cu[i], off, dev.n_cus))) return rc;
-    off += c->cu[i];
+    const int n = c->n_inst[i] == 0 ? 1 : c->n_inst[i];
+    if (n < 1 || n > CAMELOT_MAX_INSTANCES)
+      return fail(CAMELOT_EINVAL, "stage %d: instances must be in 1..%d", i, CAMELOT_MAX_INSTANCES);
+    if (n > 1 && (i == 0 || i == c->n_stages - 1))
+      return fail(CAMELOT_EINVAL, "stage %d: only stages between the first and the last can have several instances", i);
+    if (c->ring_depth < 2 * n) return fail(CAMELOT_EINVAL, "ring_depth must be >= 2 x the instances of a stage");
+    for (int j = 0; j < n; ++j) {
+      if ((rc = check_share(c->cu[i], off, dev.n_cus))) return rc;
+      off += c->cu[i];
+    }
+    p->n_inst[i] = n;
+    p->first_w[i] = p->NW;
+    for (int j = 0; j < n; ++j) p->w_stage[p->NW++] = i;
   }
+  if (p->NW > kMaxWorkers) return fail(CAMELOT_EINVAL, "more than %d stage instances", kMaxWorkers);
   if (c->max_batch < 1 || c->max_batch > kMaxBatch) return fail(CAMELOT_EINVAL, "max_batch must be in 1..%d", kMaxBatch);
   if (c->batch_target < 1) return fail(CAMELOT_EINVAL, "batch_target must be >= 1");
   if (c->batch_timeout_ns < 0) return fail(CAMELOT_EINVAL, "batch_timeout_ns must be >= 0");
@@ -724,9 +742,9 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     stride[i] = side_off[i] + round_up((int64_t)cfg->max_batch * side, 256);
     fp += (host_handoff ? 2 : 1) * (D * stride[i] + (host_handoff ? 0 : round_up(8LL * D, 256)));
   }
-  for (int i = 0; i < S; ++i) {
+  for (int w = 0; w < p->NW; ++w) {
     int st = 0;
-    fp += stage_scratch_bytes(&cfg->stages[i], &st) + round_up(sizeof(WorkerCtl), 256);
+    fp += stage_scratch_bytes(&cfg->stages[p->w_stage[w]], &st) + round_up(sizeof(WorkerCtl), 256);
   }
   p->footprint = fp;
   if (cfg->hbm_budget_bytes > 0 && fp > cfg->hbm_budget_bytes) {
@@ -796,21 +814,28 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     }
   }
 
-  // ---- stage resources, control, streams
+  // ---- stage instance (worker) resources, control, streams
   int off = cfg->cu_offset;
-  for (int i = 0; i < S; ++i) {
-    WorkerArgs& a = p->args[i];
+  for (int w = 0; w < p->NW; ++w) {
+    const int i = p->w_stage[w];
+    const int inst = w - p->first_w[i];
+    WorkerArgs& a = p->args[w];
     std::memset(&a, 0, sizeof a);
-    rc = fill_params(&cfg->stages[i], &p->res[i], &a.sp);
+    rc = fill_params(&cfg->stages[i], &p->res[w], &a.sp);
     if (rc) { free_pipeline(p); return rc; }
-    rc = dmalloc(&p->ctl[i], sizeof(WorkerCtl));
-    if (!rc) rc = dzero(p->ctl[i], sizeof(WorkerCtl));
+    rc = dmalloc(&p->ctl[w], sizeof(WorkerCtl));
+    if (!rc) rc = dzero(p->ctl[w], sizeof(WorkerCtl));
+    // instance j starts at batch j and takes every n_inst-th batch
+    const uint64_t first_seq = (uint64_t)inst;
+    if (!rc) rc = h2d(&p->ctl[w]->next_seq, &first_seq, sizeof first_seq);
     if (rc) { free_pipeline(p); return rc; }
-    rc = make_masked_stream(off, cfg->cu[i], &p->streams[i]);
+    rc = make_masked_stream(off, cfg->cu[i], &p->streams[w]);
     if (rc) { free_pipeline(p); return rc; }
     off += cfg->cu[i];
     a.stage_index = i;
     a.n_stages = S;
+    a.worker_index = w;
+    a.n_inst = p->n_inst[i];
     a.max_batch = cfg->max_batch;
     a.side_bytes = cfg->side_bytes;
     a.in_row_stride = (int32_t)(p->in_b[i] + cfg->side_bytes);
@@ -850,7 +875,7 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
       a.egress_cap = cfg->egress_capacity;
       a.rec_bytes = p->rec_bytes;
     }
-    a.ctl = p->ctl[i];
+    a.ctl = p->ctl[w];
     a.hctl = p->hctl;
     a.pub = p->pub;
   }
@@ -862,8 +887,9 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     for (int i = 0; i + 1 < S; ++i) p->relays.emplace_back(relay_loop, p, i);
 
   if (cfg->ingest == CAMELOT_INGEST_HOST) {
-    for (int i = S - 1; i >= 0; --i) {
-      rc = launch_worker(cfg->stages[i].kind, p->args[i], cfg->cu[i], p->streams[i]);
+    for (int w = p->NW - 1; w >= 0; --w) {
+      const int i = p->w_stage[w];
+      rc = launch_worker(cfg->stages[i].kind, p->args[w], cfg->cu[i], p->streams[w]);
       if (rc) { free_pipeline(p); return rc; }
     }
     p->launched = true;
@@ -877,11 +903,12 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
 extern "C" int64_t camelot_pipeline_footprint(const camelot_pipeline* p) { return p ? p->footprint : -1; }
 
 static int32_t worker_error(camelot_pipeline* p) {
-  for (int i = 0; i < p->S; ++i) {
-    const int32_t st = __atomic_load_n(&p->pub->status[i], __ATOMIC_ACQUIRE);
+  for (int w = 0; w < p->NW; ++w) {
+    const int32_t st = __atomic_load_n(&p->pub->status[w], __ATOMIC_ACQUIRE);
     if (st == kStatusTimeout || st == kStatusAborted)
-      return fail(CAMELOT_EDEVICE, "stage %d worker failed (status %d)", i, st);
-    if (st == kStatusIdleExit) return fail(CAMELOT_ESTOPPED, "stage %d worker exited after the idle timeout", i);
+      return fail(CAMELOT_EDEVICE, "stage %d worker failed (status %d)", p->w_stage[w], st);
+    if (st == kStatusIdleExit)
+      return fail(CAMELOT_ESTOPPED, "stage %d worker exited after the idle timeout", p->w_stage[w]);
   }
   return CAMELOT_OK;
 }
@@ -953,8 +980,9 @@ extern "C" int32_t camelot_pipeline_replay(camelot_pipeline* p, int32_t n_req, c
   p->args[0].ingest = p->replay_tab;
   p->args[0].n_ingest = n_req;
   p->args[0].ingest_payload = (const uint8_t*)payload;
-  for (int i = p->S - 1; i >= 0; --i) {
-    int32_t rc = launch_worker(p->cfg.stages[i].kind, p->args[i], p->cfg.cu[i], p->streams[i]);
+  for (int w = p->NW - 1; w >= 0; --w) {
+    const int i = p->w_stage[w];
+    int32_t rc = launch_worker(p->cfg.stages[i].kind, p->args[w], p->cfg.cu[i], p->streams[w]);
     if (rc) return rc;
   }
   p->launched = true;
@@ -1050,14 +1078,18 @@ extern "C" int32_t camelot_pipeline_stats_get(camelot_pipeline* p, camelot_pipel
   out->submitted_requests = p->submitted_req;
   out->submitted_rows = p->submitted_rows;
   out->delivered_rows = __atomic_load_n(&p->pub->egress_head, __ATOMIC_ACQUIRE);
-  for (int i = 0; i < p->S; ++i) {
-    out->batches[i] = __atomic_load_n(&p->pub->batches[i], __ATOMIC_ACQUIRE);
-    out->id_sum[i] = __atomic_load_n(&p->pub->id_sum[i], __ATOMIC_ACQUIRE);
-    out->id_xor[i] = __atomic_load_n(&p->pub->id_xor[i], __ATOMIC_ACQUIRE);
-    out->worker_status[i] = __atomic_load_n(&p->pub->status[i], __ATOMIC_ACQUIRE);
-    out->rows[i] = __atomic_load_n(&p->pub->rows[i], __ATOMIC_ACQUIRE);
-    out->busy_ns[i] = ticks_to_ns((int64_t)__atomic_load_n(&p->pub->busy_ticks[i], __ATOMIC_ACQUIRE), p->dev.wclk_hz);
-    out->wait_ns[i] = ticks_to_ns((int64_t)__atomic_load_n(&p->pub->wait_ticks[i], __ATOMIC_ACQUIRE), p->dev.wclk_hz);
+  // per stage: sums over its instances (the id checksums are sums and xors, so the
+  // instances' partial values combine exactly)
+  for (int w = 0; w < p->NW; ++w) {
+    const int i = p->w_stage[w];
+    out->batches[i] += __atomic_load_n(&p->pub->batches[w], __ATOMIC_ACQUIRE);
+    out->id_sum[i] += __atomic_load_n(&p->pub->id_sum[w], __ATOMIC_ACQUIRE);
+    out->id_xor[i] ^= __atomic_load_n(&p->pub->id_xor[w], __ATOMIC_ACQUIRE);
+    const int32_t st = __atomic_load_n(&p->pub->status[w], __ATOMIC_ACQUIRE);
+    if (out->worker_status[i] == 0) out->worker_status[i] = st;
+    out->rows[i] += __atomic_load_n(&p->pub->rows[w], __ATOMIC_ACQUIRE);
+    out->busy_ns[i] += ticks_to_ns((int64_t)__atomic_load_n(&p->pub->busy_ticks[w], __ATOMIC_ACQUIRE), p->dev.wclk_hz);
+    out->wait_ns[i] += ticks_to_ns((int64_t)__atomic_load_n(&p->pub->wait_ticks[w], __ATOMIC_ACQUIRE), p->dev.wclk_hz);
   }
   return CAMELOT_OK;
 }
@@ -1071,7 +1103,7 @@ extern "C" int32_t camelot_pipeline_destroy(camelot_pipeline* p, uint64_t* undel
   if (p->launched) {
     // workers poll the stop flag between batches; in-batch waits are bounded
     const int64_t deadline = host_ns() + 30LL * 1000000000LL;
-    for (int i = 0; i < p->S; ++i) {
+    for (int i = 0; i < p->NW; ++i) {
       for (;;) {
         hipError_t q = hipStreamQuery(p->streams[i]);
         if (q == hipSuccess) break;

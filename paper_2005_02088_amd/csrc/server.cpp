@@ -76,7 +76,8 @@ extern "C" int32_t camelot_server_admit(camelot_server* s, const camelot_pipelin
   if (!s || !cfg || !out) return fail(CAMELOT_EINVAL, "bad admission arguments");
   std::lock_guard<std::mutex> lk(s->mu);
   int lo = cfg->cu_offset, hi = cfg->cu_offset;
-  for (int i = 0; i < cfg->n_stages && i < CAMELOT_MAX_STAGES; ++i) hi += cfg->cu[i];
+  for (int i = 0; i < cfg->n_stages && i < CAMELOT_MAX_STAGES; ++i)
+    hi += cfg->cu[i] * (cfg->n_inst[i] > 1 ? cfg->n_inst[i] : 1);
   for (auto& m : s->members)
     if (lo < m.hi && m.lo < hi) return fail(CAMELOT_EINVAL, "CU range [%d, %d) overlaps an admitted pipeline", lo, hi);
   // weights not yet held

@@ -1114,7 +1114,7 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
   if (wg0 && tid == 0) {
     s_t0 = now_ticks();
     if (si == 0) st_relaxed_sys(&a.pub->t0, s_t0);
-    st_relaxed_sys(&a.pub->started[si], 1);
+    st_relaxed_sys(&a.pub->started[a.worker_index], 1);
   }
   if (wg0) __syncthreads();
   uint64_t seq = ctl->next_seq;
@@ -1283,18 +1283,18 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
       ctl->rows_acc += (uint64_t)rows;
       ctl->busy_acc += t_end - ctl->d_t_start;
       ctl->wait_acc += ctl->d_t_start - t_top;
-      st_relaxed_sys(&a.pub->id_sum[si], ctl->sum_acc);
-      st_relaxed_sys(&a.pub->id_xor[si], ctl->xor_acc);
-      st_relaxed_sys(&a.pub->rows[si], ctl->rows_acc);
-      st_relaxed_sys(&a.pub->busy_ticks[si], ctl->busy_acc);
-      st_relaxed_sys(&a.pub->wait_ticks[si], ctl->wait_acc);
-      st_relaxed_sys(&a.pub->batches[si], ctl->batches_acc);
+      st_relaxed_sys(&a.pub->id_sum[a.worker_index], ctl->sum_acc);
+      st_relaxed_sys(&a.pub->id_xor[a.worker_index], ctl->xor_acc);
+      st_relaxed_sys(&a.pub->rows[a.worker_index], ctl->rows_acc);
+      st_relaxed_sys(&a.pub->busy_ticks[a.worker_index], ctl->busy_acc);
+      st_relaxed_sys(&a.pub->wait_ticks[a.worker_index], ctl->wait_acc);
+      st_relaxed_sys(&a.pub->batches[a.worker_index], ctl->batches_acc);
     }
-    ++seq;
+    seq += (uint64_t)a.n_inst;          // instance j of n takes batches j, j + n, ...
   }
   if (wg0 && tid == 0) {
     ctl->next_seq = seq;
-    st_release_sys(&a.pub->status[si], (int32_t)exit_status);
+    st_release_sys(&a.pub->status[a.worker_index], (int32_t)exit_status);
   }
 }
 
