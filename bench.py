@@ -10,7 +10,8 @@ up to 128 queries; p99 QoS target 50 ms.
 Steps (all on synthetic, seeded inputs resident in HBM before any timed region):
  1. solo profile table: every stage x CU share (8..256 in steps of 8) x batch
     (1..128, powers of two), measured with the library's one-shot stage kernel;
- 2. allocation: max-peak problem (Eq. 1) over that table -> CU shares and batch;
+ 2. allocation: max-peak problem (Eq. 1) over that table -> CU shares, instances
+    of the MLP stage (up to 4, each on its own share) and batch;
  3. peak QPS at p99 <= QoS: Poisson-arrival replays (device-side arrival clock,
     payloads already in HBM), binary search on the rate, for the allocation with
     device-global handoff and for the baseline (even split 88/88/80 CUs,
@@ -42,6 +43,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 QOS_NS = 50_000_000
+MAX_INST = 4            # instances per stage the allocator may place
 HBM_PEAK = 8.0e12
 MFMA_BF16_PEAK = 2.5e15
 MLP_PARAMS = 440 * 2048 + 2048 * 2048 * 2 + 2048 * 4096
@@ -148,8 +150,9 @@ class Speech:
         mem = np.array([[self.stage_footprint(s, b) for b in BATCHES] for s in range(S)], np.int64)
         return lat, bw, mem
 
-    def trial(self, cu, rate, duration_s, handoff, batch, batch_timeout_ns, seed=0, cu_offset=0):
-        """One Poisson replay; returns dict(p50, p99, n, wall_s, achieved_qps)."""
+    def trial(self, cu, rate, duration_s, handoff, batch, batch_timeout_ns, seed=0, cu_offset=0, n_inst=(1, 1, 1)):
+        """One Poisson replay; returns dict(p50, p99, n, wall_s, achieved_qps). n_inst[i]
+        instances of stage i run side by side, each on its own share of cu[i] CUs."""
         import numpy as np
         import workload_gen as G
         cm = self.cm
@@ -158,9 +161,9 @@ class Speech:
         ids = np.arange(1, n + 1, dtype=np.uint64)
         prow = np.arange(n, dtype=np.int64) % self.pool.shape[0]
         cfg = cm.pipeline_config(self.stages, cu, cu_offset=cu_offset, max_batch=batch, batch_target=batch,
-                                 batch_timeout_ns=batch_timeout_ns, ring_depth=4, handoff=handoff,
-                                 ingest=cm.INGEST_REPLAY, egress_capacity=1 << 20,
-                                 idle_timeout_ns=5_000_000_000)
+                                 batch_timeout_ns=batch_timeout_ns, ring_depth=max(4, 2 * max(n_inst)),
+                                 handoff=handoff, ingest=cm.INGEST_REPLAY, egress_capacity=1 << 20,
+                                 idle_timeout_ns=5_000_000_000, n_inst=n_inst)
         p = cm.camelot_pipeline_create(cfg)
         lat = np.empty(n, np.int64)
         got_ids = np.empty(n, np.uint64)
@@ -205,13 +208,13 @@ class Speech:
         return {"n": n, "done": done, "p50": p50, "p99": p99, "wall_s": wall, "ok": p99 <= QOS_NS,
                 "span_s": float(arr[-1]) / 1e9, "stage": stage}
 
-    def peak_search(self, cu, handoff, batch, guess_qps, duration_s, iters, tag):
+    def peak_search(self, cu, handoff, batch, guess_qps, duration_s, iters, tag, n_inst=(1, 1, 1)):
         lo, hi = 0.0, guess_qps * 2.0
         best = None
         timeout = QOS_NS // 4
         for it in range(iters):
             rate = (lo + hi) / 2 if it else guess_qps
-            r = self.trial(cu, rate, duration_s, handoff, batch, timeout, seed=it)
+            r = self.trial(cu, rate, duration_s, handoff, batch, timeout, seed=it, n_inst=n_inst)
             log(f"  [{tag}] rate {rate / 1e6:.3f} Mq/s -> p50 {r['p50'] / 1e3:.0f} us p99 {r['p99'] / 1e3:.0f} us "
                 f"ok={r['ok']} per batch {r['stage']}")
             if r["ok"]:
@@ -371,9 +374,15 @@ def main():
     t0 = time.perf_counter()
     lat, bw, mem = sp.profile()
     log(f"profile table: {time.perf_counter() - t0:.1f} s")
-    prob = cm.ProblemArrays(cu_total=256, cu_step=8, max_instances=48, max_inst_per_stage=1, batches=BATCHES,
-                            qos_ns=QOS_NS, hbm_bytes_budget=dev.hbm_bytes, hbm_bw_budget=int(HBM_PEAK),
-                            lat_ns=lat, bw_bps=bw, mem_bytes=mem)
+    # the MLP stage may run as several instances (the first and last stages own the
+    # ingest and the egress and stay single)
+    def problem(mlp_inst_max):
+        return cm.ProblemArrays(cu_total=256, cu_step=8, max_instances=48, max_inst_per_stage=MAX_INST,
+                                batches=BATCHES, qos_ns=QOS_NS, hbm_bytes_budget=dev.hbm_bytes,
+                                hbm_bw_budget=int(HBM_PEAK), lat_ns=lat, bw_bps=bw, mem_bytes=mem,
+                                inst_max=[1, mlp_inst_max, 1])
+    prob = problem(MAX_INST)
+    prob1 = problem(1)
     t0 = time.perf_counter()
     alloc = cm.camelot_alloc_peak(prob)
     alloc_ms = (time.perf_counter() - t0) * 1e3
@@ -384,9 +393,11 @@ def main():
     ok_even, ea = cm.camelot_alloc_eval(prob, a["batch_index"], [1, 1, 1], even)
     pred_even = ea.thr_num / ea.thr_den
     batch = a["batch"]
+    ninst = tuple(a["n"])
 
     # 3: peak QPS at p99 <= QoS
-    cam = sp.peak_search(a["cu"], cm.HANDOFF_DEVICE, batch, pred, args.trial_s, args.search_iters, "camelot")
+    cam = sp.peak_search(a["cu"], cm.HANDOFF_DEVICE, batch, pred, args.trial_s, args.search_iters, "camelot",
+                         n_inst=ninst)
     base = sp.peak_search(even, cm.HANDOFF_HOST, batch, pred_even, args.trial_s, args.search_iters, "baseline")
     peak = cam[0] if cam else 0.0
     peak_base = base[0] if base else 0.0
@@ -397,13 +408,14 @@ def main():
     # step met the QoS target (the search's last good rate, lowered by 3% per retry)
     for attempt in range(6):
         for w in range(args.warmup):
-            sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w)
+            sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w,
+                     n_inst=ninst)
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         steps = []
         for k in range(args.steps):
             steps.append(sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4,
-                                  seed=200 + k))
+                                  seed=200 + k, n_inst=ninst))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         p99s = [s["p99"] for s in steps]
@@ -421,23 +433,32 @@ def main():
     if amin is not None:
         m = amin.as_dict()
         cus20 = m["cu_used"]
-        r20 = sp.trial(m["cu"], lam20, args.trial_s, cm.HANDOFF_DEVICE, m["batch"], QOS_NS // 4, seed=300)
+        r20 = sp.trial(m["cu"], lam20, args.trial_s, cm.HANDOFF_DEVICE, m["batch"], QOS_NS // 4, seed=300,
+                       n_inst=tuple(m["n"]))
         p99_20 = r20["p99"]
         log(f"20% load {lam20 / 1e6:.3f} Mq/s: allocation {m} p99 {p99_20 / 1e3:.0f} us")
 
-    # 5b: contention-aware (learned) allocation, measured the same way
+    # 5b: contention-aware (learned) allocation, measured the same way; the learned
+    # allocator places one instance per stage, so it is set against the solo-table
+    # allocation under the same one-instance rule
     learned = None
     if not args.skip_learned:
-        la, lpred, linfo = learned_allocation(cm, G, torch, sp, lat, prob)
+        la, lpred, linfo = learned_allocation(cm, G, torch, sp, lat, prob1)
         if la is not None:
+            a1 = cm.camelot_alloc_peak(prob1).as_dict()
+            t1 = sp.peak_search(a1["cu"], cm.HANDOFF_DEVICE, a1["batch"], a1["thr_num"] / a1["thr_den"],
+                                args.trial_s, args.search_iters, "table, one instance")
+            tpeak = t1[0] if t1 else 0.0
             lbest = sp.peak_search(la["cu"], cm.HANDOFF_DEVICE, la["batch"], la["thr_num"] / la["thr_den"],
                                    args.trial_s, args.search_iters, "learned")
             lpeak = lbest[0] if lbest else 0.0
             learned = {"allocation_cus": la["cu"], "batch": la["batch"], "predicted_qps": la["thr_num"] / la["thr_den"],
                        "predicted_stage_ns": lpred, "measured_peak_qps": lpeak,
-                       "ratio_vs_table_allocation": lpeak / peak if peak else None, **linfo}
-            log(f"learned allocation {la['cu']} b={la['batch']}: measured peak {lpeak / 1e6:.3f} Mq/s "
-                f"({learned['ratio_vs_table_allocation']:.3f} of the table allocation's)")
+                       "table_one_instance": {"allocation_cus": a1["cu"], "batch": a1["batch"],
+                                              "measured_peak_qps": tpeak},
+                       "ratio_vs_table_allocation": lpeak / tpeak if tpeak else None, **linfo}
+            log(f"learned allocation {la['cu']} b={la['batch']}: measured peak {lpeak / 1e6:.3f} Mq/s; "
+                f"table allocation {a1['cu']}: {tpeak / 1e6:.3f} Mq/s (both one instance per stage)")
 
     # 6: handoff GB/s
     slot = 64 << 20
@@ -459,7 +480,7 @@ def main():
         "ms_per_step": elapsed * 1e3 / max(args.steps, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": WORKLOAD, "global_batch": batch, "parallelism": "spatial CU partitions on 1 GPU",
-                   "allocation_cus": a["cu"], "ingest": "device replay of Poisson arrivals, payloads in HBM",
+                   "allocation_cus": a["cu"], "allocation_instances": a["n"], "ingest": "device replay of Poisson arrivals, payloads in HBM",
                    "handoff": "device-global ring + doorbells", "qos_ns": QOS_NS},
         "timed_steps_p99_ns": p99s, "timed_steps_qos_met": all(s["ok"] for s in steps),
         "timed_step_per_batch": steps[0].get("stage"),
