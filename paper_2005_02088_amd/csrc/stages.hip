@@ -695,13 +695,325 @@ __device__ __forceinline__ bool mlp_rest(const WorkerArgs& a, WorkerCtl* ctl, in
   return true;
 }
 
+// ---- batches of 4 or more row blocks: waves split the rows
+// A unit is (up to 4 RW row blocks) x (CT column strips); wave w owns row blocks
+// w, w + 4, ... of the unit and runs the whole K for them, with one accumulator per
+// K-chunk class (chunk index mod 4), so that every output element gets the same sum
+// as in the K-split path above: four chains over the chunks of a class in
+// increasing K order, then ((p0 + p1) + p2) + p3 (a row's result therefore does not
+// depend on which path its batch takes).
+//
+// K is walked in stages of 4 chunks (128). Global loads are row-contiguous (16
+// lanes cover the 256 bytes of one row's stage, so every group of 4 lanes reads
+// one 64-byte segment): an MFMA fragment, 16 rows of 16 bytes per 16 lanes, would
+// touch 4 cache lines per group of 4 lanes. Each wave puts its own rows' A through
+// a private LDS region; the stage's B (the same for all 4 waves) is loaded once
+// per workgroup, spread over its 256 threads, into a double-buffered LDS stage.
+// Load group g = (A of stage g, B of stage g + 1) sits in register slot g mod PA,
+// PA groups in flight. Per stage: B of the next stage and A of this stage go from
+// registers to LDS, the MFMAs read their fragments from LDS, group g + PA is
+// issued into the freed slot, one workgroup barrier.
+constexpr int kRowPitch = 256 + 16;    // one row's stage in LDS, padded (rows on other banks)
+
+template <int RW, int CT, bool F32>
+struct MlpRowSlot {
+  uint4 a[4 * RW][F32 ? 2 : 1];  // A pieces (BF16 x 8, or FP32 x 8 rounded when stored to LDS)
+  uint4 b[CT];                   // this thread's pieces of the next stage's B
+};
+
+// Raw buffer loads: a 32-bit per-lane offset (the stage's offset is a scalar), and
+// an offset past the buffer's size reads zeros.
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mlp_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint4 bld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const i32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+  uint4 q;
+  __builtin_memcpy(&q, &v, 16);
+  return q;
+}
+
+// Where this thread's loads of a unit start (stage 0). A piece m of lane L is
+// segment L % 16 (8 elements) of wave row rho = 4 m + L / 16, i.e. row block
+// w + 4 (rho / 16), row rho % 16 of it. BF16 rows past the batch read whatever the
+// hidden state holds there (only their own, never stored, outputs see it); FP32
+// rows past the batch read row 0. B piece q of thread tid is segment p % 16 of
+// strip row p / 16, p = tid + 256 q.
+template <int RW, int CT, bool F32>
+struct MlpRowSrc {
+  const float* arow[F32 ? 4 * RW : 1];
+  uint32_t aoff[F32 ? 1 : 4 * RW];
+  uint32_t boff[CT];
+  __amdgpu_buffer_rsrc_t ra, rb;
+};
+
+template <int RW, int CT, bool F32>
+__device__ __forceinline__ void mlp_row_sources(MlpRowSrc<RW, CT, F32>& src, const uint8_t* const* rowptr,
+                                                const uint16_t* hin, int stride, const uint16_t* W, int K, int N,
+                                                int rows, int row0, int col0, int w, int lane, int tid) {
+#pragma unroll
+  for (int m = 0; m < 4 * RW; ++m) {
+    const int rho = 4 * m + (lane >> 4);
+    const int r = row0 + (w + 4 * (rho >> 4)) * 16 + (rho & 15);
+    if constexpr (F32) src.arow[m] = (const float*)rowptr[r < rows ? r : 0] + (lane & 15) * 8;
+    else src.aoff[m] = (uint32_t)((r * stride + (lane & 15) * 8) * 2);
+  }
+#pragma unroll
+  for (int q = 0; q < CT; ++q) {
+    const int p = tid + kThreads * q;
+    src.boff[q] = (uint32_t)(((col0 + (p >> 4)) * K + (p & 15) * 8) * 2);
+  }
+  src.ra = mlp_rsrc(hin, (int64_t)kMaxBatch * stride * 2);
+  src.rb = mlp_rsrc(W, (int64_t)N * K * 2);
+}
+
+// B pieces of stage st (past K within a row: the next row's weights, zeroed at
+// use; past the matrix: zeros).
+template <int RW, int CT, bool F32>
+__device__ __forceinline__ void mlp_row_issue_b(uint4 (&b)[CT], const MlpRowSrc<RW, CT, F32>& src, int st) {
+#pragma unroll
+  for (int q = 0; q < CT; ++q) b[q] = bld16(src.rb, src.boff[q], (uint32_t)st * 256u);
+}
+
+template <int RW, int CT, bool F32>
+__device__ __forceinline__ void mlp_row_issue(MlpRowSlot<RW, CT, F32>& r, const MlpRowSrc<RW, CT, F32>& src, int K,
+                                              int st, int lane) {
+#pragma unroll
+  for (int m = 0; m < 4 * RW; ++m) {
+    if constexpr (F32) {
+      // FP32 rows come from separate buffers: clamped global loads (K past the end
+      // reads column 0; zeroed at use)
+      const int k = st * 128 + (lane & 15) * 8;
+      const float* p = src.arow[m] + (k < K ? st * 128 : -(lane & 15) * 8);
+      r.a[m][0] = gld16(p);
+      r.a[m][1] = gld16(p + 4);
+    } else {
+      r.a[m][0] = bld16(src.ra, src.aoff[m], (uint32_t)st * 256u);
+    }
+  }
+  mlp_row_issue_b<RW, CT, F32>(r.b, src, st + 1);
+}
+
+template <int CT>
+__device__ __forceinline__ void mlp_row_stash_b(const uint4 (&b)[CT], uint8_t* buf, int tid) {
+#pragma unroll
+  for (int q = 0; q < CT; ++q) {
+    const int p = tid + kThreads * q;
+    *(uint4*)(buf + (p >> 4) * kRowPitch + (p & 15) * 16) = b[q];
+  }
+}
+
+// This wave's A pieces of the stage into its LDS region (FP32 rounded to BF16).
+template <int RW, int CT, bool F32>
+__device__ __forceinline__ void mlp_row_stash_a(const MlpRowSlot<RW, CT, F32>& r, uint8_t* reg, int lane) {
+#pragma unroll
+  for (int m = 0; m < 4 * RW; ++m) {
+    const int rho = 4 * m + (lane >> 4);
+    uint4 v;
+    if constexpr (F32) v = f32x8_to_bf16x8_bits(u4_as_f4(r.a[m][0]), u4_as_f4(r.a[m][1]));
+    else v = r.a[m][0];
+    *(uint4*)(reg + rho * kRowPitch + (lane & 15) * 16) = v;
+  }
+}
+
+// Fragments of chunk c of a stage from LDS; TAIL zeroes A and B past K.
+template <int RW, int CT>
+struct MlpRowFrag {
+  bf16x8 a[RW], b[CT];
+};
+
+template <int RW, int CT, bool TAIL>
+__device__ __forceinline__ void mlp_row_frag(MlpRowFrag<RW, CT>& f, const uint8_t* areg, const uint8_t* buf, int fo,
+                                             int c, bool tail) {
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    f.a[j] = *(const bf16x8*)(areg + j * 16 * kRowPitch + fo + c * 64);
+    if (TAIL && tail) f.a[j] = (bf16x8){};
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    f.b[t] = *(const bf16x8*)(buf + t * 16 * kRowPitch + fo + c * 64);
+    if (TAIL && tail) f.b[t] = (bf16x8){};
+  }
+}
+
+template <int RW, int CT>
+__device__ __forceinline__ void mlp_row_mfma_chunk(f32x4 (&acc)[RW][CT][4], const MlpRowFrag<RW, CT>& f, int c) {
+#pragma unroll
+  for (int t = 0; t < CT; ++t)
+#pragma unroll
+    for (int j = 0; j < RW; ++j)
+      acc[j][t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[j], f.b[t], acc[j][t][c], 0, 0, 0);
+}
+
+// MFMAs of one stage. A stage inside K is straight-line code with the fragments of
+// chunk c + 1 read while the MFMAs of chunk c run; the last stage skips the chunks
+// past K and zeroes the K tail.
+template <int RW, int CT>
+__device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT][4], const uint8_t* areg, const uint8_t* buf,
+                                             int K, int st, int lane) {
+  const int fo = (lane & 15) * kRowPitch + (lane >> 4) * 16;
+  if ((st + 1) * 128 <= K) {
+    MlpRowFrag<RW, CT> f[2];
+    mlp_row_frag<RW, CT, false>(f[0], areg, buf, fo, 0, false);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c < 3) mlp_row_frag<RW, CT, false>(f[(c + 1) & 1], areg, buf, fo, c + 1, false);
+      __builtin_amdgcn_sched_barrier(0);
+      mlp_row_mfma_chunk<RW, CT>(acc, f[c & 1], c);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k0 = st * 128 + c * 32;
+      if (k0 < K) {
+        MlpRowFrag<RW, CT> f;
+        mlp_row_frag<RW, CT, true>(f, areg, buf, fo, c, k0 + 32 > K && k0 + (lane >> 4) * 8 >= K);
+        mlp_row_mfma_chunk<RW, CT>(acc, f, c);
+      }
+    }
+  }
+}
+
+// load groups in flight per unit shape: as many as the registers hold without spills
+#ifndef MLP_PA
+#define MLP_PA(RW, CT, F32) ((F32) ? 2 : (RW) == 2 ? 2 : (CT) == 2 ? 4 : 6)
+#endif
+// LDS of the row path: the waves' A regions, then two B stage buffers
+constexpr int kMlpRowLds = 4 * 32 * kRowPitch + 2 * 32 * kRowPitch;
+
+// One unit: rows row0 .. row0 + 64 RW - 1 (wave w: row blocks w, w + 4, ...),
+// columns col0 .. col0 + 16 CT - 1. All 4 waves run every stage (the barriers).
+template <int RW, int CT, bool F32>
+__device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const uint16_t* hin, int stride,
+                                             const uint16_t* W, int K, int N, int rows, int row0, int col0,
+                                             bool last, uint16_t* hout, float* out, uint8_t* lds, int w, int lane,
+                                             int tid) {
+  constexpr int PA = MLP_PA(RW, CT, F32);                       // load groups in flight
+  constexpr int NB = 2;                                         // B stage buffers
+  static_assert(PA % NB == 0, "buffer of a stage must be known at compile time");
+  constexpr int SB = 16 * CT * kRowPitch;                       // bytes of one B stage buffer
+  static_assert(4 * 16 * RW * kRowPitch + NB * SB <= kMlpRowLds, "row path LDS");
+  uint8_t* areg = lds + w * 16 * RW * kRowPitch;
+  uint8_t* bbuf = lds + 4 * 16 * RW * kRowPitch;
+  MlpRowSrc<RW, CT, F32> src;
+  mlp_row_sources<RW, CT, F32>(src, rowptr, hin, stride, W, K, N, rows, row0, col0, w, lane, tid);
+  f32x4 acc[RW][CT][4];
+#pragma unroll
+  for (int j = 0; j < RW; ++j)
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[j][t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  // stages padded to a multiple of PA (padding stages load and do no MFMAs)
+  const int ns = ((K + 127) / 128 + PA - 1) / PA * PA;
+  MlpRowSlot<RW, CT, F32> sl[PA];
+  {
+    uint4 b0[CT];
+    __builtin_amdgcn_sched_barrier(0);
+    mlp_row_issue_b<RW, CT, F32>(b0, src, 0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int g = 0; g < PA; ++g) {
+      mlp_row_issue<RW, CT, F32>(sl[g], src, K, g, lane);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    mlp_row_stash_b<CT>(b0, bbuf, tid);
+    __syncthreads();
+  }
+  for (int s = 0; s < ns; s += PA) {
+#pragma unroll
+    for (int i = 0; i < PA; ++i) {
+      const int st = s + i;                 // s is a multiple of NB: the buffer of stage st is i % NB
+      __builtin_amdgcn_sched_barrier(0);
+      mlp_row_stash_b<CT>(sl[i].b, bbuf + ((i + 1) % NB) * SB, tid);
+      mlp_row_stash_a<RW, CT, F32>(sl[i], areg, lane);
+      // the wave's own A region: its writes are in place before its reads
+      wave_lds_sync();
+      __builtin_amdgcn_sched_barrier(0);
+      mlp_row_mfma<RW, CT>(acc, areg, bbuf + (i % NB) * SB, K, st, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      mlp_row_issue<RW, CT, F32>(sl[i], src, K, st + PA, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int col = col0 + t * 16 + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = row0 + (w + 4 * j) * 16 + (lane >> 4) * 4 + i;
+        if (row < rows) {
+          const float v = ((acc[j][t][0][i] + acc[j][t][1][i]) + acc[j][t][2][i]) + acc[j][t][3][i];
+          if (last) out[(int64_t)row * N + col] = v;
+          else hout[(int64_t)row * stride + col] = f32_to_bf16_rne(fmaxf(v, 0.f));
+        }
+      }
+    }
+  }
+}
+
+template <int RW, int CT, bool F32>
+__device__ __forceinline__ void mlp_row_layer(const uint8_t* const* rowptr, const uint16_t* hin, int stride,
+                                              const uint16_t* W, int K, int N, int rows, bool last, uint16_t* hout,
+                                              float* out, uint8_t* lds, int w, int lane, int tid) {
+  const int rpu = 4 * RW;                               // row blocks per unit
+  const int nrg = (((rows + 15) >> 4) + rpu - 1) / rpu, ncb = N / (16 * CT);
+  for (int u = blockIdx.x; u < nrg * ncb; u += gridDim.x) {
+    const int cb = u % ncb, row0 = (u / ncb) * rpu * 16;
+    mlp_row_unit<RW, CT, F32>(rowptr, hin, stride, W, K, N, rows, row0, cb * 16 * CT, last, hout, out, lds, w,
+                              lane, tid);
+  }
+}
+
+// All layers of a batch of 4 or more row blocks. Per layer the unit shape is the
+// largest of (8 row blocks x 2 strips), (4 x 2), (4 x 1) that still gives every
+// workgroup a unit (larger units read the activations and weights fewer times);
+// the first layer, whose FP32 rows take twice the registers, uses one row block
+// per wave.
+__device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out,
+                                             uint8_t* lds, int w, int lane, int tid) {
+  const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
+  const int nrt = (rows + 15) >> 4, P = gridDim.x;
+  for (int l = 0; l < L; ++l) {
+    if (l > 0 && !grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
+    const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
+    uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
+    const uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
+    const uint16_t* W = (const uint16_t*)a.sp.w[l];
+    const bool last = (l == L - 1);
+    const bool even = (N % 32) == 0;
+    const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
+    const uint8_t* const* rp = ctl->d_rowptr;
+    float* o = (float*)out;
+    if (l == 0) {
+      if (even && u12 >= P) mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+      else mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    } else if (even && nrt > 4 && u22 >= P) {
+      mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    } else if (even && u12 >= P) {
+      mlp_row_layer<1, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    } else {
+      mlp_row_layer<1, 1, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    }
+  }
+  return true;
+}
+
 __device__ __forceinline__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kMlpTileBytes];
+  // the K-split path's tile buffers and the row path's regions share the array
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kMlpTileBytes > kMlpRowLds ? 2 * kMlpTileBytes : kMlpRowLds];
   // the wave index is uniform across the wave: in a scalar register the per-chunk
   // conditions become scalar branches instead of exec-mask regions
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int nrb = (rows + 15) >> 4;
   const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
+  if (nrb >= 4) return mlp_rows_all(a, ctl, rows, out, lds, w, lane, tid);
   {
     // first layer: FP32 input rows
     const MlpIn in{ctl->d_rowptr, nullptr, (const uint16_t*)a.sp.w[0], stride, a.sp.dims[0], rows};

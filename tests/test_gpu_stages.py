@@ -146,7 +146,7 @@ def test_logmel_silence_and_impulse(torch, cm):
     assert np.all(np.abs(y[0] - np.log(1e-10)) < 1e-5 * abs(np.log(1e-10)))
 
 
-@pytest.mark.parametrize("rows", [1, 5, 16, 128])
+@pytest.mark.parametrize("rows", [1, 5, 16, 40, 77, 128])
 def test_mlp_bf16_parity(torch, cm, rows):
     ws, d_ws, (_, mlp, _) = c1_stages(torch)
     x = O.log_mel(G.c1_audio(min(rows, 4), seed=40 + rows)).astype(np.float32)
@@ -177,6 +177,36 @@ def test_mlp_batch_and_grid_invariant(torch, cm):
     f = full.cpu().numpy()
     assert np.array_equal(one.cpu().numpy()[0], f[37])
     assert np.array_equal(other.cpu().numpy(), f)
+    # every unit shape of the row-split path (shares 8 .. 256) and the K-split path
+    # (batches of up to 48 rows) give the same bits for a row
+    for share in (8, 64, 128, 256):
+        cm.camelot_stage_run(mlp, dx.data_ptr(), other.data_ptr(), 128, share, 0)
+        assert np.array_equal(other.cpu().numpy(), f), share
+    for lo, n in ((3, 40), (11, 77), (50, 49)):
+        part = torch.empty((n, 4096), dtype=torch.float32, device="cuda")
+        cm.camelot_stage_run(mlp, dx[lo:lo + n].data_ptr(), part.data_ptr(), n, 64, 0)
+        assert np.array_equal(part.cpu().numpy(), f[lo:lo + n]), (lo, n)
+
+
+@pytest.mark.parametrize("share", [8, 64, 256])
+def test_mlp_bf16_narrow_layers_and_k_tails(torch, cm, share):
+    """Layer widths that are odd multiples of 16 (one-strip units, K tails of 16 in
+    the next layer) and an input width that is not a multiple of 32."""
+    dims = (200, 144, 208, 48)
+    ws = G.c1_mlp_weights(3, dims=dims)
+    d_ws = [to_dev(torch, w.view(np.int16)) for w in ws]
+    mlp = cm.stage_desc(cm.STAGE_MLP_BF16, dims=dims, weights=[t.data_ptr() for t in d_ws])
+    x = G.rng("handoff", 91).standard_normal((100, 200)).astype(np.float32)
+    dx = to_dev(torch, x)
+    dy = torch.empty((100, 48), dtype=torch.float32, device="cuda")
+    one = torch.empty((1, 48), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    log(f"mlp narrow share={share}")
+    cm.camelot_stage_run(mlp, dx.data_ptr(), dy.data_ptr(), 100, share, 0)
+    cm.camelot_stage_run(mlp, dx[93:94].data_ptr(), one.data_ptr(), 1, share, 0)
+    y = dy.cpu().numpy()
+    assert O.normwise_err(y, O.mlp_bf16(x, ws)) <= 2e-2
+    assert np.array_equal(one.cpu().numpy()[0], y[93])
 
 
 def test_stage_run_rejects_bad_shares(torch, cm):
