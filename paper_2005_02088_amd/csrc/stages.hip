@@ -160,10 +160,32 @@ __device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, int rows) 
   }
 }
 
+// Raw buffer loads: a 32-bit per-lane offset (a scalar offset for the rest), and an
+// offset past the buffer's size reads zeros, so a load needs neither a 64-bit
+// address register nor clamping.
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mlp_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint4 bld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const i32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+  uint4 q;
+  __builtin_memcpy(&q, &v, 16);
+  return q;
+}
+__device__ __forceinline__ float4 u4_as_f4(uint4 u) {
+  float4 f;
+  __builtin_memcpy(&f, &u, 16);
+  return f;
+}
+
+__device__ __forceinline__ float bld4f(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
 // ------------------------------------------------------------------ top-k
-// One wave per row; each lane reads its strided slice (element lane + 64 t), a few
-// passes over a row that stays in cache. Order: larger value first, ties to the
-// smaller index.
+// One wave per row; the row sits in registers (lane: elements 4 (lane + 64 t) + e),
+// loaded in one round. Order: larger value first, ties to the smaller index.
 //
 // Candidate filter: the k-th largest of the 64 lane maxima is a lower bound tau of
 // the row's k-th largest value (those k maxima are k distinct elements), so every
@@ -213,23 +235,41 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
   __shared__ float m_val[kWaves][64];
   __shared__ float s_tau[kWaves];
   const int N = a.sp.dims[0], k = a.sp.k;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nt = (N - lane + 63) >> 6;         // elements in this lane's slice
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ncol = (N + 255) >> 8;             // columns of 256 elements (the last may be partial)
   const bool filter = k <= 64 && min(N, 64) >= k;
   for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
-    const float* s = (const float*)ctl->d_rowptr[r];
+    // the row pointer is the wave's (scalar registers: the buffer resource below is
+    // then scalar too)
+    const uint64_t sp = (uint64_t)ctl->d_rowptr[r];
+    const float* s = (const float*)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sp >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)sp));
+    // the row in registers: v[4 t + e] holds element 4 (lane + 64 t) + e, 16 loads of
+    // 16 bytes per lane issued together. Past N the value is -inf with an index >= N,
+    // which every real element beats (larger, or equal with a smaller index), so
+    // such padding never enters the result; a lane's elements are a disjoint subset,
+    // so the lane maxima bound still holds.
+    const __amdgpu_buffer_rsrc_t rs = mlp_rsrc(s, (int64_t)N * 4);
+    float v[kTopkMaxN / 64];
+#pragma unroll
+    for (int t = 0; t < kTopkMaxN / 256; ++t) {
+      const float4 q = u4_as_f4(bld16(rs, (uint32_t)lane * 16u, (uint32_t)t * 1024u));
+      const int i0 = 4 * (lane + 64 * t);
+      v[4 * t + 0] = i0 + 0 < N ? q.x : -__builtin_inff();
+      v[4 * t + 1] = i0 + 1 < N ? q.y : -__builtin_inff();
+      v[4 * t + 2] = i0 + 2 < N ? q.z : -__builtin_inff();
+      v[4 * t + 3] = i0 + 3 < N ? q.w : -__builtin_inff();
+    }
     // threshold tau (all elements are candidates without the filter)
     float tau = -__builtin_inff();
     if (filter) {
       float m = -__builtin_inff();
-#pragma unroll 8
-      for (int t = 0; t < nt; ++t) {
-        const float v = s[lane + 64 * t];
-        m = v > m ? v : m;
-      }
+#pragma unroll
+      for (int j = 0; j < kTopkMaxN / 64; ++j) m = v[j] > m ? v[j] : m;
       m_val[w][lane] = m;
       wave_lds_sync();
       int rank = 0;
+#pragma unroll 16
       for (int j = 0; j < 64; ++j) {
         const float o = m_val[w][j];
         rank += (o > m || (o == m && j < lane)) ? 1 : 0;
@@ -238,12 +278,10 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
       wave_lds_sync();
       tau = s_tau[w];
     }
-    int cnt = nt;
-    if (filter) {
-      cnt = 0;
-#pragma unroll 8
-      for (int t = 0; t < nt; ++t) cnt += s[lane + 64 * t] >= tau ? 1 : 0;
-    }
+    // elements of the row's columns of 256 that pass the filter
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kTopkMaxN / 64; ++j) cnt += ((j >> 2) < ncol && v[j] >= tau) ? 1 : 0;
     int incl = cnt;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -253,12 +291,11 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
     const int C = __shfl(incl, 63, 64);
     if (C <= kTopkCand) {
       int pos = incl - cnt;
-      for (int t = 0; t < nt; ++t) {
-        const int i = lane + 64 * t;
-        const float v = s[i];
-        if (!filter || v >= tau) {
-          c_val[w][pos] = v;
-          c_idx[w][pos] = i;
+#pragma unroll
+      for (int j = 0; j < kTopkMaxN / 64; ++j) {
+        if ((j >> 2) < ncol && v[j] >= tau) {
+          c_val[w][pos] = v[j];
+          c_idx[w][pos] = 4 * (lane + 64 * (j >> 2)) + (j & 3);
           ++pos;
         }
       }
@@ -267,6 +304,7 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
         const float vc = c_val[w][c];
         const int ic = c_idx[w][c];
         int rank = 0;
+#pragma unroll 8
         for (int j = 0; j < C; ++j) {
           const float o = c_val[w][j];
           rank += (o > vc || (o == vc && c_idx[w][j] < ic)) ? 1 : 0;
@@ -300,22 +338,34 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
   const float2* tw512 = (const float2*)(tab + kTabTw512);
   const float* meta = tab + kTabMelMeta;
   const float* melw = tab + kTabMelW;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   float* Y = (float*)out;
-  const int units = rows * 11;
-  for (int u = blockIdx.x * kWaves + w; u < units; u += gridDim.x * kWaves) {
+  const int units = rows * 11, stride = gridDim.x * kWaves;
+  // the samples of a (row, frame) unit: 200 float2 per frame, lane + 64 q; the next
+  // unit's are loaded (global loads, no branches: the last piece is clamped) while
+  // this one is transformed
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  typedef const f32x2_t __attribute__((address_space(1)))* gptr_f2;
+  f32x2_t xr[4];
+  auto load_unit = [&](int uu) {
+    const int r = uu / 11, f = uu - r * 11;
+    const gptr_f2 x2 = (gptr_f2)((const float*)ctl->d_rowptr[r] + f * 160);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) xr[q] = x2[lane + 64 * q];
+    xr[3] = x2[lane + 192 < 200 ? lane + 192 : 199];
+  };
+  int u = blockIdx.x * kWaves + w;
+  if (u < units) load_unit(u);
+  for (; u < units; u += stride) {
     const int r = u / 11, f = u - r * 11;
-    const float2* x2 = (const float2*)((const float*)ctl->d_rowptr[r] + f * 160);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int n = lane + 64 * q;
       float2 z = make_float2(0.f, 0.f);
-      if (n < 200) {
-        const float2 v = x2[n];
-        z = make_float2(v.x * win[2 * n], v.y * win[2 * n + 1]);
-      }
+      if (n < 200) z = make_float2(xr[q].x * win[2 * n], xr[q].y * win[2 * n + 1]);
       fbuf[w][0][n] = z;
     }
+    if (u + stride < units) load_unit(u + stride);
     wave_lds_sync();
     int src = 0;
     for (int ns = 1; ns < 256; ns *= 4) {
@@ -358,6 +408,7 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
     if (lane < 40) {
       const int lo = (int)meta[3 * lane], cnt = (int)meta[3 * lane + 1], off = (int)meta[3 * lane + 2];
       float e = 0.f;
+#pragma unroll 4
       for (int t = 0; t < cnt; ++t) e = fmaf(melw[off + t], pbuf[w][lo + t], e);
       Y[(int64_t)r * 440 + f * 40 + lane] = logf(fmaxf(e, 1e-10f));
     }
@@ -399,12 +450,6 @@ __device__ __forceinline__ bf16x8 ld_bf16x8(const uint16_t* p) {
   bf16x8 r;
   __builtin_memcpy(&r, &q, 16);
   return r;
-}
-
-__device__ __forceinline__ float4 u4_as_f4(uint4 u) {
-  float4 f;
-  __builtin_memcpy(&f, &u, 16);
-  return f;
 }
 
 __device__ __forceinline__ uint4 f32x8_to_bf16x8_bits(const float4 a, const float4 b) {
@@ -720,19 +765,6 @@ struct MlpRowSlot {
   uint4 a[4 * RW][F32 ? 2 : 1];  // A pieces (BF16 x 8, or FP32 x 8 rounded when stored to LDS)
   uint4 b[CT];                   // this thread's pieces of the next stage's B
 };
-
-// Raw buffer loads: a 32-bit per-lane offset (the stage's offset is a scalar), and
-// an offset past the buffer's size reads zeros.
-typedef int i32x4_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t mlp_rsrc(const void* base, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ uint4 bld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  const i32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
-  uint4 q;
-  __builtin_memcpy(&q, &v, 16);
-  return q;
-}
 
 // Where this thread's loads of a unit start (stage 0). A piece m of lane L is
 // segment L % 16 (8 elements) of wave row rho = 4 m + L / 16, i.e. row block
