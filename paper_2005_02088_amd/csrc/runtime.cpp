@@ -326,6 +326,7 @@ static int64_t stage_scratch_bytes(const camelot_stage_desc* d, int* stride) {
   if (d->kind != CAMELOT_STAGE_MLP_BF16) return 0;
   int mx = 0;
   for (int l = 0; l <= d->n_layers; ++l) mx = std::max(mx, d->dims[l]);
+  mx = (mx + 31) & ~31;    // whole 32-wide chunks (the fragment layout of the row path)
   *stride = mx;
   return 2LL * kMaxBatch * mx * 2;
 }

@@ -775,7 +775,7 @@ struct MlpRowSlot {
 template <int RW, int CT, bool F32>
 struct MlpRowSrc {
   const float* arow[F32 ? 4 * RW : 1];
-  uint32_t aoff[F32 ? 1 : 4 * RW];
+  uint32_t aoff[F32 ? 1 : RW];
   uint32_t boff[CT];
   __amdgpu_buffer_rsrc_t ra, rb;
 };
@@ -784,12 +784,20 @@ template <int RW, int CT, bool F32>
 __device__ __forceinline__ void mlp_row_sources(MlpRowSrc<RW, CT, F32>& src, const uint8_t* const* rowptr,
                                                 const uint16_t* hin, int stride, const uint16_t* W, int K, int N,
                                                 int rows, int row0, int col0, int w, int lane, int tid) {
+  if constexpr (F32) {
 #pragma unroll
-  for (int m = 0; m < 4 * RW; ++m) {
-    const int rho = 4 * m + (lane >> 4);
-    const int r = row0 + (w + 4 * (rho >> 4)) * 16 + (rho & 15);
-    if constexpr (F32) src.arow[m] = (const float*)rowptr[r < rows ? r : 0] + (lane & 15) * 8;
-    else src.aoff[m] = (uint32_t)((r * stride + (lane & 15) * 8) * 2);
+    for (int m = 0; m < 4 * RW; ++m) {
+      const int rho = 4 * m + (lane >> 4);
+      const int r = row0 + (w + 4 * (rho >> 4)) * 16 + (rho & 15);
+      src.arow[m] = (const float*)rowptr[r < rows ? r : 0] + (lane & 15) * 8;
+    }
+  } else {
+    // the hidden state is in fragment order: row block rb, chunk c at
+    // (rb nck + c) KiB, lane l's 16 bytes at 16 l (rows past the batch hold
+    // whatever is there; only their own, never stored, outputs see it)
+    const int nck = (K + 31) >> 5;
+#pragma unroll
+    for (int j = 0; j < RW; ++j) src.aoff[j] = (uint32_t)((((row0 >> 4) + w + 4 * j) * nck * 64 + lane) * 16);
   }
 #pragma unroll
   for (int q = 0; q < CT; ++q) {
@@ -821,7 +829,8 @@ __device__ __forceinline__ void mlp_row_issue(MlpRowSlot<RW, CT, F32>& r, const 
       r.a[m][0] = gld16(p);
       r.a[m][1] = gld16(p + 4);
     } else {
-      r.a[m][0] = bld16(src.ra, src.aoff[m], (uint32_t)st * 256u);
+      // fragment m = c RW + j: chunk c of the stage, row block j
+      r.a[m][0] = bld16(src.ra, src.aoff[m % RW] + (m / RW) * 1024u, (uint32_t)st * 4096u);
     }
   }
   mlp_row_issue_b<RW, CT, F32>(r.b, src, st + 1);
@@ -849,19 +858,26 @@ __device__ __forceinline__ void mlp_row_stash_a(const MlpRowSlot<RW, CT, F32>& r
   }
 }
 
-// Fragments of chunk c of a stage from LDS; TAIL zeroes A and B past K.
+// Fragments of chunk c of a stage: B from LDS; A from the wave's LDS region (FP32
+// rows, staged) or straight from the slot registers (the hidden state, loaded in
+// fragment order). TAIL zeroes A and B past K.
 template <int RW, int CT>
 struct MlpRowFrag {
   bf16x8 a[RW], b[CT];
 };
 
-template <int RW, int CT, bool TAIL>
-__device__ __forceinline__ void mlp_row_frag(MlpRowFrag<RW, CT>& f, const uint8_t* areg, const uint8_t* buf, int fo,
-                                             int c, bool tail) {
+template <int RW, int CT, bool F32, bool TAIL>
+__device__ __forceinline__ void mlp_row_frag(MlpRowFrag<RW, CT>& f, const MlpRowSlot<RW, CT, F32>& sl,
+                                             const uint8_t* areg, const uint8_t* buf, int fo, int c, bool tail) {
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
-    f.a[j] = *(const bf16x8*)(areg + j * 16 * kRowPitch + fo + c * 64);
-    if (TAIL && tail) f.a[j] = (bf16x8){};
+    if constexpr (F32) {
+      f.a[j] = *(const bf16x8*)(areg + j * 16 * kRowPitch + fo + c * 64);
+      if (TAIL && tail) f.a[j] = (bf16x8){};
+    } else if constexpr (TAIL) {
+      __builtin_memcpy(&f.a[j], &sl.a[c * RW + j][0], 16);
+      if (tail) f.a[j] = (bf16x8){};
+    }
   }
 #pragma unroll
   for (int t = 0; t < CT; ++t) {
@@ -870,30 +886,37 @@ __device__ __forceinline__ void mlp_row_frag(MlpRowFrag<RW, CT>& f, const uint8_
   }
 }
 
-template <int RW, int CT>
-__device__ __forceinline__ void mlp_row_mfma_chunk(f32x4 (&acc)[RW][CT][4], const MlpRowFrag<RW, CT>& f, int c) {
+// A operand: the fragment read into f (FP32 rows, or a zeroed tail), else the slot
+// register itself (no copy).
+template <int RW, int CT, bool F32, bool TAIL>
+__device__ __forceinline__ void mlp_row_mfma_chunk(f32x4 (&acc)[RW][CT][4], const MlpRowFrag<RW, CT>& f,
+                                                   const MlpRowSlot<RW, CT, F32>& sl, int c) {
 #pragma unroll
   for (int t = 0; t < CT; ++t)
 #pragma unroll
-    for (int j = 0; j < RW; ++j)
-      acc[j][t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[j], f.b[t], acc[j][t][c], 0, 0, 0);
+    for (int j = 0; j < RW; ++j) {
+      bf16x8 av;
+      if constexpr (F32 || TAIL) av = f.a[j];
+      else __builtin_memcpy(&av, &sl.a[c * RW + j][0], 16);
+      acc[j][t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, f.b[t], acc[j][t][c], 0, 0, 0);
+    }
 }
 
 // MFMAs of one stage. A stage inside K is straight-line code with the fragments of
 // chunk c + 1 read while the MFMAs of chunk c run; the last stage skips the chunks
 // past K and zeroes the K tail.
-template <int RW, int CT>
-__device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT][4], const uint8_t* areg, const uint8_t* buf,
-                                             int K, int st, int lane) {
+template <int RW, int CT, bool F32>
+__device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT][4], const MlpRowSlot<RW, CT, F32>& sl,
+                                             const uint8_t* areg, const uint8_t* buf, int K, int st, int lane) {
   const int fo = (lane & 15) * kRowPitch + (lane >> 4) * 16;
   if ((st + 1) * 128 <= K) {
     MlpRowFrag<RW, CT> f[2];
-    mlp_row_frag<RW, CT, false>(f[0], areg, buf, fo, 0, false);
+    mlp_row_frag<RW, CT, F32, false>(f[0], sl, areg, buf, fo, 0, false);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      if (c < 3) mlp_row_frag<RW, CT, false>(f[(c + 1) & 1], areg, buf, fo, c + 1, false);
+      if (c < 3) mlp_row_frag<RW, CT, F32, false>(f[(c + 1) & 1], sl, areg, buf, fo, c + 1, false);
       __builtin_amdgcn_sched_barrier(0);
-      mlp_row_mfma_chunk<RW, CT>(acc, f[c & 1], c);
+      mlp_row_mfma_chunk<RW, CT, F32, false>(acc, f[c & 1], sl, c);
       __builtin_amdgcn_sched_barrier(0);
     }
   } else {
@@ -902,8 +925,8 @@ __device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT][4], const uint
       const int k0 = st * 128 + c * 32;
       if (k0 < K) {
         MlpRowFrag<RW, CT> f;
-        mlp_row_frag<RW, CT, true>(f, areg, buf, fo, c, k0 + 32 > K && k0 + (lane >> 4) * 8 >= K);
-        mlp_row_mfma_chunk<RW, CT>(acc, f, c);
+        mlp_row_frag<RW, CT, F32, true>(f, sl, areg, buf, fo, c, k0 + 32 > K && k0 + (lane >> 4) * 8 >= K);
+        mlp_row_mfma_chunk<RW, CT, F32, true>(acc, f, sl, c);
       }
     }
   }
@@ -961,17 +984,20 @@ __device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const
       const int st = s + i;                 // s is a multiple of NB: the buffer of stage st is i % NB
       __builtin_amdgcn_sched_barrier(0);
       mlp_row_stash_b<CT>(sl[i].b, bbuf + ((i + 1) % NB) * SB, tid);
-      mlp_row_stash_a<RW, CT, F32>(sl[i], areg, lane);
-      // the wave's own A region: its writes are in place before its reads
-      wave_lds_sync();
+      if constexpr (F32) {
+        mlp_row_stash_a<RW, CT, F32>(sl[i], areg, lane);
+        // the wave's own A region: its writes are in place before its reads
+        wave_lds_sync();
+      }
       __builtin_amdgcn_sched_barrier(0);
-      mlp_row_mfma<RW, CT>(acc, areg, bbuf + (i % NB) * SB, K, st, lane);
+      mlp_row_mfma<RW, CT, F32>(acc, sl[i], areg, bbuf + (i % NB) * SB, K, st, lane);
       __builtin_amdgcn_sched_barrier(0);
       mlp_row_issue<RW, CT, F32>(sl[i], src, K, st + PA, lane);
       __builtin_amdgcn_sched_barrier(0);
       __syncthreads();
     }
   }
+  const int nckn = (N + 31) >> 5;
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
 #pragma unroll
@@ -982,8 +1008,15 @@ __device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const
         const int row = row0 + (w + 4 * j) * 16 + (lane >> 4) * 4 + i;
         if (row < rows) {
           const float v = ((acc[j][t][0][i] + acc[j][t][1][i]) + acc[j][t][2][i]) + acc[j][t][3][i];
-          if (last) out[(int64_t)row * N + col] = v;
-          else hout[(int64_t)row * stride + col] = f32_to_bf16_rne(fmaxf(v, 0.f));
+          if (last) {
+            out[(int64_t)row * N + col] = v;
+          } else {
+            // the next layer reads the hidden state in fragment order (row block,
+            // 32-wide chunk, lane = row % 16 + 16 ((col % 32) / 8), element col % 8)
+            const int64_t e = ((int64_t)((row >> 4) * nckn + (col >> 5)) * 64 + (row & 15) + 16 * ((col & 31) >> 3)) * 8 +
+                              (col & 7);
+            hout[e] = f32_to_bf16_rne(fmaxf(v, 0.f));
+          }
         }
       }
     }
