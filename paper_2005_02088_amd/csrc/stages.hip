@@ -417,22 +417,6 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
 }
 
 // ------------------------------------------------------------------ BF16 MLP chain on MFMA
-// Per layer: unit = 16 output columns (one strip) per workgroup; the 4 waves split
-// K in interleaved 32-wide chunks (wave w owns chunks w, w + 4, w + 8, ...) on
-// v_mfma_f32_16x16x32_bf16 for up to 8 row blocks of 16 rows; the 4 partial tiles
-// are added in LDS as ((p0 + p1) + p2) + p3, then ReLU and BF16 rounding (hidden
-// layers) or the FP32 store (last layer). Layers are separated by grid barriers.
-// Weights are [N][K] BF16 (K contiguous). Every output element's sum therefore has
-// one fixed order, whatever the batch, the row's position or the grid.
-//
-// Data movement: each wave keeps its weight fragments of a 2048-wide K segment in
-// registers (64 KB per strip and workgroup, loaded once; the next layer's first
-// segment is loaded while the workgroup waits at the layer barrier). Activations
-// go through LDS in tiles of (row blocks x K chunks) = 32 chunk-blocks (32 KB): all
-// 256 threads load a tile with 16-byte loads, two tiles ahead in registers, while
-// the waves run the MFMAs of the tile in LDS, so an L2 round trip is hidden behind
-// two tiles of MFMAs. With NP2 row blocks (1, 2, 4 or 8; the batch rounded up) a
-// tile spans 32 / NP2 chunks.
 // 16-byte load from global memory (explicitly in the global address space, so it
 // is a global load counted by vmcnt only, never a flat load that also holds up
 // every LDS wait).
@@ -461,303 +445,27 @@ __device__ __forceinline__ uint4 f32x8_to_bf16x8_bits(const float4 a, const floa
   return q;
 }
 
-constexpr int kMlpTilePieces = 1024;    // 16-byte pieces per activation tile (16 KB)
-constexpr int kMlpPiecesPerThread = kMlpTilePieces / kThreads;
-constexpr int kMlpTileBytes = 64 * (4 * 64 + 16);    // largest tile with its row padding
-static_assert(kMlpTilePieces % kThreads == 0, "tile pieces per thread");
-
-// Geometry of an activation tile in LDS: RB row blocks of 16 rows x TKC chunks of
-// 32, elements BF16 (hidden layers) or FP32 (the first layer's input rows, rounded
-// to BF16 when read for the MFMA). Every tile is 1024 pieces of 16 bytes, 4 per
-// thread; a thread's piece j lies in row block j * RB / 4 of the tile. Each wave
-// takes Q = TKC / 4 of a tile's chunks (wave w: chunks w, w + 4, ...). A batch of
-// more than 16 RB rows is done in passes of 16 RB rows over the strip's K.
-template <int RB_, int TKC_, bool F32_>
-struct MlpGeo {
-  static constexpr int RB = RB_, TKC = TKC_;
-  static constexpr bool F32 = F32_;
-  static constexpr int ESZ = F32 ? 4 : 2;
-  static constexpr int EPP = 16 / ESZ;                 // elements per piece
-  static constexpr int PPR = TKC * 32 / EPP;           // pieces per tile row
-  static constexpr int PITCH = TKC * 32 * ESZ + 16;    // padded row: rows fall on different banks
-  static constexpr int Q = TKC / 4;
-  static_assert(RB * 16 * PPR == kMlpTilePieces, "tile size");
-  static_assert(RB * 16 * PITCH <= kMlpTileBytes, "tile bytes");
-};
-using MlpGeoWide = MlpGeo<4, 4, false>;    // BF16, batches of 17..128 rows, 64 rows per pass
-using MlpGeoOne = MlpGeo<1, 16, false>;    // BF16, up to 16 rows
-using MlpGeoF32 = MlpGeo<2, 4, true>;      // FP32 first layer, 32 rows per pass
-
-struct MlpIn {
-  const uint8_t* const* rowptr;   // FP32 input rows (first layer)
-  const uint16_t* hin;            // BF16 hidden state [rows][stride] (later layers)
-  const uint16_t* W;              // weights [N][K]
-  int stride, K, rows;
-};
-
-// A tile in flight: its activation pieces and this wave's weight fragments.
-template <class G>
-struct MlpTileRegs {
-  uint4 a[kMlpPiecesPerThread];
-  bf16x8 b[G::Q];
-};
-
-// Activation pieces of tile g (chunks g * TKC ..) for rows row0 .. row0 + 16 RB - 1.
-// Rows past the batch read row 0 and K past the end reads column 0: those values
-// only meet zero weights or feed output rows that are never stored. The loads of
-// the tile pipeline are never inside a branch: the compiler then knows exactly
-// which loads are still in flight and waits only for the ones a step needs.
-template <class G>
-__device__ __forceinline__ void mlp_issue_a(MlpTileRegs<G>& r, const MlpIn& in, int row0, int g, int tid) {
-#pragma unroll
-  for (int j = 0; j < kMlpPiecesPerThread; ++j) {
-    const int p = tid + kThreads * j;
-    const int row = row0 + p / G::PPR, cp = p % G::PPR;
-    const int r0 = row < in.rows ? row : 0;
-    const int k = g * G::TKC * 32 + cp * G::EPP;
-    const int kc = k < in.K ? k : 0;
-    if constexpr (G::F32) r.a[j] = gld16((const float*)in.rowptr[r0] + kc);
-    else r.a[j] = gld16(in.hin + (int64_t)r0 * in.stride + kc);
-  }
-}
-
-// This wave's weight fragments of tile g of a strip (clamped past K; a K tail that
-// is not a multiple of 32 is zeroed at use).
-template <class G>
-__device__ __forceinline__ void mlp_issue_b(MlpTileRegs<G>& r, const uint16_t* W, int K, int strip, int g, int w,
-                                            int lane) {
-  const uint16_t* wrow = W + (int64_t)(strip * 16 + (lane & 15)) * K;
-#pragma unroll
-  for (int q = 0; q < G::Q; ++q) {
-    const int kb = (g * G::TKC + w + 4 * q) * 32 + (lane >> 4) * 8;
-    r.b[q] = ld_bf16x8(wrow + (kb < K ? kb : 0));
-  }
-}
-
-template <class G>
-__device__ __forceinline__ void mlp_store_a(const MlpTileRegs<G>& r, uint8_t* lds, int tid) {
-#pragma unroll
-  for (int j = 0; j < kMlpPiecesPerThread; ++j) {
-    const int p = tid + kThreads * j;
-    *(uint4*)(lds + (p / G::PPR) * G::PITCH + (p % G::PPR) * 16) = r.a[j];
-  }
-}
-
-// A fragment (16 rows x 32 of chunk c) of row block rb from the tile in LDS.
-template <class G>
-__device__ __forceinline__ bf16x8 mlp_lds_frag(const uint8_t* lds, int rb, int c, int lane) {
-  const uint8_t* p = lds + (rb * 16 + (lane & 15)) * G::PITCH + (c * 32 + (lane >> 4) * 8) * G::ESZ;
-  if constexpr (G::F32) {
-    const uint4 q = f32x8_to_bf16x8_bits(*(const float4*)p, *(const float4*)(p + 16));
-    bf16x8 r;
-    __builtin_memcpy(&r, &q, 16);
-    return r;
-  } else {
-    return *(const bf16x8*)p;
-  }
-}
-
-// MFMAs of tile g (in LDS) for this wave's chunks; row block rb of the tile
-// accumulates into acc[AB + rb].
-template <class G, int AB>
-__device__ __forceinline__ void mlp_mfma_tile(f32x4 (&acc)[8], const MlpTileRegs<G>& r, const uint8_t* lds,
-                                              int g, int K, int nrb, int w, int lane) {
-#pragma unroll
-  for (int q = 0; q < G::Q; ++q) {
-    const int c = w + 4 * q;
-    const int k0 = (g * G::TKC + c) * 32;
-    if (k0 < K) {
-      bf16x8 bf = r.b[q];
-      if (k0 + 32 > K && k0 + (lane >> 4) * 8 >= K) bf = (bf16x8){};
-#pragma unroll
-      for (int rb = 0; rb < G::RB; ++rb) {
-        if (rb < nrb) acc[AB + rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mlp_lds_frag<G>(lds, rb, c, lane), bf,
-                                                                             acc[AB + rb], 0, 0, 0);
-      }
-    }
-  }
-}
-
-// One step of the tile pipeline: tile g from registers to LDS buffer BUF, the
-// loads of tile g + 2 into the same registers (the last tile again near the end:
-// unused, but it keeps the loads out of branches), the MFMAs of tile g.
-template <class G, int AB, int BUF>
-__device__ __forceinline__ void mlp_step(f32x4 (&acc)[8], MlpTileRegs<G>& cur, uint8_t* lds, const MlpIn& in,
-                                         int row0, int nrb, int strip, int g, int ntiles, int w, int lane, int tid) {
-  uint8_t* buf = lds + BUF * kMlpTileBytes;
-  const int gn = min(g + 2, ntiles - 1);
-  // scheduling barriers keep the load groups in program order, so that the wait
-  // before a tile's store only covers that tile's loads (the other register set's,
-  // issued later, stay in flight)
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_store_a<G>(cur, buf, tid);
-  __syncthreads();
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_issue_a<G>(cur, in, row0, gn, tid);
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_mfma_tile<G, AB>(acc, cur, buf, g, in.K, nrb, w, lane);
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_issue_b<G>(cur, in.W, in.K, strip, gn, w, lane);
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-// One pass over the K of a strip for rows row0 .. row0 + 16 RB - 1 (nrb row blocks
-// of them in the batch). Two tiles are in flight in registers while the tile in
-// LDS (double-buffered, one workgroup barrier per tile) feeds the MFMAs; every
-// wave adds its chunks in increasing K order. have_b: the weight fragments of
-// tiles 0 and 1 are already in ra / rb_ (loaded across the layer barrier).
-template <class G, int AB>
-__device__ __forceinline__ void mlp_pass(f32x4 (&acc)[8], MlpTileRegs<G>& ra, MlpTileRegs<G>& rb_, bool have_b,
-                                         uint8_t* lds, const MlpIn& in, int row0, int nrb, int strip, int w,
-                                         int lane, int tid) {
-  // an even number of tiles (a padding tile past K does no MFMAs)
-  const int ntiles = ((in.K + G::TKC * 32 - 1) / (G::TKC * 32) + 1) & ~1;
-  // same load order as the steady state (pieces, then weights, per register set)
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_issue_a<G>(ra, in, row0, 0, tid);
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_issue_b<G>(ra, in.W, in.K, strip, 0, w, lane);
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_issue_a<G>(rb_, in, row0, 1, tid);
-  __builtin_amdgcn_sched_barrier(0);
-  mlp_issue_b<G>(rb_, in.W, in.K, strip, 1, w, lane);
-  __builtin_amdgcn_sched_barrier(0);
-  for (int g = 0; g < ntiles; g += 2) {
-    mlp_step<G, AB, 0>(acc, ra, lds, in, row0, nrb, strip, g, ntiles, w, lane, tid);
-    mlp_step<G, AB, 1>(acc, rb_, lds, in, row0, nrb, strip, g + 1, ntiles, w, lane, tid);
-  }
-  __syncthreads();                           // tile buffers free for the next pass or the reduction
-}
-
-// The passes of a strip: rows 16 RB H .. 16 RB (H + 1) - 1 in pass H (only the
-// first pass can use weight registers loaded across the layer barrier).
-template <class G, int H>
-__device__ __forceinline__ void mlp_passes(f32x4 (&acc)[8], MlpTileRegs<G>& ra, MlpTileRegs<G>& rb_, bool have_b,
-                                           uint8_t* lds, const MlpIn& in, int nrb, int strip, int w, int lane,
-                                           int tid) {
-  if constexpr (H * G::RB < 8) {
-    if (H * G::RB < nrb) {
-      mlp_pass<G, H * G::RB>(acc, ra, rb_, have_b, lds, in, H * G::RB * 16, min(nrb - H * G::RB, G::RB), strip, w,
-                             lane, tid);
-      mlp_passes<G, H + 1>(acc, ra, rb_, false, lds, in, nrb, strip, w, lane, tid);
-    }
-  }
-}
-
-// One layer: every strip of this workgroup, then ReLU + BF16 (hidden layers) or the
-// FP32 store (last layer).
-template <class G>
-__device__ __forceinline__ void mlp_layer(bool have_b, uint8_t* lds, const MlpIn& in, int N, bool last,
-                                          uint16_t* hout, uint8_t* out, int nrb, int w, int lane, int tid) {
-  float (*part)[8][256] = (float (*)[8][256])lds;      // the reduction reuses the tile buffers
-  MlpTileRegs<G> ra, rb_;
-  for (int strip = blockIdx.x; strip < (N >> 4); strip += gridDim.x) {
-    f32x4 acc[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) acc[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    mlp_passes<G, 0>(acc, ra, rb_, have_b, lds, in, nrb, strip, w, lane, tid);
-    have_b = false;
-#pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
-      if (rb < nrb) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) part[w][rb][((lane >> 4) * 4 + i) * 16 + (lane & 15)] = acc[rb][i];
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < nrb * 256; i += kThreads) {
-      const int rb = i >> 8, e = i & 255, row = rb * 16 + (e >> 4), col = strip * 16 + (e & 15);
-      if (row < in.rows) {
-        const float s = ((part[0][rb][e] + part[1][rb][e]) + part[2][rb][e]) + part[3][rb][e];
-        if (last) ((float*)out)[(int64_t)row * N + col] = s;
-        else hout[(int64_t)row * in.stride + col] = f32_to_bf16_rne(fmaxf(s, 0.f));
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Layer l + 1's first two weight tiles for this workgroup's first strip, loaded
-// while waiting at the layer barrier (weights are constant; only the activations
-// need the barrier); the registers are handed to that layer's first pass.
-template <class G>
-__device__ __forceinline__ bool mlp_barrier_prefetch(WorkerCtl* ctl, const WorkerArgs& a, int l, int nrb_unused,
-                                                     MlpTileRegs<G>& ra, MlpTileRegs<G>& rb_, int w, int lane,
-                                                     bool* have_b) {
-  const BarTicket t = grid_arrive(ctl, gridDim.x);
-  const int K = a.sp.dims[l + 1], N = a.sp.dims[l + 2];
-  *have_b = (int)blockIdx.x < (N >> 4);
-  if (*have_b) {
-    const uint16_t* W = (const uint16_t*)a.sp.w[l + 1];
-    mlp_issue_b<G>(ra, W, K, blockIdx.x, 0, w, lane);
-    mlp_issue_b<G>(rb_, W, K, blockIdx.x, 1, w, lane);
-  }
-  return grid_wait(ctl, gridDim.x, t, a.spin_ticks);
-}
-
-// Hidden and last layers (l >= 1) with geometry G; the first layer is run by the
-// caller. The registers of the first two weight tiles cross the layer barriers.
-template <class G>
-__device__ __forceinline__ bool mlp_rest(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out, uint8_t* lds,
-                                         int w, int lane, int tid) {
-  const int L = a.sp.n_layers, nrb = (rows + 15) >> 4, stride = a.sp.scratch_stride;
-  MlpTileRegs<G> ra, rb_;
-  bool have_b = false;
-  if (!mlp_barrier_prefetch<G>(ctl, a, 0, nrb, ra, rb_, w, lane, &have_b)) return false;
-  for (int l = 1; l < L; ++l) {
-    const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
-    uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
-    const MlpIn in{ctl->d_rowptr, a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride,
-                   (const uint16_t*)a.sp.w[l], stride, K, rows};
-    const bool last = (l == L - 1);
-    // the first strip takes over the prefetched weight registers
-    float (*part)[8][256] = (float (*)[8][256])lds;
-    for (int strip = blockIdx.x; strip < (N >> 4); strip += gridDim.x) {
-      f32x4 acc[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) acc[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      mlp_passes<G, 0>(acc, ra, rb_, have_b && strip == (int)blockIdx.x, lds, in, nrb, strip, w, lane, tid);
-#pragma unroll
-      for (int rb = 0; rb < 8; ++rb) {
-        if (rb < nrb) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) part[w][rb][((lane >> 4) * 4 + i) * 16 + (lane & 15)] = acc[rb][i];
-        }
-      }
-      __syncthreads();
-      for (int i = tid; i < nrb * 256; i += kThreads) {
-        const int rb = i >> 8, e = i & 255, row = rb * 16 + (e >> 4), col = strip * 16 + (e & 15);
-        if (row < rows) {
-          const float s = ((part[0][rb][e] + part[1][rb][e]) + part[2][rb][e]) + part[3][rb][e];
-          if (last) ((float*)out)[(int64_t)row * N + col] = s;
-          else hout[(int64_t)row * stride + col] = f32_to_bf16_rne(fmaxf(s, 0.f));
-        }
-      }
-      __syncthreads();
-    }
-    if (!last && !mlp_barrier_prefetch<G>(ctl, a, l, nrb, ra, rb_, w, lane, &have_b)) return false;
-  }
-  return true;
-}
-
-// ---- batches of 4 or more row blocks: waves split the rows
-// A unit is (up to 4 RW row blocks) x (CT column strips); wave w owns row blocks
-// w, w + 4, ... of the unit and runs the whole K for them, with one accumulator per
-// K-chunk class (chunk index mod 4), so that every output element gets the same sum
-// as in the K-split path above: four chains over the chunks of a class in
-// increasing K order, then ((p0 + p1) + p2) + p3 (a row's result therefore does not
-// depend on which path its batch takes).
+// Per layer, out = act W^T with W [N][K] BF16 (K contiguous), on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation; ReLU and BF16 rounding for the
+// hidden layers, an FP32 store for the last; layers are separated by grid barriers.
+// A unit is (up to 4 RW row blocks of 16 rows) x (CT column strips of 16); wave w
+// owns row blocks w, w + 4, ... of the unit and runs the whole K for them, one MFMA
+// chain per output tile in increasing K order. Every output element's sum therefore
+// has one fixed order, whatever the batch, the row's position, the unit shape or
+// the grid, and a row's result does not depend on the other rows.
 //
-// K is walked in stages of 4 chunks (128). Global loads are row-contiguous (16
-// lanes cover the 256 bytes of one row's stage, so every group of 4 lanes reads
-// one 64-byte segment): an MFMA fragment, 16 rows of 16 bytes per 16 lanes, would
-// touch 4 cache lines per group of 4 lanes. Each wave puts its own rows' A through
-// a private LDS region; the stage's B (the same for all 4 waves) is loaded once
-// per workgroup, spread over its 256 threads, into a double-buffered LDS stage.
-// Load group g = (A of stage g, B of stage g + 1) sits in register slot g mod PA,
-// PA groups in flight. Per stage: B of the next stage and A of this stage go from
-// registers to LDS, the MFMAs read their fragments from LDS, group g + PA is
-// issued into the freed slot, one workgroup barrier.
+// K is walked in stages of 4 chunks of 32. The stage's B (the weights, the same for
+// all 4 waves) is loaded once per workgroup, spread over its 256 threads with
+// row-contiguous 16-byte loads (16 lanes cover one weight row's 256 bytes), into a
+// double-buffered LDS stage that the waves read as MFMA fragments (an MFMA fragment
+// loaded from global memory directly would touch 4 cache lines per group of 4
+// lanes). The hidden state between layers is stored in MFMA fragment order, so the
+// A fragments of the next layer are single contiguous 1 KiB loads straight into
+// registers; the first layer's FP32 rows are loaded row-contiguously and go
+// through a per-wave LDS region. Load group g = (A of stage g, B of stage g + 1)
+// sits in register slot g mod PA, PA groups in flight. Per stage: B of the next
+// stage (and for FP32 rows A of this stage) go from registers to LDS, the MFMAs run,
+// group g + PA is issued into the freed slot, one workgroup barrier.
 constexpr int kRowPitch = 256 + 16;    // one row's stage in LDS, padded (rows on other banks)
 
 template <int RW, int CT, bool F32>
@@ -889,7 +597,7 @@ __device__ __forceinline__ void mlp_row_frag(MlpRowFrag<RW, CT>& f, const MlpRow
 // A operand: the fragment read into f (FP32 rows, or a zeroed tail), else the slot
 // register itself (no copy).
 template <int RW, int CT, bool F32, bool TAIL>
-__device__ __forceinline__ void mlp_row_mfma_chunk(f32x4 (&acc)[RW][CT][4], const MlpRowFrag<RW, CT>& f,
+__device__ __forceinline__ void mlp_row_mfma_chunk(f32x4 (&acc)[RW][CT], const MlpRowFrag<RW, CT>& f,
                                                    const MlpRowSlot<RW, CT, F32>& sl, int c) {
 #pragma unroll
   for (int t = 0; t < CT; ++t)
@@ -898,7 +606,7 @@ __device__ __forceinline__ void mlp_row_mfma_chunk(f32x4 (&acc)[RW][CT][4], cons
       bf16x8 av;
       if constexpr (F32 || TAIL) av = f.a[j];
       else __builtin_memcpy(&av, &sl.a[c * RW + j][0], 16);
-      acc[j][t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, f.b[t], acc[j][t][c], 0, 0, 0);
+      acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, f.b[t], acc[j][t], 0, 0, 0);
     }
 }
 
@@ -906,7 +614,7 @@ __device__ __forceinline__ void mlp_row_mfma_chunk(f32x4 (&acc)[RW][CT][4], cons
 // chunk c + 1 read while the MFMAs of chunk c run; the last stage skips the chunks
 // past K and zeroes the K tail.
 template <int RW, int CT, bool F32>
-__device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT][4], const MlpRowSlot<RW, CT, F32>& sl,
+__device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT], const MlpRowSlot<RW, CT, F32>& sl,
                                              const uint8_t* areg, const uint8_t* buf, int K, int st, int lane) {
   const int fo = (lane & 15) * kRowPitch + (lane >> 4) * 16;
   if ((st + 1) * 128 <= K) {
@@ -934,10 +642,10 @@ __device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT][4], const MlpR
 
 // load groups in flight per unit shape: as many as the registers hold without spills
 #ifndef MLP_PA
-#define MLP_PA(RW, CT, F32) ((F32) ? 2 : (RW) == 2 ? 2 : (CT) == 2 ? 4 : 6)
+#define MLP_PA(RW, CT, F32) ((F32) ? 4 : (RW) == 2 ? 4 : 8)
 #endif
-// LDS of the row path: the waves' A regions, then two B stage buffers
-constexpr int kMlpRowLds = 4 * 32 * kRowPitch + 2 * 32 * kRowPitch;
+// LDS of the row path: the waves' A regions (FP32 rows), then the B stage buffers
+constexpr int kMlpRowLds = 8 * 32 * kRowPitch;
 
 // One unit: rows row0 .. row0 + 64 RW - 1 (wave w: row blocks w, w + 4, ...),
 // columns col0 .. col0 + 16 CT - 1. All 4 waves run every stage (the barriers).
@@ -947,21 +655,20 @@ __device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const
                                              bool last, uint16_t* hout, float* out, uint8_t* lds, int w, int lane,
                                              int tid) {
   constexpr int PA = MLP_PA(RW, CT, F32);                       // load groups in flight
-  constexpr int NB = 2;                                         // B stage buffers
+  constexpr int NB = (PA % 2 == 0) ? 2 : PA;                    // B stage buffers
   static_assert(PA % NB == 0, "buffer of a stage must be known at compile time");
   constexpr int SB = 16 * CT * kRowPitch;                       // bytes of one B stage buffer
-  static_assert(4 * 16 * RW * kRowPitch + NB * SB <= kMlpRowLds, "row path LDS");
-  uint8_t* areg = lds + w * 16 * RW * kRowPitch;
-  uint8_t* bbuf = lds + 4 * 16 * RW * kRowPitch;
+  constexpr int SA = F32 ? 16 * RW * kRowPitch : 0;             // a wave's A region (FP32 rows only)
+  static_assert(4 * SA + NB * SB <= kMlpRowLds, "row path LDS");
+  uint8_t* areg = lds + w * SA;
+  uint8_t* bbuf = lds + 4 * SA;
   MlpRowSrc<RW, CT, F32> src;
   mlp_row_sources<RW, CT, F32>(src, rowptr, hin, stride, W, K, N, rows, row0, col0, w, lane, tid);
-  f32x4 acc[RW][CT][4];
+  f32x4 acc[RW][CT];
 #pragma unroll
   for (int j = 0; j < RW; ++j)
 #pragma unroll
-    for (int t = 0; t < CT; ++t)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[j][t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < CT; ++t) acc[j][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
   // stages padded to a multiple of PA (padding stages load and do no MFMAs)
   const int ns = ((K + 127) / 128 + PA - 1) / PA * PA;
   MlpRowSlot<RW, CT, F32> sl[PA];
@@ -1007,7 +714,7 @@ __device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const
       for (int i = 0; i < 4; ++i) {
         const int row = row0 + (w + 4 * j) * 16 + (lane >> 4) * 4 + i;
         if (row < rows) {
-          const float v = ((acc[j][t][0][i] + acc[j][t][1][i]) + acc[j][t][2][i]) + acc[j][t][3][i];
+          const float v = acc[j][t][i];
           if (last) {
             out[(int64_t)row * N + col] = v;
           } else {
@@ -1036,7 +743,7 @@ __device__ __forceinline__ void mlp_row_layer(const uint8_t* const* rowptr, cons
   }
 }
 
-// All layers of a batch of 4 or more row blocks. Per layer the unit shape is the
+// All layers of a batch. Per layer the unit shape is the
 // largest of (8 row blocks x 2 strips), (4 x 2), (4 x 1) that still gives every
 // workgroup a unit (larger units read the activations and weights fewer times);
 // the first layer, whose FP32 rows take twice the registers, uses one row block
@@ -1071,22 +778,11 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
 }
 
 __device__ __forceinline__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
-  // the K-split path's tile buffers and the row path's regions share the array
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kMlpTileBytes > kMlpRowLds ? 2 * kMlpTileBytes : kMlpRowLds];
-  // the wave index is uniform across the wave: in a scalar register the per-chunk
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kMlpRowLds];
+  // the wave index is uniform across the wave: in a scalar register the per-wave
   // conditions become scalar branches instead of exec-mask regions
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int nrb = (rows + 15) >> 4;
-  const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
-  if (nrb >= 4) return mlp_rows_all(a, ctl, rows, out, lds, w, lane, tid);
-  {
-    // first layer: FP32 input rows
-    const MlpIn in{ctl->d_rowptr, nullptr, (const uint16_t*)a.sp.w[0], stride, a.sp.dims[0], rows};
-    mlp_layer<MlpGeoF32>(false, lds, in, a.sp.dims[1], L == 1, a.sp.scratch, out, nrb, w, lane, tid);
-  }
-  if (L == 1) return true;
-  if (nrb <= 1) return mlp_rest<MlpGeoOne>(a, ctl, rows, out, lds, w, lane, tid);
-  return mlp_rest<MlpGeoWide>(a, ctl, rows, out, lds, w, lane, tid);
+  return mlp_rows_all(a, ctl, rows, out, lds, w, lane, tid);
 }
 
 // ------------------------------------------------------------------ embedding gather

@@ -177,8 +177,8 @@ def test_mlp_batch_and_grid_invariant(torch, cm):
     f = full.cpu().numpy()
     assert np.array_equal(one.cpu().numpy()[0], f[37])
     assert np.array_equal(other.cpu().numpy(), f)
-    # every unit shape of the row-split path (shares 8 .. 256) and the K-split path
-    # (batches of up to 48 rows) give the same bits for a row
+    # every unit shape (shares 8 .. 256, batches above and below 4 row blocks) gives
+    # the same bits for a row
     for share in (8, 64, 128, 256):
         cm.camelot_stage_run(mlp, dx.data_ptr(), other.data_ptr(), 128, share, 0)
         assert np.array_equal(other.cpu().numpy(), f), share
