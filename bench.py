@@ -10,17 +10,20 @@ up to 128 queries; p99 QoS target 50 ms.
 Steps (all on synthetic, seeded inputs resident in HBM before any timed region):
  1. solo profile table: every stage x CU share (8..256 in steps of 8) x batch
     (1..128, powers of two), measured with the library's one-shot stage kernel;
- 2. allocation: max-peak problem (Eq. 1) over that table -> CU shares, instances
-    of the MLP stage (up to 4, each on its own share) and batch;
+ 2. allocations: the max-peak problem (Eq. 1) -> CU shares, instances of the MLP
+    stage (up to 4, each on its own share) and batch, solved twice: over the solo
+    table, and contention-aware (co-location profiles, the learned predictor
+    trained on them, Eq. 1 over its predicted co-located latencies). The
+    contention-aware one is Camelot's allocation and the reported value; the
+    solo-table one is measured next to it (with --skip-learned the solo-table
+    allocation is the reported one);
  3. peak QPS at p99 <= QoS: Poisson-arrival replays (device-side arrival clock,
-    payloads already in HBM), binary search on the rate, for the allocation with
+    payloads already in HBM), binary search on the rate, for both allocations with
     device-global handoff and for the baseline (even split 88/88/80 CUs,
     host-staged handoff, same batching rule);
  4. timed steps: K replays at the found peak rate (one step = one trial);
  5. CUs at 20% load: min-resource problem (Eq. 3) at 20% of the baseline's peak,
-    checked with a replay; then the contention-aware allocation: co-location
-    profiles, the learned predictor trained on them, Eq. 1 over its predictions,
-    and that allocation's measured peak next to the table allocation's;
+    checked with a replay;
  6. device-global handoff GB/s (1 GiB ring, 128 + 128 CUs) vs the 8 TB/s HBM peak;
  7. roofline of the dominant kernel (the BF16 MLP stage at batch 128 on its share);
  8. the CPU oracle timed on a bounded sample on this host (1 thread).
@@ -392,14 +395,29 @@ def main():
     even = [88, 88, 80]
     ok_even, ea = cm.camelot_alloc_eval(prob, a["batch_index"], [1, 1, 1], even)
     pred_even = ea.thr_num / ea.thr_den
-    batch = a["batch"]
-    ninst = tuple(a["n"])
+
+    # 2b: the contention-aware (learned) allocation over the same candidates
+    # (instances included): co-location profiles, the predictor trained on them,
+    # Eq. 1 over its predicted co-located latencies. It is Camelot's allocation; the
+    # solo-table allocation is measured next to it.
+    la, lpred, linfo = (None, None, None)
+    if not args.skip_learned:
+        la, lpred, linfo = learned_allocation(cm, G, torch, sp, lat, prob)
+    use = la if la is not None else a
+    ninst = tuple(use["n"])
+    batch = use["batch"]
+    upred = use["thr_num"] / use["thr_den"]
 
     # 3: peak QPS at p99 <= QoS
-    cam = sp.peak_search(a["cu"], cm.HANDOFF_DEVICE, batch, pred, args.trial_s, args.search_iters, "camelot",
+    cam = sp.peak_search(use["cu"], cm.HANDOFF_DEVICE, batch, upred, args.trial_s, args.search_iters, "camelot",
                          n_inst=ninst)
-    base = sp.peak_search(even, cm.HANDOFF_HOST, batch, pred_even, args.trial_s, args.search_iters, "baseline")
+    table = None
+    if la is not None:
+        table = sp.peak_search(a["cu"], cm.HANDOFF_DEVICE, a["batch"], pred, args.trial_s, args.search_iters,
+                               "solo table", n_inst=tuple(a["n"]))
+    base = sp.peak_search(even, cm.HANDOFF_HOST, a["batch"], pred_even, args.trial_s, args.search_iters, "baseline")
     peak = cam[0] if cam else 0.0
+    peak_table = (table[0] if table else 0.0) if la is not None else peak
     peak_base = base[0] if base else 0.0
 
     if peak <= 0:
@@ -408,13 +426,13 @@ def main():
     # step met the QoS target (the search's last good rate, lowered by 3% per retry)
     for attempt in range(6):
         for w in range(args.warmup):
-            sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w,
+            sp.trial(use["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w,
                      n_inst=ninst)
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         steps = []
         for k in range(args.steps):
-            steps.append(sp.trial(a["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4,
+            steps.append(sp.trial(use["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4,
                                   seed=200 + k, n_inst=ninst))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
@@ -438,27 +456,18 @@ def main():
         p99_20 = r20["p99"]
         log(f"20% load {lam20 / 1e6:.3f} Mq/s: allocation {m} p99 {p99_20 / 1e3:.0f} us")
 
-    # 5b: contention-aware (learned) allocation, measured the same way; the learned
-    # allocator places one instance per stage, so it is set against the solo-table
-    # allocation under the same one-instance rule
     learned = None
-    if not args.skip_learned:
-        la, lpred, linfo = learned_allocation(cm, G, torch, sp, lat, prob1)
-        if la is not None:
-            a1 = cm.camelot_alloc_peak(prob1).as_dict()
-            t1 = sp.peak_search(a1["cu"], cm.HANDOFF_DEVICE, a1["batch"], a1["thr_num"] / a1["thr_den"],
-                                args.trial_s, args.search_iters, "table, one instance")
-            tpeak = t1[0] if t1 else 0.0
-            lbest = sp.peak_search(la["cu"], cm.HANDOFF_DEVICE, la["batch"], la["thr_num"] / la["thr_den"],
-                                   args.trial_s, args.search_iters, "learned")
-            lpeak = lbest[0] if lbest else 0.0
-            learned = {"allocation_cus": la["cu"], "batch": la["batch"], "predicted_qps": la["thr_num"] / la["thr_den"],
-                       "predicted_stage_ns": lpred, "measured_peak_qps": lpeak,
-                       "table_one_instance": {"allocation_cus": a1["cu"], "batch": a1["batch"],
-                                              "measured_peak_qps": tpeak},
-                       "ratio_vs_table_allocation": lpeak / tpeak if tpeak else None, **linfo}
-            log(f"learned allocation {la['cu']} b={la['batch']}: measured peak {lpeak / 1e6:.3f} Mq/s; "
-                f"table allocation {a1['cu']}: {tpeak / 1e6:.3f} Mq/s (both one instance per stage)")
+    if la is not None:
+        learned = {"allocation_cus": la["cu"], "allocation_instances": la["n"], "batch": la["batch"],
+                   "predicted_qps": la["thr_num"] / la["thr_den"], "predicted_stage_ns": lpred,
+                   "measured_peak_qps": cam[0] if cam else 0.0,
+                   "solo_table_allocation": {"allocation_cus": a["cu"], "allocation_instances": a["n"],
+                                             "batch": a["batch"], "predicted_qps": pred,
+                                             "measured_peak_qps": peak_table},
+                   "ratio_vs_solo_table_allocation": (cam[0] / peak_table) if (cam and peak_table) else None,
+                   **linfo}
+        log(f"learned allocation {la['cu']} x {la['n']}: measured peak {learned['measured_peak_qps'] / 1e6:.3f} "
+            f"Mq/s; solo-table allocation {a['cu']} x {a['n']}: {peak_table / 1e6:.3f} Mq/s")
 
     # 6: handoff GB/s
     slot = 64 << 20
@@ -469,7 +478,7 @@ def main():
     log(f"handoff device {h['gbs']:.0f} GB/s (checksum ok={handoff_ok}), host-staged {hh['gbs']:.1f} GB/s")
 
     # 7: roofline of the dominant kernel (MLP stage, batch 128, on its share)
-    roof = mlp_roofline(a["cu"][1])
+    roof = mlp_roofline(use["cu"][1])
 
     # 8: CPU baseline
     cpu = None if args.skip_cpu else run_cpu_baseline(args.cpu_sample)
@@ -480,11 +489,13 @@ def main():
         "ms_per_step": elapsed * 1e3 / max(args.steps, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": WORKLOAD, "global_batch": batch, "parallelism": "spatial CU partitions on 1 GPU",
-                   "allocation_cus": a["cu"], "allocation_instances": a["n"], "ingest": "device replay of Poisson arrivals, payloads in HBM",
+                   "allocation_cus": use["cu"], "allocation_instances": use["n"],
+                   "allocator": "contention-aware (learned predictor)" if la is not None else "solo profile table",
+                   "ingest": "device replay of Poisson arrivals, payloads in HBM",
                    "handoff": "device-global ring + doorbells", "qos_ns": QOS_NS},
         "timed_steps_p99_ns": p99s, "timed_steps_qos_met": all(s["ok"] for s in steps),
         "timed_step_per_batch": steps[0].get("stage"),
-        "predicted_qps": pred, "alloc_ms": alloc_ms, "profile_failures": sp.failures,
+        "predicted_qps": upred, "alloc_ms": alloc_ms, "profile_failures": sp.failures,
         "baseline": {"kind": "even split 88/88/80 CUs, host-staged handoff", "peak_qps": peak_base,
                      "predicted_qps": pred_even},
         "gain_vs_even_split_host_staged": (peak / peak_base) if peak_base else None,

@@ -445,20 +445,24 @@ int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stages, const v
                             void* const* out, const int32_t* rows, const int32_t* n_cus,
                             const int32_t* cu_offset, int64_t duration_ns, double* ns_per_batch);
 
+#define CAMELOT_MAX_CORUN 6     /* kernels of one co-location profile or candidate */
+
 typedef struct {
-  int32_t m;                   /* stages in this run, 1..3                            */
-  int32_t kinds[3];            /* which of the n_kinds stages                         */
-  int32_t cu[3];               /* CUs of each                                         */
-  int32_t bi[3];               /* batch index of each                                 */
-  double ns[3];                /* measured time per batch of each                    */
+  int32_t m;                            /* kernels in this run, 1..CAMELOT_MAX_CORUN     */
+  int32_t kinds[CAMELOT_MAX_CORUN];     /* which of the n_kinds stages (repeats allowed) */
+  int32_t cu[CAMELOT_MAX_CORUN];        /* CUs of each                                   */
+  int32_t bi[CAMELOT_MAX_CORUN];        /* batch index of each                           */
+  double ns[CAMELOT_MAX_CORUN];         /* measured time per batch of each               */
 } camelot_corun_record;
 
-/* Random co-location profiles: n_runs runs, each of m = 1, 2 or 3 distinct stage
- * kinds (probabilities 0.1, 0.3, 0.6, capped at n_kinds), shares drawn uniformly in
- * cu_step steps with total <= cu_total and placed side by side from bit 0, batch
- * indices equal for all stages with probability 1/2 and independent otherwise;
- * the draws come from a SplitMix64 stream seeded with `seed`. in[k]/out[k] are
- * kind k's device buffers for max(batches) rows. */
+/* Random co-location profiles: n_runs runs, each of m kernels, m uniform in
+ * 1..min(CAMELOT_MAX_CORUN, cu_total / cu_step), each kernel's kind uniform over the
+ * n_kinds stages (independently, so a kind can run as several instances, as in an
+ * allocation with N_i > 1), shares drawn uniformly in cu_step steps with total <=
+ * cu_total and placed side by side from bit 0, batch indices equal for all kernels
+ * with probability 1/2 and independent otherwise; the draws come from a SplitMix64
+ * stream seeded with `seed`. in[k]/out[k] are kind k's device buffers for
+ * max(batches) rows (instances of one kind share them). */
 int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_desc* stages, const void* const* in,
                                void* const* out, int32_t cu_total, int32_t cu_step, int32_t n_batches,
                                const int32_t* batches, int32_t n_runs, uint64_t seed,
@@ -478,11 +482,13 @@ typedef struct {
 
 #define CAMELOT_PRED_FEATURES 16
 
-/* Features of one co-location of m <= 3 stages: stage j has kind kinds[j] (< 3),
- * share cu[j] and batch index bi[j]. Row j (16 floats) of feat (host) is:
- * own share / 256, log2(own batch) / 7, own solo hbm, own solo mfma, one-hot kind (3),
- * then for each other stage in order (2 slots, zeros if absent): share / 256,
- * log2(batch) / 7, solo hbm, solo mfma; last, the CUs of all m stages / 256. */
+/* Features of one co-location of m <= CAMELOT_MAX_CORUN kernels: kernel j has kind
+ * kinds[j] (< 3), share cu[j] and batch index bi[j]. Row j (16 floats) of feat (host)
+ * is: own share / 256, log2(own batch) / 7, own solo hbm, own solo mfma, one-hot kind
+ * (3); then two aggregate co-runner slots, the other kernels of the same kind (its
+ * sibling instances) and the kernels of other kinds, each holding the sum of their
+ * shares / 256, the mean of their log2(batch) / 7, the sum of their solo hbm and the
+ * sum of their solo mfma (zeros when empty); last, the CUs of all m kernels / 256. */
 int32_t camelot_predictor_features(const camelot_solo_tables* t, int32_t m, const int32_t* kinds,
                                    const int32_t* cu, const int32_t* bi, float* feat);
 
@@ -491,13 +497,16 @@ int32_t camelot_predictor_features(const camelot_solo_tables* t, int32_t m, cons
 int32_t camelot_predictor_fit_norm(const float* x, int32_t n, float* mean, float* std);
 int32_t camelot_predictor_standardize(float* x, int32_t n, const float* mean, const float* std);
 
-/* Contention-aware Eq. 1: as camelot_alloc_peak with one instance per stage (n_stages
- * <= 3, stage i of kind i), but every stage's latency is its solo latency (lat_ns)
- * times exp(y), y = the learned predictor's output for the co-location the candidate
- * forms (the network predicts the log slowdown over the solo profile), rounded up to
- * ns. params: device [CAMELOT_PRED_NPARAMS]; mean/std: host [16]. bw_bps, mem_bytes
- * and the tie rules are those of camelot_alloc_peak. lat_pred_ns (host [n_stages], may
- * be NULL) receives the predicted latencies of the chosen point. */
+/* Contention-aware Eq. 1: camelot_alloc_peak's problem (N_i up to max_inst_per_stage
+ * and inst_max, at most CAMELOT_MAX_CORUN instances in all; n_stages <= 3, stage i of
+ * kind i), but every stage's latency is its solo latency (lat_ns) times exp(y), y =
+ * the learned predictor's output for one of its instances in the co-location the
+ * candidate forms (all instances of every stage; the network predicts the log
+ * slowdown over the solo profile), rounded up to ns. Candidates are taken in the
+ * lexicographic order (batch index, N_1, share_1, N_2, share_2, ...) and the
+ * objective, constraints and tie rules are those of camelot_alloc_peak. params:
+ * device [CAMELOT_PRED_NPARAMS]; mean/std: host [16]. lat_pred_ns (host [n_stages],
+ * may be NULL) receives the predicted latencies of the chosen point. */
 int32_t camelot_alloc_peak_learned(const camelot_problem* problem, const camelot_solo_tables* t,
                                    const float* params, const float* mean, const float* std,
                                    camelot_alloc* out, int64_t* lat_pred_ns);

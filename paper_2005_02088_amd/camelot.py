@@ -97,9 +97,12 @@ class PipelineStats(C.Structure):
                 ("wait_ns", C.c_int64 * MAX_STAGES)]
 
 
+MAX_CORUN = 6
+
+
 class CorunRecord(C.Structure):
-    _fields_ = [("m", C.c_int32), ("kinds", C.c_int32 * 3), ("cu", C.c_int32 * 3), ("bi", C.c_int32 * 3),
-                ("ns", C.c_double * 3)]
+    _fields_ = [("m", C.c_int32), ("kinds", C.c_int32 * MAX_CORUN), ("cu", C.c_int32 * MAX_CORUN),
+                ("bi", C.c_int32 * MAX_CORUN), ("ns", C.c_double * MAX_CORUN)]
 
 
 class SoloTables(C.Structure):

@@ -43,6 +43,8 @@ int32_t d2h(void* dst, const void* src, size_t bytes);
 int32_t h2d(void* dst, const void* src, size_t bytes);
 int64_t ns_to_ticks(int64_t ns, int64_t hz);
 int32_t cached_stream(int offset, int n, hipStream_t* s);
+// A new CU-masked stream the caller owns (and destroys).
+int32_t new_masked_stream(int offset, int n, hipStream_t* s);
 int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp);
 int32_t check_share(int n_cus, int offset, int total);
 int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s);

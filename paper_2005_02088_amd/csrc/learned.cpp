@@ -60,13 +60,22 @@ extern "C" int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stag
   std::vector<StageRes> res(n);
   std::vector<CtlBuf> ctl(n);
   std::vector<WorkerArgs> args(n);
-  std::vector<hipStream_t> streams(n);
+  // own streams (a co-run can hold more kernels than the cache keeps streams)
+  struct Streams {
+    std::vector<hipStream_t> s;
+    ~Streams() {
+      for (hipStream_t x : s)
+        if (x) (void)hipStreamDestroy(x);
+    }
+  } own;
+  own.s.assign(n, nullptr);
+  std::vector<hipStream_t>& streams = own.s;
   for (int j = 0; j < n; ++j) {
     WorkerArgs& a = args[j];
     std::memset(&a, 0, sizeof a);
     if ((rc = fill_params(&stages[j], &res[j], &a.sp))) return rc;
     if ((rc = dmalloc(&ctl[j].p, sizeof(WorkerCtl))) || (rc = dzero(ctl[j].p, sizeof(WorkerCtl)))) return rc;
-    if ((rc = cached_stream(cu_offset[j], n_cus[j], &streams[j]))) return rc;
+    if ((rc = new_masked_stream(cu_offset[j], n_cus[j], &streams[j]))) return rc;
     a.n_stages = 1;
     a.max_batch = kMaxBatch;
     a.spin_ticks = 2 * dev.wclk_hz;
@@ -105,17 +114,13 @@ extern "C" int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_d
       !records || cu_step < 8 || cu_step % 8 != 0 || cu_total < cu_step * n_kinds)
     return fail(CAMELOT_EINVAL, "bad co-run profiling arguments");
   uint64_t st = seed;
+  const int steps = cu_total / cu_step;
+  const int mmax = std::min(CAMELOT_MAX_CORUN, steps);
   for (int r = 0; r < n_runs; ++r) {
     camelot_corun_record& rec = records[r];
     std::memset(&rec, 0, sizeof rec);
-    const int u = uniform(st, 10);
-    int m = u < 1 ? 1 : (u < 4 ? 2 : 3);
-    m = std::min(m, n_kinds);
-    // distinct kinds: partial Fisher-Yates over 0..n_kinds-1
-    int perm[3] = {0, 1, 2};
-    for (int i = 0; i < m; ++i) std::swap(perm[i], perm[i + uniform(st, n_kinds - i)]);
-    const int steps = cu_total / cu_step;
-    int sh[3];
+    const int m = 1 + uniform(st, mmax);
+    int sh[CAMELOT_MAX_CORUN];
     for (;;) {
       int tot = 0;
       for (int i = 0; i < m; ++i) { sh[i] = 1 + uniform(st, steps - (m - 1)); tot += sh[i]; }
@@ -123,14 +128,14 @@ extern "C" int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_d
     }
     const bool same = uniform(st, 2) == 0;
     const int b0 = uniform(st, n_batches);
-    camelot_stage_desc d[3];
-    const void* ins[3];
-    void* outs[3];
-    int32_t rows[3], cus[3], offs[3];
+    camelot_stage_desc d[CAMELOT_MAX_CORUN];
+    const void* ins[CAMELOT_MAX_CORUN];
+    void* outs[CAMELOT_MAX_CORUN];
+    int32_t rows[CAMELOT_MAX_CORUN], cus[CAMELOT_MAX_CORUN], offs[CAMELOT_MAX_CORUN];
     int off = 0;
     rec.m = m;
     for (int i = 0; i < m; ++i) {
-      const int k = perm[i];
+      const int k = uniform(st, n_kinds);
       rec.kinds[i] = k;
       rec.cu[i] = sh[i] * cu_step;
       rec.bi[i] = same ? b0 : uniform(st, n_batches);
@@ -159,7 +164,7 @@ int32_t check_tables(const camelot_solo_tables* t) {
 
 inline float log2b(int b) { return std::log2((float)std::max(b, 1)) / 7.f; }
 
-// one row of 16 features for stage j of a co-location (no validation)
+// one row of 16 features for kernel j of a co-location (no validation)
 void feature_row(const camelot_solo_tables* t, int m, const int32_t* kinds, const int32_t* cu,
                  const int32_t* bi, int j, float* f) {
   auto at = [&](const float* tab, int k, int share_cus, int b) {
@@ -172,17 +177,22 @@ void feature_row(const camelot_solo_tables* t, int m, const int32_t* kinds, cons
   f[2] = at(t->hbm, kinds[j], cu[j], bi[j]);
   f[3] = at(t->mfma, kinds[j], cu[j], bi[j]);
   f[4 + kinds[j]] = 1.f;
-  int slot = 0, total = 0;
+  // slot 0 (features 7..10): the other instances of kind[j]; slot 1 (11..14): the
+  // kernels of other kinds
+  int cnt[2] = {0, 0}, total = 0;
   for (int q = 0; q < m; ++q) {
     total += cu[q];
-    if (q == j || slot >= 2) continue;
+    if (q == j) continue;
+    const int slot = kinds[q] == kinds[j] ? 0 : 1;
     float* g = f + 7 + 4 * slot;
-    g[0] = cu[q] / 256.f;
-    g[1] = log2b(t->batches[bi[q]]);
-    g[2] = at(t->hbm, kinds[q], cu[q], bi[q]);
-    g[3] = at(t->mfma, kinds[q], cu[q], bi[q]);
-    ++slot;
+    g[0] += cu[q] / 256.f;
+    g[1] += log2b(t->batches[bi[q]]);
+    g[2] += at(t->hbm, kinds[q], cu[q], bi[q]);
+    g[3] += at(t->mfma, kinds[q], cu[q], bi[q]);
+    ++cnt[slot];
   }
+  for (int slot = 0; slot < 2; ++slot)
+    if (cnt[slot] > 1) f[7 + 4 * slot + 1] /= (float)cnt[slot];
   f[15] = total / 256.f;
 }
 }  // namespace
@@ -192,7 +202,8 @@ extern "C" int32_t camelot_predictor_features(const camelot_solo_tables* t, int3
   clear_error();
   int32_t rc = check_tables(t);
   if (rc) return rc;
-  if (m < 1 || m > 3 || !kinds || !cu || !bi || !feat) return fail(CAMELOT_EINVAL, "bad feature arguments");
+  if (m < 1 || m > CAMELOT_MAX_CORUN || !kinds || !cu || !bi || !feat)
+    return fail(CAMELOT_EINVAL, "bad feature arguments");
   for (int j = 0; j < m; ++j) {
     if (kinds[j] < 0 || kinds[j] >= t->n_kinds) return fail(CAMELOT_EINVAL, "kind out of range");
     if (cu[j] < t->cu_step || cu[j] % t->cu_step != 0 || cu[j] / t->cu_step > t->n_shares)
@@ -236,11 +247,32 @@ namespace {
 typedef __int128 i128;
 struct Cand {
   int bi;
+  int n[3];
   int k[3];
 };
 inline int cmp_rat(int64_t an, int64_t ad, int64_t bn, int64_t bd) {
   const i128 l = (i128)an * bd, r = (i128)bn * ad;
   return l < r ? -1 : (l > r ? 1 : 0);
+}
+
+// Candidates in lexicographic order (batch index, N_1, k_1, N_2, k_2, ...) that fit
+// the CUs, the instance caps and the measured solo table.
+void enumerate(const camelot_problem* p, int S, int K, const int* nmax, int total_inst, int bi, int s, int cu_used,
+               int inst, Cand& c, std::vector<Cand>& out) {
+  if (s == S) {
+    out.push_back(c);
+    return;
+  }
+  for (int nn = 1; nn <= nmax[s] && inst + nn <= total_inst; ++nn) {
+    for (int kk = 0; kk < K; ++kk) {
+      const int cu2 = cu_used + nn * (kk + 1) * p->cu_step;
+      if (cu2 > p->cu_total) break;
+      if (p->lat_ns[((int64_t)s * K + kk) * p->n_batches + bi] <= 0) continue;
+      c.n[s] = nn;
+      c.k[s] = kk;
+      enumerate(p, S, K, nmax, total_inst, bi, s + 1, cu2, inst + nn, c, out);
+    }
+  }
 }
 }  // namespace
 
@@ -256,53 +288,78 @@ extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const ca
   if (p->cu_step != t->cu_step || p->cu_total / p->cu_step > t->n_shares || p->n_batches != t->n_batches)
     return fail(CAMELOT_EINVAL, "solo tables do not cover the problem's shares and batches");
   if (!p->lat_ns || !p->bw_bps || !p->mem_bytes || !p->batches) return fail(CAMELOT_EINVAL, "incomplete problem");
+  if (p->max_instances < 1 || p->max_inst_per_stage < 1) return fail(CAMELOT_EINVAL, "instance caps must be >= 1");
+  if (p->inst_max)
+    for (int i = 0; i < S; ++i)
+      if (p->inst_max[i] < 1) return fail(CAMELOT_EINVAL, "inst_max[%d] must be >= 1", i);
   const int K = p->cu_total / p->cu_step;
-  // candidates in lexicographic order (batch index, k_0, k_1, ...), shares fitting the GPU
+  int nmax[3];
+  const int cap = std::min(p->max_inst_per_stage, p->max_instances);
+  for (int i = 0; i < S; ++i) nmax[i] = std::min(cap, p->inst_max ? p->inst_max[i] : cap);
+  const int total_inst = std::min(p->max_instances, CAMELOT_MAX_CORUN);
   std::vector<Cand> cands;
   for (int bi = 0; bi < p->n_batches; ++bi) {
     const int64_t wait = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
     if (wait > p->qos_ns) continue;
-    int k[3] = {0, 0, 0};
-    const int total = (int)std::pow((double)K, S);
-    for (int c = 0; c < total; ++c) {
-      int rem = c, used = 0;
-      bool ok = true;
-      for (int s = S - 1; s >= 0; --s) { k[s] = rem % K; rem /= K; }
-      for (int s = 0; s < S; ++s) {
-        used += (k[s] + 1) * p->cu_step;
-        if (p->lat_ns[((int64_t)s * K + k[s]) * p->n_batches + bi] <= 0) ok = false;
-      }
-      if (ok && used <= p->cu_total) cands.push_back(Cand{bi, {k[0], k[1], k[2]}});
-    }
+    Cand c{bi, {1, 1, 1}, {0, 0, 0}};
+    enumerate(p, S, K, nmax, total_inst, bi, 0, 0, 0, c, cands);
   }
   if (cands.empty()) return fail(CAMELOT_EINFEASIBLE, "no candidate allocation");
-  const int64_t nrows = (int64_t)cands.size() * S;
-  std::vector<float> x((size_t)nrows * CAMELOT_PRED_FEATURES);
-  for (size_t c = 0; c < cands.size(); ++c) {
-    int32_t kinds[3], cu[3], bis[3];
-    for (int s = 0; s < S; ++s) { kinds[s] = s; cu[s] = (cands[c].k[s] + 1) * p->cu_step; bis[s] = cands[c].bi; }
-    for (int s = 0; s < S; ++s)
-      feature_row(t, S, kinds, cu, bis, s, x.data() + ((int64_t)c * S + s) * CAMELOT_PRED_FEATURES);
-  }
-  camelot_predictor_standardize(x.data(), (int32_t)nrows, mean, std);
-  float *dx = nullptr, *dy = nullptr;
-  if ((rc = dmalloc(&dx, x.size() * sizeof(float))) || (rc = dmalloc(&dy, nrows * sizeof(float)))) {
+  // predicted latencies, in chunks of candidates (one feature row per stage: its
+  // instances are alike)
+  constexpr int64_t kChunk = 16384;
+  std::vector<int64_t> L((size_t)cands.size() * S);
+  {
+    float *dx = nullptr, *dy = nullptr;
+    if ((rc = dmalloc(&dx, kChunk * S * CAMELOT_PRED_FEATURES * sizeof(float))) ||
+        (rc = dmalloc(&dy, kChunk * S * sizeof(float)))) {
+      dfree(dx);
+      return rc;
+    }
+    std::vector<float> x((size_t)kChunk * S * CAMELOT_PRED_FEATURES), yhat((size_t)kChunk * S);
+    for (int64_t c0 = 0; c0 < (int64_t)cands.size() && !rc; c0 += kChunk) {
+      const int64_t nc = std::min<int64_t>(kChunk, (int64_t)cands.size() - c0);
+      for (int64_t c = 0; c < nc; ++c) {
+        const Cand& cd = cands[c0 + c];
+        int32_t kinds[CAMELOT_MAX_CORUN], cu[CAMELOT_MAX_CORUN], bis[CAMELOT_MAX_CORUN], first[3];
+        int m = 0;
+        for (int s = 0; s < S; ++s) {
+          first[s] = m;
+          for (int q = 0; q < cd.n[s]; ++q) {
+            kinds[m] = s;
+            cu[m] = (cd.k[s] + 1) * p->cu_step;
+            bis[m] = cd.bi;
+            ++m;
+          }
+        }
+        for (int s = 0; s < S; ++s)
+          feature_row(t, m, kinds, cu, bis, first[s], x.data() + (c * S + s) * CAMELOT_PRED_FEATURES);
+      }
+      const int32_t nrows = (int32_t)(nc * S);
+      camelot_predictor_standardize(x.data(), nrows, mean, std);
+      rc = h2d(dx, x.data(), (size_t)nrows * CAMELOT_PRED_FEATURES * sizeof(float));
+      if (!rc) {
+        hipStream_t s = mem_stream();
+        hipLaunchKernelGGL(camelot_pred_forward, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, params,
+                           (const float*)dx, (int)nrows, dy);
+        if (hipGetLastError() != hipSuccess) rc = fail(CAMELOT_EDEVICE, "predictor forward launch failed");
+        if (!rc) rc = d2h(yhat.data(), dy, (size_t)nrows * sizeof(float));
+      }
+      for (int64_t c = 0; c < nc && !rc; ++c) {
+        const Cand& cd = cands[c0 + c];
+        for (int s = 0; s < S; ++s) {
+          // the network predicts the log of the co-location slowdown over the solo latency
+          const double y = std::max(-10.0, std::min<double>(yhat[c * S + s], 10.0));
+          const double solo = (double)p->lat_ns[((int64_t)s * K + cd.k[s]) * p->n_batches + cd.bi];
+          L[(c0 + c) * S + s] = std::max<int64_t>(1, (int64_t)std::ceil(solo * std::exp(y)));
+        }
+      }
+    }
     dfree(dx);
-    return rc;
+    dfree(dy);
+    if (rc) return rc;
   }
-  std::vector<float> yhat((size_t)nrows);
-  rc = h2d(dx, x.data(), x.size() * sizeof(float));
-  if (!rc) {
-    hipStream_t s = mem_stream();
-    hipLaunchKernelGGL(camelot_pred_forward, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, params,
-                       (const float*)dx, (int)nrows, dy);
-    if (hipGetLastError() != hipSuccess) rc = fail(CAMELOT_EDEVICE, "predictor forward launch failed");
-    if (!rc) rc = d2h(yhat.data(), dy, nrows * sizeof(float));
-  }
-  dfree(dx);
-  dfree(dy);
-  if (rc) return rc;
-  // exact search with the predicted integer latencies (same rules as camelot_alloc_peak)
+  // exact selection with the predicted integer latencies (rules of camelot_alloc_peak)
   bool have = false;
   camelot_alloc best;
   int64_t best_lat[3] = {0, 0, 0};
@@ -310,25 +367,22 @@ extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const ca
     const Cand& cd = cands[c];
     const int bi = cd.bi;
     const int64_t b = p->batches[bi];
-    int64_t cu = 0, bw = 0, mem = 0, lat = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
+    int64_t cu = 0, inst = 0, bw = 0, mem = 0, lat = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
     int64_t tn = 0, td = 1;
     bool has = false;
-    int64_t L[3];
     for (int s = 0; s < S; ++s) {
-      const int kk = cd.k[s];
-      // the network predicts the log of the co-location slowdown over the solo latency
-      const double y = std::max(-10.0, std::min<double>(yhat[c * S + s], 10.0));
-      const double solo = (double)p->lat_ns[((int64_t)s * K + kk) * p->n_batches + bi];
-      L[s] = std::max<int64_t>(1, (int64_t)std::ceil(solo * std::exp(y)));
-      cu += (int64_t)(kk + 1) * p->cu_step;
-      bw += p->bw_bps[((int64_t)s * K + kk) * p->n_batches + bi];
-      mem += p->mem_bytes[(int64_t)s * p->n_batches + bi];
-      lat += L[s];
-      const int64_t n1 = b * 1000000000LL;
-      if (!has || cmp_rat(n1, L[s], tn, td) < 0) { tn = n1; td = L[s]; }
+      const int kk = cd.k[s], nn = cd.n[s];
+      const int64_t Ls = L[c * S + s];
+      cu += (int64_t)nn * (kk + 1) * p->cu_step;
+      inst += nn;
+      bw += nn * p->bw_bps[((int64_t)s * K + kk) * p->n_batches + bi];
+      mem += nn * p->mem_bytes[(int64_t)s * p->n_batches + bi];
+      lat += Ls;
+      const int64_t n1 = (int64_t)nn * b * 1000000000LL;
+      if (!has || cmp_rat(n1, Ls, tn, td) < 0) { tn = n1; td = Ls; }
       has = true;
     }
-    if (cu > p->cu_total || S > p->max_instances || bw > p->hbm_bw_budget || mem > p->hbm_bytes_budget ||
+    if (cu > p->cu_total || inst > p->max_instances || bw > p->hbm_bw_budget || mem > p->hbm_bytes_budget ||
         lat > p->qos_ns)
       continue;
     bool better = !have;
@@ -342,7 +396,11 @@ extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const ca
     best.n_stages = S;
     best.batch = (int32_t)b;
     best.batch_index = bi;
-    for (int s = 0; s < S; ++s) { best.n[s] = 1; best.cu[s] = (cd.k[s] + 1) * p->cu_step; best_lat[s] = L[s]; }
+    for (int s = 0; s < S; ++s) {
+      best.n[s] = cd.n[s];
+      best.cu[s] = (cd.k[s] + 1) * p->cu_step;
+      best_lat[s] = L[c * S + s];
+    }
     const int64_t g = std::gcd(tn, td);
     best.thr_num = tn / g;
     best.thr_den = td / g;

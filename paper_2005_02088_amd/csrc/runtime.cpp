@@ -147,6 +147,8 @@ struct CachedStream {
 };
 static std::map<std::pair<int, int>, CachedStream> g_streams;
 static uint64_t g_stream_clock = 0;
+int32_t new_masked_stream(int offset, int n, hipStream_t* s) { return make_masked_stream(offset, n, s); }
+
 int32_t cached_stream(int offset, int n, hipStream_t* s) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_streams.find({offset, n});
