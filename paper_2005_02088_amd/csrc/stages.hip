@@ -250,10 +250,16 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
     // such padding never enters the result; a lane's elements are a disjoint subset,
     // so the lane maxima bound still holds.
     const __amdgpu_buffer_rsrc_t rs = mlp_rsrc(s, (int64_t)N * 4);
+    uint4 raw[kTopkMaxN / 256];
+#pragma unroll
+    for (int t = 0; t < kTopkMaxN / 256; ++t) raw[t] = bld16(rs, (uint32_t)lane * 16u, (uint32_t)t * 1024u);
+    // all 16 loads in flight before the first use (the scheduler would otherwise
+    // reuse one register set and wait for each load in turn)
+    __builtin_amdgcn_sched_barrier(0);
     float v[kTopkMaxN / 64];
 #pragma unroll
     for (int t = 0; t < kTopkMaxN / 256; ++t) {
-      const float4 q = u4_as_f4(bld16(rs, (uint32_t)lane * 16u, (uint32_t)t * 1024u));
+      const float4 q = u4_as_f4(raw[t]);
       const int i0 = 4 * (lane + 64 * t);
       v[4 * t + 0] = i0 + 0 < N ? q.x : -__builtin_inff();
       v[4 * t + 1] = i0 + 1 < N ? q.y : -__builtin_inff();
