@@ -230,7 +230,7 @@ class Speech:
         return best
 
 
-def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=800, epochs=150):
+def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1200, epochs=150):
     """The contention-aware allocator: co-location profiles of the three stages at
     random shares and batches, the 16-64-64-1 predictor trained on them with the
     library's kernels (target: log slowdown over the solo profile), then Eq. 1 over
@@ -403,14 +403,28 @@ def main():
     la, lpred, linfo = (None, None, None)
     if not args.skip_learned:
         la, lpred, linfo = learned_allocation(cm, G, torch, sp, lat, prob)
+    if la is not None:
+        log(f"learned allocation {la} predicted stage ns {lpred}")
     use = la if la is not None else a
     ninst = tuple(use["n"])
     batch = use["batch"]
     upred = use["thr_num"] / use["thr_den"]
 
     # 3: peak QPS at p99 <= QoS
-    cam = sp.peak_search(use["cu"], cm.HANDOFF_DEVICE, batch, upred, args.trial_s, args.search_iters, "camelot",
-                         n_inst=ninst)
+    try:
+        cam = sp.peak_search(use["cu"], cm.HANDOFF_DEVICE, batch, upred, args.trial_s, args.search_iters,
+                             "camelot", n_inst=ninst)
+    except cm.CamelotError as e:
+        if la is None:
+            raise
+        # a worker of this allocation failed (reported, not hung): fall back to the
+        # solo-table allocation for the reported value
+        log(f"learned allocation failed: {e}; reporting the solo-table allocation")
+        sp.failures.append(f"learned allocation {la['cu']} x {la['n']}: {e}")
+        la = None
+        use, ninst, batch, upred = a, tuple(a["n"]), a["batch"], pred
+        cam = sp.peak_search(use["cu"], cm.HANDOFF_DEVICE, batch, upred, args.trial_s, args.search_iters,
+                             "camelot", n_inst=ninst)
     table = None
     if la is not None:
         table = sp.peak_search(a["cu"], cm.HANDOFF_DEVICE, a["batch"], pred, args.trial_s, args.search_iters,

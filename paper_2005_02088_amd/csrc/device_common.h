@@ -123,6 +123,7 @@ struct WorkerCtl {
   uint64_t next_seq;              // next batch sequence number
   uint64_t ingest_cursor;         // stage 0: next request to take
   uint64_t egress_head;            // result rows written (terminal stage)
+  uint64_t egress_tail_seen;       // the host's egress tail as last read (it only grows)
   uint64_t ticks_bench;           // bench mode: elapsed device ticks
   uint64_t reps_bench;            // bench mode: batches run
   uint32_t bench_stop[2];         // bench mode: workgroup 0's decision to stop, by rep parity

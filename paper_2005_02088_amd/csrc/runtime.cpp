@@ -528,6 +528,7 @@ struct camelot_pipeline {
   // w_stage[w]; stage i's instances are workers first_w[i] .. first_w[i] + n_inst[i] - 1)
   int NW = 0;
   int n_inst[kMaxStages] = {0}, first_w[kMaxStages] = {0}, w_stage[kMaxWorkers] = {0};
+  int w_off[kMaxWorkers] = {0};    // first CU mask bit of each worker's share
   StageRes res[kMaxWorkers];
   hipStream_t streams[kMaxWorkers] = {nullptr};
   WorkerArgs args[kMaxWorkers];
@@ -834,6 +835,7 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     if (rc) { free_pipeline(p); return rc; }
     rc = make_masked_stream(off, cfg->cu[i], &p->streams[w]);
     if (rc) { free_pipeline(p); return rc; }
+    p->w_off[w] = off;
     off += cfg->cu[i];
     a.stage_index = i;
     a.n_stages = S;
@@ -908,8 +910,17 @@ extern "C" int64_t camelot_pipeline_footprint(const camelot_pipeline* p) { retur
 static int32_t worker_error(camelot_pipeline* p) {
   for (int w = 0; w < p->NW; ++w) {
     const int32_t st = __atomic_load_n(&p->pub->status[w], __ATOMIC_ACQUIRE);
-    if (st == kStatusTimeout || st == kStatusAborted)
-      return fail(CAMELOT_EDEVICE, "stage %d worker failed (status %d)", p->w_stage[w], st);
+    if (st == kStatusTimeout || st == kStatusAborted) {
+      // a grid barrier that timed out recorded which counter was short
+      uint32_t diag[3] = {0, 0, 0};
+      (void)d2h(diag, &p->ctl[w]->diag_arrived, sizeof diag);
+      const int i = p->w_stage[w];
+      return fail(CAMELOT_EDEVICE,
+                  "stage %d worker %d (%d CUs at %d) failed (status %d); barrier diagnostics: %u workgroups, "
+                  "group %u had %u arrivals, top counter %u",
+                  i, w - p->first_w[i], p->cfg.cu[i], p->w_off[w], st, diag[1], diag[2], diag[0] & 0xffff,
+                  diag[0] >> 16);
+    }
     if (st == kStatusIdleExit)
       return fail(CAMELOT_ESTOPPED, "stage %d worker exited after the idle timeout", p->w_stage[w]);
   }

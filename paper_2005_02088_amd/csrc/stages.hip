@@ -1097,7 +1097,12 @@ __device__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq,
       const uint64_t want = seq < (uint64_t)a.out_depth ? 0 : 2 * (seq - a.out_depth) + 2;
       ok = ring_load(&a.out_state[slot], a.out_state_sys != 0) == want;
     } else {
+      // the tail last read is a lower bound of the host's (it only grows): a PCIe read
+      // only when that bound leaves too little room; space already seen was acquired
+      // when it was read
+      if (ctl->egress_head + (uint64_t)rows - ctl->egress_tail_seen <= (uint64_t)a.egress_cap) return 0;
       const uint64_t tail = __hip_atomic_load(&a.hctl->egress_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      ctl->egress_tail_seen = tail;
       ok = ctl->egress_head + (uint64_t)rows - tail <= (uint64_t)a.egress_cap;
     }
     if (ok) {
