@@ -330,11 +330,14 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
 // One wave per (row, frame): window 400 samples, pack into 256 complex points,
 // radix-4 Stockham FFT in LDS (4 passes), split into the 257-bin spectrum of the
 // 512-point real transform, power, sparse mel filters, natural log with floor.
+// Each wave runs two (row, frame) units in lockstep (the LDS round trips of one hide
+// behind the other's arithmetic) and loads the next pair's samples while the
+// current pair is transformed.
 constexpr int kTabFloats = 2304;     // room for the window, twiddles and filters
 
 __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
-  __shared__ float2 fbuf[kWaves][2][256];
-  __shared__ float pbuf[kWaves][260];
+  __shared__ float2 fbuf[kWaves][2][2][256];   // [wave][unit of the pair][ping-pong][point]
+  __shared__ float pbuf[kWaves][2][260];
   __shared__ float tab[kTabFloats];
   // stage the small tables in LDS once per batch
   for (int i = threadIdx.x; i < kTabFloats; i += kThreads) tab[i] = a.sp.tables[i];
@@ -347,76 +350,107 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   float* Y = (float*)out;
   const int units = rows * 11, stride = gridDim.x * kWaves;
-  // the samples of a (row, frame) unit: 200 float2 per frame, lane + 64 q; the next
-  // unit's are loaded (global loads, no branches: the last piece is clamped) while
-  // this one is transformed
+  // the samples of a (row, frame) unit: 200 float2 per frame, lane + 64 q (global
+  // loads, no branches: the last piece is clamped)
   typedef float f32x2_t __attribute__((ext_vector_type(2)));
   typedef const f32x2_t __attribute__((address_space(1)))* gptr_f2;
-  f32x2_t xr[4];
-  auto load_unit = [&](int uu) {
+  f32x2_t xr[2][4];
+  auto load_unit = [&](int slot, int uu) {
     const int r = uu / 11, f = uu - r * 11;
     const gptr_f2 x2 = (gptr_f2)((const float*)ctl->d_rowptr[r] + f * 160);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) xr[q] = x2[lane + 64 * q];
-    xr[3] = x2[lane + 192 < 200 ? lane + 192 : 199];
+    for (int q = 0; q < 3; ++q) xr[slot][q] = x2[lane + 64 * q];
+    xr[slot][3] = x2[lane + 192 < 200 ? lane + 192 : 199];
   };
+  // pairs (u, u + stride); a pair without a second unit runs its first twice and
+  // stores once
   int u = blockIdx.x * kWaves + w;
-  if (u < units) load_unit(u);
-  for (; u < units; u += stride) {
-    const int r = u / 11, f = u - r * 11;
+  if (u < units) {
+    load_unit(0, u);
+    load_unit(1, u + stride < units ? u + stride : u);
+  }
+  for (; u < units; u += 2 * stride) {
+    const int u1 = u + stride < units ? u + stride : u;
+    const bool second = u + stride < units;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int n = lane + 64 * q;
-      float2 z = make_float2(0.f, 0.f);
-      if (n < 200) z = make_float2(xr[q].x * win[2 * n], xr[q].y * win[2 * n + 1]);
-      fbuf[w][0][n] = z;
+    for (int sl = 0; sl < 2; ++sl) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = lane + 64 * q;
+        float2 z = make_float2(0.f, 0.f);
+        if (n < 200) z = make_float2(xr[sl][q].x * win[2 * n], xr[sl][q].y * win[2 * n + 1]);
+        fbuf[w][sl][0][n] = z;
+      }
     }
-    if (u + stride < units) load_unit(u + stride);
+    {
+      const int un = u + 2 * stride;
+      if (un < units) {
+        load_unit(0, un);
+        load_unit(1, un + stride < units ? un + stride : un);
+      }
+    }
     wave_lds_sync();
     int src = 0;
     for (int ns = 1; ns < 256; ns *= 4) {
       const int j = lane, jm = j % ns, step = 64 / ns;
-      float2 v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float2 e = fbuf[w][src][j + 64 * q];
-        const float2 t = tw256[q * jm * step];
-        v[q] = make_float2(e.x * t.x - e.y * t.y, e.x * t.y + e.y * t.x);
-      }
-      // forward radix-4 butterfly (omega = -i)
-      const float2 s02 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
-      const float2 d02 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
-      const float2 s13 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
-      const float2 d13 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
-      float2 y[4];
-      y[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
-      y[2] = make_float2(s02.x - s13.x, s02.y - s13.y);
-      y[1] = make_float2(d02.x + d13.y, d02.y - d13.x);   // d02 - i d13
-      y[3] = make_float2(d02.x - d13.y, d02.y + d13.x);   // d02 + i d13
       const int d = (j / ns) * ns * 4 + jm;
+      float2 y[2][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) fbuf[w][src ^ 1][d + q * ns] = y[q];
+      for (int sl = 0; sl < 2; ++sl) {
+        float2 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float2 e = fbuf[w][sl][src][j + 64 * q];
+          const float2 t = tw256[q * jm * step];
+          v[q] = make_float2(e.x * t.x - e.y * t.y, e.x * t.y + e.y * t.x);
+        }
+        // forward radix-4 butterfly (omega = -i)
+        const float2 s02 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const float2 d02 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const float2 s13 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const float2 d13 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+        y[sl][0] = make_float2(s02.x + s13.x, s02.y + s13.y);
+        y[sl][2] = make_float2(s02.x - s13.x, s02.y - s13.y);
+        y[sl][1] = make_float2(d02.x + d13.y, d02.y - d13.x);   // d02 - i d13
+        y[sl][3] = make_float2(d02.x - d13.y, d02.y + d13.x);   // d02 + i d13
+      }
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fbuf[w][sl][src ^ 1][d + q * ns] = y[sl][q];
       wave_lds_sync();
       src ^= 1;
     }
     for (int kk = lane; kk <= 256; kk += 64) {
-      const float2 za = fbuf[w][src][kk & 255];
-      const float2 zb = fbuf[w][src][(256 - kk) & 255];
-      const float er = 0.5f * (za.x + zb.x), ei = 0.5f * (za.y - zb.y);
-      const float dr = za.x - zb.x, di = za.y + zb.y;            // a - conj(b)
-      const float orr = 0.5f * di, oi = -0.5f * dr;               // (a - conj b) / 2i
       const float2 t = tw512[kk];
-      const float xr = er + (t.x * orr - t.y * oi);
-      const float xi = ei + (t.x * oi + t.y * orr);
-      pbuf[w][kk] = xr * xr + xi * xi;
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        const float2 za = fbuf[w][sl][src][kk & 255];
+        const float2 zb = fbuf[w][sl][src][(256 - kk) & 255];
+        const float er = 0.5f * (za.x + zb.x), ei = 0.5f * (za.y - zb.y);
+        const float dr = za.x - zb.x, di = za.y + zb.y;            // a - conj(b)
+        const float orr = 0.5f * di, oi = -0.5f * dr;               // (a - conj b) / 2i
+        const float xr_ = er + (t.x * orr - t.y * oi);
+        const float xi_ = ei + (t.x * oi + t.y * orr);
+        pbuf[w][sl][kk] = xr_ * xr_ + xi_ * xi_;
+      }
     }
     wave_lds_sync();
     if (lane < 40) {
       const int lo = (int)meta[3 * lane], cnt = (int)meta[3 * lane + 1], off = (int)meta[3 * lane + 2];
-      float e = 0.f;
+      float e0 = 0.f, e1 = 0.f;
 #pragma unroll 4
-      for (int t = 0; t < cnt; ++t) e = fmaf(melw[off + t], pbuf[w][lo + t], e);
-      Y[(int64_t)r * 440 + f * 40 + lane] = logf(fmaxf(e, 1e-10f));
+      for (int t = 0; t < cnt; ++t) {
+        const float wt = melw[off + t];
+        e0 = fmaf(wt, pbuf[w][0][lo + t], e0);
+        e1 = fmaf(wt, pbuf[w][1][lo + t], e1);
+      }
+      const int r0 = u / 11, f0 = u - r0 * 11;
+      Y[(int64_t)r0 * 440 + f0 * 40 + lane] = logf(fmaxf(e0, 1e-10f));
+      if (second) {
+        const int r1 = u1 / 11, f1 = u1 - r1 * 11;
+        Y[(int64_t)r1 * 440 + f1 * 40 + lane] = logf(fmaxf(e1, 1e-10f));
+      }
     }
     wave_lds_sync();
   }
