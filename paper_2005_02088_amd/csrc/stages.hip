@@ -682,7 +682,7 @@ __device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT], const MlpRowS
 
 // load groups in flight per unit shape: as many as the registers hold without spills
 #ifndef MLP_PA
-#define MLP_PA(RW, CT, F32) ((F32) ? 4 : (RW) == 2 ? 4 : 8)
+#define MLP_PA(RW, CT, F32) ((F32) ? ((RW) == 2 ? 2 : 4) : (RW) == 2 ? 4 : 8)
 #endif
 // LDS of the row path: the waves' A regions (FP32 rows), then the B stage buffers
 constexpr int kMlpRowLds = 8 * 32 * kRowPitch;
@@ -785,9 +785,7 @@ __device__ __forceinline__ void mlp_row_layer(const uint8_t* const* rowptr, cons
 
 // All layers of a batch. Per layer the unit shape is the
 // largest of (8 row blocks x 2 strips), (4 x 2), (4 x 1) that still gives every
-// workgroup a unit (larger units read the activations and weights fewer times);
-// the first layer, whose FP32 rows take twice the registers, uses one row block
-// per wave.
+// workgroup a unit (larger units read the activations and weights fewer times).
 __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out,
                                              uint8_t* lds, int w, int lane, int tid) {
   const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
@@ -804,8 +802,12 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
     const uint8_t* const* rp = ctl->d_rowptr;
     float* o = (float*)out;
     if (l == 0) {
-      if (even && u12 >= P) mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
-      else mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+      if (even && nrt > 4 && u22 >= P)
+        mlp_row_layer<2, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+      else if (even && u12 >= P)
+        mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+      else
+        mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
     } else if (even && nrt > 4 && u22 >= P) {
       mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
     } else if (even && u12 >= P) {
