@@ -682,7 +682,7 @@ __device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT], const MlpRowS
 
 // load groups in flight per unit shape: as many as the registers hold without spills
 #ifndef MLP_PA
-#define MLP_PA(RW, CT, F32) ((F32) ? ((RW) == 2 ? 2 : 4) : (RW) == 2 ? 4 : 8)
+#define MLP_PA(RW, CT, F32) ((F32) ? ((RW) == 2 ? 2 : 4) : (RW) == 2 ? ((CT) == 4 ? 2 : 4) : 8)
 #endif
 // LDS of the row path: the waves' A regions (FP32 rows), then the B stage buffers
 constexpr int kMlpRowLds = 8 * 32 * kRowPitch;
@@ -783,8 +783,8 @@ __device__ __forceinline__ void mlp_row_layer(const uint8_t* const* rowptr, cons
   }
 }
 
-// All layers of a batch. Per layer the unit shape is the
-// largest of (8 row blocks x 2 strips), (4 x 2), (4 x 1) that still gives every
+// All layers of a batch. Per layer the unit shape is the largest of (8 row blocks x
+// 4 strips; hidden layers only), (8 x 2), (4 x 2), (4 x 1) that still gives every
 // workgroup a unit (larger units read the activations and weights fewer times).
 __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out,
                                              uint8_t* lds, int w, int lane, int tid) {
@@ -808,6 +808,8 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
         mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
       else
         mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    } else if (N % 64 == 0 && nrt > 4 && ((nrt + 7) / 8) * (N / 64) >= P) {
+      mlp_row_layer<2, 4, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
     } else if (even && nrt > 4 && u22 >= P) {
       mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
     } else if (even && u12 >= P) {
