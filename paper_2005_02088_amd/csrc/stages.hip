@@ -336,6 +336,9 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
 constexpr int kTabFloats = 2304;     // room for the window, twiddles and filters
 
 __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+  // no multiply-add contraction: the two units of a pair are separate code, and a
+  // frame must get the same bits in either slot (explicit fmaf calls stay fused)
+#pragma clang fp contract(off)
   __shared__ float2 fbuf[kWaves][2][2][256];   // [wave][unit of the pair][ping-pong][point]
   __shared__ float pbuf[kWaves][2][260];
   __shared__ float tab[kTabFloats];

@@ -133,6 +133,27 @@ def test_logmel_parity(torch, cm, rows):
     assert err <= 1e-5
 
 
+def test_logmel_batch_and_grid_invariant(torch, cm):
+    """A row's log-mel frames are bit-identical alone and at any position of any batch,
+    on any share (the frames of a batch are spread over waves in pairs, so a frame
+    runs in either slot of a pair)."""
+    audio = G.c1_audio(37, seed=11)
+    da = to_dev(torch, audio)
+    desc = cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0)
+    full = torch.empty((37, 440), dtype=torch.float32, device="cuda")
+    one = torch.empty((1, 440), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    cm.camelot_stage_run(desc, da.data_ptr(), full.data_ptr(), 37, 32, 0)
+    f = full.cpu().numpy()
+    for share in (8, 16, 64):
+        for r in (0, 5, 36):
+            cm.camelot_stage_run(desc, da[r:r + 1].data_ptr(), one.data_ptr(), 1, share, 0)
+            assert np.array_equal(one.cpu().numpy()[0].view(np.uint32), f[r].view(np.uint32)), (share, r)
+        part = torch.empty((20, 440), dtype=torch.float32, device="cuda")
+        cm.camelot_stage_run(desc, da[9:29].data_ptr(), part.data_ptr(), 20, share, 0)
+        assert np.array_equal(part.cpu().numpy().view(np.uint32), f[9:29].view(np.uint32)), share
+
+
 def test_logmel_silence_and_impulse(torch, cm):
     audio = np.zeros((2, 2000), np.float32)
     audio[1, 170] = 1.0
