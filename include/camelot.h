@@ -456,9 +456,11 @@ typedef struct {
 } camelot_corun_record;
 
 /* Random co-location profiles: n_runs runs, each of m kernels, m uniform in
- * 1..min(CAMELOT_MAX_CORUN, cu_total / cu_step), each kernel's kind uniform over the
- * n_kinds stages (independently, so a kind can run as several instances, as in an
- * allocation with N_i > 1), shares drawn uniformly in cu_step steps with total <=
+ * 1..min(CAMELOT_MAX_CORUN, cu_total / cu_step); with probability 1/2 (when m >=
+ * n_kinds) the first n_kinds kernels are one of each stage (a deployment's shape),
+ * and every other kernel's kind is uniform over the n_kinds stages (independently,
+ * so a kind can run as several instances, as in an allocation with N_i > 1);
+ * shares drawn uniformly in cu_step steps with total <=
  * cu_total and placed side by side from bit 0, batch indices equal for all kernels
  * with probability 1/2 and independent otherwise; the draws come from a SplitMix64
  * stream seeded with `seed`. in[k]/out[k] are kind k's device buffers for

@@ -134,8 +134,11 @@ extern "C" int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_d
     int32_t rows[CAMELOT_MAX_CORUN], cus[CAMELOT_MAX_CORUN], offs[CAMELOT_MAX_CORUN];
     int off = 0;
     rec.m = m;
+    // half the runs are shaped like a deployment: every stage present, extra
+    // kernels repeating stages (instances); the rest draw kinds independently
+    const bool shaped = m >= n_kinds && uniform(st, 2) == 0;
     for (int i = 0; i < m; ++i) {
-      const int k = uniform(st, n_kinds);
+      const int k = (shaped && i < n_kinds) ? i : uniform(st, n_kinds);
       rec.kinds[i] = k;
       rec.cu[i] = sh[i] * cu_step;
       rec.bi[i] = same ? b0 : uniform(st, n_batches);

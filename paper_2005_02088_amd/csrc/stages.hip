@@ -67,13 +67,35 @@ __device__ __forceinline__ void emit_row(const WorkerArgs& a, WorkerCtl* ctl, in
   }
 }
 
+// Where the rows of the current batch are: contiguous in the input ring slot (stages
+// after the first) or in the one-shot kernel's input, at a computed address; or, for
+// the first stage, wherever each request's payload put them (the per-row table
+// workgroup 0 fills). Kernels read rows through this, so after the batch broadcast
+// no workgroup waits on a table load before its first row load.
+struct BatchRows {
+  const uint8_t* base;          // row r at base + r * stride, or
+  int64_t stride;
+  const uint8_t* const* table;  // row r at table[r]
+  __device__ __forceinline__ const uint8_t* row(int r) const {
+    return base ? base + (int64_t)r * stride : table[r];
+  }
+};
+
+__device__ __forceinline__ BatchRows batch_rows(const WorkerArgs& a, const WorkerCtl* ctl, uint64_t seq) {
+  if (a.in_kind == kInRing)
+    return BatchRows{a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride + kSlotHeaderBytes,
+                     a.sp.in_row_bytes, nullptr};
+  if (a.in_kind == kInBench) return BatchRows{a.bench_in, a.in_row_stride, nullptr};
+  return BatchRows{nullptr, 0, ctl->d_rowptr};
+}
+
 // ------------------------------------------------------------------ GEMM + ReLU (FP32)
 // Unit = (64 output columns, 8 rows) per workgroup; the 4 waves split K in
 // interleaved 64-wide chunks and their partial sums are added in a fixed order,
 // so every output's arithmetic is independent of the batch and of the grid.
 constexpr int kGemmMaxK = 1024;
 
-__device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+__device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
   __shared__ float xs[8][kGemmMaxK];
   __shared__ float part[kWaves][8][64];
   const int K = a.sp.dims[0], N = a.sp.dims[1];
@@ -85,7 +107,7 @@ __device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, int rows, ui
     const int cb = u % n_cb, rb = u / n_cb;
     for (int i = tid; i < 8 * K; i += kThreads) {
       const int r = i / K, kk = i - r * K, row = rb * 8 + r;
-      xs[r][kk] = row < rows ? ((const float*)ctl->d_rowptr[row])[kk] : 0.f;
+      xs[r][kk] = row < rows ? ((const float*)br.row(row))[kk] : 0.f;
     }
     __syncthreads();
     const int col = cb * 64 + lane;
@@ -121,14 +143,14 @@ __device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, int rows, ui
 // lane 0 picks the first maximum.
 constexpr int kArgmaxMaxN = 16;
 
-__device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
+__device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows) {
   __shared__ int32_t s_idx[kWaves][1];
   __shared__ float s_val[kWaves][1];
   const int K = a.sp.dims[0], N = a.sp.dims[1];
   const float* W = (const float*)a.sp.w[0];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
-    const float* x = (const float*)ctl->d_rowptr[r];
+    const float* x = (const float*)br.row(r);
     float acc[kArgmaxMaxN];
 #pragma unroll
     for (int j = 0; j < kArgmaxMaxN; ++j) acc[j] = 0.f;
@@ -227,7 +249,7 @@ __device__ __forceinline__ void topk_rounds(const float* s, int N, int k, int la
   }
 }
 
-__device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
+__device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows) {
   __shared__ int32_t s_idx[kWaves][CAMELOT_MAX_K];
   __shared__ float s_val[kWaves][CAMELOT_MAX_K];
   __shared__ float c_val[kWaves][kTopkCand];
@@ -241,7 +263,7 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
   for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
     // the row pointer is the wave's (scalar registers: the buffer resource below is
     // then scalar too)
-    const uint64_t sp = (uint64_t)ctl->d_rowptr[r];
+    const uint64_t sp = (uint64_t)br.row(r);
     const float* s = (const float*)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sp >> 32)) << 32) |
                                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)sp));
     // the row in registers: v[4 t + e] holds element 4 (lane + 64 t) + e, 16 loads of
@@ -335,7 +357,7 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
 // current pair is transformed.
 constexpr int kTabFloats = 2304;     // room for the window, twiddles and filters
 
-__device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+__device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
   // no multiply-add contraction: the two units of a pair are separate code, and a
   // frame must get the same bits in either slot (explicit fmaf calls stay fused)
 #pragma clang fp contract(off)
@@ -360,7 +382,7 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
   f32x2_t xr[2][4];
   auto load_unit = [&](int slot, int uu) {
     const int r = uu / 11, f = uu - r * 11;
-    const gptr_f2 x2 = (gptr_f2)((const float*)ctl->d_rowptr[r] + f * 160);
+    const gptr_f2 x2 = (gptr_f2)((const float*)br.row(r) + f * 160);
 #pragma unroll
     for (int q = 0; q < 3; ++q) xr[slot][q] = x2[lane + 64 * q];
     xr[slot][3] = x2[lane + 192 < 200 ? lane + 192 : 199];
@@ -532,7 +554,7 @@ struct MlpRowSrc {
 };
 
 template <int RW, int CT, bool F32>
-__device__ __forceinline__ void mlp_row_sources(MlpRowSrc<RW, CT, F32>& src, const uint8_t* const* rowptr,
+__device__ __forceinline__ void mlp_row_sources(MlpRowSrc<RW, CT, F32>& src, const BatchRows& br,
                                                 const uint16_t* hin, int stride, const uint16_t* W, int K, int N,
                                                 int rows, int row0, int col0, int w, int lane, int tid) {
   if constexpr (F32) {
@@ -540,7 +562,7 @@ __device__ __forceinline__ void mlp_row_sources(MlpRowSrc<RW, CT, F32>& src, con
     for (int m = 0; m < 4 * RW; ++m) {
       const int rho = 4 * m + (lane >> 4);
       const int r = row0 + (w + 4 * (rho >> 4)) * 16 + (rho & 15);
-      src.arow[m] = (const float*)rowptr[r < rows ? r : 0] + (lane & 15) * 8;
+      src.arow[m] = (const float*)br.row(r < rows ? r : 0) + (lane & 15) * 8;
     }
   } else {
     // the hidden state is in fragment order: row block rb, chunk c at
@@ -693,7 +715,7 @@ constexpr int kMlpRowLds = 8 * 32 * kRowPitch;
 // One unit: rows row0 .. row0 + 64 RW - 1 (wave w: row blocks w, w + 4, ...),
 // columns col0 .. col0 + 16 CT - 1. All 4 waves run every stage (the barriers).
 template <int RW, int CT, bool F32>
-__device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const uint16_t* hin, int stride,
+__device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t* hin, int stride,
                                              const uint16_t* W, int K, int N, int rows, int row0, int col0,
                                              bool last, uint16_t* hout, float* out, uint8_t* lds, int w, int lane,
                                              int tid) {
@@ -706,7 +728,7 @@ __device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const
   uint8_t* areg = lds + w * SA;
   uint8_t* bbuf = lds + 4 * SA;
   MlpRowSrc<RW, CT, F32> src;
-  mlp_row_sources<RW, CT, F32>(src, rowptr, hin, stride, W, K, N, rows, row0, col0, w, lane, tid);
+  mlp_row_sources<RW, CT, F32>(src, br, hin, stride, W, K, N, rows, row0, col0, w, lane, tid);
   f32x4 acc[RW][CT];
 #pragma unroll
   for (int j = 0; j < RW; ++j)
@@ -774,14 +796,14 @@ __device__ __forceinline__ void mlp_row_unit(const uint8_t* const* rowptr, const
 }
 
 template <int RW, int CT, bool F32>
-__device__ __forceinline__ void mlp_row_layer(const uint8_t* const* rowptr, const uint16_t* hin, int stride,
+__device__ __forceinline__ void mlp_row_layer(const BatchRows& br, const uint16_t* hin, int stride,
                                               const uint16_t* W, int K, int N, int rows, bool last, uint16_t* hout,
                                               float* out, uint8_t* lds, int w, int lane, int tid) {
   const int rpu = 4 * RW;                               // row blocks per unit
   const int nrg = (((rows + 15) >> 4) + rpu - 1) / rpu, ncb = N / (16 * CT);
   for (int u = blockIdx.x; u < nrg * ncb; u += gridDim.x) {
     const int cb = u % ncb, row0 = (u / ncb) * rpu * 16;
-    mlp_row_unit<RW, CT, F32>(rowptr, hin, stride, W, K, N, rows, row0, cb * 16 * CT, last, hout, out, lds, w,
+    mlp_row_unit<RW, CT, F32>(br, hin, stride, W, K, N, rows, row0, cb * 16 * CT, last, hout, out, lds, w,
                               lane, tid);
   }
 }
@@ -789,7 +811,7 @@ __device__ __forceinline__ void mlp_row_layer(const uint8_t* const* rowptr, cons
 // All layers of a batch. Per layer the unit shape is the largest of (8 row blocks x
 // 4 strips; hidden layers only), (8 x 2), (4 x 2), (4 x 1) that still gives every
 // workgroup a unit (larger units read the activations and weights fewer times).
-__device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out,
+__device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& rp, int rows, uint8_t* out,
                                              uint8_t* lds, int w, int lane, int tid) {
   const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
   const int nrt = (rows + 15) >> 4, P = gridDim.x;
@@ -802,7 +824,6 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
     const bool last = (l == L - 1);
     const bool even = (N % 32) == 0;
     const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
-    const uint8_t* const* rp = ctl->d_rowptr;
     float* o = (float*)out;
     if (l == 0) {
       if (even && nrt > 4 && u22 >= P)
@@ -824,12 +845,12 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
   return true;
 }
 
-__device__ __forceinline__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+__device__ __forceinline__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kMlpRowLds];
   // the wave index is uniform across the wave: in a scalar register the per-wave
   // conditions become scalar branches instead of exec-mask regions
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  return mlp_rows_all(a, ctl, rows, out, lds, w, lane, tid);
+  return mlp_rows_all(a, ctl, br, rows, out, lds, w, lane, tid);
 }
 
 // ------------------------------------------------------------------ embedding gather
@@ -838,7 +859,7 @@ __device__ __forceinline__ bool exec_mlp(const WorkerArgs& a, WorkerCtl* ctl, in
 // row's result does not depend on the batch. Ids outside [0, table rows) add zero.
 constexpr int kGatherMaxDim = 1024;
 
-__device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+__device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
   const int n_ids = a.sp.dims[0], dim = a.sp.dims[1];
   const int64_t trows = a.sp.k;
   const __half* T = (const __half*)a.sp.w[0];
@@ -846,7 +867,7 @@ __device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
   const int per = dim >> 6;                  // columns per lane (dim is a multiple of 64)
   float* Y = (float*)out;
   for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
-    const int32_t* ids = (const int32_t*)ctl->d_rowptr[r];
+    const int32_t* ids = (const int32_t*)br.row(r);
     float acc[kGatherMaxDim / 64];
 #pragma unroll
     for (int c = 0; c < kGatherMaxDim / 64; ++c) acc[c] = 0.f;
@@ -878,7 +899,7 @@ __device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8
 // grid barrier, adds the tiles of each query in tile order and divides by H*W.
 constexpr int kConvC = 64, kConvCout = 64, kConvTile = 64;
 
-__device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+__device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
   __shared__ float wsum[kWaves][kConvCout];
   const int H = a.sp.dims[0], Wd = a.sp.dims[1];
   const int npix = H * Wd, ntiles = (npix + kConvTile - 1) / kConvTile;
@@ -888,7 +909,7 @@ __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, int rows, ui
   const int units = rows * ntiles;
   for (int u = blockIdx.x; u < units; u += gridDim.x) {
     const int r = u / ntiles, tile = u - r * ntiles;
-    const uint16_t* X = (const uint16_t*)ctl->d_rowptr[r];
+    const uint16_t* X = (const uint16_t*)br.row(r);
     const int p = tile * kConvTile + w * 16 + (lane & 15);   // A-operand pixel of this lane
     const int py = p / Wd, px = p - py * Wd;
     const bool pin = p < npix;
@@ -950,7 +971,7 @@ __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, int rows, ui
 // ...; lanes of the same id read the same table row, which stays in L1.
 constexpr int kScoreMaxQ = 1024;
 
-__device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
+__device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
   __shared__ float q_s[kWaves][kScoreMaxQ];
   const int qdim = a.sp.dims[0], dim = a.sp.dims[1], n_ids = a.sp.dims[2];
   const int heads = qdim / dim;
@@ -959,7 +980,7 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, int rows,
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* Y = (float*)out;
   for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
-    const float* q = (const float*)ctl->d_rowptr[r];
+    const float* q = (const float*)br.row(r);
     const int32_t* ids = (const int32_t*)ctl->d_rowside[r];
     for (int i = lane; i < qdim; i += 64) q_s[w][i] = q[i];
     wave_lds_sync();
@@ -992,15 +1013,16 @@ __device__ void copy_side(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
 
 // ------------------------------------------------------------------ stage dispatch
 template <int KIND>
-__device__ __forceinline__ bool exec_stage(const WorkerArgs& a, WorkerCtl* ctl, int rows, uint8_t* out) {
-  if constexpr (KIND == CAMELOT_STAGE_GEMM_RELU) { exec_gemm_relu(a, ctl, rows, out); return true; }
-  if constexpr (KIND == CAMELOT_STAGE_GEMM_ARGMAX) { exec_gemm_argmax(a, ctl, rows); return true; }
-  if constexpr (KIND == CAMELOT_STAGE_LOGMEL) { exec_logmel(a, ctl, rows, out); return true; }
-  if constexpr (KIND == CAMELOT_STAGE_MLP_BF16) { return exec_mlp(a, ctl, rows, out); }
-  if constexpr (KIND == CAMELOT_STAGE_TOPK) { exec_topk(a, ctl, rows); return true; }
-  if constexpr (KIND == CAMELOT_STAGE_GATHER) { exec_gather(a, ctl, rows, out); return true; }
-  if constexpr (KIND == CAMELOT_STAGE_CONV_POOL) { return exec_conv_pool(a, ctl, rows, out); }
-  if constexpr (KIND == CAMELOT_STAGE_GATHER_SCORE) { exec_gather_score(a, ctl, rows, out); return true; }
+__device__ __forceinline__ bool exec_stage(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows,
+                                           uint8_t* out) {
+  if constexpr (KIND == CAMELOT_STAGE_GEMM_RELU) { exec_gemm_relu(a, ctl, br, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_GEMM_ARGMAX) { exec_gemm_argmax(a, ctl, br, rows); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_LOGMEL) { exec_logmel(a, ctl, br, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_MLP_BF16) { return exec_mlp(a, ctl, br, rows, out); }
+  if constexpr (KIND == CAMELOT_STAGE_TOPK) { exec_topk(a, ctl, br, rows); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_GATHER) { exec_gather(a, ctl, br, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_CONV_POOL) { return exec_conv_pool(a, ctl, br, rows, out); }
+  if constexpr (KIND == CAMELOT_STAGE_GATHER_SCORE) { exec_gather_score(a, ctl, br, rows, out); return true; }
   return false;
 }
 
@@ -1173,7 +1195,7 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_bench(Wor
   const uint64_t t0 = now_ticks();
   int rep = 0;
   while (rep < a.bench_reps) {
-    if (!exec_stage<KIND>(a, ctl, a.bench_rows, a.bench_out)) return;
+    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, 0), a.bench_rows, a.bench_out)) return;
     ++rep;
     // duration mode: workgroup 0 decides for the whole grid, published by the barrier;
     // two slots by parity so a fast workgroup 0 never overwrites a decision that a
@@ -1366,7 +1388,7 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
     const uint32_t stop = ctl->d_stop;
     if (stop) { exit_status = (int)stop; break; }
     const int rows = (int)ctl->d_rows;
-    if (!exec_stage<KIND>(a, ctl, rows, ctl->d_out)) { exit_status = kStatusTimeout; break; }
+    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, seq), rows, ctl->d_out)) { exit_status = kStatusTimeout; break; }
     copy_side(a, ctl, rows);
     // batch done: every workgroup arrives, only workgroup 0 waits (it publishes and
     // then forms the next batch; the others go on to wait for its broadcast).
