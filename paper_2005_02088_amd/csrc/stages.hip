@@ -589,24 +589,28 @@ __device__ __forceinline__ void mlp_row_issue_b(uint4 (&b)[CT], const MlpRowSrc<
   for (int q = 0; q < CT; ++q) b[q] = bld16(src.rb, src.boff[q], (uint32_t)st * 256u);
 }
 
+// Load group st (A of stage st, B of stage st + 1). Stages past the last one with
+// data (stl) re-load stage stl (the pipeline runs ahead of the end; those values
+// are never used), so the over-run costs cache hits, not memory traffic.
 template <int RW, int CT, bool F32>
 __device__ __forceinline__ void mlp_row_issue(MlpRowSlot<RW, CT, F32>& r, const MlpRowSrc<RW, CT, F32>& src, int K,
-                                              int st, int lane) {
+                                              int st, int stl, int lane) {
+  const int sa = min(st, stl);
 #pragma unroll
   for (int m = 0; m < 4 * RW; ++m) {
     if constexpr (F32) {
       // FP32 rows come from separate buffers: clamped global loads (K past the end
       // reads column 0; zeroed at use)
-      const int k = st * 128 + (lane & 15) * 8;
-      const float* p = src.arow[m] + (k < K ? st * 128 : -(lane & 15) * 8);
+      const int k = sa * 128 + (lane & 15) * 8;
+      const float* p = src.arow[m] + (k < K ? sa * 128 : -(lane & 15) * 8);
       r.a[m][0] = gld16(p);
       r.a[m][1] = gld16(p + 4);
     } else {
       // fragment m = c RW + j: chunk c of the stage, row block j
-      r.a[m][0] = bld16(src.ra, src.aoff[m % RW] + (m / RW) * 1024u, (uint32_t)st * 4096u);
+      r.a[m][0] = bld16(src.ra, src.aoff[m % RW] + (m / RW) * 1024u, (uint32_t)sa * 4096u);
     }
   }
-  mlp_row_issue_b<RW, CT, F32>(r.b, src, st + 1);
+  mlp_row_issue_b<RW, CT, F32>(r.b, src, min(st + 1, stl));
 }
 
 template <int CT>
@@ -736,6 +740,7 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
     for (int t = 0; t < CT; ++t) acc[j][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
   // stages padded to a multiple of PA (padding stages load and do no MFMAs)
   const int ns = ((K + 127) / 128 + PA - 1) / PA * PA;
+  const int stl = (K + 127) / 128 - 1;      // the last stage with data
   MlpRowSlot<RW, CT, F32> sl[PA];
   {
     uint4 b0[CT];
@@ -744,7 +749,7 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int g = 0; g < PA; ++g) {
-      mlp_row_issue<RW, CT, F32>(sl[g], src, K, g, lane);
+      mlp_row_issue<RW, CT, F32>(sl[g], src, K, g, stl, lane);
       __builtin_amdgcn_sched_barrier(0);
     }
     mlp_row_stash_b<CT>(b0, bbuf, tid);
@@ -764,7 +769,7 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
       __builtin_amdgcn_sched_barrier(0);
       mlp_row_mfma<RW, CT, F32>(acc, sl[i], areg, bbuf + (i % NB) * SB, K, st, lane);
       __builtin_amdgcn_sched_barrier(0);
-      mlp_row_issue<RW, CT, F32>(sl[i], src, K, st + PA, lane);
+      mlp_row_issue<RW, CT, F32>(sl[i], src, K, st + PA, stl, lane);
       __builtin_amdgcn_sched_barrier(0);
       __syncthreads();
     }
