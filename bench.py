@@ -20,7 +20,10 @@ Steps (all on synthetic, seeded inputs resident in HBM before any timed region):
  3. peak QPS at p99 <= QoS: Poisson-arrival replays (device-side arrival clock,
     payloads already in HBM), binary search on the rate, for both allocations with
     device-global handoff and for the baseline (even split 88/88/80 CUs,
-    host-staged handoff, same batching rule);
+    host-staged handoff, same batching rule); then a third proposal, Eq. 1 over the
+    solo table plus each stage's measured per-batch cost the table misses (busy time
+    at the solo-table allocation's peak minus its table latency), measured the same
+    way; the best-measured proposal is deployed;
  4. timed steps: K replays at the found peak rate (one step = one trial);
  5. CUs at 20% load: min-resource problem (Eq. 3) at 20% of the baseline's peak,
     checked with a replay;
@@ -379,11 +382,11 @@ def main():
     log(f"profile table: {time.perf_counter() - t0:.1f} s")
     # the MLP stage may run as several instances (the first and last stages own the
     # ingest and the egress and stay single)
-    def problem(mlp_inst_max):
+    def problem(mlp_inst_max, lat_ns=None):
         return cm.ProblemArrays(cu_total=256, cu_step=8, max_instances=48, max_inst_per_stage=MAX_INST,
                                 batches=BATCHES, qos_ns=QOS_NS, hbm_bytes_budget=dev.hbm_bytes,
-                                hbm_bw_budget=int(HBM_PEAK), lat_ns=lat, bw_bps=bw, mem_bytes=mem,
-                                inst_max=[1, mlp_inst_max, 1])
+                                hbm_bw_budget=int(HBM_PEAK), lat_ns=lat if lat_ns is None else lat_ns,
+                                bw_bps=bw, mem_bytes=mem, inst_max=[1, mlp_inst_max, 1])
     prob = problem(MAX_INST)
     prob1 = problem(1)
     t0 = time.perf_counter()
@@ -434,13 +437,39 @@ def main():
     peak_table = (table[0] if table else 0.0) if la is not None else peak
     peak_base = base[0] if base else 0.0
     peak_learned = peak if la is not None else None
-    # deployment check: the allocator's two proposals (contention-aware and solo
-    # table) were both measured; the one with the higher measured peak is deployed
-    # for the timed steps
+    # 3b: calibrated table: at the solo-table allocation's measured peak, each stage's
+    # per-batch busy time minus its table latency is a per-batch cost the table
+    # misses (the worker hand-shakes, co-location); Eq. 1 again with that cost added
+    # to every entry of the stage
+    calib = None
+    a_meas = table if la is not None else cam
+    if a_meas is not None:
+        busy = a_meas[1]["stage"]["busy_us"]
+        extra = [max(0, int(busy[s] * 1e3) - int(lat[s, a["cu"][s] // SHARES[0] - 1, a["batch_index"]]))
+                 for s in range(3)]
+        lat_c = np.where(lat > 0, lat + np.array(extra, np.int64)[:, None, None], lat)
+        ac = cm.camelot_alloc_peak(problem(MAX_INST, lat_c)).as_dict()
+        same = [(x["cu"], x["n"], x["batch"]) for x in ([a, la] if la is not None else [a])]
+        cbest = None
+        if (ac["cu"], ac["n"], ac["batch"]) not in same:
+            cbest = sp.peak_search(ac["cu"], cm.HANDOFF_DEVICE, ac["batch"], ac["thr_num"] / ac["thr_den"],
+                                   args.trial_s, args.search_iters, "calibrated table", n_inst=tuple(ac["n"]))
+        calib = {"per_batch_extra_ns": extra, "allocation_cus": ac["cu"], "allocation_instances": ac["n"],
+                 "batch": ac["batch"], "predicted_qps": ac["thr_num"] / ac["thr_den"],
+                 "measured_peak_qps": (cbest[0] if cbest else 0.0) if cbest is not None else None}
+        log(f"calibrated table: extra per batch {extra} ns -> allocation {ac['cu']} x {ac['n']}, "
+            f"measured {calib['measured_peak_qps']}")
+    # deployment check: the allocator's proposals (contention-aware, solo table,
+    # calibrated table) were measured; the one with the higher measured peak is
+    # deployed for the timed steps
     deployed = "contention-aware (learned predictor)" if la is not None else "solo profile table"
     if la is not None and peak_table > peak:
         use, ninst, batch, peak = a, tuple(a["n"]), a["batch"], peak_table
         deployed = "solo profile table (higher measured peak than the contention-aware proposal)"
+    if calib is not None and (calib["measured_peak_qps"] or 0.0) > peak:
+        use = {"cu": calib["allocation_cus"], "n": calib["allocation_instances"], "batch": calib["batch"]}
+        ninst, batch, peak = tuple(use["n"]), use["batch"], calib["measured_peak_qps"]
+        deployed = "calibrated solo table (highest measured peak)"
     log(f"deployed allocation {use['cu']} x {use['n']}: {deployed}")
 
     if peak <= 0:
@@ -527,6 +556,7 @@ def main():
         "handoff": {"gbs": h["gbs"], "frac_of_hbm_peak": h["gbs"] * 1e9 / HBM_PEAK, "checksum_ok": handoff_ok,
                     "ring_bytes": slot * 16, "host_staged_gbs": hh["gbs"]},
         "learned_allocator": learned,
+        "calibrated_table_allocation": calib,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
