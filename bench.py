@@ -49,7 +49,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 QOS_NS = 50_000_000
-MAX_INST = 4            # instances per stage the allocator may place
+MAX_INST = 4            # instances per stage the allocator may place (every instance is a
+                        # hardware queue; with 7 workers a barrier timeout was seen)
 HBM_PEAK = 8.0e12
 MFMA_BF16_PEAK = 2.5e15
 MLP_PARAMS = 440 * 2048 + 2048 * 2048 * 2 + 2048 * 4096
@@ -461,38 +462,50 @@ def main():
             f"measured {calib['measured_peak_qps']}")
     # deployment check: the allocator's proposals (contention-aware, solo table,
     # calibrated table) were measured; the one with the higher measured peak is
-    # deployed for the timed steps
-    deployed = "contention-aware (learned predictor)" if la is not None else "solo profile table"
-    if la is not None and peak_table > peak:
-        use, ninst, batch, peak = a, tuple(a["n"]), a["batch"], peak_table
-        deployed = "solo profile table (higher measured peak than the contention-aware proposal)"
-    if calib is not None and (calib["measured_peak_qps"] or 0.0) > peak:
-        use = {"cu": calib["allocation_cus"], "n": calib["allocation_instances"], "batch": calib["batch"]}
-        ninst, batch, peak = tuple(use["n"]), use["batch"], calib["measured_peak_qps"]
-        deployed = "calibrated solo table (highest measured peak)"
-    log(f"deployed allocation {use['cu']} x {use['n']}: {deployed}")
-
-    if peak <= 0:
+    # deployed for the timed steps (the next one if its workers fail there)
+    cands = []
+    if la is not None and peak_learned:
+        cands.append((peak_learned, la, "contention-aware (learned predictor)"))
+    if peak_table:
+        cands.append((peak_table, a, "solo profile table"))
+    if calib is not None and calib["measured_peak_qps"]:
+        cands.append((calib["measured_peak_qps"], {"cu": calib["allocation_cus"], "n": calib["allocation_instances"],
+                                                  "batch": calib["batch"]}, "calibrated solo table"))
+    cands.sort(key=lambda c: -c[0])
+    if not cands:
         raise SystemExit("no rate met the QoS target; see the trial log above")
-    # 4: timed steps at the found peak; the reported rate is one at which every timed
-    # step met the QoS target (the search's last good rate, lowered by 3% per retry)
-    for attempt in range(6):
-        for w in range(args.warmup):
-            sp.trial(use["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w,
-                     n_inst=ninst)
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        steps = []
-        for k in range(args.steps):
-            steps.append(sp.trial(use["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4,
-                                  seed=200 + k, n_inst=ninst))
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        p99s = [s["p99"] for s in steps]
-        log(f"timed steps at {peak / 1e6:.3f} Mq/s: p99 {p99s}")
-        if all(s["ok"] for s in steps):
+    steps, p99s, elapsed = None, None, None
+    for peak, use, deployed in cands:
+        ninst, batch = tuple(use["n"]), use["batch"]
+        log(f"deployed allocation {use['cu']} x {use['n']}: {deployed}")
+        try:
+            # 4: timed steps at the found peak; the reported rate is one at which every
+            # timed step met the QoS target (the search's last good rate, lowered by 3%
+            # per retry)
+            for attempt in range(6):
+                for w in range(args.warmup):
+                    sp.trial(use["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4, seed=100 + w,
+                             n_inst=ninst)
+                torch.cuda.synchronize()
+                t_start = time.perf_counter()
+                steps = []
+                for k in range(args.steps):
+                    steps.append(sp.trial(use["cu"], peak, args.trial_s, cm.HANDOFF_DEVICE, batch, QOS_NS // 4,
+                                          seed=200 + k, n_inst=ninst))
+                torch.cuda.synchronize()
+                elapsed = time.perf_counter() - t_start
+                p99s = [s["p99"] for s in steps]
+                log(f"timed steps at {peak / 1e6:.3f} Mq/s: p99 {p99s}")
+                if all(s["ok"] for s in steps):
+                    break
+                peak *= 0.97
             break
-        peak *= 0.97
+        except cm.CamelotError as e:
+            log(f"deployed allocation failed in the timed steps: {e}")
+            sp.failures.append(f"timed steps, allocation {use['cu']} x {use['n']}: {e}")
+            steps = None
+    if steps is None:
+        raise SystemExit("every allocation proposal failed in the timed steps")
 
     # 5: CUs at 20% load
     lam20 = 0.2 * peak_base

@@ -91,7 +91,7 @@ int32_t camelot_device_query(camelot_device_info* out);
  * bounded by max_inst_per_stage alone). All owned by the caller, read only.
  */
 #define CAMELOT_MAX_STAGES 8
-#define CAMELOT_MAX_INSTANCES 4     /* instances of one pipeline stage              */
+#define CAMELOT_MAX_INSTANCES 6     /* instances of one pipeline stage              */
 #define CAMELOT_MAX_WORKERS 16      /* stage instances of one pipeline in total     */
 
 typedef struct {
@@ -445,7 +445,7 @@ int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stages, const v
                             void* const* out, const int32_t* rows, const int32_t* n_cus,
                             const int32_t* cu_offset, int64_t duration_ns, double* ns_per_batch);
 
-#define CAMELOT_MAX_CORUN 6     /* kernels of one co-location profile or candidate */
+#define CAMELOT_MAX_CORUN 8     /* kernels of one co-location profile or candidate */
 
 typedef struct {
   int32_t m;                            /* kernels in this run, 1..CAMELOT_MAX_CORUN     */

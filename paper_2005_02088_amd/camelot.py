@@ -97,7 +97,7 @@ class PipelineStats(C.Structure):
                 ("wait_ns", C.c_int64 * MAX_STAGES)]
 
 
-MAX_CORUN = 6
+MAX_CORUN = 8
 
 
 class CorunRecord(C.Structure):

@@ -149,6 +149,17 @@ static std::map<std::pair<int, int>, CachedStream> g_streams;
 static uint64_t g_stream_clock = 0;
 int32_t new_masked_stream(int offset, int n, hipStream_t* s) { return make_masked_stream(offset, n, s); }
 
+// Drops the cached streams (all idle): a pipeline's persistent workers then share
+// the device's hardware queues with as few other queues as possible.
+static void release_cached_streams() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_streams) {
+    (void)hipStreamSynchronize(kv.second.s);
+    (void)hipStreamDestroy(kv.second.s);
+  }
+  g_streams.clear();
+}
+
 int32_t cached_stream(int offset, int n, hipStream_t* s) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_streams.find({offset, n});
@@ -818,6 +829,7 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     }
   }
 
+  release_cached_streams();
   // ---- stage instance (worker) resources, control, streams
   int off = cfg->cu_offset;
   for (int w = 0; w < p->NW; ++w) {

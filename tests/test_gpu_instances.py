@@ -53,9 +53,10 @@ def run_c1(torch, cm, n_inst, shares, handoff, n=96, ring_depth=8):
     ((1, 2, 1), (32, 96, 32), 0),
     ((1, 2, 1), (32, 96, 32), 1),
     ((1, 3, 1), (32, 64, 32), 0),
+    ((1, 6, 1), (32, 32, 32), 0),
 ])
 def test_c1_mlp_instances_match_single_instance(torch, cm, n_inst, shares, handoff):
-    ws, audio, vals, idx = run_c1(torch, cm, n_inst, shares, handoff)
+    ws, audio, vals, idx = run_c1(torch, cm, n_inst, shares, handoff, ring_depth=max(8, 2 * n_inst[1]))
     # the MLP result of a row does not depend on the batch it rides in nor on the
     # instance (or CU share) that runs it, so the one-instance pipeline agrees bit for bit
     _, _, vals1, idx1 = run_c1(torch, cm, (1, 1, 1), (32, 96, 32), 0)
@@ -71,7 +72,7 @@ def test_instances_rejected_where_not_allowed(torch, cm):
     bad = [
         cm.pipeline_config(stages, (32, 32, 32), n_inst=(2, 1, 1)),              # first stage
         cm.pipeline_config(stages, (32, 32, 32), n_inst=(1, 1, 2)),              # last stage
-        cm.pipeline_config(stages, (8, 32, 8), n_inst=(1, 5, 1), ring_depth=16),  # above the maximum
+        cm.pipeline_config(stages, (8, 16, 8), n_inst=(1, 7, 1), ring_depth=16),  # above the maximum
         cm.pipeline_config(stages, (32, 32, 32), n_inst=(1, 3, 1), ring_depth=4),  # ring too shallow
         cm.pipeline_config(stages, (32, 112, 32), n_inst=(1, 2, 1)),             # 288 CUs in all
     ]

@@ -63,7 +63,7 @@ def test_feature_layout_solo_has_empty_corunner_slots():
 def test_feature_validation():
     t = _tables()
     for kinds, cu, bi in (([3], [8], [0]), ([0], [12], [0]), ([0], [264], [0]), ([0], [8], [8]),
-                          ([0] * 7, [8] * 7, [0] * 7)):
+                          ([0] * 9, [8] * 9, [0] * 9)):
         with pytest.raises(cm.CamelotError):
             cm.camelot_predictor_features(t, kinds, cu, bi)
 
