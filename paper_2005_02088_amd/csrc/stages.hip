@@ -1006,7 +1006,7 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const Bat
 
 // ------------------------------------------------------------------ side bytes
 // Copies every row's side bytes from the input to the output slot's side plane.
-__device__ void copy_side(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
+__device__ __forceinline__ void copy_side(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
   if (a.side_bytes <= 0 || a.out_kind != kOutRing) return;
   uint8_t* dst = (uint8_t*)ctl->d_out_hdr + a.out_side_off;
   const int words = a.side_bytes >> 2;
@@ -1060,14 +1060,17 @@ __device__ __forceinline__ bool host_stop(const WorkerArgs& a, uint32_t& polls) 
   return __hip_atomic_load(&a.hctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
 }
 
-// Stage 0: form a batch from the ingest (wave 0 of workgroup 0). Requests are
-// taken whole, in order, while the rows fit in max_batch; the batch starts when
-// batch_target rows wait, when the next waiting request does not fit, or when the
-// oldest waited batch_timeout. Writes the chosen requests into LDS arrays.
-__device__ Acq acquire_ingest(const WorkerArgs& a, WorkerCtl* ctl, uint64_t t0, uint64_t* s_id,
+// Status of a one-poll acquisition that found the batch not ready (never published).
+constexpr int kAcqNotReady = -1;
+
+// Stage 0: form a batch from the ingest (wave 0 of workgroup 0), starting at
+// ingest record c. Requests are taken whole, in order, while the rows fit in
+// max_batch; the batch starts when batch_target rows wait, when the next waiting
+// request does not fit, or when the oldest waited batch_timeout. Writes the chosen
+// requests into LDS arrays. try_only: one pass, kAcqNotReady if no batch starts.
+__device__ __forceinline__ Acq acquire_ingest(const WorkerArgs& a, uint64_t c, uint64_t t0, bool try_only, uint64_t* s_id,
                               uint64_t* s_tarr, uint32_t* s_rows, const uint8_t** s_ptr) {
   const int lane = threadIdx.x & 63;
-  const uint64_t c = ctl->ingest_cursor;
   // replay arrival times are relative to the epoch t0; host ones are absolute
   const uint64_t base = a.in_kind == kInHost ? 0 : t0;
   const uint64_t t_wait0 = now_ticks();
@@ -1129,14 +1132,15 @@ __device__ Acq acquire_ingest(const WorkerArgs& a, WorkerCtl* ctl, uint64_t t0, 
         return Acq{0, taken, rows};
       }
     }
+    if (try_only) return Acq{kAcqNotReady, 0, 0};
     if (host_stop(a, polls)) return Acq{kStatusStopped, 0, 0};
     if ((int64_t)(now - t_wait0) > a.idle_ticks) return Acq{kStatusIdleExit, 0, 0};
     __builtin_amdgcn_s_sleep(2);
   }
 }
 
-// Stages > 0: wait for the doorbell of input slot seq.
-__device__ Acq acquire_ring(const WorkerArgs& a, uint64_t seq) {
+// Stages > 0: wait for the doorbell of input slot seq (try_only: one poll).
+__device__ __forceinline__ Acq acquire_ring(const WorkerArgs& a, uint64_t seq, bool try_only) {
   const uint64_t slot = seq % (uint64_t)a.in_depth;
   const uint64_t want = 2 * seq + 1;
   const uint64_t t_wait0 = now_ticks();
@@ -1148,14 +1152,17 @@ __device__ Acq acquire_ring(const WorkerArgs& a, uint64_t seq) {
       const SlotHeader* h = (const SlotHeader*)(a.in_ring + slot * (uint64_t)a.in_stride);
       return Acq{0, (int)h->n_req, (int)h->n_rows};
     }
+    if (try_only) return Acq{kAcqNotReady, 0, 0};
     if (host_stop(a, polls)) return Acq{kStatusStopped, 0, 0};
     if ((int64_t)(now_ticks() - t_wait0) > a.idle_ticks) return Acq{kStatusIdleExit, 0, 0};
     __builtin_amdgcn_s_sleep(1);
   }
 }
 
-// Wait until the output can take batch seq of `rows` rows.
-__device__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq, int rows) {
+// Wait until the output can take batch seq of `rows` rows (try_only: one poll).
+// Egress space is counted from ctl->egress_head, the rows of every batch formed
+// so far (formation reserves them).
+__device__ __forceinline__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq, int rows, bool try_only) {
   const uint64_t t_wait0 = now_ticks();
   uint32_t polls = 0;
   for (;;) {
@@ -1177,6 +1184,7 @@ __device__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq,
       ring_acquire(a.out_kind != kOutRing || a.out_state_sys != 0);
       return 0;
     }
+    if (try_only) return kAcqNotReady;
     if (host_stop(a, polls)) return kStatusStopped;
     if ((int64_t)(now_ticks() - t_wait0) > a.idle_ticks) return kStatusIdleExit;
     __builtin_amdgcn_s_sleep(1);
@@ -1246,6 +1254,107 @@ __device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t s
   return s_go != 0;
 }
 
+// What workgroup 0 stages in LDS for one batch while forming it.
+struct BatchLds {
+  uint64_t id[kMaxBatch];               // request ids
+  uint64_t tarr[kMaxBatch];             // request arrival ticks
+  uint32_t rows[kMaxBatch];             // rows per request
+  const uint8_t* ptr[kMaxBatch];        // stage 0: first payload row of each request
+  uint32_t rbase[kMaxBatch + 1];        // first row of each request in the batch
+  uint64_t t_stage[2 * kMaxStages];     // stage timestamps carried by the input slot
+  uint64_t red[2][kWaves];              // per-wave id checksums (sum, xor)
+  uint64_t cursor;                      // stage 0: next ingest record not in a batch
+  uint64_t egress_base;                 // terminal stage: first egress row of the batch
+  int acq[3];                           // status, requests, rows
+};
+
+// Formation of batch seq by all threads of workgroup 0: acquire its input (ingest
+// requests, or the full ring slot seq) and its output space, then stage the
+// requests, their row offsets, the input's stage timestamps and the id checksums
+// in LDS. Stage 0 takes the requests (advances the ingest cursor) and a terminal
+// stage reserves the egress rows only when the batch is formed. try_only: one poll,
+// kAcqNotReady when the batch is not ready, and then nothing is taken.
+// Returns 0 when the batch is staged, else the status.
+__device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq, uint64_t t0, bool try_only,
+                          BatchLds& s) {
+  const int tid = threadIdx.x;
+  const int si = a.stage_index;
+  if (tid < 64) {
+    Acq q;
+    if (si == 0) {
+      q = acquire_ingest(a, s.cursor, t0, try_only, s.id, s.tarr, s.rows, s.ptr);
+    } else {
+      q = (tid == 0) ? acquire_ring(a, seq, try_only) : Acq{0, 0, 0};
+      q.status = __shfl(q.status, 0, 64);
+      q.nreq = __shfl(q.nreq, 0, 64);
+      q.rows = __shfl(q.rows, 0, 64);
+    }
+    if (q.status == 0 && tid == 0) q.status = acquire_output(a, ctl, seq, q.rows, try_only);
+    if (tid == 0) { s.acq[0] = q.status; s.acq[1] = q.nreq; s.acq[2] = q.rows; }
+  }
+  __syncthreads();
+  const int st = s.acq[0], nreq = s.acq[1];
+  if (st != 0) return st;
+  if (si > 0) {
+    const SlotHeader* ih = (const SlotHeader*)(a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride);
+    for (int q = tid; q < nreq; q += kThreads) {
+      s.id[q] = ih->req_id[q];
+      s.tarr[q] = ih->req_tarr[q];
+      s.rows[q] = ih->req_rows[q];
+    }
+    if (tid < 2 * kMaxStages) s.t_stage[tid] = ih->t_stage[tid];
+  } else if (tid < 2 * kMaxStages) {
+    s.t_stage[tid] = 0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // first row of each request: exclusive prefix sum of the row counts, 64 at a time
+    uint32_t carry = 0;
+    for (int b = 0; b < nreq; b += 64) {
+      const int q = b + tid;
+      const uint32_t v = q < nreq ? s.rows[q] : 0u;
+      uint32_t inc = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (tid >= d) inc += t;
+      }
+      if (q < nreq) s.rbase[q] = carry + inc - v;
+      carry += __shfl(inc, 63, 64);
+    }
+    if (tid == 0) {
+      s.rbase[nreq] = carry;
+      if (si == 0) s.cursor += (uint64_t)nreq;
+      if (a.out_kind == kOutEgress) {
+        s.egress_base = ctl->egress_head;
+        ctl->egress_head += (uint64_t)s.acq[2];
+      }
+    }
+  }
+  // id checksums of the requests of this batch
+  uint64_t hs = 0, hx = 0;
+  for (int q = tid; q < nreq; q += kThreads) {
+    const uint64_t h = id_hash(s.id[q]);
+    hs += h;
+    hx ^= h;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    hs += __shfl_xor(hs, off, 64);
+    hx ^= __shfl_xor(hx, off, 64);
+  }
+  if ((tid & 63) == 0) { s.red[0][tid >> 6] = hs; s.red[1][tid >> 6] = hx; }
+  __syncthreads();
+  return 0;
+}
+
+// Persistent worker. Per batch: workgroup 0 forms the batch (or takes the one it
+// formed early), writes its descriptor and broadcasts it; every workgroup runs
+// its share of the stage; all arrive at the batch barrier. While the others
+// finish, workgroup 0 tries once to form the next batch (seq + n_inst) so that
+// acquisition and staging leave the path between two batches; then it waits for
+// the barrier and publishes the batch (output doorbell, input slot release or
+// ingest tail, egress head, counters).
 template <int KIND>
 __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(WorkerArgs a) {
   WorkerCtl* ctl = a.ctl;
@@ -1253,124 +1362,85 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
   const bool wg0 = blockIdx.x == 0;
   const int si = a.stage_index;
 
-  // ---------------- pipeline mode
-  __shared__ uint64_t s_id[kMaxBatch];
-  __shared__ uint64_t s_tarr[kMaxBatch];
-  __shared__ uint32_t s_rows[kMaxBatch];
-  __shared__ const uint8_t* s_ptr[kMaxBatch];
-  __shared__ uint32_t s_rbase[kMaxBatch + 1];
-  __shared__ int s_acq[3];
-  __shared__ uint64_t s_red[2][kWaves];
-
+  __shared__ BatchLds s;
   __shared__ uint64_t s_t0;
   if (wg0 && tid == 0) {
     s_t0 = now_ticks();
+    s.cursor = ctl->ingest_cursor;
     if (si == 0) st_relaxed_sys(&a.pub->t0, s_t0);
     st_relaxed_sys(&a.pub->started[a.worker_index], 1);
   }
   if (wg0) __syncthreads();
   uint64_t seq = ctl->next_seq;
   int exit_status = kStatusOk;
+  bool pending = false;          // workgroup 0: batch seq is already formed and staged
+  // workgroup 0: what the publication of the current batch needs (kept in LDS, out
+  // of the registers the stage needs)
+  __shared__ struct {
+    uint64_t hs, hx, t_start, t_top, ingest_end, egress_end;
+    int rows;
+  } b;
   for (;;) {
-    const uint64_t t_top = now_ticks();
-    // ---------------- control: acquire the next batch (workgroup 0)
+    // ---------------- control: form the batch, write its descriptor, broadcast (workgroup 0)
     if (wg0) {
-      if (tid < 64) {
-        Acq q;
-        if (si == 0) {
-          q = acquire_ingest(a, ctl, s_t0, s_id, s_tarr, s_rows, s_ptr);
-        } else {
-          q = (tid == 0) ? acquire_ring(a, seq) : Acq{0, 0, 0};
-          q.status = __shfl(q.status, 0, 64);
-          q.nreq = __shfl(q.nreq, 0, 64);
-          q.rows = __shfl(q.rows, 0, 64);
-        }
-        if (q.status == 0 && tid == 0) q.status = acquire_output(a, ctl, seq, q.rows);
-        if (tid == 0) { s_acq[0] = q.status; s_acq[1] = q.nreq; s_acq[2] = q.rows; }
-      }
-      __syncthreads();
-      const int st = s_acq[0], nreq = s_acq[1], rows = s_acq[2];
+      const uint64_t t_top = now_ticks();
+      const int st = pending ? 0 : form_batch(a, ctl, seq, s_t0, false, s);
+      pending = false;
       if (st == 0) {
+        const int nreq = s.acq[1], rows = s.acq[2];
         const uint64_t t_start = now_ticks();
-        const SlotHeader* ih = nullptr;
-        if (si > 0) {
-          ih = (const SlotHeader*)(a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride);
-          for (int q = tid; q < nreq; q += kThreads) {
-            s_id[q] = ih->req_id[q];
-            s_tarr[q] = ih->req_tarr[q];
-            s_rows[q] = ih->req_rows[q];
-          }
-        }
-        __syncthreads();
-        if (tid == 0) {
-          uint32_t acc = 0;
-          for (int q = 0; q < nreq; ++q) { s_rbase[q] = acc; acc += s_rows[q]; }
-          s_rbase[nreq] = acc;
-        }
-        __syncthreads();
-        // per-row descriptor
-        const uint8_t* in_payload = ih ? (const uint8_t*)ih + kSlotHeaderBytes : nullptr;
+        // per-row descriptors: input row pointers (ingest), side bytes, and the
+        // request of each row (egress records)
+        const uint8_t* in_payload = si > 0 ? a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride +
+                                                 kSlotHeaderBytes
+                                           : nullptr;
+        const uint8_t* in_hdr = si > 0 ? in_payload - kSlotHeaderBytes : nullptr;
         for (int q = tid; q < nreq; q += kThreads) {
-          for (uint32_t j = 0; j < s_rows[q]; ++j) {
-            const uint32_t row = s_rbase[q] + j;
-            const uint8_t* rp = ih ? in_payload + (int64_t)row * a.sp.in_row_bytes
-                                   : s_ptr[q] + (int64_t)j * a.in_row_stride;
-            ctl->d_rowptr[row] = rp;
-            ctl->d_rowside[row] = ih ? (const uint8_t*)ih + a.in_side_off + (int64_t)row * a.side_bytes
-                                     : rp + a.sp.in_row_bytes;
-            ctl->d_row_id[row] = s_id[q];
-            ctl->d_row_idx[row] = j;
-            ctl->d_row_tarr[row] = s_tarr[q];
+          for (uint32_t j = 0; j < s.rows[q]; ++j) {
+            const uint32_t row = s.rbase[q] + j;
+            const uint8_t* rp = si > 0 ? in_payload + (int64_t)row * a.sp.in_row_bytes
+                                       : s.ptr[q] + (int64_t)j * a.in_row_stride;
+            if (si == 0) ctl->d_rowptr[row] = rp;
+            ctl->d_rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
+                                         : rp + a.sp.in_row_bytes;
+            if (a.out_kind == kOutEgress) {
+              ctl->d_row_id[row] = s.id[q];
+              ctl->d_row_idx[row] = j;
+              ctl->d_row_tarr[row] = s.tarr[q];
+            }
           }
         }
-        if (tid < 2 * kMaxStages) {
-          uint64_t tv = ih ? ih->t_stage[tid] : 0;
-          if (tid == 2 * si) tv = t_start;
-          ctl->d_t_stage[tid] = tv;
-        }
+        if (tid < 2 * kMaxStages) ctl->d_t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
         if (a.out_kind == kOutRing) {
           SlotHeader* oh = (SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
           for (int q = tid; q < nreq; q += kThreads) {
-            oh->req_id[q] = s_id[q];
-            oh->req_tarr[q] = s_tarr[q];
-            oh->req_rows[q] = s_rows[q];
+            oh->req_id[q] = s.id[q];
+            oh->req_tarr[q] = s.tarr[q];
+            oh->req_rows[q] = s.rows[q];
           }
+          if (tid < 2 * kMaxStages) oh->t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
           if (tid == 0) {
             oh->seq = seq;
             oh->n_req = (uint32_t)nreq;
             oh->n_rows = (uint32_t)rows;
-          }
-          if (tid < 2 * kMaxStages) {
-            uint64_t tv = ih ? ih->t_stage[tid] : 0;
-            if (tid == 2 * si) tv = t_start;
-            oh->t_stage[tid] = tv;
-          }
-          if (tid == 0) {
             ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
             ctl->d_out_hdr = oh;
           }
         } else if (tid == 0) {
-          ctl->d_egress_base = ctl->egress_head;
+          ctl->d_egress_base = s.egress_base;
           ctl->d_out = nullptr;
         }
-        // id checksums of the requests of this batch
-        uint64_t hs = 0, hx = 0;
-        for (int q = tid; q < nreq; q += kThreads) {
-          const uint64_t h = id_hash(s_id[q]);
-          hs += h;
-          hx ^= h;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          hs += __shfl_xor(hs, off, 64);
-          hx ^= __shfl_xor(hx, off, 64);
-        }
-        if ((tid & 63) == 0) { s_red[0][tid >> 6] = hs; s_red[1][tid >> 6] = hx; }
         if (tid == 0) {
           ctl->d_rows = (uint32_t)rows;
-          ctl->d_nreq = (uint32_t)nreq;
-          ctl->d_seq = seq;
-          ctl->d_t_start = t_start;
+          uint64_t hs = 0, hx = 0;
+          for (int w = 0; w < kWaves; ++w) { hs += s.red[0][w]; hx ^= s.red[1][w]; }
+          b.hs = hs;
+          b.hx = hx;
+          b.rows = rows;
+          b.t_start = t_start;
+          b.t_top = t_top;
+          b.ingest_end = s.cursor;
+          b.egress_end = s.egress_base + (uint64_t)rows;
         }
       }
       if (tid == 0) ctl->d_stop = (uint32_t)st;
@@ -1392,49 +1462,62 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
     if (a.in_state_sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     const uint32_t stop = ctl->d_stop;
     if (stop) { exit_status = (int)stop; break; }
-    const int rows = (int)ctl->d_rows;
-    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, seq), rows, ctl->d_out)) { exit_status = kStatusTimeout; break; }
+    // the descriptor is the same for every lane: keep it in scalar registers
+    const int rows = __builtin_amdgcn_readfirstlane((int)ctl->d_rows);
+    const uint64_t outp = (uint64_t)ctl->d_out;
+    uint8_t* const out = (uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(outp >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)outp));
+    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, seq), rows, out)) { exit_status = kStatusTimeout; break; }
     copy_side(a, ctl, rows);
     // batch done: every workgroup arrives, only workgroup 0 waits (it publishes and
     // then forms the next batch; the others go on to wait for its broadcast).
     // Results go to pinned host memory, a host-staged output slot is read by DMA:
     // those are published at system scope.
     const BarTicket done = grid_arrive(ctl, gridDim.x, a.out_kind == kOutEgress || a.out_state_sys != 0);
-    if (wg0 && !grid_wait(ctl, gridDim.x, done, a.spin_ticks)) {
+    if (!wg0) {
+      seq += (uint64_t)a.n_inst;
+      continue;
+    }
+    // the next batch, if it is ready now; it touches only workgroup 0's LDS, the
+    // slots of batch seq + n_inst and the cursors that formation advances
+    pending = form_batch(a, ctl, seq + (uint64_t)a.n_inst, s_t0, true, s) == 0;
+    if (!grid_wait(ctl, gridDim.x, done, a.spin_ticks)) {
       exit_status = kStatusTimeout;
       break;
     }
-    // ---------------- publish (workgroup 0, thread 0)
-    if (wg0 && tid == 0) {
+    // ---------------- publish (workgroup 0, thread 0): one release fence for the
+    // output doorbell and the input slot release
+    if (tid == 0) {
       const uint64_t t_end = now_ticks();
-      const int nreq = (int)ctl->d_nreq;
+      const bool sys = a.out_kind == kOutEgress || a.out_state_sys != 0 || a.in_state_sys != 0;
       if (a.out_kind == kOutRing) {
         SlotHeader* oh = (SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
         oh->t_stage[2 * si + 1] = t_end;
-        if (a.out_state_sys) {
-          // host-staged boundary: the relay reads the row count next to the state word
-          st_relaxed_sys(&a.out_state[a.out_depth + seq % (uint64_t)a.out_depth], (uint64_t)rows);
-          __threadfence_system();
-        }
-        ring_store(&a.out_state[seq % (uint64_t)a.out_depth], 2 * seq + 1, a.out_state_sys != 0);
+        // host-staged boundary: the relay reads the row count next to the state word
+        if (a.out_state_sys) st_relaxed_sys(&a.out_state[a.out_depth + seq % (uint64_t)a.out_depth], (uint64_t)b.rows);
+      }
+      if (sys) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (a.out_kind == kOutRing) {
+        uint64_t* p = &a.out_state[seq % (uint64_t)a.out_depth];
+        if (a.out_state_sys) st_relaxed_sys(p, 2 * seq + 1);
+        else __hip_atomic_store(p, 2 * seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
-        ctl->egress_head += (uint64_t)rows;
-        st_release_sys(&a.pub->egress_head, ctl->egress_head);
+        st_relaxed_sys(&a.pub->egress_head, b.egress_end);
       }
       if (si == 0) {
-        ctl->ingest_cursor += (uint64_t)nreq;
-        st_relaxed_sys(&a.pub->ingest_tail, ctl->ingest_cursor);
+        st_relaxed_sys(&a.pub->ingest_tail, b.ingest_end);
       } else {
-        ring_store(&a.in_state[seq % (uint64_t)a.in_depth], 2 * seq + 2, a.in_state_sys != 0);
+        uint64_t* p = &a.in_state[seq % (uint64_t)a.in_depth];
+        if (a.in_state_sys) st_relaxed_sys(p, 2 * seq + 2);
+        else __hip_atomic_store(p, 2 * seq + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      uint64_t hs = 0, hx = 0;
-      for (int w = 0; w < kWaves; ++w) { hs += s_red[0][w]; hx ^= s_red[1][w]; }
-      ctl->sum_acc += hs;
-      ctl->xor_acc ^= hx;
+      ctl->sum_acc += b.hs;
+      ctl->xor_acc ^= b.hx;
       ctl->batches_acc += 1;
-      ctl->rows_acc += (uint64_t)rows;
-      ctl->busy_acc += t_end - ctl->d_t_start;
-      ctl->wait_acc += ctl->d_t_start - t_top;
+      ctl->rows_acc += (uint64_t)b.rows;
+      ctl->busy_acc += t_end - b.t_start;
+      ctl->wait_acc += b.t_start - b.t_top;
       st_relaxed_sys(&a.pub->id_sum[a.worker_index], ctl->sum_acc);
       st_relaxed_sys(&a.pub->id_xor[a.worker_index], ctl->xor_acc);
       st_relaxed_sys(&a.pub->rows[a.worker_index], ctl->rows_acc);
@@ -1446,6 +1529,7 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
   }
   if (wg0 && tid == 0) {
     ctl->next_seq = seq;
+    ctl->ingest_cursor = s.cursor;
     st_release_sys(&a.pub->status[a.worker_index], (int32_t)exit_status);
   }
 }
