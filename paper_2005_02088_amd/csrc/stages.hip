@@ -813,9 +813,49 @@ __device__ __forceinline__ void mlp_row_layer(const BatchRows& br, const uint16_
   }
 }
 
-// All layers of a batch. Per layer the unit shape is the largest of (8 row blocks x
-// 4 strips; hidden layers only), (8 x 2), (4 x 2), (4 x 1) that still gives every
+// The batch's FP32 input rows rounded to BF16 (nearest even, as the FP32 unit path
+// rounds them) into the hidden-state buffer in fragment order, zeros past K; rows
+// past the batch are not written. Threads take consecutive 8-element groups of a
+// row, so the reads are contiguous.
+__device__ __forceinline__ void mlp_input_to_frag(const BatchRows& br, uint16_t* h, int K, int rows) {
+  const int nck = (K + 31) >> 5, ngr = nck * 4;             // 8-element groups per padded row
+  const int total = rows * ngr;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
+    const int row = i / ngr, g = i - row * ngr, k0 = g * 8;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (k0 < K) {
+      const float* x = (const float*)br.row(row) + k0;
+      v = f32x8_to_bf16x8_bits(u4_as_f4(gld16(x)), u4_as_f4(gld16(x + 4)));
+    }
+    const int c = g >> 2, lane = (row & 15) + 16 * (g & 3);
+    *(uint4*)(h + ((int64_t)((row >> 4) * nck + c) * 64 + lane) * 8) = v;
+  }
+}
+
+// One layer on the BF16 (fragment-order) input: the unit shape is the largest of
+// (8 row blocks x 4 strips), (8 x 2), (4 x 2), (4 x 1) that still gives every
 // workgroup a unit (larger units read the activations and weights fewer times).
+__device__ __forceinline__ void mlp_bf16_layer(const BatchRows& rp, const uint16_t* hin, int stride, const uint16_t* W,
+                                               int K, int N, int rows, bool last, uint16_t* hout, float* o,
+                                               uint8_t* lds, int w, int lane, int tid) {
+  const int nrt = (rows + 15) >> 4, P = gridDim.x;
+  const bool even = (N % 32) == 0;
+  const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
+  if (N % 64 == 0 && nrt > 4 && ((nrt + 7) / 8) * (N / 64) >= P)
+    mlp_row_layer<2, 4, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+  else if (even && nrt > 4 && u22 >= P)
+    mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+  else if (even && u12 >= P)
+    mlp_row_layer<1, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+  else
+    mlp_row_layer<1, 1, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+}
+
+// All layers of a batch. The first layer reads the FP32 input rows: the units read
+// and round them themselves (unit shapes (8 x 2), (4 x 2), (4 x 1)), or, for batches
+// of more than 32 rows whose units would take two or more rounds of the grid, the
+// rows are first rounded into fragment order once for the whole grid (one more
+// grid barrier) and the layer runs like the others. Both give the same bits.
 __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& rp, int rows, uint8_t* out,
                                              uint8_t* lds, int w, int lane, int tid) {
   const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
@@ -824,28 +864,30 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
     if (l > 0 && !grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
     const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
     uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
-    const uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
+    uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
     const uint16_t* W = (const uint16_t*)a.sp.w[l];
     const bool last = (l == L - 1);
-    const bool even = (N % 32) == 0;
-    const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
     float* o = (float*)out;
     if (l == 0) {
-      if (even && nrt > 4 && u22 >= P)
-        mlp_row_layer<2, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
-      else if (even && u12 >= P)
-        mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
-      else
-        mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
-    } else if (N % 64 == 0 && nrt > 4 && ((nrt + 7) / 8) * (N / 64) >= P) {
-      mlp_row_layer<2, 4, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
-    } else if (even && nrt > 4 && u22 >= P) {
-      mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
-    } else if (even && u12 >= P) {
-      mlp_row_layer<1, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
-    } else {
-      mlp_row_layer<1, 1, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+      // units of the FP32 path: rounding the rows once pays when they would be read
+      // by two or more rounds of units
+      const bool even = (N % 32) == 0;
+      const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
+      const int shape = (even && nrt > 4 && u22 >= P) ? 2 : (even && u12 >= P) ? 1 : 0;
+      const int units = shape == 2 ? u22 : shape == 1 ? u12 : ((nrt + 3) / 4) * (N / 16);
+      if (nrt <= 2 || units < 2 * P) {
+        if (shape == 2)
+          mlp_row_layer<2, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+        else if (shape == 1)
+          mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+        else
+          mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+        continue;
+      }
+      mlp_input_to_frag(rp, hin, K, rows);
+      if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
     }
+    mlp_bf16_layer(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
   }
   return true;
 }
@@ -1364,9 +1406,17 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
 
   __shared__ BatchLds s;
   __shared__ uint64_t s_t0;
+  // running counters of this worker (workgroup 0, thread 0), published per batch
+  __shared__ uint64_t acc_sum, acc_xor, acc_batches, acc_rows, acc_busy, acc_wait;
   if (wg0 && tid == 0) {
     s_t0 = now_ticks();
     s.cursor = ctl->ingest_cursor;
+    acc_sum = ctl->sum_acc;
+    acc_xor = ctl->xor_acc;
+    acc_batches = ctl->batches_acc;
+    acc_rows = ctl->rows_acc;
+    acc_busy = ctl->busy_acc;
+    acc_wait = ctl->wait_acc;
     if (si == 0) st_relaxed_sys(&a.pub->t0, s_t0);
     st_relaxed_sys(&a.pub->started[a.worker_index], 1);
   }
@@ -1379,6 +1429,8 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
   __shared__ struct {
     uint64_t hs, hx, t_start, t_top, ingest_end, egress_end;
     int rows;
+    uint32_t stop;               // the broadcast descriptor, as workgroup 0 reads it
+    uint8_t* out;
   } b;
   for (;;) {
     // ---------------- control: form the batch, write its descriptor, broadcast (workgroup 0)
@@ -1401,8 +1453,9 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
             const uint8_t* rp = si > 0 ? in_payload + (int64_t)row * a.sp.in_row_bytes
                                        : s.ptr[q] + (int64_t)j * a.in_row_stride;
             if (si == 0) ctl->d_rowptr[row] = rp;
-            ctl->d_rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
-                                         : rp + a.sp.in_row_bytes;
+            if (a.side_bytes > 0 || KIND == CAMELOT_STAGE_GATHER_SCORE)
+              ctl->d_rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
+                                           : rp + a.sp.in_row_bytes;
             if (a.out_kind == kOutEgress) {
               ctl->d_row_id[row] = s.id[q];
               ctl->d_row_idx[row] = j;
@@ -1425,10 +1478,12 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
             oh->n_rows = (uint32_t)rows;
             ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
             ctl->d_out_hdr = oh;
+            b.out = (uint8_t*)oh + kSlotHeaderBytes;
           }
         } else if (tid == 0) {
           ctl->d_egress_base = s.egress_base;
           ctl->d_out = nullptr;
+          b.out = nullptr;
         }
         if (tid == 0) {
           ctl->d_rows = (uint32_t)rows;
@@ -1443,16 +1498,20 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
           b.egress_end = s.egress_base + (uint64_t)rows;
         }
       }
-      if (tid == 0) ctl->d_stop = (uint32_t)st;
+      if (tid == 0) {
+        ctl->d_stop = (uint32_t)st;
+        b.stop = (uint32_t)st;
+      }
       // broadcast: the batch descriptor (or the stop) is in place
       wg_barrier_stores_done();
       if (tid == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         for (int g = 0; g < 8; ++g)
           __hip_atomic_store(&ctl->go[g][0], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
+      // the descriptor's writers are this workgroup's own threads
       __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     } else if (!wait_go(ctl, (uint32_t)(seq + 1), 2 * a.idle_ticks + a.spin_ticks)) {
       // workgroup 0 may wait for input (up to the idle limit) and then for output space
       exit_status = kStatusTimeout;
@@ -1460,11 +1519,12 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
     }
     // a host-staged input slot was written by a DMA copy: acquire at system scope
     if (a.in_state_sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-    const uint32_t stop = ctl->d_stop;
+    // the descriptor (workgroup 0 has its own copy in LDS), the same for every lane:
+    // kept in scalar registers
+    const uint32_t stop = __builtin_amdgcn_readfirstlane(wg0 ? b.stop : ctl->d_stop);
     if (stop) { exit_status = (int)stop; break; }
-    // the descriptor is the same for every lane: keep it in scalar registers
-    const int rows = __builtin_amdgcn_readfirstlane((int)ctl->d_rows);
-    const uint64_t outp = (uint64_t)ctl->d_out;
+    const int rows = __builtin_amdgcn_readfirstlane(wg0 ? b.rows : (int)ctl->d_rows);
+    const uint64_t outp = wg0 ? (uint64_t)b.out : (uint64_t)ctl->d_out;
     uint8_t* const out = (uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(outp >> 32)) << 32) |
                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)outp));
     if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, seq), rows, out)) { exit_status = kStatusTimeout; break; }
@@ -1512,24 +1572,33 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
         if (a.in_state_sys) st_relaxed_sys(p, 2 * seq + 2);
         else __hip_atomic_store(p, 2 * seq + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      ctl->sum_acc += b.hs;
-      ctl->xor_acc ^= b.hx;
-      ctl->batches_acc += 1;
-      ctl->rows_acc += (uint64_t)b.rows;
-      ctl->busy_acc += t_end - b.t_start;
-      ctl->wait_acc += b.t_start - b.t_top;
-      st_relaxed_sys(&a.pub->id_sum[a.worker_index], ctl->sum_acc);
-      st_relaxed_sys(&a.pub->id_xor[a.worker_index], ctl->xor_acc);
-      st_relaxed_sys(&a.pub->rows[a.worker_index], ctl->rows_acc);
-      st_relaxed_sys(&a.pub->busy_ticks[a.worker_index], ctl->busy_acc);
-      st_relaxed_sys(&a.pub->wait_ticks[a.worker_index], ctl->wait_acc);
-      st_relaxed_sys(&a.pub->batches[a.worker_index], ctl->batches_acc);
+      const uint64_t sum = acc_sum + b.hs, xr = acc_xor ^ b.hx, nb = acc_batches + 1;
+      const uint64_t nr = acc_rows + (uint64_t)b.rows, busy = acc_busy + (t_end - b.t_start);
+      const uint64_t wait = acc_wait + (b.t_start - b.t_top);
+      acc_sum = sum;
+      acc_xor = xr;
+      acc_batches = nb;
+      acc_rows = nr;
+      acc_busy = busy;
+      acc_wait = wait;
+      st_relaxed_sys(&a.pub->id_sum[a.worker_index], sum);
+      st_relaxed_sys(&a.pub->id_xor[a.worker_index], xr);
+      st_relaxed_sys(&a.pub->rows[a.worker_index], nr);
+      st_relaxed_sys(&a.pub->busy_ticks[a.worker_index], busy);
+      st_relaxed_sys(&a.pub->wait_ticks[a.worker_index], wait);
+      st_relaxed_sys(&a.pub->batches[a.worker_index], nb);
     }
     seq += (uint64_t)a.n_inst;          // instance j of n takes batches j, j + n, ...
   }
   if (wg0 && tid == 0) {
     ctl->next_seq = seq;
     ctl->ingest_cursor = s.cursor;
+    ctl->sum_acc = acc_sum;
+    ctl->xor_acc = acc_xor;
+    ctl->batches_acc = acc_batches;
+    ctl->rows_acc = acc_rows;
+    ctl->busy_acc = acc_busy;
+    ctl->wait_acc = acc_wait;
     st_release_sys(&a.pub->status[a.worker_index], (int32_t)exit_status);
   }
 }
