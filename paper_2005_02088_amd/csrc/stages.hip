@@ -1181,30 +1181,37 @@ __device__ __forceinline__ Acq acquire_ingest(const WorkerArgs& a, uint64_t c, u
   }
 }
 
-// Stages > 0: wait for the doorbell of input slot seq (try_only: one poll).
-__device__ __forceinline__ Acq acquire_ring(const WorkerArgs& a, uint64_t seq, bool try_only) {
-  const uint64_t slot = seq % (uint64_t)a.in_depth;
-  const uint64_t want = 2 * seq + 1;
+// Stages > 0: wait until input slot seq is full and, for a ring output, output slot
+// seq is free: both doorbells in each poll, one acquire once both are seen
+// (try_only: one poll). Returns 0 or the status to exit with.
+__device__ __forceinline__ int acquire_ring_slots(const WorkerArgs& a, uint64_t seq, bool try_only) {
+  const bool in_sys = a.in_state_sys != 0, out_sys = a.out_state_sys != 0;
+  const bool ring_out = a.out_kind == kOutRing;
+  const uint64_t* in_p = &a.in_state[seq % (uint64_t)a.in_depth];
+  const uint64_t want_in = 2 * seq + 1;
+  const uint64_t* out_p = ring_out ? &a.out_state[seq % (uint64_t)a.out_depth] : nullptr;
+  const uint64_t want_out = !ring_out || seq < (uint64_t)a.out_depth ? 0 : 2 * (seq - a.out_depth) + 2;
   const uint64_t t_wait0 = now_ticks();
   uint32_t polls = 0;
-  const bool st_sys = a.in_state_sys != 0;
   for (;;) {
-    if (ring_load(&a.in_state[slot], st_sys) == want) {
-      ring_acquire(st_sys);
-      const SlotHeader* h = (const SlotHeader*)(a.in_ring + slot * (uint64_t)a.in_stride);
-      return Acq{0, (int)h->n_req, (int)h->n_rows};
+    const uint64_t vi = ring_load(in_p, in_sys);
+    const uint64_t vo = ring_out ? ring_load(out_p, out_sys) : 0;
+    if (vi == want_in && vo == want_out) {
+      ring_acquire(in_sys || (ring_out && out_sys));
+      return 0;
     }
-    if (try_only) return Acq{kAcqNotReady, 0, 0};
-    if (host_stop(a, polls)) return Acq{kStatusStopped, 0, 0};
-    if ((int64_t)(now_ticks() - t_wait0) > a.idle_ticks) return Acq{kStatusIdleExit, 0, 0};
+    if (try_only) return kAcqNotReady;
+    if (host_stop(a, polls)) return kStatusStopped;
+    if ((int64_t)(now_ticks() - t_wait0) > a.idle_ticks) return kStatusIdleExit;
     __builtin_amdgcn_s_sleep(1);
   }
 }
 
 // Wait until the output can take batch seq of `rows` rows (try_only: one poll).
-// Egress space is counted from ctl->egress_head, the rows of every batch formed
-// so far (formation reserves them).
-__device__ __forceinline__ int acquire_output(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq, int rows, bool try_only) {
+// Egress space is counted from egress_head, the rows of every batch formed so far
+// (formation reserves them); tail_seen is the host's tail as last read.
+__device__ __forceinline__ int acquire_output(const WorkerArgs& a, uint64_t egress_head, uint64_t& tail_seen,
+                                              uint64_t seq, int rows, bool try_only) {
   const uint64_t t_wait0 = now_ticks();
   uint32_t polls = 0;
   for (;;) {
@@ -1217,10 +1224,10 @@ __device__ __forceinline__ int acquire_output(const WorkerArgs& a, WorkerCtl* ct
       // the tail last read is a lower bound of the host's (it only grows): a PCIe read
       // only when that bound leaves too little room; space already seen was acquired
       // when it was read
-      if (ctl->egress_head + (uint64_t)rows - ctl->egress_tail_seen <= (uint64_t)a.egress_cap) return 0;
+      if (egress_head + (uint64_t)rows - tail_seen <= (uint64_t)a.egress_cap) return 0;
       const uint64_t tail = __hip_atomic_load(&a.hctl->egress_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      ctl->egress_tail_seen = tail;
-      ok = ctl->egress_head + (uint64_t)rows - tail <= (uint64_t)a.egress_cap;
+      tail_seen = tail;
+      ok = egress_head + (uint64_t)rows - tail <= (uint64_t)a.egress_cap;
     }
     if (ok) {
       ring_acquire(a.out_kind != kOutRing || a.out_state_sys != 0);
@@ -1307,6 +1314,8 @@ struct BatchLds {
   uint64_t red[2][kWaves];              // per-wave id checksums (sum, xor)
   uint64_t cursor;                      // stage 0: next ingest record not in a batch
   uint64_t egress_base;                 // terminal stage: first egress row of the batch
+  uint64_t egress_head;                 // terminal stage: egress rows of the batches formed
+  uint64_t egress_tail_seen;            // terminal stage: the host's egress tail as last read
   int acq[3];                           // status, requests, rows
 };
 
@@ -1321,34 +1330,44 @@ __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, u
                           BatchLds& s) {
   const int tid = threadIdx.x;
   const int si = a.stage_index;
-  if (tid < 64) {
-    Acq q;
-    if (si == 0) {
-      q = acquire_ingest(a, s.cursor, t0, try_only, s.id, s.tarr, s.rows, s.ptr);
-    } else {
-      q = (tid == 0) ? acquire_ring(a, seq, try_only) : Acq{0, 0, 0};
-      q.status = __shfl(q.status, 0, 64);
-      q.nreq = __shfl(q.nreq, 0, 64);
-      q.rows = __shfl(q.rows, 0, 64);
+  int nreq;
+  if (si == 0) {
+    if (tid < 64) {
+      Acq q = acquire_ingest(a, s.cursor, t0, try_only, s.id, s.tarr, s.rows, s.ptr);
+      if (q.status == 0 && tid == 0)
+        q.status = acquire_output(a, s.egress_head, s.egress_tail_seen, seq, q.rows, try_only);
+      if (tid == 0) { s.acq[0] = q.status; s.acq[1] = q.nreq; s.acq[2] = q.rows; }
     }
-    if (q.status == 0 && tid == 0) q.status = acquire_output(a, ctl, seq, q.rows, try_only);
-    if (tid == 0) { s.acq[0] = q.status; s.acq[1] = q.nreq; s.acq[2] = q.rows; }
-  }
-  __syncthreads();
-  const int st = s.acq[0], nreq = s.acq[1];
-  if (st != 0) return st;
-  if (si > 0) {
+    if (tid < 2 * kMaxStages) s.t_stage[tid] = 0;
+    __syncthreads();
+    if (s.acq[0] != 0) return s.acq[0];
+    nreq = s.acq[1];
+  } else {
+    if (tid == 0) s.acq[0] = acquire_ring_slots(a, seq, try_only);
+    __syncthreads();
+    if (s.acq[0] != 0) return s.acq[0];
+    // the whole header in one round of loads: the counts, the stage times and every
+    // request entry (those past n_req are not used)
     const SlotHeader* ih = (const SlotHeader*)(a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride);
-    for (int q = tid; q < nreq; q += kThreads) {
+    const int hreq = (int)ih->n_req, hrows = (int)ih->n_rows;
+    for (int q = tid; q < kMaxBatch; q += kThreads) {
       s.id[q] = ih->req_id[q];
       s.tarr[q] = ih->req_tarr[q];
       s.rows[q] = ih->req_rows[q];
     }
     if (tid < 2 * kMaxStages) s.t_stage[tid] = ih->t_stage[tid];
-  } else if (tid < 2 * kMaxStages) {
-    s.t_stage[tid] = 0;
+    __syncthreads();       // every thread has read s.acq[0]
+    if (tid == 0) {
+      // a terminal stage's egress space needs the row count (usually no round trip)
+      s.acq[0] = a.out_kind == kOutEgress
+                     ? acquire_output(a, s.egress_head, s.egress_tail_seen, seq, hrows, try_only) : 0;
+      s.acq[1] = hreq;
+      s.acq[2] = hrows;
+    }
+    __syncthreads();
+    if (s.acq[0] != 0) return s.acq[0];
+    nreq = hreq;
   }
-  __syncthreads();
   if (tid < 64) {
     // first row of each request: exclusive prefix sum of the row counts, 64 at a time
     uint32_t carry = 0;
@@ -1368,8 +1387,8 @@ __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, u
       s.rbase[nreq] = carry;
       if (si == 0) s.cursor += (uint64_t)nreq;
       if (a.out_kind == kOutEgress) {
-        s.egress_base = ctl->egress_head;
-        ctl->egress_head += (uint64_t)s.acq[2];
+        s.egress_base = s.egress_head;
+        s.egress_head += (uint64_t)s.acq[2];
       }
     }
   }
@@ -1406,17 +1425,34 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
 
   __shared__ BatchLds s;
   __shared__ uint64_t s_t0;
-  // running counters of this worker (workgroup 0, thread 0), published per batch
+  // running counters of this worker (workgroup 0, thread 0). A terminal stage
+  // publishes them with each batch, before its results; the others every 16th batch
+  // after the broadcast (their stores to host memory would hold up the next loads of
+  // the thread that issued them), before workgroup 0 waits for a batch, and at exit
+  // (acc_dirty: not published yet)
   __shared__ uint64_t acc_sum, acc_xor, acc_batches, acc_rows, acc_busy, acc_wait;
+  __shared__ int acc_dirty;
+  auto publish_counters = [&]() {
+    st_relaxed_sys(&a.pub->id_sum[a.worker_index], acc_sum);
+    st_relaxed_sys(&a.pub->id_xor[a.worker_index], acc_xor);
+    st_relaxed_sys(&a.pub->rows[a.worker_index], acc_rows);
+    st_relaxed_sys(&a.pub->busy_ticks[a.worker_index], acc_busy);
+    st_relaxed_sys(&a.pub->wait_ticks[a.worker_index], acc_wait);
+    st_relaxed_sys(&a.pub->batches[a.worker_index], acc_batches);
+    acc_dirty = 0;
+  };
   if (wg0 && tid == 0) {
     s_t0 = now_ticks();
     s.cursor = ctl->ingest_cursor;
+    s.egress_head = ctl->egress_head;
+    s.egress_tail_seen = ctl->egress_tail_seen;
     acc_sum = ctl->sum_acc;
     acc_xor = ctl->xor_acc;
     acc_batches = ctl->batches_acc;
     acc_rows = ctl->rows_acc;
     acc_busy = ctl->busy_acc;
     acc_wait = ctl->wait_acc;
+    acc_dirty = 0;
     if (si == 0) st_relaxed_sys(&a.pub->t0, s_t0);
     st_relaxed_sys(&a.pub->started[a.worker_index], 1);
   }
@@ -1436,7 +1472,12 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
     // ---------------- control: form the batch, write its descriptor, broadcast (workgroup 0)
     if (wg0) {
       const uint64_t t_top = now_ticks();
-      const int st = pending ? 0 : form_batch(a, ctl, seq, s_t0, false, s);
+      // one poll first; before waiting for the batch the counters reach the host
+      int st = pending ? 0 : kAcqNotReady;
+      for (int attempt = 0; st == kAcqNotReady; ++attempt) {
+        if (attempt == 1 && tid == 0 && acc_dirty) publish_counters();
+        st = form_batch(a, ctl, seq, s_t0, attempt == 0, s);
+      }
       pending = false;
       if (st == 0) {
         const int nreq = s.acq[1], rows = s.acq[2];
@@ -1508,6 +1549,7 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         for (int g = 0; g < 8; ++g)
           __hip_atomic_store(&ctl->go[g][0], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (acc_dirty && (acc_batches & 15) == 0) publish_counters();
       }
       // the descriptor's writers are this workgroup's own threads
       __syncthreads();
@@ -1556,6 +1598,17 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
         // host-staged boundary: the relay reads the row count next to the state word
         if (a.out_state_sys) st_relaxed_sys(&a.out_state[a.out_depth + seq % (uint64_t)a.out_depth], (uint64_t)b.rows);
       }
+      const uint64_t sum = acc_sum + b.hs, xr = acc_xor ^ b.hx, nb = acc_batches + 1;
+      const uint64_t nr = acc_rows + (uint64_t)b.rows, busy = acc_busy + (t_end - b.t_start);
+      const uint64_t wait = acc_wait + (b.t_start - b.t_top);
+      acc_sum = sum;
+      acc_xor = xr;
+      acc_batches = nb;
+      acc_rows = nr;
+      acc_busy = busy;
+      acc_wait = wait;
+      acc_dirty = 1;
+      if (a.out_kind == kOutEgress) publish_counters();     // ordered before the results by the fence
       if (sys) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
       else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (a.out_kind == kOutRing) {
@@ -1572,33 +1625,21 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
         if (a.in_state_sys) st_relaxed_sys(p, 2 * seq + 2);
         else __hip_atomic_store(p, 2 * seq + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      const uint64_t sum = acc_sum + b.hs, xr = acc_xor ^ b.hx, nb = acc_batches + 1;
-      const uint64_t nr = acc_rows + (uint64_t)b.rows, busy = acc_busy + (t_end - b.t_start);
-      const uint64_t wait = acc_wait + (b.t_start - b.t_top);
-      acc_sum = sum;
-      acc_xor = xr;
-      acc_batches = nb;
-      acc_rows = nr;
-      acc_busy = busy;
-      acc_wait = wait;
-      st_relaxed_sys(&a.pub->id_sum[a.worker_index], sum);
-      st_relaxed_sys(&a.pub->id_xor[a.worker_index], xr);
-      st_relaxed_sys(&a.pub->rows[a.worker_index], nr);
-      st_relaxed_sys(&a.pub->busy_ticks[a.worker_index], busy);
-      st_relaxed_sys(&a.pub->wait_ticks[a.worker_index], wait);
-      st_relaxed_sys(&a.pub->batches[a.worker_index], nb);
     }
     seq += (uint64_t)a.n_inst;          // instance j of n takes batches j, j + n, ...
   }
   if (wg0 && tid == 0) {
     ctl->next_seq = seq;
     ctl->ingest_cursor = s.cursor;
+    ctl->egress_head = s.egress_head;
+    ctl->egress_tail_seen = s.egress_tail_seen;
     ctl->sum_acc = acc_sum;
     ctl->xor_acc = acc_xor;
     ctl->batches_acc = acc_batches;
     ctl->rows_acc = acc_rows;
     ctl->busy_acc = acc_busy;
     ctl->wait_acc = acc_wait;
+    publish_counters();
     st_release_sys(&a.pub->status[a.worker_index], (int32_t)exit_status);
   }
 }
