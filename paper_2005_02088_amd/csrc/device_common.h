@@ -34,7 +34,7 @@ enum WorkerStatus : int32_t {
 };
 
 // Header at the start of every ring slot (device memory). Written by the producer
-// stage's workgroup 0 before the slot's doorbell is rung.
+// stage's control workgroup before the slot's doorbell is rung.
 struct SlotHeader {
   uint64_t seq;
   uint32_t n_req;
@@ -102,7 +102,7 @@ struct WorkerCtl {
   uint32_t abort;      uint32_t pad2[31];
   uint32_t diag_arrived, diag_nwg, diag_group;   // filled on a barrier timeout
   uint32_t diag_pad;
-  // batch descriptor broadcast by workgroup 0 through the grid barrier
+  // batch descriptor written by the control workgroup before its broadcast
   uint64_t d_seq;
   uint32_t d_stop;
   uint32_t d_rows;
@@ -129,9 +129,12 @@ struct WorkerCtl {
   uint32_t bench_stop[2];         // bench mode: workgroup 0's decision to stop, by rep parity
   uint64_t sum_acc, xor_acc, batches_acc;
   uint64_t rows_acc, busy_acc, wait_acc;
-  // workgroup 0's batch broadcast (seq + 1), one 128-byte line per barrier group so
+  // the control workgroup's batch broadcast (seq + 1), one 128-byte line per group so
   // that the idle workgroups' polls spread over 8 lines instead of one
   alignas(128) uint32_t go[8][32];
+  // per group of compute workgroups (index mod 8): batches finished, summed over the
+  // group's workgroups (cumulative; the control workgroup waits on these)
+  alignas(128) uint32_t done[8][32];
 };
 
 // Stage parameters (device pointers borrowed from the caller or owned by the
@@ -159,6 +162,7 @@ struct WorkerArgs {
   int32_t n_stages;
   int32_t worker_index;           // slot of this stage instance in the published counters
   int32_t n_inst;                 // instances of this stage: this one takes every n_inst-th batch
+  int32_t ctl_wg;                 // 1: one more workgroup, the last, only controls (persistent worker)
   int32_t max_batch;
   int32_t side_bytes;             // per-row bytes carried through the stages
   int32_t in_row_stride;          // stage 0: bytes between payload rows (row + side)
@@ -283,11 +287,13 @@ struct BarTicket {
   bool wait;       // false for the workgroup that released the barrier
 };
 
-__device__ __forceinline__ BarTicket grid_arrive(WorkerCtl* ctl, uint32_t nwg, bool sys_release = false) {
+// wgi: this workgroup's index among the nwg that take part (default: blockIdx.x).
+__device__ __forceinline__ BarTicket grid_arrive(WorkerCtl* ctl, uint32_t nwg, bool sys_release = false,
+                                                 int wgi = -1) {
   BarTicket t{0u, false};
   wg_barrier_stores_done();
   if (threadIdx.x == 0) {
-    const uint32_t g = blockIdx.x & 7u;
+    const uint32_t g = (wgi < 0 ? blockIdx.x : (uint32_t)wgi) & 7u;
     const uint32_t ngroups = nwg < 8u ? nwg : 8u;
     const uint32_t members = (nwg - g + 7u) >> 3;
     uint32_t* genp = &ctl->bar_gen[g][0];
@@ -313,11 +319,12 @@ __device__ __forceinline__ BarTicket grid_arrive(WorkerCtl* ctl, uint32_t nwg, b
   return t;
 }
 
-__device__ __forceinline__ bool grid_wait(WorkerCtl* ctl, uint32_t nwg, BarTicket t, int64_t spin_ticks) {
+__device__ __forceinline__ bool grid_wait(WorkerCtl* ctl, uint32_t nwg, BarTicket t, int64_t spin_ticks,
+                                          int wgi = -1) {
   __shared__ int s_ok;
   if (threadIdx.x == 0) {
     int ok = 1;
-    const uint32_t g = blockIdx.x & 7u;
+    const uint32_t g = (wgi < 0 ? blockIdx.x : (uint32_t)wgi) & 7u;
     uint32_t* genp = &ctl->bar_gen[g][0];
     if (t.wait) {
       const uint64_t t0 = now_ticks();
@@ -349,8 +356,8 @@ __device__ __forceinline__ bool grid_wait(WorkerCtl* ctl, uint32_t nwg, BarTicke
 }
 
 __device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64_t spin_ticks,
-                                             bool sys_release = false) {
-  return grid_wait(ctl, nwg, grid_arrive(ctl, nwg, sys_release), spin_ticks);
+                                             bool sys_release = false, int wgi = -1) {
+  return grid_wait(ctl, nwg, grid_arrive(ctl, nwg, sys_release, wgi), spin_ticks, wgi);
 }
 
 // Intra-wave LDS hand-off: orders this wave's LDS writes before its later reads

@@ -397,7 +397,9 @@ int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
     return fail(CAMELOT_EDEVICE, "stage kind %d: %d registers and %zu LDS bytes per workgroup leave fewer than %d "
                 "workgroups per CU", kind, fa.numRegs, (size_t)fa.sharedSizeBytes, kMinWgPerCuResident);
   void* args[] = {(void*)&a};
-  HIP_TRY(hipLaunchKernel(fn, dim3(kWgPerCu * n_cus), dim3(kThreads), args, 0, s));
+  // a persistent worker adds its control workgroup last: it shares a CU with one of
+  // the compute workgroups, which are placed first, one per CU
+  HIP_TRY(hipLaunchKernel(fn, dim3(kWgPerCu * n_cus + a.ctl_wg), dim3(kThreads), args, 0, s));
   return CAMELOT_OK;
 }
 
@@ -853,6 +855,7 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     a.n_stages = S;
     a.worker_index = w;
     a.n_inst = p->n_inst[i];
+    a.ctl_wg = 1;             // a worker's last workgroup forms, broadcasts and publishes batches
     a.max_batch = cfg->max_batch;
     a.side_bytes = cfg->side_bytes;
     a.in_row_stride = (int32_t)(p->in_b[i] + cfg->side_bytes);

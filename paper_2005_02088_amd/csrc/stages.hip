@@ -70,7 +70,7 @@ __device__ __forceinline__ void emit_row(const WorkerArgs& a, WorkerCtl* ctl, in
 // Where the rows of the current batch are: contiguous in the input ring slot (stages
 // after the first) or in the one-shot kernel's input, at a computed address; or, for
 // the first stage, wherever each request's payload put them (the per-row table
-// workgroup 0 fills). Kernels read rows through this, so after the batch broadcast
+// the control workgroup fills). Kernels read rows through this, so after the batch broadcast
 // no workgroup waits on a table load before its first row load.
 struct BatchRows {
   const uint8_t* base;          // row r at base + r * stride, or
@@ -89,6 +89,11 @@ __device__ __forceinline__ BatchRows batch_rows(const WorkerArgs& a, const Worke
   return BatchRows{nullptr, 0, ctl->d_rowptr};
 }
 
+// Workgroups that run the stage: all of them in a one-shot launch; a persistent
+// worker has one more, the last, which only controls.
+__device__ __forceinline__ int xwg(const WorkerArgs&) { return (int)blockIdx.x; }
+__device__ __forceinline__ int xnwg(const WorkerArgs& a) { return (int)gridDim.x - a.ctl_wg; }
+
 // ------------------------------------------------------------------ GEMM + ReLU (FP32)
 // Unit = (64 output columns, 8 rows) per workgroup; the 4 waves split K in
 // interleaved 64-wide chunks and their partial sums are added in a fixed order,
@@ -103,7 +108,7 @@ __device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
   float* Y = (float*)out;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int n_cb = (N + 63) / 64, n_rb = (rows + 7) / 8;
-  for (int u = blockIdx.x; u < n_cb * n_rb; u += gridDim.x) {
+  for (int u = xwg(a); u < n_cb * n_rb; u += xnwg(a)) {
     const int cb = u % n_cb, rb = u / n_cb;
     for (int i = tid; i < 8 * K; i += kThreads) {
       const int r = i / K, kk = i - r * K, row = rb * 8 + r;
@@ -149,7 +154,7 @@ __device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, const Batc
   const int K = a.sp.dims[0], N = a.sp.dims[1];
   const float* W = (const float*)a.sp.w[0];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+  for (int r = xwg(a) * kWaves + w; r < rows; r += xnwg(a) * kWaves) {
     const float* x = (const float*)br.row(r);
     float acc[kArgmaxMaxN];
 #pragma unroll
@@ -260,7 +265,7 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& 
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int ncol = (N + 255) >> 8;             // columns of 256 elements (the last may be partial)
   const bool filter = k <= 64 && min(N, 64) >= k;
-  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+  for (int r = xwg(a) * kWaves + w; r < rows; r += xnwg(a) * kWaves) {
     // the row pointer is the wave's (scalar registers: the buffer resource below is
     // then scalar too)
     const uint64_t sp = (uint64_t)br.row(r);
@@ -374,7 +379,7 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows
   const float* melw = tab + kTabMelW;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   float* Y = (float*)out;
-  const int units = rows * 11, stride = gridDim.x * kWaves;
+  const int units = rows * 11, stride = xnwg(a) * kWaves;
   // the samples of a (row, frame) unit: 200 float2 per frame, lane + 64 q (global
   // loads, no branches: the last piece is clamped)
   typedef float f32x2_t __attribute__((ext_vector_type(2)));
@@ -389,7 +394,7 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows
   };
   // pairs (u, u + stride); a pair without a second unit runs its first twice and
   // stores once
-  int u = blockIdx.x * kWaves + w;
+  int u = xwg(a) * kWaves + w;
   if (u < units) {
     load_unit(0, u);
     load_unit(1, u + stride < units ? u + stride : u);
@@ -803,10 +808,10 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
 template <int RW, int CT, bool F32>
 __device__ __forceinline__ void mlp_row_layer(const BatchRows& br, const uint16_t* hin, int stride,
                                               const uint16_t* W, int K, int N, int rows, bool last, uint16_t* hout,
-                                              float* out, uint8_t* lds, int w, int lane, int tid) {
+                                              float* out, uint8_t* lds, int w, int lane, int tid, int wgi, int nwg) {
   const int rpu = 4 * RW;                               // row blocks per unit
   const int nrg = (((rows + 15) >> 4) + rpu - 1) / rpu, ncb = N / (16 * CT);
-  for (int u = blockIdx.x; u < nrg * ncb; u += gridDim.x) {
+  for (int u = wgi; u < nrg * ncb; u += nwg) {
     const int cb = u % ncb, row0 = (u / ncb) * rpu * 16;
     mlp_row_unit<RW, CT, F32>(br, hin, stride, W, K, N, rows, row0, cb * 16 * CT, last, hout, out, lds, w,
                               lane, tid);
@@ -817,10 +822,10 @@ __device__ __forceinline__ void mlp_row_layer(const BatchRows& br, const uint16_
 // rounds them) into the hidden-state buffer in fragment order, zeros past K; rows
 // past the batch are not written. Threads take consecutive 8-element groups of a
 // row, so the reads are contiguous.
-__device__ __forceinline__ void mlp_input_to_frag(const BatchRows& br, uint16_t* h, int K, int rows) {
+__device__ __forceinline__ void mlp_input_to_frag(const BatchRows& br, uint16_t* h, int K, int rows, int wgi, int nwg) {
   const int nck = (K + 31) >> 5, ngr = nck * 4;             // 8-element groups per padded row
   const int total = rows * ngr;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
+  for (int i = wgi * kThreads + threadIdx.x; i < total; i += nwg * kThreads) {
     const int row = i / ngr, g = i - row * ngr, k0 = g * 8;
     uint4 v = {0u, 0u, 0u, 0u};
     if (k0 < K) {
@@ -837,18 +842,18 @@ __device__ __forceinline__ void mlp_input_to_frag(const BatchRows& br, uint16_t*
 // workgroup a unit (larger units read the activations and weights fewer times).
 __device__ __forceinline__ void mlp_bf16_layer(const BatchRows& rp, const uint16_t* hin, int stride, const uint16_t* W,
                                                int K, int N, int rows, bool last, uint16_t* hout, float* o,
-                                               uint8_t* lds, int w, int lane, int tid) {
-  const int nrt = (rows + 15) >> 4, P = gridDim.x;
+                                               uint8_t* lds, int w, int lane, int tid, int wgi, int nwg) {
+  const int nrt = (rows + 15) >> 4, P = nwg;
   const bool even = (N % 32) == 0;
   const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
   if (N % 64 == 0 && nrt > 4 && ((nrt + 7) / 8) * (N / 64) >= P)
-    mlp_row_layer<2, 4, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    mlp_row_layer<2, 4, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
   else if (even && nrt > 4 && u22 >= P)
-    mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
   else if (even && u12 >= P)
-    mlp_row_layer<1, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    mlp_row_layer<1, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
   else
-    mlp_row_layer<1, 1, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    mlp_row_layer<1, 1, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
 }
 
 // All layers of a batch. The first layer reads the FP32 input rows: the units read
@@ -859,9 +864,10 @@ __device__ __forceinline__ void mlp_bf16_layer(const BatchRows& rp, const uint16
 __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& rp, int rows, uint8_t* out,
                                              uint8_t* lds, int w, int lane, int tid) {
   const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
-  const int nrt = (rows + 15) >> 4, P = gridDim.x;
+  const int wgi = xwg(a), nwg = xnwg(a);
+  const int nrt = (rows + 15) >> 4, P = nwg;
   for (int l = 0; l < L; ++l) {
-    if (l > 0 && !grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
+    if (l > 0 && !grid_barrier(ctl, nwg, a.spin_ticks, false, wgi)) return false;
     const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
     uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
     uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
@@ -877,17 +883,17 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
       const int units = shape == 2 ? u22 : shape == 1 ? u12 : ((nrt + 3) / 4) * (N / 16);
       if (nrt <= 2 || units < 2 * P) {
         if (shape == 2)
-          mlp_row_layer<2, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+          mlp_row_layer<2, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
         else if (shape == 1)
-          mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+          mlp_row_layer<1, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
         else
-          mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+          mlp_row_layer<1, 1, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
         continue;
       }
-      mlp_input_to_frag(rp, hin, K, rows);
-      if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
+      mlp_input_to_frag(rp, hin, K, rows, wgi, nwg);
+      if (!grid_barrier(ctl, nwg, a.spin_ticks, false, wgi)) return false;
     }
-    mlp_bf16_layer(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid);
+    mlp_bf16_layer(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
   }
   return true;
 }
@@ -913,7 +919,7 @@ __device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int per = dim >> 6;                  // columns per lane (dim is a multiple of 64)
   float* Y = (float*)out;
-  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+  for (int r = xwg(a) * kWaves + w; r < rows; r += xnwg(a) * kWaves) {
     const int32_t* ids = (const int32_t*)br.row(r);
     float acc[kGatherMaxDim / 64];
 #pragma unroll
@@ -954,7 +960,7 @@ __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int cin0 = (lane >> 4) * 8;                          // this lane's 8 channels in a chunk
   const int units = rows * ntiles;
-  for (int u = blockIdx.x; u < units; u += gridDim.x) {
+  for (int u = xwg(a); u < units; u += xnwg(a)) {
     const int r = u / ntiles, tile = u - r * ntiles;
     const uint16_t* X = (const uint16_t*)br.row(r);
     const int p = tile * kConvTile + w * 16 + (lane & 15);   // A-operand pixel of this lane
@@ -1000,9 +1006,9 @@ __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
     }
     __syncthreads();
   }
-  if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return false;
+  if (!grid_barrier(ctl, xnwg(a), a.spin_ticks, false, xwg(a))) return false;
   const float inv = 1.f / (float)npix;
-  for (int i = blockIdx.x * kThreads + tid; i < rows * kConvCout; i += gridDim.x * kThreads) {
+  for (int i = xwg(a) * kThreads + tid; i < rows * kConvCout; i += xnwg(a) * kThreads) {
     const int r = i / kConvCout, c = i - r * kConvCout;
     const float* pp = a.sp.partial + (int64_t)r * ntiles * kConvCout + c;
     float t = 0.f;
@@ -1026,7 +1032,7 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const Bat
   const __half* T = (const __half*)a.sp.w[0];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* Y = (float*)out;
-  for (int r = blockIdx.x * kWaves + w; r < rows; r += gridDim.x * kWaves) {
+  for (int r = xwg(a) * kWaves + w; r < rows; r += xnwg(a) * kWaves) {
     const float* q = (const float*)br.row(r);
     const int32_t* ids = (const int32_t*)ctl->d_rowside[r];
     for (int i = lane; i < qdim; i += 64) q_s[w][i] = q[i];
@@ -1052,7 +1058,7 @@ __device__ __forceinline__ void copy_side(const WorkerArgs& a, WorkerCtl* ctl, i
   if (a.side_bytes <= 0 || a.out_kind != kOutRing) return;
   uint8_t* dst = (uint8_t*)ctl->d_out_hdr + a.out_side_off;
   const int words = a.side_bytes >> 2;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < rows * words; i += gridDim.x * kThreads) {
+  for (int i = xwg(a) * kThreads + threadIdx.x; i < rows * words; i += xnwg(a) * kThreads) {
     const int r = i / words, wd = i - r * words;
     ((uint32_t*)(dst + (int64_t)r * a.side_bytes))[wd] = ((const uint32_t*)ctl->d_rowside[r])[wd];
   }
@@ -1105,7 +1111,7 @@ __device__ __forceinline__ bool host_stop(const WorkerArgs& a, uint32_t& polls) 
 // Status of a one-poll acquisition that found the batch not ready (never published).
 constexpr int kAcqNotReady = -1;
 
-// Stage 0: form a batch from the ingest (wave 0 of workgroup 0), starting at
+// Stage 0: form a batch from the ingest (wave 0 of the control workgroup), starting at
 // ingest record c. Requests are taken whole, in order, while the rows fit in
 // max_batch; the batch starts when batch_target rows wait, when the next waiting
 // request does not fit, or when the oldest waited batch_timeout. Writes the chosen
@@ -1274,7 +1280,7 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_bench(Wor
 }
 
 // ------------------------------------------------------------------ worker kernel
-// Workgroups other than 0 wait here for workgroup 0's broadcast of batch `want`
+// Compute workgroups wait here for the control workgroup's broadcast of batch `want`
 // (bounded; an abort raised anywhere ends the wait).
 __device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t spin_ticks) {
   __shared__ int s_go;
@@ -1303,7 +1309,7 @@ __device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t s
   return s_go != 0;
 }
 
-// What workgroup 0 stages in LDS for one batch while forming it.
+// What the control workgroup stages in LDS for one batch while forming it.
 struct BatchLds {
   uint64_t id[kMaxBatch];               // request ids
   uint64_t tarr[kMaxBatch];             // request arrival ticks
@@ -1319,7 +1325,7 @@ struct BatchLds {
   int acq[3];                           // status, requests, rows
 };
 
-// Formation of batch seq by all threads of workgroup 0: acquire its input (ingest
+// Formation of batch seq by all threads of the control workgroup: acquire its input (ingest
 // requests, or the full ring slot seq) and its output space, then stage the
 // requests, their row offsets, the input's stage timestamps and the id checksums
 // in LDS. Stage 0 takes the requests (advances the ingest cursor) and a terminal
@@ -1409,29 +1415,43 @@ __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, u
   return 0;
 }
 
-// Persistent worker. Per batch: workgroup 0 forms the batch (or takes the one it
-// formed early), writes its descriptor and broadcasts it; every workgroup runs
-// its share of the stage; all arrive at the batch barrier. While the others
-// finish, workgroup 0 tries once to form the next batch (seq + n_inst) so that
-// acquisition and staging leave the path between two batches; then it waits for
-// the barrier and publishes the batch (output doorbell, input slot release or
-// ingest tail, egress head, counters).
-template <int KIND>
-__global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(WorkerArgs a) {
+// A formation try while a batch runs only this long before its expected end (ticks).
+constexpr int64_t kTryMarginTicks = 500;
+
+// What the publication of a batch needs (control workgroup).
+struct BatchPub {
+  uint64_t seq, hs, hx, t_start, t_top, t_end, ingest_end, egress_end;
+  int rows;
+};
+
+// Persistent worker, control side (the last workgroup). Per batch: form it (or take the
+// one formed early), write its descriptor and broadcast it; then, while the compute
+// workgroups run the batch, try to form the next one (seq + n_inst) and wait until
+// every compute workgroup has counted the batch done. The batch is published
+// (output doorbell, input slot release or ingest tail, egress head, counters) right
+// after the next batch's broadcast, or before waiting for input when the next batch
+// is not ready. Acquisition, staging and publication thus run beside the stage's
+// compute; between two batches remain the descriptor and the broadcast.
+// side_ptrs: the stage reads each row's side bytes.
+__device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_ptrs) {
   WorkerCtl* ctl = a.ctl;
   const int tid = threadIdx.x;
-  const bool wg0 = blockIdx.x == 0;
   const int si = a.stage_index;
+  const int nx = (int)gridDim.x - 1;              // compute workgroups
+  const int ng = nx < 8 ? nx : 8;                 // their groups (index mod 8)
 
   __shared__ BatchLds s;
   __shared__ uint64_t s_t0;
-  // running counters of this worker (workgroup 0, thread 0). A terminal stage
-  // publishes them with each batch, before its results; the others every 16th batch
-  // after the broadcast (their stores to host memory would hold up the next loads of
-  // the thread that issued them), before workgroup 0 waits for a batch, and at exit
-  // (acc_dirty: not published yet)
+  // running counters (thread 0). A terminal stage publishes them with each batch,
+  // before its results; the others every 16th batch (their stores to host memory
+  // would hold up the next loads of the thread that issued them), before waiting for
+  // input, and at exit (acc_dirty: not published yet)
   __shared__ uint64_t acc_sum, acc_xor, acc_batches, acc_rows, acc_busy, acc_wait;
   __shared__ int acc_dirty;
+  __shared__ uint32_t done_base[8];               // the done counters at start
+  __shared__ int s_flag;
+  __shared__ int64_t s_dur;                       // how long the last batch ran (ticks)
+  __shared__ BatchPub pb;                         // the batch awaiting publication
   auto publish_counters = [&]() {
     st_relaxed_sys(&a.pub->id_sum[a.worker_index], acc_sum);
     st_relaxed_sys(&a.pub->id_xor[a.worker_index], acc_xor);
@@ -1441,7 +1461,44 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
     st_relaxed_sys(&a.pub->batches[a.worker_index], acc_batches);
     acc_dirty = 0;
   };
-  if (wg0 && tid == 0) {
+  // publication of batch pb (thread 0): one release fence for the output doorbell
+  // and the input slot release
+  auto publish_batch = [&]() {
+    const uint64_t q = pb.seq;
+    const bool sys = a.out_kind == kOutEgress || a.out_state_sys != 0 || a.in_state_sys != 0;
+    if (a.out_kind == kOutRing) {
+      SlotHeader* oh = (SlotHeader*)(a.out_ring + (q % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
+      oh->t_stage[2 * si + 1] = pb.t_end;
+      // host-staged boundary: the relay reads the row count next to the state word
+      if (a.out_state_sys) st_relaxed_sys(&a.out_state[a.out_depth + q % (uint64_t)a.out_depth], (uint64_t)pb.rows);
+    }
+    acc_sum += pb.hs;
+    acc_xor ^= pb.hx;
+    acc_batches += 1;
+    acc_rows += (uint64_t)pb.rows;
+    acc_busy += pb.t_end - pb.t_start;
+    acc_wait += pb.t_start - pb.t_top;
+    acc_dirty = 1;
+    if (a.out_kind == kOutEgress) publish_counters();     // ordered before the results by the fence
+    if (sys) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (a.out_kind == kOutRing) {
+      uint64_t* p = &a.out_state[q % (uint64_t)a.out_depth];
+      if (a.out_state_sys) st_relaxed_sys(p, 2 * q + 1);
+      else __hip_atomic_store(p, 2 * q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      st_relaxed_sys(&a.pub->egress_head, pb.egress_end);
+    }
+    if (si == 0) {
+      st_relaxed_sys(&a.pub->ingest_tail, pb.ingest_end);
+    } else {
+      uint64_t* p = &a.in_state[q % (uint64_t)a.in_depth];
+      if (a.in_state_sys) st_relaxed_sys(p, 2 * q + 2);
+      else __hip_atomic_store(p, 2 * q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+
+  if (tid == 0) {
     s_t0 = now_ticks();
     s.cursor = ctl->ingest_cursor;
     s.egress_head = ctl->egress_head;
@@ -1453,182 +1510,158 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
     acc_busy = ctl->busy_acc;
     acc_wait = ctl->wait_acc;
     acc_dirty = 0;
+    s_dur = 0;
+    // the compute workgroups count a batch only after its broadcast
+    for (int g = 0; g < 8; ++g) done_base[g] = __hip_atomic_load(&ctl->done[g][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (si == 0) st_relaxed_sys(&a.pub->t0, s_t0);
     st_relaxed_sys(&a.pub->started[a.worker_index], 1);
   }
-  if (wg0) __syncthreads();
+  __syncthreads();
   uint64_t seq = ctl->next_seq;
+  uint32_t issued = 0;            // batches broadcast by this launch
   int exit_status = kStatusOk;
-  bool pending = false;          // workgroup 0: batch seq is already formed and staged
-  // workgroup 0: what the publication of the current batch needs (kept in LDS, out
-  // of the registers the stage needs)
-  __shared__ struct {
-    uint64_t hs, hx, t_start, t_top, ingest_end, egress_end;
-    int rows;
-    uint32_t stop;               // the broadcast descriptor, as workgroup 0 reads it
-    uint8_t* out;
-  } b;
+  bool pending = false;           // batch seq is already formed and staged
+  bool unpublished = false;       // pb holds a finished batch not yet published
   for (;;) {
-    // ---------------- control: form the batch, write its descriptor, broadcast (workgroup 0)
-    if (wg0) {
-      const uint64_t t_top = now_ticks();
-      // one poll first; before waiting for the batch the counters reach the host
-      int st = pending ? 0 : kAcqNotReady;
-      for (int attempt = 0; st == kAcqNotReady; ++attempt) {
-        if (attempt == 1 && tid == 0 && acc_dirty) publish_counters();
-        st = form_batch(a, ctl, seq, s_t0, attempt == 0, s);
-      }
-      pending = false;
-      if (st == 0) {
-        const int nreq = s.acq[1], rows = s.acq[2];
-        const uint64_t t_start = now_ticks();
-        // per-row descriptors: input row pointers (ingest), side bytes, and the
-        // request of each row (egress records)
-        const uint8_t* in_payload = si > 0 ? a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride +
-                                                 kSlotHeaderBytes
-                                           : nullptr;
-        const uint8_t* in_hdr = si > 0 ? in_payload - kSlotHeaderBytes : nullptr;
-        for (int q = tid; q < nreq; q += kThreads) {
-          for (uint32_t j = 0; j < s.rows[q]; ++j) {
-            const uint32_t row = s.rbase[q] + j;
-            const uint8_t* rp = si > 0 ? in_payload + (int64_t)row * a.sp.in_row_bytes
-                                       : s.ptr[q] + (int64_t)j * a.in_row_stride;
-            if (si == 0) ctl->d_rowptr[row] = rp;
-            if (a.side_bytes > 0 || KIND == CAMELOT_STAGE_GATHER_SCORE)
-              ctl->d_rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
-                                           : rp + a.sp.in_row_bytes;
-            if (a.out_kind == kOutEgress) {
-              ctl->d_row_id[row] = s.id[q];
-              ctl->d_row_idx[row] = j;
-              ctl->d_row_tarr[row] = s.tarr[q];
-            }
-          }
-        }
-        if (tid < 2 * kMaxStages) ctl->d_t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
-        if (a.out_kind == kOutRing) {
-          SlotHeader* oh = (SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
-          for (int q = tid; q < nreq; q += kThreads) {
-            oh->req_id[q] = s.id[q];
-            oh->req_tarr[q] = s.tarr[q];
-            oh->req_rows[q] = s.rows[q];
-          }
-          if (tid < 2 * kMaxStages) oh->t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
-          if (tid == 0) {
-            oh->seq = seq;
-            oh->n_req = (uint32_t)nreq;
-            oh->n_rows = (uint32_t)rows;
-            ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
-            ctl->d_out_hdr = oh;
-            b.out = (uint8_t*)oh + kSlotHeaderBytes;
-          }
-        } else if (tid == 0) {
-          ctl->d_egress_base = s.egress_base;
-          ctl->d_out = nullptr;
-          b.out = nullptr;
-        }
+    const uint64_t t_top = now_ticks();
+    int st = pending ? 0 : kAcqNotReady;
+    for (int attempt = 0; st == kAcqNotReady; ++attempt) {
+      if (attempt == 1) {
+        // about to wait for input: what is finished reaches the consumers and the host
         if (tid == 0) {
-          ctl->d_rows = (uint32_t)rows;
-          uint64_t hs = 0, hx = 0;
-          for (int w = 0; w < kWaves; ++w) { hs += s.red[0][w]; hx ^= s.red[1][w]; }
-          b.hs = hs;
-          b.hx = hx;
-          b.rows = rows;
-          b.t_start = t_start;
-          b.t_top = t_top;
-          b.ingest_end = s.cursor;
-          b.egress_end = s.egress_base + (uint64_t)rows;
+          if (unpublished) publish_batch();
+          if (acc_dirty) publish_counters();
+        }
+        unpublished = false;
+      }
+      st = form_batch(a, ctl, seq, s_t0, attempt == 0, s);
+    }
+    pending = false;
+    uint64_t t_start = 0;
+    if (st == 0) {
+      const int nreq = s.acq[1], rows = s.acq[2];
+      t_start = now_ticks();
+      // per-row descriptors: input row pointers (ingest), side bytes, and the
+      // request of each row (egress records)
+      const uint8_t* in_payload = si > 0 ? a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride +
+                                               kSlotHeaderBytes
+                                         : nullptr;
+      const uint8_t* in_hdr = si > 0 ? in_payload - kSlotHeaderBytes : nullptr;
+      for (int q = tid; q < nreq; q += kThreads) {
+        for (uint32_t j = 0; j < s.rows[q]; ++j) {
+          const uint32_t row = s.rbase[q] + j;
+          const uint8_t* rp = si > 0 ? in_payload + (int64_t)row * a.sp.in_row_bytes
+                                     : s.ptr[q] + (int64_t)j * a.in_row_stride;
+          if (si == 0) ctl->d_rowptr[row] = rp;
+          if (side_ptrs)
+            ctl->d_rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
+                                         : rp + a.sp.in_row_bytes;
+          if (a.out_kind == kOutEgress) {
+            ctl->d_row_id[row] = s.id[q];
+            ctl->d_row_idx[row] = j;
+            ctl->d_row_tarr[row] = s.tarr[q];
+          }
         }
       }
-      if (tid == 0) {
-        ctl->d_stop = (uint32_t)st;
-        b.stop = (uint32_t)st;
-      }
-      // broadcast: the batch descriptor (or the stop) is in place
-      wg_barrier_stores_done();
-      if (tid == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        for (int g = 0; g < 8; ++g)
-          __hip_atomic_store(&ctl->go[g][0], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (acc_dirty && (acc_batches & 15) == 0) publish_counters();
-      }
-      // the descriptor's writers are this workgroup's own threads
-      __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    } else if (!wait_go(ctl, (uint32_t)(seq + 1), 2 * a.idle_ticks + a.spin_ticks)) {
-      // workgroup 0 may wait for input (up to the idle limit) and then for output space
-      exit_status = kStatusTimeout;
-      break;
-    }
-    // a host-staged input slot was written by a DMA copy: acquire at system scope
-    if (a.in_state_sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-    // the descriptor (workgroup 0 has its own copy in LDS), the same for every lane:
-    // kept in scalar registers
-    const uint32_t stop = __builtin_amdgcn_readfirstlane(wg0 ? b.stop : ctl->d_stop);
-    if (stop) { exit_status = (int)stop; break; }
-    const int rows = __builtin_amdgcn_readfirstlane(wg0 ? b.rows : (int)ctl->d_rows);
-    const uint64_t outp = wg0 ? (uint64_t)b.out : (uint64_t)ctl->d_out;
-    uint8_t* const out = (uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(outp >> 32)) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)outp));
-    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, seq), rows, out)) { exit_status = kStatusTimeout; break; }
-    copy_side(a, ctl, rows);
-    // batch done: every workgroup arrives, only workgroup 0 waits (it publishes and
-    // then forms the next batch; the others go on to wait for its broadcast).
-    // Results go to pinned host memory, a host-staged output slot is read by DMA:
-    // those are published at system scope.
-    const BarTicket done = grid_arrive(ctl, gridDim.x, a.out_kind == kOutEgress || a.out_state_sys != 0);
-    if (!wg0) {
-      seq += (uint64_t)a.n_inst;
-      continue;
-    }
-    // the next batch, if it is ready now; it touches only workgroup 0's LDS, the
-    // slots of batch seq + n_inst and the cursors that formation advances
-    pending = form_batch(a, ctl, seq + (uint64_t)a.n_inst, s_t0, true, s) == 0;
-    if (!grid_wait(ctl, gridDim.x, done, a.spin_ticks)) {
-      exit_status = kStatusTimeout;
-      break;
-    }
-    // ---------------- publish (workgroup 0, thread 0): one release fence for the
-    // output doorbell and the input slot release
-    if (tid == 0) {
-      const uint64_t t_end = now_ticks();
-      const bool sys = a.out_kind == kOutEgress || a.out_state_sys != 0 || a.in_state_sys != 0;
+      if (tid < 2 * kMaxStages) ctl->d_t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
       if (a.out_kind == kOutRing) {
         SlotHeader* oh = (SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
-        oh->t_stage[2 * si + 1] = t_end;
-        // host-staged boundary: the relay reads the row count next to the state word
-        if (a.out_state_sys) st_relaxed_sys(&a.out_state[a.out_depth + seq % (uint64_t)a.out_depth], (uint64_t)b.rows);
+        for (int q = tid; q < nreq; q += kThreads) {
+          oh->req_id[q] = s.id[q];
+          oh->req_tarr[q] = s.tarr[q];
+          oh->req_rows[q] = s.rows[q];
+        }
+        if (tid < 2 * kMaxStages) oh->t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
+        if (tid == 0) {
+          oh->seq = seq;
+          oh->n_req = (uint32_t)nreq;
+          oh->n_rows = (uint32_t)rows;
+          ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
+          ctl->d_out_hdr = oh;
+        }
+      } else if (tid == 0) {
+        ctl->d_egress_base = s.egress_base;
+        ctl->d_out = nullptr;
       }
-      const uint64_t sum = acc_sum + b.hs, xr = acc_xor ^ b.hx, nb = acc_batches + 1;
-      const uint64_t nr = acc_rows + (uint64_t)b.rows, busy = acc_busy + (t_end - b.t_start);
-      const uint64_t wait = acc_wait + (b.t_start - b.t_top);
-      acc_sum = sum;
-      acc_xor = xr;
-      acc_batches = nb;
-      acc_rows = nr;
-      acc_busy = busy;
-      acc_wait = wait;
-      acc_dirty = 1;
-      if (a.out_kind == kOutEgress) publish_counters();     // ordered before the results by the fence
-      if (sys) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-      else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (a.out_kind == kOutRing) {
-        uint64_t* p = &a.out_state[seq % (uint64_t)a.out_depth];
-        if (a.out_state_sys) st_relaxed_sys(p, 2 * seq + 1);
-        else __hip_atomic_store(p, 2 * seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        st_relaxed_sys(&a.pub->egress_head, b.egress_end);
-      }
-      if (si == 0) {
-        st_relaxed_sys(&a.pub->ingest_tail, b.ingest_end);
-      } else {
-        uint64_t* p = &a.in_state[seq % (uint64_t)a.in_depth];
-        if (a.in_state_sys) st_relaxed_sys(p, 2 * seq + 2);
-        else __hip_atomic_store(p, 2 * seq + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (tid == 0) ctl->d_rows = (uint32_t)rows;
     }
+    if (tid == 0) ctl->d_stop = (uint32_t)st;
+    // broadcast: the batch descriptor (or the stop) is in place
+    wg_barrier_stores_done();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int g = 0; g < 8; ++g)
+        __hip_atomic_store(&ctl->go[g][0], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the previous batch, and now and then the counters, after the broadcast
+      if (unpublished) publish_batch();
+      if (acc_dirty && (acc_batches & 15) == 0) publish_counters();
+    }
+    unpublished = false;
+    if (st != 0) { exit_status = st; break; }
+    ++issued;
+    // what the publication of this batch will need (staged data of the next batch
+    // may overwrite s from here on)
+    if (tid == 0) {
+      uint64_t hs = 0, hx = 0;
+      for (int w = 0; w < kWaves; ++w) { hs += s.red[0][w]; hx ^= s.red[1][w]; }
+      pb.seq = seq;
+      pb.hs = hs;
+      pb.hx = hx;
+      pb.rows = s.acq[2];
+      pb.t_start = t_start;
+      pb.t_top = t_top;
+      pb.ingest_end = s.cursor;
+      pb.egress_end = s.egress_base + (uint64_t)s.acq[2];
+    }
+    __syncthreads();
+    // while the batch runs: wait until every compute workgroup has counted it done
+    // (bounded; an abort ends it), and form the next batch once it is ready, with
+    // tries only while the batch is expected to run for a while longer (a try must
+    // not hold up noticing the end)
+    const uint64_t t_w0 = now_ticks();
+    uint32_t polls = 0;
+    int f = 0;
+    for (;;) {
+      if (tid == 0) {
+        bool all = true;
+        for (int g = 0; g < ng; ++g) {
+          const uint32_t members = (uint32_t)(nx - g + 7) >> 3;
+          const uint32_t v = __hip_atomic_load(&ctl->done[g][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v - done_base[g] != issued * members) all = false;
+        }
+        int r = all ? 1 : 0;
+        if (!all) {
+          const int64_t el = (int64_t)(now_ticks() - t_w0);
+          if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            r = -1;
+          } else if (el > a.spin_ticks) {
+            __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            r = -1;
+          } else if (!pending && el + kTryMarginTicks < s_dur) {
+            r = 2;
+          } else {
+            poll_backoff(++polls);
+          }
+        }
+        s_flag = r;
+      }
+      __syncthreads();
+      f = s_flag;
+      __syncthreads();
+      if (f != 2 && f != 0) break;
+      if (f == 2) pending = form_batch(a, ctl, seq + (uint64_t)a.n_inst, s_t0, true, s) == 0;
+    }
+    if (f < 0) { exit_status = kStatusTimeout; break; }
+    if (tid == 0) {
+      // the compute workgroups' results (released before they counted) are visible
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      pb.t_end = now_ticks();
+      s_dur = (int64_t)(pb.t_end - t_w0);
+    }
+    unpublished = true;
     seq += (uint64_t)a.n_inst;          // instance j of n takes batches j, j + n, ...
   }
-  if (wg0 && tid == 0) {
+  if (tid == 0) {
     ctl->next_seq = seq;
     ctl->ingest_cursor = s.cursor;
     ctl->egress_head = s.egress_head;
@@ -1642,6 +1675,50 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(Wo
     publish_counters();
     st_release_sys(&a.pub->status[a.worker_index], (int32_t)exit_status);
   }
+}
+
+// Persistent worker, compute side (the other workgroups, one per CU of the share): wait for the broadcast of each
+// batch this instance takes, run the stage on it, make the results visible (system
+// scope for results in host memory or slots a DMA copy reads) and count the batch
+// done in the group's counter. A stop in the descriptor, an expired wait or a failed
+// stage ends the loop (the control workgroup then times out on the counters, or
+// sees the abort).
+template <int KIND>
+__device__ __forceinline__ void worker_compute(const WorkerArgs& a) {
+  WorkerCtl* ctl = a.ctl;
+  const int tid = threadIdx.x;
+  const uint32_t g = (uint32_t)xwg(a) & 7u;
+  const bool sys = a.out_kind == kOutEgress || a.out_state_sys != 0;
+  uint64_t seq = ctl->next_seq;
+  for (;;) {
+    // the control workgroup may wait for input (up to the idle limit) and then for
+    // output space
+    if (!wait_go(ctl, (uint32_t)(seq + 1), 2 * a.idle_ticks + a.spin_ticks)) break;
+    // a host-staged input slot was written by a DMA copy: acquire at system scope
+    if (a.in_state_sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    // the descriptor is the same for every lane: kept in scalar registers
+    const uint32_t stop = __builtin_amdgcn_readfirstlane(ctl->d_stop);
+    if (stop) break;
+    const int rows = __builtin_amdgcn_readfirstlane((int)ctl->d_rows);
+    const uint64_t outp = (uint64_t)ctl->d_out;
+    uint8_t* const out = (uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(outp >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)outp));
+    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, seq), rows, out)) break;
+    copy_side(a, ctl, rows);
+    wg_barrier_stores_done();
+    if (tid == 0) {
+      if (sys) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(&ctl->done[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    seq += (uint64_t)a.n_inst;
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_worker(WorkerArgs a) {
+  if ((int)blockIdx.x == xnwg(a)) worker_control(a, a.side_bytes > 0 || KIND == CAMELOT_STAGE_GATHER_SCORE);
+  else worker_compute<KIND>(a);
 }
 
 template __global__ void stage_worker<CAMELOT_STAGE_GEMM_RELU>(WorkerArgs);
