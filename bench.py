@@ -11,7 +11,7 @@ Steps (all on synthetic, seeded inputs resident in HBM before any timed region):
  1. solo profile table: every stage x CU share (8..256 in steps of 8) x batch
     (1..128, powers of two), measured with the library's one-shot stage kernel;
  2. allocations: the max-peak problem (Eq. 1) -> CU shares, instances of the MLP
-    stage (up to 4, each on its own share) and batch, solved twice: contention-aware
+    stage (up to 5, each on its own share) and batch, solved twice: contention-aware
     (co-location profiles, the learned predictor trained on them, Eq. 1 over its
     predicted co-located latencies) and over the solo table. Both proposals are
     measured (step 3) and the one with the higher measured peak is deployed for the
@@ -49,8 +49,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 QOS_NS = 50_000_000
-MAX_INST = 4            # instances per stage the allocator may place (every instance is a
-                        # hardware queue; with 7 workers a barrier timeout was seen)
+MAX_INST = 5            # instances per stage the allocator may place (every instance is a
+                        # persistent kernel on a hardware queue of its own)
 HBM_PEAK = 8.0e12
 MFMA_BF16_PEAK = 2.5e15
 MLP_PARAMS = 440 * 2048 + 2048 * 2048 * 2 + 2048 * 4096
