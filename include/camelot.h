@@ -201,8 +201,9 @@ int64_t camelot_stage_row_bytes_out(const camelot_stage_desc* stage);
 /* Run one stage over `rows` rows (0..CAMELOT_MAX_BATCH) on `n_cus` CUs starting
  * at CU-mask bit `cu_offset` (n_cus and cu_offset multiples of 8; 0 n_cus = all
  * CUs), `reps` times back to back (the same input each time), with the compute
- * code and grid of the persistent worker (one kernel launch, grid barriers
- * between reps).
+ * code and compute grid of the persistent worker (one workgroup per CU; one
+ * kernel launch, grid barriers between reps; a pipeline's worker adds one control
+ * workgroup that forms and publishes the batches).
  *   in   device, rows * row_bytes_in
  *   out  device, rows * row_bytes_out (result stages: [rows][k] int32 indices
  *        followed by [rows][k] f32 values, i.e. 2 planes)
