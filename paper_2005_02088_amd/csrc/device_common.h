@@ -103,15 +103,10 @@ struct WorkerCtl {
   uint32_t diag_arrived, diag_nwg, diag_group;   // filled on a barrier timeout
   uint32_t diag_pad;
   // batch descriptor written by the control workgroup before its broadcast
-  uint64_t d_seq;
-  uint32_t d_stop;
+  uint32_t d_stop;                // nonzero: the workers exit with this status
   uint32_t d_rows;
-  uint32_t d_nreq;
-  uint32_t d_pad;
   uint8_t* d_out;                 // payload of the output slot (ring output)
   SlotHeader* d_out_hdr;          // header of the output slot (ring output)
-  const SlotHeader* d_in_hdr;     // header of the input slot (ring input)
-  uint64_t d_t_start;
   uint64_t d_egress_base;               // egress row index of this batch's first row
   uint64_t d_t_stage[2 * kMaxStages];   // stage timestamps of the batch so far
   const uint8_t* d_rowptr[kMaxBatch];   // input row pointers
