@@ -24,7 +24,7 @@ import numpy as np
 _STREAMS = {
     "c0_weights": 1, "c0_queries": 2, "c1_audio": 3, "c1_weights": 4,
     "arrivals": 5, "requests": 6, "tables": 7, "predictor": 8, "c4": 9,
-    "handoff": 10,
+    "handoff": 10, "dtree": 11,
 }
 
 
