@@ -283,17 +283,28 @@ def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1200, epochs=150):
     co = multi[te]
     mape_l = float(np.mean(np.abs(pred[co] - meas[co]) / meas[co]))
     mape_s = float(np.mean(np.abs(solo[te][co] - meas[co]) / meas[co]))
+    # the paper's predictor kind beside it: a regression tree on the same samples
+    # and target (host code in the library)
+    t0 = time.perf_counter()
+    dt = cm.camelot_dt_fit(X[tr], y[tr], DT_MAX_DEPTH, DT_MIN_LEAF)
+    t_dt = time.perf_counter() - t0
+    pred_dt = solo[te] * np.exp(dt.predict(X[te]).astype(np.float64))
+    mape_dt = float(np.mean(np.abs(pred_dt[co] - meas[co]) / meas[co]))
+    dt_nodes = int(len(dt.export()["feat"]))
     t0 = time.perf_counter()
     a, lp = cm.camelot_alloc_peak_learned(prob, tabs, dp.data_ptr(), mean, std)
     t_alloc = time.perf_counter() - t0
     info = {"samples": int(len(y)), "profile_s": t_prof, "train_s": t_train, "epochs": epochs,
             "loss_first_last": [float(losses[0]), float(losses[-1])], "mape_colocated_learned": mape_l,
-            "mape_colocated_solo_table": mape_s, "alloc_ms": t_alloc * 1e3}
+            "mape_colocated_solo_table": mape_s, "alloc_ms": t_alloc * 1e3,
+            "decision_tree": {"mape_colocated": mape_dt, "max_depth": DT_MAX_DEPTH, "min_leaf": DT_MIN_LEAF,
+                              "nodes": dt_nodes, "fit_ms": t_dt * 1e3}}
     log(f"learned predictor: {info}")
     return (a.as_dict() if a is not None else None), [int(v) for v in lp[:3]], info
 
 
 ROOF_LAUNCHES, ROOF_REPS = 10, 50
+DT_MAX_DEPTH, DT_MIN_LEAF = 12, 5      # the regression tree beside the learned predictor
 
 
 ROOFLINE_EXE = os.path.join(ROOT, "paper_2005_02088_amd", "camelot_mlp_roofline")
@@ -396,6 +407,19 @@ def main():
     a = alloc.as_dict()
     pred = a["thr_num"] / a["thr_den"]
     log(f"allocation {a} predicted {pred / 1e6:.3f} Mq/s ({alloc_ms:.2f} ms)")
+    # ablation without the bandwidth constraint (the paper's Camelot-NC): Eq. 1 with an
+    # unlimited HBM bandwidth budget; it differs only where the constraint binds
+    prob_nc = cm.ProblemArrays(cu_total=256, cu_step=8, max_instances=48, max_inst_per_stage=MAX_INST,
+                               batches=BATCHES, qos_ns=QOS_NS, hbm_bytes_budget=dev.hbm_bytes,
+                               hbm_bw_budget=1 << 62, lat_ns=lat, bw_bps=bw, mem_bytes=mem,
+                               inst_max=[1, MAX_INST, 1])
+    anc = cm.camelot_alloc_peak(prob_nc).as_dict()
+    nc = {"allocation_cus": anc["cu"], "allocation_instances": anc["n"], "batch": anc["batch"],
+          "predicted_qps": anc["thr_num"] / anc["thr_den"],
+          "bw_constraint_binding": (anc["cu"], anc["n"], anc["batch"]) != (a["cu"], a["n"], a["batch"]),
+          "predicted_bw_bytes_per_s": int(sum(n * int(bw[i, c // 8 - 1, anc["batch_index"]])
+                                              for i, (c, n) in enumerate(zip(anc["cu"], anc["n"]))))}
+    log(f"allocation without the bandwidth constraint: {nc}")
     even = [88, 88, 80]
     ok_even, ea = cm.camelot_alloc_eval(prob, a["batch_index"], [1, 1, 1], even)
     pred_even = ea.thr_num / ea.thr_den
@@ -570,6 +594,7 @@ def main():
                     "ring_bytes": slot * 16, "host_staged_gbs": hh["gbs"]},
         "learned_allocator": learned,
         "calibrated_table_allocation": calib,
+        "no_bw_constraint_allocation": nc,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

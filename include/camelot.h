@@ -514,6 +514,31 @@ int32_t camelot_alloc_peak_learned(const camelot_problem* problem, const camelot
                                    const float* params, const float* mean, const float* std,
                                    camelot_alloc* out, int64_t* lat_pred_ns);
 
+/* ---------------------------------------------------------------- decision tree */
+/* Decision-tree regressor, the kind of latency predictor the paper fits to its
+ * co-location profiles (Section V-A). CART regression with the squared error: a node
+ * splits on the feature and threshold (midpoint between consecutive distinct values;
+ * x <= thr goes left) that maximise sum_L^2/n_L + sum_R^2/n_R, both children keeping
+ * at least min_leaf samples, if that lowers the error; otherwise, or at max_depth,
+ * it is a leaf predicting the mean of its y. Deterministic: features in index order,
+ * samples in (value, index) order, sums in double in that order, the first best
+ * split kept. Host code, host memory throughout.
+ *   x    [n][n_feat] f32, y [n] f32 (all finite); 1 <= n, 1 <= n_feat,
+ *        0 <= max_depth <= 64, min_leaf >= 1.
+ *   *out receives the tree (caller frees it with camelot_dt_destroy).
+ * EINVAL on bad arguments or a non-finite value, ENOMEM. */
+typedef struct camelot_dt camelot_dt;
+int32_t camelot_dt_fit(const float* x, const float* y, int32_t n, int32_t n_feat, int32_t max_depth,
+                       int32_t min_leaf, camelot_dt** out);
+/* Predictions for n host rows x [n][n_feat] into host out [n]. */
+int32_t camelot_dt_predict(const camelot_dt* t, const float* x, int32_t n, float* out);
+/* The nodes in creation (depth-first, left first) order: *n_nodes always; with
+ * cap >= *n_nodes also feat (-1: leaf), thr, value, left, right (host arrays [cap];
+ * -1 children for a leaf). cap 0 asks for the count only. */
+int32_t camelot_dt_export(const camelot_dt* t, int32_t cap, int32_t* n_nodes, int32_t* feat, double* thr,
+                          double* value, int32_t* left, int32_t* right);
+void camelot_dt_destroy(camelot_dt* t);
+
 #ifdef __cplusplus
 }
 #endif

@@ -164,6 +164,10 @@ _SIGS = {
     "camelot_predictor_adam": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_float, _P]),
     "camelot_predictor_train": (C.c_int32, [_P, _P, _P, C.POINTER(C.c_int32), _P, _P, C.c_int32,
                                             C.c_int32, C.c_int32, _P, C.c_float, _P, _P]),
+    "camelot_dt_fit": (C.c_int32, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "camelot_dt_predict": (C.c_int32, [_P, _P, C.c_int32, _P]),
+    "camelot_dt_export": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, _P, _P]),
+    "camelot_dt_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -494,6 +498,44 @@ def camelot_predictor_standardize(x: np.ndarray, mean, std) -> np.ndarray:
     std = np.ascontiguousarray(std, dtype=np.float32)
     _check(_lib.camelot_predictor_standardize(x.ctypes.data, x.shape[0], mean.ctypes.data, std.ctypes.data))
     return x
+
+
+class DecisionTree:
+    """A fitted camelot_dt (include/camelot.h); freed with the object."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.camelot_dt_destroy(self._h)
+            self._h = None
+
+    def predict(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        out = np.empty(x.shape[0], np.float32)
+        _check(_lib.camelot_dt_predict(self._h, x.ctypes.data, x.shape[0], out.ctypes.data))
+        return out
+
+    def export(self) -> dict:
+        """Nodes in creation order: feat (-1 leaf), thr, value, left, right."""
+        n = C.c_int32(0)
+        _check(_lib.camelot_dt_export(self._h, 0, C.byref(n), None, None, None, None, None))
+        m = n.value
+        feat, left, right = (np.empty(m, np.int32) for _ in range(3))
+        thr, value = np.empty(m, np.float64), np.empty(m, np.float64)
+        _check(_lib.camelot_dt_export(self._h, m, C.byref(n), feat.ctypes.data, thr.ctypes.data,
+                                      value.ctypes.data, left.ctypes.data, right.ctypes.data))
+        return {"feat": feat, "thr": thr, "value": value, "left": left, "right": right}
+
+
+def camelot_dt_fit(x, y, max_depth: int, min_leaf: int) -> DecisionTree:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    h = _P()
+    _check(_lib.camelot_dt_fit(x.ctypes.data, y.ctypes.data, x.shape[0], x.shape[1], max_depth, min_leaf,
+                               C.byref(h)))
+    return DecisionTree(h)
 
 
 def camelot_alloc_peak_learned(problem: ProblemArrays, tables: SoloTablesArrays, params_ptr: int, mean, std):
