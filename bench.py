@@ -375,7 +375,7 @@ def main():
         print(json.dumps(cpu_baseline(args.cpu_baseline_only)))
         return 0
     if args.gpus != 1:
-        print("bench.py measures one MI355X: this build runs on a single GPU only (use --gpus 1).",
+        print("bench.py measures one MI355X: the pipelines run on a single GPU (use --gpus 1); sharding over GPUs is not implemented.",
               file=sys.stderr)
         return 2
 
