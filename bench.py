@@ -22,8 +22,10 @@ Steps (all on synthetic, seeded inputs resident in HBM before any timed region):
     device-global handoff and for the baseline (even split 88/88/80 CUs,
     host-staged handoff, same batching rule); then a third proposal, Eq. 1 over the
     solo table plus each stage's measured per-batch cost the table misses (busy time
-    at the solo-table allocation's peak minus its table latency), measured the same
-    way; the best-measured proposal is deployed;
+    at the solo-table allocation's peak minus its table latency), and a fourth, Eq. 1
+    with a regression tree (fitted to the same co-location samples) as the predictor,
+    each measured the same way when new; the best-measured proposal is deployed;
+    Eq. 1 without the bandwidth constraint is reported beside them (not measured);
  4. timed steps: K replays at the found peak rate (one step = one trial);
  5. CUs at 20% load: min-resource problem (Eq. 3) at 20% of the baseline's peak,
     checked with a replay;
@@ -294,11 +296,18 @@ def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1200, epochs=150):
     t0 = time.perf_counter()
     a, lp = cm.camelot_alloc_peak_learned(prob, tabs, dp.data_ptr(), mean, std)
     t_alloc = time.perf_counter() - t0
+    # Eq. 1 with the tree as the predictor instead (the paper's arrangement)
+    adt, ldt = cm.camelot_alloc_peak_dt(prob, tabs, dt)
+    dt_alloc = None
+    if adt is not None:
+        dd = adt.as_dict()
+        dt_alloc = {"allocation_cus": dd["cu"], "allocation_instances": dd["n"], "batch": dd["batch"],
+                    "predicted_qps": dd["thr_num"] / dd["thr_den"], "predicted_stage_ns": [int(v) for v in ldt[:3]]}
     info = {"samples": int(len(y)), "profile_s": t_prof, "train_s": t_train, "epochs": epochs,
             "loss_first_last": [float(losses[0]), float(losses[-1])], "mape_colocated_learned": mape_l,
             "mape_colocated_solo_table": mape_s, "alloc_ms": t_alloc * 1e3,
             "decision_tree": {"mape_colocated": mape_dt, "max_depth": DT_MAX_DEPTH, "min_leaf": DT_MIN_LEAF,
-                              "nodes": dt_nodes, "fit_ms": t_dt * 1e3}}
+                              "nodes": dt_nodes, "fit_ms": t_dt * 1e3, "allocation": dt_alloc}}
     log(f"learned predictor: {info}")
     return (a.as_dict() if a is not None else None), [int(v) for v in lp[:3]], info
 
@@ -484,9 +493,26 @@ def main():
                  "measured_peak_qps": (cbest[0] if cbest else 0.0) if cbest is not None else None}
         log(f"calibrated table: extra per batch {extra} ns -> allocation {ac['cu']} x {ac['n']}, "
             f"measured {calib['measured_peak_qps']}")
+    # the decision-tree allocation, measured when it is a new proposal
+    dtp = linfo["decision_tree"]["allocation"] if linfo is not None else None
+    if dtp is not None:
+        seen = [(x["cu"], x["n"], x["batch"]) for x in [a] + ([la] if la is not None else [])]
+        if calib is not None:
+            seen.append((calib["allocation_cus"], calib["allocation_instances"], calib["batch"]))
+        dtp["measured_peak_qps"] = None
+        if (dtp["allocation_cus"], dtp["allocation_instances"], dtp["batch"]) not in seen:
+            try:
+                r = sp.peak_search(dtp["allocation_cus"], cm.HANDOFF_DEVICE, dtp["batch"], dtp["predicted_qps"],
+                                   args.trial_s, args.search_iters, "decision tree",
+                                   n_inst=tuple(dtp["allocation_instances"]))
+                dtp["measured_peak_qps"] = r[0] if r else 0.0
+            except cm.CamelotError as e:
+                sp.failures.append(f"decision-tree allocation {dtp['allocation_cus']}: {e}")
+        log(f"decision-tree allocation {dtp}")
     # deployment check: the allocator's proposals (contention-aware, solo table,
-    # calibrated table) were measured; the one with the higher measured peak is
-    # deployed for the timed steps (the next one if its workers fail there)
+    # calibrated table, decision tree) were measured; the one with the higher
+    # measured peak is deployed for the timed steps (the next one if its workers
+    # fail there)
     cands = []
     if la is not None and peak_learned:
         cands.append((peak_learned, la, "contention-aware (learned predictor)"))
@@ -495,6 +521,9 @@ def main():
     if calib is not None and calib["measured_peak_qps"]:
         cands.append((calib["measured_peak_qps"], {"cu": calib["allocation_cus"], "n": calib["allocation_instances"],
                                                   "batch": calib["batch"]}, "calibrated solo table"))
+    if dtp is not None and dtp["measured_peak_qps"]:
+        cands.append((dtp["measured_peak_qps"], {"cu": dtp["allocation_cus"], "n": dtp["allocation_instances"],
+                                                "batch": dtp["batch"]}, "contention-aware (decision tree)"))
     cands.sort(key=lambda c: -c[0])
     if not cands:
         raise SystemExit("no rate met the QoS target; see the trial log above")

@@ -539,6 +539,14 @@ int32_t camelot_dt_export(const camelot_dt* t, int32_t cap, int32_t* n_nodes, in
                           double* value, int32_t* left, int32_t* right);
 void camelot_dt_destroy(camelot_dt* t);
 
+/* Contention-aware Eq. 1 with the tree as the predictor: the candidates, features,
+ * objective, constraints and tie rules of camelot_alloc_peak_learned, each stage's
+ * latency its solo latency times exp(the tree's prediction for one of its
+ * instances in the candidate's co-location), rounded up to ns; the tree is applied
+ * to the raw (not standardised) 16 features. Host code. */
+int32_t camelot_alloc_peak_dt(const camelot_problem* problem, const camelot_solo_tables* t, const camelot_dt* dt,
+                              camelot_alloc* out, int64_t* lat_pred_ns);
+
 #ifdef __cplusplus
 }
 #endif

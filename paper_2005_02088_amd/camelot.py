@@ -168,6 +168,7 @@ _SIGS = {
     "camelot_dt_predict": (C.c_int32, [_P, _P, C.c_int32, _P]),
     "camelot_dt_export": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, _P, _P]),
     "camelot_dt_destroy": (None, [_P]),
+    "camelot_alloc_peak_dt": (C.c_int32, [C.POINTER(Problem), C.POINTER(SoloTables), _P, C.POINTER(Alloc), _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -546,6 +547,18 @@ def camelot_alloc_peak_learned(problem: ProblemArrays, tables: SoloTablesArrays,
     lat = np.zeros(MAX_STAGES, np.int64)
     rc = _lib.camelot_alloc_peak_learned(C.byref(problem.struct), C.byref(tables.struct), params_ptr,
                                          mean.ctypes.data, std.ctypes.data, C.byref(a), lat.ctypes.data)
+    if rc == EINFEASIBLE:
+        return None, None
+    _check(rc)
+    return a, lat[: problem.struct.n_stages]
+
+
+def camelot_alloc_peak_dt(problem: ProblemArrays, tables: SoloTablesArrays, tree: DecisionTree):
+    """Returns (Alloc or None, predicted stage latencies in ns)."""
+    a = Alloc()
+    lat = np.zeros(MAX_STAGES, np.int64)
+    rc = _lib.camelot_alloc_peak_dt(C.byref(problem.struct), C.byref(tables.struct), tree._h, C.byref(a),
+                                    lat.ctypes.data)
     if rc == EINFEASIBLE:
         return None, None
     _check(rc)

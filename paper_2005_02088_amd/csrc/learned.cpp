@@ -279,13 +279,54 @@ void enumerate(const camelot_problem* p, int S, int K, const int* nmax, int tota
 }
 }  // namespace
 
-extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const camelot_solo_tables* t,
-                                              const float* params, const float* mean, const float* std,
-                                              camelot_alloc* out, int64_t* lat_pred_ns) {
-  clear_error();
+namespace {
+// Predicts the log co-location slowdown of n feature rows x [n][16] into y [n].
+struct SlowdownPredictor {
+  virtual ~SlowdownPredictor() = default;
+  virtual int32_t predict(float* x, int32_t n, float* y) = 0;
+};
+
+// The learned network on the GPU (standardised features).
+struct NetPredictor : SlowdownPredictor {
+  const float *params, *mean, *std;
+  float *dx = nullptr, *dy = nullptr;
+  int64_t cap = 0;
+  ~NetPredictor() override {
+    dfree(dx);
+    dfree(dy);
+  }
+  int32_t predict(float* x, int32_t n, float* y) override {
+    int32_t rc = 0;
+    if (n > cap) {
+      dfree(dx);
+      dfree(dy);
+      dx = dy = nullptr;
+      cap = 0;
+      if ((rc = dmalloc(&dx, (size_t)n * CAMELOT_PRED_FEATURES * sizeof(float))) ||
+          (rc = dmalloc(&dy, (size_t)n * sizeof(float))))
+        return rc;
+      cap = n;
+    }
+    camelot_predictor_standardize(x, n, mean, std);
+    if ((rc = h2d(dx, x, (size_t)n * CAMELOT_PRED_FEATURES * sizeof(float)))) return rc;
+    hipStream_t s = mem_stream();
+    hipLaunchKernelGGL(camelot_pred_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params,
+                       (const float*)dx, (int)n, dy);
+    if (hipGetLastError() != hipSuccess) return fail(CAMELOT_EDEVICE, "predictor forward launch failed");
+    return d2h(y, dy, (size_t)n * sizeof(float));
+  }
+};
+
+// A regression tree on the host (raw features).
+struct TreePredictor : SlowdownPredictor {
+  const camelot_dt* dt;
+  int32_t predict(float* x, int32_t n, float* y) override { return camelot_dt_predict(dt, x, n, y); }
+};
+
+int32_t alloc_peak_predicted(const camelot_problem* p, const camelot_solo_tables* t, SlowdownPredictor& pred,
+                             camelot_alloc* out, int64_t* lat_pred_ns) {
   int32_t rc = check_tables(t);
   if (rc) return rc;
-  if (!p || !params || !mean || !std || !out) return fail(CAMELOT_EINVAL, "bad learned allocation arguments");
   const int S = p->n_stages;
   if (S < 1 || S > 3 || t->n_kinds != S) return fail(CAMELOT_EINVAL, "learned allocation needs 1..3 stages matching the tables");
   if (p->cu_step != t->cu_step || p->cu_total / p->cu_step > t->n_shares || p->n_batches != t->n_batches)
@@ -313,12 +354,6 @@ extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const ca
   constexpr int64_t kChunk = 16384;
   std::vector<int64_t> L((size_t)cands.size() * S);
   {
-    float *dx = nullptr, *dy = nullptr;
-    if ((rc = dmalloc(&dx, kChunk * S * CAMELOT_PRED_FEATURES * sizeof(float))) ||
-        (rc = dmalloc(&dy, kChunk * S * sizeof(float)))) {
-      dfree(dx);
-      return rc;
-    }
     std::vector<float> x((size_t)kChunk * S * CAMELOT_PRED_FEATURES), yhat((size_t)kChunk * S);
     for (int64_t c0 = 0; c0 < (int64_t)cands.size() && !rc; c0 += kChunk) {
       const int64_t nc = std::min<int64_t>(kChunk, (int64_t)cands.size() - c0);
@@ -338,28 +373,17 @@ extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const ca
         for (int s = 0; s < S; ++s)
           feature_row(t, m, kinds, cu, bis, first[s], x.data() + (c * S + s) * CAMELOT_PRED_FEATURES);
       }
-      const int32_t nrows = (int32_t)(nc * S);
-      camelot_predictor_standardize(x.data(), nrows, mean, std);
-      rc = h2d(dx, x.data(), (size_t)nrows * CAMELOT_PRED_FEATURES * sizeof(float));
-      if (!rc) {
-        hipStream_t s = mem_stream();
-        hipLaunchKernelGGL(camelot_pred_forward, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, params,
-                           (const float*)dx, (int)nrows, dy);
-        if (hipGetLastError() != hipSuccess) rc = fail(CAMELOT_EDEVICE, "predictor forward launch failed");
-        if (!rc) rc = d2h(yhat.data(), dy, (size_t)nrows * sizeof(float));
-      }
+      rc = pred.predict(x.data(), (int32_t)(nc * S), yhat.data());
       for (int64_t c = 0; c < nc && !rc; ++c) {
         const Cand& cd = cands[c0 + c];
         for (int s = 0; s < S; ++s) {
-          // the network predicts the log of the co-location slowdown over the solo latency
+          // the predictor gives the log of the co-location slowdown over the solo latency
           const double y = std::max(-10.0, std::min<double>(yhat[c * S + s], 10.0));
           const double solo = (double)p->lat_ns[((int64_t)s * K + cd.k[s]) * p->n_batches + cd.bi];
           L[(c0 + c) * S + s] = std::max<int64_t>(1, (int64_t)std::ceil(solo * std::exp(y)));
         }
       }
     }
-    dfree(dx);
-    dfree(dy);
     if (rc) return rc;
   }
   // exact selection with the predicted integer latencies (rules of camelot_alloc_peak)
@@ -415,4 +439,26 @@ extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const ca
   if (lat_pred_ns)
     for (int s = 0; s < S; ++s) lat_pred_ns[s] = best_lat[s];
   return CAMELOT_OK;
+}
+}  // namespace
+
+extern "C" int32_t camelot_alloc_peak_learned(const camelot_problem* p, const camelot_solo_tables* t,
+                                              const float* params, const float* mean, const float* std,
+                                              camelot_alloc* out, int64_t* lat_pred_ns) {
+  clear_error();
+  if (!p || !params || !mean || !std || !out) return fail(CAMELOT_EINVAL, "bad learned allocation arguments");
+  NetPredictor net;
+  net.params = params;
+  net.mean = mean;
+  net.std = std;
+  return alloc_peak_predicted(p, t, net, out, lat_pred_ns);
+}
+
+extern "C" int32_t camelot_alloc_peak_dt(const camelot_problem* p, const camelot_solo_tables* t, const camelot_dt* dt,
+                                         camelot_alloc* out, int64_t* lat_pred_ns) {
+  clear_error();
+  if (!p || !dt || !out) return fail(CAMELOT_EINVAL, "bad tree allocation arguments");
+  TreePredictor tree;
+  tree.dt = dt;
+  return alloc_peak_predicted(p, t, tree, out, lat_pred_ns);
 }

@@ -144,3 +144,73 @@ def test_library_rejects_bad_input():
     xn[1, 1] = np.nan
     with pytest.raises(cm.CamelotError):
         cm.camelot_dt_fit(xn, y, 3, 1)
+
+
+# ---------------------------------------------------------------- the tree as the allocator's predictor
+def test_tree_allocator_matches_brute_force():
+    """camelot_alloc_peak_dt against a brute force written from Eq. 1: every candidate
+    (batch, N_i, share_i) in lexicographic order, each stage's latency its solo
+    latency times exp(the oracle tree's prediction from the candidate's co-location
+    features), the most throughput, then fewer CUs, then less latency, the first
+    candidate on a full tie."""
+    import math
+    from fractions import Fraction
+
+    g = G.rng("dtree", 30)
+    S, step, cu_total, batches = 2, 8, 32, [1, 2, 4]
+    K, nb = cu_total // step, len(batches)
+    lat = g.integers(5_000, 200_000, (S, K, nb)).astype(np.int64)
+    lat[1, 0, 2] = 0                                  # an unmeasured point is skipped
+    hbm = g.uniform(0, 1, (S, K, nb)).astype(np.float32)
+    mfma = g.uniform(0, 1, (S, K, nb)).astype(np.float32)
+    tabs = cm.SoloTablesArrays(step, batches, hbm, mfma)
+    prob = cm.ProblemArrays(cu_total=cu_total, cu_step=step, max_instances=4, max_inst_per_stage=3,
+                            batches=batches, qos_ns=400_000, hbm_bytes_budget=1 << 62, hbm_bw_budget=1 << 62,
+                            lat_ns=lat, bw_bps=np.zeros_like(lat), mem_bytes=np.zeros((S, nb), np.int64),
+                            inst_max=[1, 3])
+    # a tree fitted to random features -> log slowdowns in [0, 1)
+    xt = g.uniform(0, 1, (300, 16)).astype(np.float32)
+    yt = g.uniform(0, 1, 300).astype(np.float32)
+    tree = cm.camelot_dt_fit(xt, yt, 5, 4)
+    otree = OD.fit(xt, yt, 5, 4)
+
+    best = None
+    for bi, b in enumerate(batches):
+        nmax = [1, 3]
+        for n0 in range(1, nmax[0] + 1):
+            for k0 in range(K):
+                cu0 = n0 * (k0 + 1) * step
+                if cu0 > cu_total:
+                    break
+                if lat[0, k0, bi] <= 0:
+                    continue
+                for n1 in range(1, nmax[1] + 1):
+                    if n0 + n1 > 4:
+                        break
+                    for k1 in range(K):
+                        cu = cu0 + n1 * (k1 + 1) * step
+                        if cu > cu_total:
+                            break
+                        if lat[1, k1, bi] <= 0:
+                            continue
+                        kinds = [0] * n0 + [1] * n1
+                        cus = [(k0 + 1) * step] * n0 + [(k1 + 1) * step] * n1
+                        f = cm.camelot_predictor_features(tabs, kinds, cus, [bi] * (n0 + n1))
+                        yp = OD.predict(otree, f[[0, n0]])
+                        L = []
+                        for s, k in ((0, k0), (1, k1)):
+                            y = max(-10.0, min(float(yp[s]), 10.0))
+                            L.append(max(1, math.ceil(float(lat[s, k, bi]) * math.exp(y))))
+                        tot = sum(L)
+                        if tot > 400_000:
+                            continue
+                        thr = min(Fraction(n * b * 10**9, l) for n, l in ((n0, L[0]), (n1, L[1])))
+                        key = (thr, -cu, -tot)
+                        if best is None or key > best[0]:
+                            best = (key, bi, [n0, n1], [(k0 + 1) * step, (k1 + 1) * step], L)
+    a, lp = cm.camelot_alloc_peak_dt(prob, tabs, tree)
+    assert best is not None and a is not None
+    d = a.as_dict()
+    assert (d["batch_index"], d["n"][:S], d["cu"][:S]) == (best[1], best[2], best[3])
+    assert Fraction(d["thr_num"], d["thr_den"]) == best[0][0]
+    assert list(lp) == best[4]
