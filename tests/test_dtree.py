@@ -214,3 +214,17 @@ def test_tree_allocator_matches_brute_force():
     assert (d["batch_index"], d["n"][:S], d["cu"][:S]) == (best[1], best[2], best[3])
     assert Fraction(d["thr_num"], d["thr_den"]) == best[0][0]
     assert list(lp) == best[4]
+
+
+def test_tree_allocator_infeasible_and_predict_empty():
+    g = G.rng("dtree", 31)
+    S, step, batches = 2, 8, [1, 2]
+    lat = g.integers(5_000, 20_000, (S, 4, 2)).astype(np.int64)
+    tabs = cm.SoloTablesArrays(step, batches, np.zeros((S, 4, 2), np.float32), np.zeros((S, 4, 2), np.float32))
+    tree = cm.camelot_dt_fit(g.uniform(0, 1, (20, 16)).astype(np.float32), np.zeros(20, np.float32), 3, 1)
+    prob = cm.ProblemArrays(cu_total=32, cu_step=step, max_instances=2, max_inst_per_stage=1, batches=batches,
+                            qos_ns=1_000, hbm_bytes_budget=1 << 62, hbm_bw_budget=1 << 62, lat_ns=lat,
+                            bw_bps=np.zeros_like(lat), mem_bytes=np.zeros((S, 2), np.int64))
+    a, lp = cm.camelot_alloc_peak_dt(prob, tabs, tree)      # no candidate meets a 1 us QoS
+    assert a is None and lp is None
+    assert tree.predict(np.zeros((0, 16), np.float32)).shape == (0,)
