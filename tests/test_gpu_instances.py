@@ -98,3 +98,44 @@ def test_c0_host_ingest_unaffected_by_instance_field(torch, cm):
     finally:
         cm.camelot_pipeline_destroy(p)
     assert [r.query_id for r in res] == list(range(1, 9))
+
+
+def run_c1_full_batches(torch, cm, n_inst, shares, n=768):
+    """Every request arrives at once, batches of 128 rows: the MLP worker forms the
+    next batch while the current one runs; on 32-CU shares the first layer rounds
+    its rows into fragment order in a pass of its own."""
+    ws, d_ws, stages = c1_stages(torch)
+    audio = G.c1_audio(n, seed=41)
+    da = to_dev(torch, audio)
+    torch.cuda.synchronize()
+    log(f"c1 full batches n_inst={n_inst} shares={shares}")
+    cfg = cm.pipeline_config(stages, shares, max_batch=128, batch_target=128, ring_depth=max(4, 2 * n_inst[1]),
+                             ingest=cm.INGEST_REPLAY, idle_timeout_ns=5_000_000_000, n_inst=n_inst,
+                             egress_capacity=4096)
+    p = cm.camelot_pipeline_create(cfg)
+    try:
+        cm.camelot_pipeline_replay(p, np.arange(1, n + 1), np.ones(n), np.zeros(n, np.int64), np.arange(n),
+                                   da.data_ptr(), n)
+        res = drain_all(cm, p, n)
+        stats = cm.camelot_pipeline_stats_get(p)
+    finally:
+        und = cm.camelot_pipeline_destroy(p)
+    assert und == 0 and len(res) == n
+    check_common(cm, res, stats, list(range(1, n + 1)), 3)
+    vals = np.array([list(r.val[:10]) for r in res], dtype=np.float32)
+    idx = np.array([list(r.idx[:10]) for r in res])
+    return ws, audio, vals, idx
+
+
+def test_mlp_full_batches_same_bits_on_both_first_layer_paths(torch, cm):
+    # 32-CU MLP shares: the first layer rounds its rows in a pass of its own; a
+    # 64-CU share: the units round them; two instances: batches alternate
+    ws, audio, v32, i32 = run_c1_full_batches(torch, cm, (1, 1, 1), (32, 32, 32))
+    _, _, v2x, i2x = run_c1_full_batches(torch, cm, (1, 2, 1), (32, 32, 32))
+    _, _, v64, i64 = run_c1_full_batches(torch, cm, (1, 1, 1), (32, 64, 32))
+    for v, i in ((v2x, i2x), (v64, i64)):
+        assert np.array_equal(v.view(np.uint32), v32.view(np.uint32))
+        assert np.array_equal(i, i32)
+    scores = O.mlp_bf16(O.log_mel(audio[:64]), ws)
+    _, rval = O.topk(scores, 10)
+    assert O.normwise_err(v32[:64].astype(np.float64), rval) <= 2e-2
