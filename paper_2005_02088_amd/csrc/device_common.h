@@ -92,6 +92,21 @@ struct DevPub {
   uint64_t pad[16];
 };
 
+// One batch's descriptor, written by the control workgroup before its broadcast.
+struct BatchDesc {
+  uint32_t stop;                  // nonzero: the workers exit with this status
+  uint32_t rows;
+  uint8_t* out;                   // payload of the output slot (ring output)
+  SlotHeader* out_hdr;            // header of the output slot (ring output)
+  uint64_t egress_base;           // egress row index of this batch's first row
+  uint64_t t_stage[2 * kMaxStages];   // stage timestamps of the batch so far
+  const uint8_t* rowptr[kMaxBatch];   // input row pointers
+  const uint8_t* rowside[kMaxBatch];  // input side bytes of each row (side_bytes > 0)
+  uint64_t row_id[kMaxBatch];         // (request id) per row
+  uint32_t row_idx[kMaxBatch];        // row index within its request
+  uint64_t row_tarr[kMaxBatch];
+};
+
 // Per-worker device control block (device memory, zeroed at creation).
 struct WorkerCtl {
   // hierarchical grid barrier: workgroup g arrives on group counter g % 8, the last
@@ -102,18 +117,9 @@ struct WorkerCtl {
   uint32_t abort;      uint32_t pad2[31];
   uint32_t diag_arrived, diag_nwg, diag_group;   // filled on a barrier timeout
   uint32_t diag_pad;
-  // batch descriptor written by the control workgroup before its broadcast
-  uint32_t d_stop;                // nonzero: the workers exit with this status
-  uint32_t d_rows;
-  uint8_t* d_out;                 // payload of the output slot (ring output)
-  SlotHeader* d_out_hdr;          // header of the output slot (ring output)
-  uint64_t d_egress_base;               // egress row index of this batch's first row
-  uint64_t d_t_stage[2 * kMaxStages];   // stage timestamps of the batch so far
-  const uint8_t* d_rowptr[kMaxBatch];   // input row pointers
-  const uint8_t* d_rowside[kMaxBatch];  // input side bytes of each row (side_bytes > 0)
-  uint64_t d_row_id[kMaxBatch];         // (request id) per row
-  uint32_t d_row_idx[kMaxBatch];        // row index within its request
-  uint64_t d_row_tarr[kMaxBatch];
+  // batch descriptors, double-buffered by the batch's number in the launch (the
+  // control workgroup writes the next batch's while the current one runs)
+  BatchDesc dd[2];
   // persistent state
   uint64_t next_seq;              // next batch sequence number
   uint64_t ingest_cursor;         // stage 0: next request to take

@@ -35,7 +35,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 // ------------------------------------------------------------------ result emit
 // Writes one result row (k indices + k values held in LDS) either into the
 // planar bench output or into the pinned egress ring. Called by a whole wave.
-__device__ __forceinline__ void emit_row(const WorkerArgs& a, WorkerCtl* ctl, int rows, int r,
+__device__ __forceinline__ void emit_row(const WorkerArgs& a, const BatchDesc* bd, int rows, int r,
                                          int k, const int32_t* idx, const float* val, int lane) {
   if (a.out_kind == kOutBench) {
     int32_t* ip = (int32_t*)a.bench_out;
@@ -46,7 +46,7 @@ __device__ __forceinline__ void emit_row(const WorkerArgs& a, WorkerCtl* ctl, in
     }
     return;
   }
-  uint64_t slot = (ctl->d_egress_base + (uint64_t)r) % (uint64_t)a.egress_cap;
+  uint64_t slot = (bd->egress_base + (uint64_t)r) % (uint64_t)a.egress_cap;
   uint8_t* rec = a.egress + slot * (uint64_t)a.rec_bytes;
   int32_t* ip = (int32_t*)(rec + sizeof(EgressRec));
   float* vp = (float*)(ip + k);
@@ -55,14 +55,14 @@ __device__ __forceinline__ void emit_row(const WorkerArgs& a, WorkerCtl* ctl, in
     vp[j] = val[j];
   }
   if (lane < 2 * kMaxStages) {
-    ((EgressRec*)rec)->t_stage[lane] = ctl->d_t_stage[lane];
+    ((EgressRec*)rec)->t_stage[lane] = bd->t_stage[lane];
   }
   if (lane == 0) {
     EgressRec* h = (EgressRec*)rec;
-    h->id = ctl->d_row_id[r];
-    h->row = ctl->d_row_idx[r];
+    h->id = bd->row_id[r];
+    h->row = bd->row_idx[r];
     h->n_out = (uint32_t)k;
-    h->t_arr = ctl->d_row_tarr[r];
+    h->t_arr = bd->row_tarr[r];
     h->t_done = now_ticks();
   }
 }
@@ -76,17 +76,18 @@ struct BatchRows {
   const uint8_t* base;          // row r at base + r * stride, or
   int64_t stride;
   const uint8_t* const* table;  // row r at table[r]
+  const BatchDesc* bd;          // the batch's descriptor (side bytes, egress records)
   __device__ __forceinline__ const uint8_t* row(int r) const {
     return base ? base + (int64_t)r * stride : table[r];
   }
 };
 
-__device__ __forceinline__ BatchRows batch_rows(const WorkerArgs& a, const WorkerCtl* ctl, uint64_t seq) {
+__device__ __forceinline__ BatchRows batch_rows(const WorkerArgs& a, const BatchDesc* bd, uint64_t seq) {
   if (a.in_kind == kInRing)
     return BatchRows{a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride + kSlotHeaderBytes,
-                     a.sp.in_row_bytes, nullptr};
-  if (a.in_kind == kInBench) return BatchRows{a.bench_in, a.in_row_stride, nullptr};
-  return BatchRows{nullptr, 0, ctl->d_rowptr};
+                     a.sp.in_row_bytes, nullptr, bd};
+  if (a.in_kind == kInBench) return BatchRows{a.bench_in, a.in_row_stride, nullptr, bd};
+  return BatchRows{nullptr, 0, bd->rowptr, bd};
 }
 
 // Workgroups that run the stage: all of them in a one-shot launch; a persistent
@@ -182,7 +183,7 @@ __device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, const Batc
       s_val[w][0] = bv;
     }
     wave_lds_sync();
-    emit_row(a, ctl, rows, r, 1, s_idx[w], s_val[w], lane);
+    emit_row(a, br.bd, rows, r, 1, s_idx[w], s_val[w], lane);
     wave_lds_sync();
   }
 }
@@ -348,7 +349,7 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& 
       topk_rounds(s, N, k, lane, s_idx[w], s_val[w]);
     }
     wave_lds_sync();
-    emit_row(a, ctl, rows, r, k, s_idx[w], s_val[w], lane);
+    emit_row(a, br.bd, rows, r, k, s_idx[w], s_val[w], lane);
     wave_lds_sync();
   }
 }
@@ -1034,7 +1035,7 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const Bat
   float* Y = (float*)out;
   for (int r = xwg(a) * kWaves + w; r < rows; r += xnwg(a) * kWaves) {
     const float* q = (const float*)br.row(r);
-    const int32_t* ids = (const int32_t*)ctl->d_rowside[r];
+    const int32_t* ids = (const int32_t*)br.bd->rowside[r];
     for (int i = lane; i < qdim; i += 64) q_s[w][i] = q[i];
     wave_lds_sync();
     for (int o = lane; o < heads * n_ids; o += 64) {
@@ -1054,13 +1055,13 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const Bat
 
 // ------------------------------------------------------------------ side bytes
 // Copies every row's side bytes from the input to the output slot's side plane.
-__device__ __forceinline__ void copy_side(const WorkerArgs& a, WorkerCtl* ctl, int rows) {
+__device__ __forceinline__ void copy_side(const WorkerArgs& a, const BatchDesc* bd, int rows) {
   if (a.side_bytes <= 0 || a.out_kind != kOutRing) return;
-  uint8_t* dst = (uint8_t*)ctl->d_out_hdr + a.out_side_off;
+  uint8_t* dst = (uint8_t*)bd->out_hdr + a.out_side_off;
   const int words = a.side_bytes >> 2;
   for (int i = xwg(a) * kThreads + threadIdx.x; i < rows * words; i += xnwg(a) * kThreads) {
     const int r = i / words, wd = i - r * words;
-    ((uint32_t*)(dst + (int64_t)r * a.side_bytes))[wd] = ((const uint32_t*)ctl->d_rowside[r])[wd];
+    ((uint32_t*)(dst + (int64_t)r * a.side_bytes))[wd] = ((const uint32_t*)bd->rowside[r])[wd];
   }
 }
 
@@ -1256,14 +1257,14 @@ __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void stage_bench(Wor
   const int tid = threadIdx.x;
   if (blockIdx.x == 0)
     for (int i = tid; i < a.bench_rows; i += kThreads) {
-      ctl->d_rowptr[i] = a.bench_in + (int64_t)i * a.in_row_stride;
-      ctl->d_rowside[i] = ctl->d_rowptr[i] + a.sp.in_row_bytes;
+      ctl->dd[0].rowptr[i] = a.bench_in + (int64_t)i * a.in_row_stride;
+      ctl->dd[0].rowside[i] = ctl->dd[0].rowptr[i] + a.sp.in_row_bytes;
     }
   if (!grid_barrier(ctl, gridDim.x, a.spin_ticks)) return;
   const uint64_t t0 = now_ticks();
   int rep = 0;
   while (rep < a.bench_reps) {
-    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, 0), a.bench_rows, a.bench_out)) return;
+    if (!exec_stage<KIND>(a, ctl, batch_rows(a, &ctl->dd[0], 0), a.bench_rows, a.bench_out)) return;
     ++rep;
     // duration mode: workgroup 0 decides for the whole grid, published by the barrier;
     // two slots by parity so a fast workgroup 0 never overwrites a decision that a
@@ -1522,6 +1523,60 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
   int exit_status = kStatusOk;
   bool pending = false;           // batch seq is already formed and staged
   bool unpublished = false;       // pb holds a finished batch not yet published
+  bool desc_ready = false;        // batch seq's descriptor is already written
+  // The descriptor of batch q (staged in s) into slot `slot` (the batch's number in
+  // the launch mod 2), and its output slot's header; st != 0: only the stop.
+  auto write_desc = [&](uint32_t slot, uint64_t q, int st) {
+    BatchDesc& d = ctl->dd[slot];
+    if (st == 0) {
+      const int nreq = s.acq[1], rows = s.acq[2];
+      // per-row descriptors: input row pointers (ingest), side bytes, and the
+      // request of each row (egress records)
+      const uint8_t* in_payload = si > 0 ? a.in_ring + (q % (uint64_t)a.in_depth) * (uint64_t)a.in_stride +
+                                               kSlotHeaderBytes
+                                         : nullptr;
+      const uint8_t* in_hdr = si > 0 ? in_payload - kSlotHeaderBytes : nullptr;
+      for (int r = tid; r < nreq; r += kThreads) {
+        for (uint32_t j = 0; j < s.rows[r]; ++j) {
+          const uint32_t row = s.rbase[r] + j;
+          const uint8_t* rp = si > 0 ? in_payload + (int64_t)row * a.sp.in_row_bytes
+                                     : s.ptr[r] + (int64_t)j * a.in_row_stride;
+          if (si == 0) d.rowptr[row] = rp;
+          if (side_ptrs)
+            d.rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
+                                    : rp + a.sp.in_row_bytes;
+          if (a.out_kind == kOutEgress) {
+            d.row_id[row] = s.id[r];
+            d.row_idx[row] = j;
+            d.row_tarr[row] = s.tarr[r];
+          }
+        }
+      }
+      // this stage's start time is filled in at the broadcast
+      if (tid < 2 * kMaxStages && tid != 2 * si) d.t_stage[tid] = s.t_stage[tid];
+      if (a.out_kind == kOutRing) {
+        SlotHeader* oh = (SlotHeader*)(a.out_ring + (q % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
+        for (int r = tid; r < nreq; r += kThreads) {
+          oh->req_id[r] = s.id[r];
+          oh->req_tarr[r] = s.tarr[r];
+          oh->req_rows[r] = s.rows[r];
+        }
+        if (tid < 2 * kMaxStages && tid != 2 * si) oh->t_stage[tid] = s.t_stage[tid];
+        if (tid == 0) {
+          oh->seq = q;
+          oh->n_req = (uint32_t)nreq;
+          oh->n_rows = (uint32_t)rows;
+          d.out = (uint8_t*)oh + kSlotHeaderBytes;
+          d.out_hdr = oh;
+        }
+      } else if (tid == 0) {
+        d.egress_base = s.egress_base;
+        d.out = nullptr;
+      }
+      if (tid == 0) d.rows = (uint32_t)rows;
+    }
+    if (tid == 0) d.stop = (uint32_t)st;
+  };
   for (;;) {
     const uint64_t t_top = now_ticks();
     int st = pending ? 0 : kAcqNotReady;
@@ -1536,56 +1591,21 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
       }
       st = form_batch(a, ctl, seq, s_t0, attempt == 0, s);
     }
-    pending = false;
     uint64_t t_start = 0;
+    const uint32_t slot = issued & 1u;
+    if (!desc_ready) write_desc(slot, seq, st);
+    pending = false;
+    desc_ready = false;
     if (st == 0) {
-      const int nreq = s.acq[1], rows = s.acq[2];
+      // the batch's start time, into its descriptor and its output slot's header
       t_start = now_ticks();
-      // per-row descriptors: input row pointers (ingest), side bytes, and the
-      // request of each row (egress records)
-      const uint8_t* in_payload = si > 0 ? a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride +
-                                               kSlotHeaderBytes
-                                         : nullptr;
-      const uint8_t* in_hdr = si > 0 ? in_payload - kSlotHeaderBytes : nullptr;
-      for (int q = tid; q < nreq; q += kThreads) {
-        for (uint32_t j = 0; j < s.rows[q]; ++j) {
-          const uint32_t row = s.rbase[q] + j;
-          const uint8_t* rp = si > 0 ? in_payload + (int64_t)row * a.sp.in_row_bytes
-                                     : s.ptr[q] + (int64_t)j * a.in_row_stride;
-          if (si == 0) ctl->d_rowptr[row] = rp;
-          if (side_ptrs)
-            ctl->d_rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
-                                         : rp + a.sp.in_row_bytes;
-          if (a.out_kind == kOutEgress) {
-            ctl->d_row_id[row] = s.id[q];
-            ctl->d_row_idx[row] = j;
-            ctl->d_row_tarr[row] = s.tarr[q];
-          }
-        }
+      if (tid == 0) {
+        ctl->dd[slot].t_stage[2 * si] = t_start;
+        if (a.out_kind == kOutRing)
+          ((SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride))->t_stage[2 * si] =
+              t_start;
       }
-      if (tid < 2 * kMaxStages) ctl->d_t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
-      if (a.out_kind == kOutRing) {
-        SlotHeader* oh = (SlotHeader*)(a.out_ring + (seq % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
-        for (int q = tid; q < nreq; q += kThreads) {
-          oh->req_id[q] = s.id[q];
-          oh->req_tarr[q] = s.tarr[q];
-          oh->req_rows[q] = s.rows[q];
-        }
-        if (tid < 2 * kMaxStages) oh->t_stage[tid] = tid == 2 * si ? t_start : s.t_stage[tid];
-        if (tid == 0) {
-          oh->seq = seq;
-          oh->n_req = (uint32_t)nreq;
-          oh->n_rows = (uint32_t)rows;
-          ctl->d_out = (uint8_t*)oh + kSlotHeaderBytes;
-          ctl->d_out_hdr = oh;
-        }
-      } else if (tid == 0) {
-        ctl->d_egress_base = s.egress_base;
-        ctl->d_out = nullptr;
-      }
-      if (tid == 0) ctl->d_rows = (uint32_t)rows;
     }
-    if (tid == 0) ctl->d_stop = (uint32_t)st;
     // broadcast: the batch descriptor (or the stop) is in place
     wg_barrier_stores_done();
     if (tid == 0) {
@@ -1649,7 +1669,15 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
       f = s_flag;
       __syncthreads();
       if (f != 2 && f != 0) break;
-      if (f == 2) pending = form_batch(a, ctl, seq + (uint64_t)a.n_inst, s_t0, true, s) == 0;
+      if (f == 2) {
+        pending = form_batch(a, ctl, seq + (uint64_t)a.n_inst, s_t0, true, s) == 0;
+        // the next batch's descriptor now, into the other slot (the batch two back,
+        // which used it, has finished)
+        if (pending) {
+          write_desc(issued & 1u, seq + (uint64_t)a.n_inst, 0);
+          desc_ready = true;
+        }
+      }
     }
     if (f < 0) { exit_status = kStatusTimeout; break; }
     if (tid == 0) {
@@ -1690,21 +1718,23 @@ __device__ __forceinline__ void worker_compute(const WorkerArgs& a) {
   const uint32_t g = (uint32_t)xwg(a) & 7u;
   const bool sys = a.out_kind == kOutEgress || a.out_state_sys != 0;
   uint64_t seq = ctl->next_seq;
+  uint32_t c = 0;                 // batches started in this launch: descriptor slot c mod 2
   for (;;) {
     // the control workgroup may wait for input (up to the idle limit) and then for
     // output space
     if (!wait_go(ctl, (uint32_t)(seq + 1), 2 * a.idle_ticks + a.spin_ticks)) break;
     // a host-staged input slot was written by a DMA copy: acquire at system scope
     if (a.in_state_sys) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    const BatchDesc* bd = &ctl->dd[c & 1u];
     // the descriptor is the same for every lane: kept in scalar registers
-    const uint32_t stop = __builtin_amdgcn_readfirstlane(ctl->d_stop);
+    const uint32_t stop = __builtin_amdgcn_readfirstlane(bd->stop);
     if (stop) break;
-    const int rows = __builtin_amdgcn_readfirstlane((int)ctl->d_rows);
-    const uint64_t outp = (uint64_t)ctl->d_out;
+    const int rows = __builtin_amdgcn_readfirstlane((int)bd->rows);
+    const uint64_t outp = (uint64_t)bd->out;
     uint8_t* const out = (uint8_t*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(outp >> 32)) << 32) |
                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)outp));
-    if (!exec_stage<KIND>(a, ctl, batch_rows(a, ctl, seq), rows, out)) break;
-    copy_side(a, ctl, rows);
+    if (!exec_stage<KIND>(a, ctl, batch_rows(a, bd, seq), rows, out)) break;
+    copy_side(a, bd, rows);
     wg_barrier_stores_done();
     if (tid == 0) {
       if (sys) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
@@ -1712,6 +1742,7 @@ __device__ __forceinline__ void worker_compute(const WorkerArgs& a) {
       __hip_atomic_fetch_add(&ctl->done[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     seq += (uint64_t)a.n_inst;
+    ++c;
   }
 }
 
