@@ -5,14 +5,14 @@
  * What the library implements (Zhang et al., "Towards QoS-Aware and
  * Resource-Efficient GPU Microservices Based on Spatial Multitasking GPUs In
  * Datacenters", arXiv 2005.02088):
- *   - global-memory communication between pipeline stages on one GPU (Section IV-B):
+ *   - global-memory communication between pipeline stages on one GPU (Section VI-B):
  *     here a device-global ring buffer with doorbell flags between persistent stage
  *     workers, one copy of the data, no host round trip; the host-staged
- *     (device->host->device) path of Section IV-A is kept as the baseline;
- *   - the allocation problems of Section V: maximise the supported peak load under
+ *     (device->host->device) path of Section VI-A is kept as the baseline;
+ *   - the allocation problems of Section VII: maximise the supported peak load under
  *     the QoS target (Eq. 1) and minimise the computational resources at low load
  *     (Eq. 3), solved exactly over a measured integer profile table;
- *   - the query flow of Section III-B: a wait queue, batch formation, per-stage
+ *   - the query flow of Section V-B: a wait queue, batch formation, per-stage
  *     processing on the stage's CU share.
  *
  * Conventions (every entry point):
@@ -69,7 +69,7 @@ typedef struct {
 int32_t camelot_device_query(camelot_device_info* out);
 
 /* ------------------------------------------------------------------ allocation
- * Section V, Eq. 1 and Eq. 3 over an integer profile table.
+ * Section VII, Eq. 1 and Eq. 3 over an integer profile table.
  *
  * Decision variables per stage i: instance count N_i (1..max_inst_per_stage, or
  * 1..inst_max[i] when inst_max is given) and
@@ -217,11 +217,17 @@ int32_t camelot_stage_run(const camelot_stage_desc* stage, const void* in, void*
                           double* ns_per_rep, double* device_ns_per_rep);
 
 /* ------------------------------------------------------------------ pipelines
- * A pipeline is a chain of stages, each run by one persistent worker kernel on its
- * own CU-masked stream (stage i on cu[i] CUs). Stage i hands its batch to stage
- * i+1 through a device-global ring of ring_depth slots with doorbells
- * (CAMELOT_HANDOFF_DEVICE) or, for the baseline, by a device->pinned host->device
- * copy per batch driven by a host thread (CAMELOT_HANDOFF_HOST).
+ * The query flow of Section V-B (queries wait in a queue, are batched, and pass
+ * through the microservice stages in order, each stage on its own share of the
+ * GPU) with the communication of Section VI: a pipeline is a chain of stages, each
+ * run by one persistent worker kernel on its own CU-masked stream (stage i on
+ * cu[i] CUs). Stage i hands its batch to stage i+1 through a device-global ring of
+ * ring_depth slots with doorbells, one copy of the data in device memory
+ * (CAMELOT_HANDOFF_DEVICE, Section VI-B) or, for the baseline, by a device->pinned
+ * host->device copy per batch driven by a host thread (CAMELOT_HANDOFF_HOST, the
+ * main-memory communication of Section VI-A). The CU shares, instance counts and
+ * batch size come from an allocation (camelot_alloc: cu[], n[], batch), copied into
+ * cu[], n_inst[] and max_batch / batch_target here.
  *
  * Queries arrive as requests of 1..max_rows_per_request rows. Stage 0 forms a
  * batch from whole waiting requests in arrival order, at most max_batch rows,
@@ -281,6 +287,12 @@ int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, camelot_pipe
 /* HBM bytes the pipeline holds (rings, scratch, control; weights are borrowed and
  * not counted). */
 int64_t camelot_pipeline_footprint(const camelot_pipeline* p);
+
+/* The device-clock time (ns) of the pipeline's epoch, the zero of its result
+ * timestamps: the create call (host ingest) or the workers' start (replay ingest;
+ * EAGAIN until the replay has started). Pipelines on one device share the clock, so
+ * epoch + t_ns puts the results of several pipelines on one time line. */
+int32_t camelot_pipeline_epoch_ns(const camelot_pipeline* p, int64_t* epoch_ns);
 
 /* Host ingest. Copies `rows` rows of payload (host pointer, rows * row_bytes_in of
  * stage 0) before returning. query_id must exceed every id submitted before on this
@@ -352,10 +364,10 @@ int32_t camelot_pipeline_destroy(camelot_pipeline* p, uint64_t* undelivered);
 /* ------------------------------------------------------------------ serving: admission
  * A server is a set of pipelines co-located on one GPU under one HBM budget (F of
  * Eq. 1 / Eq. 3; global memory capacity is the binding resource for co-location,
- * Section III-C). A pipeline is admitted only if its footprint - the library's
+ * Section IV-C). A pipeline is admitted only if its footprint - the library's
  * rings, scratch and control (camelot_pipeline_footprint) plus every weight buffer
  * not already held by an admitted pipeline - fits what is left. Weight buffers are
- * identified by pointer, so instances sharing a model count it once (Section V-D).
+ * identified by pointer, so instances sharing a model count it once (Section VII-D).
  * Admission does not place CUs: the configs' cu_offset/cu ranges must not overlap
  * those of admitted pipelines (EINVAL otherwise). */
 typedef struct camelot_server camelot_server;
@@ -382,7 +394,7 @@ int32_t camelot_stage_kernel_info(int32_t kind, int32_t one_shot, int32_t* regs,
                                   int32_t* fits);
 
 /* ------------------------------------------------------------------ handoff benchmark
- * Section IV-B's claim, measured: a producer worker on cu_producer CUs writes
+ * Section VI-B's claim, measured: a producer worker on cu_producer CUs writes
  * n_slots_total slots of slot_bytes into a device ring of depth slots; a consumer
  * worker on the next cu_consumer CUs waits on each slot's doorbell, reads every
  * word into a checksum and frees the slot. Both run concurrently.
@@ -400,7 +412,7 @@ int32_t camelot_handoff_expected(int64_t slot_bytes, int64_t n_slots_total,
                                  uint64_t* sum, uint64_t* xr);
 
 /* ------------------------------------------------------------------ predictor
- * Learned contention predictor (replaces Section V-A's per-microservice model):
+ * Learned contention predictor (replaces Section VII-A's per-microservice model):
  * MLP 16 -> 64 (ReLU) -> 64 (ReLU) -> 1, FP32, predicting ln(latency ns).
  * Parameters live in one device buffer of CAMELOT_PRED_NPARAMS floats in the order
  * W1[16][64], b1[64], W2[64][64], b2[64], W3[64][1], b3[1] (weights [in, out]).
@@ -435,7 +447,7 @@ int32_t camelot_predictor_train(float* params, float* m1, float* m2, int32_t* t,
 
 /* ------------------------------------------------------------------ contention profiles
  * The paper profiles each microservice alone and observes that co-located stages
- * run slower than their solo profiles (Section III-A, the balanced deployment
+ * run slower than their solo profiles (Section IV-A, the balanced deployment
  * policy). These calls measure that contention.
  *
  * camelot_stage_corun: runs n stages at once, stage j on n_cus[j] CUs from mask bit
@@ -516,7 +528,7 @@ int32_t camelot_alloc_peak_learned(const camelot_problem* problem, const camelot
 
 /* ---------------------------------------------------------------- decision tree */
 /* Decision-tree regressor, the kind of latency predictor the paper fits to its
- * co-location profiles (Section V-A). CART regression with the squared error: a node
+ * co-location profiles (Section VII-A). CART regression with the squared error: a node
  * splits on the feature and threshold (midpoint between consecutive distinct values;
  * x <= thr goes left) that maximise sum_L^2/n_L + sum_R^2/n_R, both children keeping
  * at least min_leaf samples, if that lowers the error; otherwise, or at max_depth,

@@ -1,6 +1,6 @@
 """Brute-force solver of Camelot's two allocation problems (test infrastructure only).
 
-Max peak load (Section V-B, Eq. 1): choose a batch size b, an instance count N_i
+Max peak load (Section VII-B, Eq. 1): choose a batch size b, an instance count N_i
 and a CU share p_i per stage to maximise the pipeline throughput
     T = min_i N_i * b / L_i(p_i, b)          (queries/s, L_i in seconds)
 subject to
@@ -12,7 +12,7 @@ subject to
     sum_i N_i M(i, b) <= F                    (global-memory capacity)
     W(b) + sum_i L_i(p_i, b) <= QoS           (latency target)
 
-Minimum resource at load lambda (Section V-C, Eq. 3): minimise sum_i N_i p_i under
+Minimum resource at load lambda (Section VII-C, Eq. 3): minimise sum_i N_i p_i under
 the same constraints plus T >= lambda.
 
 Readings where the paper is loose (each listed in the design notes):

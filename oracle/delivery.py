@@ -11,7 +11,7 @@ The hash is the output function of SplitMix64 (Steele, Lea and Flood, "Fast
 splittable pseudorandom number generators", OOPSLA 2014) applied to
 id + 0x9E3779B97F4A7C15, i.e. the first output of a SplitMix64 generator seeded
 with the id. Pinned by the generator's published first outputs
-(tests/test_oracle_delivery.py).
+(tests/test_oracle_misc.py, fixture tests/golden/splitmix64.txt).
 """
 from __future__ import annotations
 

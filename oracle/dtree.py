@@ -1,7 +1,7 @@
 """Decision-tree regressor, plain NumPy (test infrastructure only).
 
 The paper fits a decision tree to its co-location profiles to predict a stage's
-latency under contention (Section V-A). This is the regression tree of CART
+latency under contention (Section VII-A). This is the regression tree of CART
 (Breiman, Friedman, Olshen & Stone, 1984) with the squared error, written from that
 definition:
 

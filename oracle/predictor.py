@@ -1,7 +1,7 @@
 """FP64 learned contention predictor: forward, backward and Adam (test infrastructure).
 
 The paper predicts each microservice's duration from its batch size and compute
-share with offline-trained models (Section V-A, where a decision tree is chosen
+share with offline-trained models (Section VII-A, where a decision tree is chosen
 among linear regression, decision tree and random forest). The learned
 predictor here replaces that model with a small MLP
     16 -> 64 (ReLU) -> 64 (ReLU) -> 1 (linear)
@@ -12,8 +12,12 @@ Loss: L = (1/M) sum_r (yhat_r - y_r)^2 over a minibatch of M rows.
 Adam: Kingma & Ba (2015), bias-corrected moments, beta1 0.9, beta2 0.999,
 eps 1e-8.
 
-Pinned by central finite differences of the loss (tests/test_oracle_predictor.py)
-and by Adam's first step, whose size is lr * sign(g) up to eps by construction.
+Pinned (tests/test_oracle_misc.py) by central finite differences of the loss, by
+Adam's first step (lr * sign(g) up to eps), and by hand-derived values of the
+second and third steps for scalar gradient sequences (g = 1 then -1: the second
+bias-corrected second moment is exactly 1 and the step is -lr/19; g = 1 then 0:
+the step is lr * (9/19) / sqrt(999/1999)), which fix beta1, beta2 and both bias
+corrections beyond t = 1.
 """
 from __future__ import annotations
 

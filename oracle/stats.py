@@ -1,7 +1,7 @@
 """Latency statistics and timing invariants (test infrastructure only).
 
 Tail latency is the quantity the paper's QoS target bounds (the 99%-ile latency,
-Section VI-A). Percentiles use the nearest-rank definition: the q-quantile of n
+Section VIII-A). Percentiles use the nearest-rank definition: the q-quantile of n
 sorted values is the ceil(q n)-th smallest.
 
 Per query, with arrival a, stage i start s_i / end e_i and completion d:

@@ -131,6 +131,7 @@ _SIGS = {
                                       C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "camelot_pipeline_create": (C.c_int32, [C.POINTER(PipelineConfig), C.POINTER(_P)]),
     "camelot_pipeline_footprint": (C.c_int64, [_P]),
+    "camelot_pipeline_epoch_ns": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
     "camelot_pipeline_submit": (C.c_int32, [_P, C.c_uint64, _P, C.c_int32]),
     "camelot_pipeline_drain": (C.c_int32, [_P, C.POINTER(Result), C.c_int32, C.POINTER(C.c_int32),
                                            C.c_int64]),
@@ -326,6 +327,12 @@ def camelot_pipeline_create(cfg: PipelineConfig) -> int:
 
 def camelot_pipeline_footprint(p: int) -> int:
     return _lib.camelot_pipeline_footprint(p)
+
+
+def camelot_pipeline_epoch_ns(p: int) -> int:
+    e = C.c_int64()
+    _check(_lib.camelot_pipeline_epoch_ns(p, C.byref(e)))
+    return e.value
 
 
 def camelot_pipeline_submit(p: int, query_id: int, payload: np.ndarray, rows: int) -> int:

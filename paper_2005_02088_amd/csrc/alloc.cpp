@@ -1,4 +1,4 @@
-// Exact solver of the allocation problems of Section V over an integer profile
+// Exact solver of the allocation problems of Section VII over an integer profile
 // table: Eq. 1 (maximise the pipeline throughput under the QoS target and the
 // resource constraints) and Eq. 3 (minimise the computational resources while the
 // throughput reaches a given load).

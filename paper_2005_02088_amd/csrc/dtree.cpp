@@ -1,5 +1,5 @@
 // Decision-tree regressor: the kind of latency predictor the paper trains on its
-// co-location profiles (Section V-A), here beside the learned MLP predictor.
+// co-location profiles (Section VII-A), here beside the learned MLP predictor.
 // CART regression (Breiman et al., 1984) with the squared error: a node holding
 // samples S splits on the feature and threshold that maximise
 //   sum_L^2 / n_L + sum_R^2 / n_R

@@ -1,4 +1,4 @@
-// Device-global handoff benchmark (the global-memory communication of Section IV-B
+// Device-global handoff benchmark (the global-memory communication of Section VI-B
 // measured on its own): a persistent producer grid writes ring slots and rings a
 // doorbell per (slot, workgroup) channel; a persistent consumer grid on other CUs
 // waits on each doorbell, folds every 32-bit word of the chunk into a checksum and

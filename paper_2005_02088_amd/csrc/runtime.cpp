@@ -536,6 +536,7 @@ struct camelot_pipeline {
   DevInfo dev;
   int S = 0;
   int64_t in_b[kMaxStages] = {0}, out_b[kMaxStages] = {0};
+  int64_t side_off[kMaxStages] = {0};  // offset of boundary i's side plane in a slot
   int k_out = 1;
   // workers: the instances of every stage, stage by stage (worker w runs stage
   // w_stage[w]; stage i's instances are workers first_w[i] .. first_w[i] + n_inst[i] - 1)
@@ -634,8 +635,12 @@ static void relay_loop(camelot_pipeline* p, int i) {
       std::this_thread::yield();
     }
     const uint64_t rows = __atomic_load_n(&sa[D + slot], __ATOMIC_ACQUIRE);
+    // the slot's header and rows, then its side plane (each row's side bytes)
     const int64_t bytes = kSlotHeaderBytes + (int64_t)rows * p->out_b[i];
+    const int64_t soff = p->side_off[i], sbytes = (int64_t)rows * p->cfg.side_bytes;
     if (hipMemcpyAsync(p->staging[i], A.buf + slot * A.stride, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (sbytes > 0 && hipMemcpyAsync(p->staging[i] + soff, A.buf + slot * A.stride + soff, sbytes,
+                                      hipMemcpyDeviceToHost, s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess)
       return;
     __atomic_store_n(&sa[slot], 2 * seq + 2, __ATOMIC_RELEASE);
@@ -645,6 +650,8 @@ static void relay_loop(camelot_pipeline* p, int i) {
       std::this_thread::yield();
     }
     if (hipMemcpyAsync(B.buf + slot * B.stride, p->staging[i], bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (sbytes > 0 && hipMemcpyAsync(B.buf + slot * B.stride + soff, p->staging[i] + soff, sbytes,
+                                      hipMemcpyHostToDevice, s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess)
       return;
     __atomic_store_n(&sb[slot], 2 * seq + 1, __ATOMIC_RELEASE);
@@ -755,7 +762,7 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
   const int64_t side = cfg->side_bytes;
   int64_t side_off[kMaxStages] = {0};
   for (int i = 0; i + 1 < S; ++i) {
-    side_off[i] = kSlotHeaderBytes + round_up((int64_t)cfg->max_batch * p->out_b[i], 256);
+    side_off[i] = p->side_off[i] = kSlotHeaderBytes + round_up((int64_t)cfg->max_batch * p->out_b[i], 256);
     stride[i] = side_off[i] + round_up((int64_t)cfg->max_batch * side, 256);
     fp += (host_handoff ? 2 : 1) * (D * stride[i] + (host_handoff ? 0 : round_up(8LL * D, 256)));
   }
@@ -921,6 +928,18 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
 }
 
 extern "C" int64_t camelot_pipeline_footprint(const camelot_pipeline* p) { return p ? p->footprint : -1; }
+
+extern "C" int32_t camelot_pipeline_epoch_ns(const camelot_pipeline* p, int64_t* epoch_ns) {
+  clear_error();
+  if (!p || !epoch_ns) return fail(CAMELOT_EINVAL, "bad epoch arguments");
+  int64_t ticks = p->epoch_ticks;
+  if (p->cfg.ingest == CAMELOT_INGEST_REPLAY) {
+    ticks = (int64_t)__atomic_load_n(&p->pub->t0, __ATOMIC_ACQUIRE);
+    if (!p->launched || ticks == 0) return fail(CAMELOT_EAGAIN, "the replay has not started");
+  }
+  *epoch_ns = (int64_t)ticks_to_ns(ticks, p->dev.wclk_hz);
+  return CAMELOT_OK;
+}
 
 static int32_t worker_error(camelot_pipeline* p) {
   for (int w = 0; w < p->NW; ++w) {

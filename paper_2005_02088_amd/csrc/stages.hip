@@ -1,12 +1,13 @@
 // Stage kernels and the persistent stage worker.
 //
-// One worker kernel is launched per stage on the stage's CU-masked stream with a
-// grid of kWgPerCu workgroups per CU of its share; every workgroup stays resident
-// for the life of the pipeline. Workgroup 0 runs the control side (batch
-// formation or doorbell wait, header copy, publication); all workgroups run the
-// stage's compute, separated by grid barriers where a stage has dependent phases.
-// Every wait is bounded (idle limit between batches, spin limit inside a batch),
-// so every wave reaches the kernel's end.
+// One worker kernel is launched per stage instance on its CU-masked stream with one
+// compute workgroup per CU of its share plus one control workgroup, the last; every
+// workgroup stays resident for the life of the pipeline. The control workgroup
+// forms batches (ingest or input doorbell), writes and broadcasts each batch's
+// descriptor and publishes finished batches; the compute workgroups run the
+// stage, separated by grid barriers where a stage has dependent phases. Every
+// wait is bounded (idle limit between batches, spin limit inside a batch), so
+// every wave reaches the kernel's end.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <math.h>
@@ -19,7 +20,7 @@ namespace camelot {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// LOGMEL table layout (floats), built by the host (stage_tables.cpp)
+// LOGMEL table layout (floats), built by the host (logmel_tables in runtime.cpp)
 constexpr int kTabWin = 0;          // 400 Hamming window values
 constexpr int kTabTw256 = 400;      // 256 complex exp(-2 pi i t / 256)
 constexpr int kTabTw512 = 912;      // 257 complex exp(-2 pi i k / 512)

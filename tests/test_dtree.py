@@ -1,5 +1,5 @@
 """Decision-tree latency predictor (CART regression, the paper's predictor kind,
-Section V-A): the oracle against what the definition fixes, then the library's
+Section VII-A): the oracle against what the definition fixes, then the library's
 host implementation against the oracle, node for node and prediction for prediction."""
 import numpy as np
 import pytest

@@ -126,14 +126,20 @@ def c4(torch, cm):
     return dict(stages=stages, dev=d, wc=wc, wm=wm, table=table, x=x, ids=ids, n=n)
 
 
-def test_c4_pipeline_replay(torch, cm, c4):
+@pytest.mark.parametrize("handoff", ["device", "host"])
+def test_c4_pipeline_replay(torch, cm, c4, handoff):
+    """The item ids ride in the side plane through every boundary: in the host-staged
+    mode the relay must carry them too (else the scores would read stale ids)."""
+    mode = cm.HANDOFF_DEVICE if handoff == "device" else cm.HANDOFF_HOST
     cfg = cm.pipeline_config(c4["stages"], (128, 64, 32, 32), max_batch=16, ring_depth=4, ingest=cm.INGEST_REPLAY,
-                             max_rows_per_request=4, side_bytes=4 * N_IDS, idle_timeout_ns=5_000_000_000)
+                             max_rows_per_request=4, side_bytes=4 * N_IDS, idle_timeout_ns=5_000_000_000,
+                             handoff=mode)
     rows = np.array([1, 3, 2, 4, 1, 1, 2, 3], np.int32)
     prow = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)
     ids = np.arange(1, len(rows) + 1, dtype=np.uint64)
     arr = G.poisson_arrivals_ns(len(rows), 2000, seed=3)
-    log("c4 pipeline: conv+pool(128 CUs) -> mlp(64) -> gather+score(32) -> top-100(32), 8 requests, 17 rows")
+    log(f"c4 pipeline ({handoff} handoff): conv+pool(128 CUs) -> mlp(64) -> gather+score(32) -> top-100(32), "
+        f"8 requests, 17 rows")
     p = cm.camelot_pipeline_create(cfg)
     try:
         cm.camelot_pipeline_replay(p, ids, rows, arr, prow, c4["dev"]["pool"].data_ptr(), c4["n"])
@@ -153,12 +159,19 @@ def test_c4_pipeline_replay(torch, cm, c4):
     got = {(r.query_id, r.row): r for r in res}
     gv = np.zeros((n, 100))
     exact_idx = 0
+    tol = 2e-2 * np.max(np.abs(scores))
     for qi, (i0, nr) in enumerate(zip(prow, rows)):
         for j in range(nr):
             r = got[(int(ids[qi]), j)]
             assert r.n_out == 100
             gv[i0 + j] = r.val[:100]
-            exact_idx += int(list(r.idx[:100]) == list(ridx[i0 + j]))
+            gi = np.array(r.idx[:100])
+            # indices distinct, in range, and each a valid top-100 member within tolerance;
+            # the returned value is that index's oracle score within tolerance
+            assert len(set(gi.tolist())) == 100 and gi.min() >= 0 and gi.max() < HEADS * N_IDS
+            assert np.all(scores[i0 + j, gi] >= rval[i0 + j, -1] - tol)
+            assert np.max(np.abs(scores[i0 + j, gi] - gv[i0 + j])) <= tol
+            exact_idx += int(list(gi) == list(ridx[i0 + j]))
     err = O.normwise_err(gv, rval)
     log(f"  top-100 values err={err:.3e}; rows with identical index lists {exact_idx}/{n}")
     assert err <= 2e-2

@@ -132,34 +132,43 @@ def test_alone_vs_mix_bit_identical(torch, cm, world):
             cm.camelot_pipeline_destroy(p)
         assert len(res) == probe_rows
         alone[i] = [(r.row, list(r.idx[:r.n_out]), list(r.val[:r.n_out])) for r in res]
-    # the mix: all four pipelines admitted at once, Poisson requests of 1..128 rows,
-    # the probe request arriving together with a neighbour
+    # the mix: all four pipelines admitted at once, 400 Poisson requests of 1..128 rows
+    # each, at a rate above what the pipelines serve, so that every pipeline is busy
+    # from its start until its queue drains (tens of ms, far longer than the few ms
+    # between the replay starts); the probe request arrives together with a neighbour
+    # in the middle of the stream
     server = cm.camelot_server_create(1 << 40)
-    mixed = {}
+    mixed, spans = {}, {}
+    nreq, probe = 400, 200
     try:
         handles = [cm.camelot_server_admit(server, _cfg(cm, world, i)) for i in range(4)]
         plans = []
         for i, p in enumerate(handles):
-            nreq = 40
             rows = G.request_rows(nreq, seed=10 + i)
-            rows[20] = probe_rows
+            rows[probe] = probe_rows
             arr = G.poisson_arrivals_ns(nreq, 20_000, seed=i)
-            arr[20] = arr[19]
+            arr[probe] = arr[probe - 1]
             prow = np.concatenate([[0], np.cumsum(rows)[:-1]]) % (len(world["pools"][i]) - 128)
-            prow[20] = probe_first
+            prow[probe] = probe_first
             ids = np.arange(1, nreq + 1)
-            ids[20:] += 1000
-            ids[20] = 1007
-            ids[21:] += 1000
+            ids[probe:] += 2000
+            ids[probe] = 1007
             plans.append((ids, rows, prow))
             cm.camelot_pipeline_replay(p, ids, rows, arr, prow, world["dpools"][i].data_ptr(), len(world["pools"][i]))
         for i, p in enumerate(handles):
             ids, rows, prow = plans[i]
-            res = _drain(cm, p, int(rows.sum()))
+            res = _drain(cm, p, int(rows.sum()), timeout_s=60.0)
             assert len(res) == int(rows.sum())
             want_ids = [int(q) for q, r in zip(ids, rows) for _ in range(r)]
             assert OD.check_delivery(list(dict.fromkeys(want_ids)), list(dict.fromkeys(r.query_id for r in res))) == []
             mixed[i] = [(r.row, list(r.idx[:r.n_out]), list(r.val[:r.n_out])) for r in res if r.query_id == 1007]
+            # every batch's device-time span (first stage start .. last stage end) on
+            # the common device clock
+            S = len(world["stages"][i])
+            epoch = cm.camelot_pipeline_epoch_ns(p)
+            spans[i] = (np.array(sorted({(epoch + r.t_ns[1], epoch + r.t_ns[2 * S]) for r in res})),
+                        [(epoch + r.t_ns[1 + 2 * s], epoch + r.t_ns[2 + 2 * s])
+                         for r in res if r.query_id == 1007 for s in range(S)])
             # a sample request of the mix against the oracle
             q = 5
             got = [r for r in res if r.query_id == int(ids[q])]
@@ -168,6 +177,13 @@ def test_alone_vs_mix_bit_identical(torch, cm, world):
             assert O.normwise_err(gval, rval) <= (2e-2 if i in (1, 3) else 1e-5)
     finally:
         cm.camelot_server_destroy(server)
+    # the probe's stage batches ran while other pipelines' batches ran: for every
+    # pipeline, some stage interval of its probe overlaps a batch of another pipeline
+    for i in range(4):
+        others = np.concatenate([spans[j][0] for j in range(4) if j != i])
+        hits = sum(int(np.any((others[:, 0] < e) & (others[:, 1] > s))) for s, e in spans[i][1])
+        log(f"  pipeline {i}: {hits} of the probe's {len(spans[i][1])} stage intervals overlap other pipelines' batches")
+        assert hits > 0, f"pipeline {i}: the probe ran while no other pipeline ran"
     for i in range(4):
         assert mixed[i] == alone[i], f"pipeline {i}: probe request differs alone vs in the mix"
     log("  probe request bit-identical alone and in the 4-pipeline mix")

@@ -97,6 +97,40 @@ def test_predictor_adam_first_step_is_lr_sign():
         assert np.allclose(step[big], -1e-3 * np.sign(gi[big]), rtol=1e-3)
 
 
+def _adam_scalar(gs, lr=0.1):
+    p, m, v = [np.zeros(1)], [np.zeros(1)], [np.zeros(1)]
+    for t, g in enumerate(gs, start=1):
+        p, m, v = P.adam_step(p, [np.array([g], np.float64)], m, v, t, lr=lr)
+    return p[0][0], m[0][0], v[0][0]
+
+
+def test_predictor_adam_later_steps_hand_derived():
+    """Kingma & Ba with beta1 = 0.9, beta2 = 0.999, eps = 1e-8, worked by hand for
+    scalar gradient sequences from zero moments, lr = 0.1.
+
+    g = (1, -1): m2 = 0.9 * 0.1 - 0.1 = -0.01, v2 = 0.999 * 0.001 + 0.001 = 0.001999;
+    the corrected moments are -0.01 / 0.19 = -1/19 and 0.001999 / 0.001999 = 1, so
+    the second step is +0.1 / 19 / (1 + eps) after a first step of -0.1 / (1 + eps).
+    g = (1, 0): m2 = 0.09, v2 = 0.000999, corrected 9/19 and 999/1999.
+    g = (1, 0, 0): m3 = 0.081, v3 = 0.000998001, corrected 0.081 / 0.271 = 81/271 and
+    0.000998001 / 0.002997001 = 998001/2997001."""
+    eps = 1e-8
+    first = -0.1 / (1 + eps)
+    p, m, v = _adam_scalar([1.0, -1.0])
+    assert np.isclose(m, -0.01, rtol=1e-12, atol=0) and np.isclose(v, 0.001999, rtol=1e-12, atol=0)
+    assert np.isclose(p, first + 0.1 / 19 / (1 + eps), rtol=1e-12, atol=0)
+    p, m, v = _adam_scalar([1.0, 0.0])
+    assert np.isclose(m, 0.09, rtol=1e-12, atol=0) and np.isclose(v, 0.000999, rtol=1e-12, atol=0)
+    step2 = 0.1 * (9 / 19) / (np.sqrt(999 / 1999) + eps)
+    assert np.isclose(p, first - step2, rtol=1e-12, atol=0)
+    p, m, v = _adam_scalar([1.0, 0.0, 0.0])
+    assert np.isclose(m, 0.081, rtol=1e-12, atol=0) and np.isclose(v, 0.000998001, rtol=1e-12, atol=0)
+    step3 = 0.1 * (81 / 271) / (np.sqrt(998001 / 2997001) + eps)
+    assert np.isclose(p, first - step2 - step3, rtol=1e-12, atol=0)
+    # the numbers themselves, written out (9/19 = 0.47368..., sqrt(999/1999) = 0.70693...)
+    assert abs(step2 - 0.067005816) < 1e-8
+
+
 def test_predictor_training_reduces_loss():
     params, x, y = _small_problem()
     m = [np.zeros_like(np.asarray(p, np.float64)) for p in params]
