@@ -216,6 +216,33 @@ int32_t camelot_stage_run(const camelot_stage_desc* stage, const void* in, void*
                           int32_t rows, int32_t n_cus, int32_t cu_offset, int32_t reps,
                           double* ns_per_rep, double* device_ns_per_rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): camelot_stage_run's
+ * computation with no allocation of any kind on the device. The control block, the
+ * log-mel tables and the stage's scratch live in one static device array per GPU of
+ * at most CAMELOT_NOALLOC_SCRATCH_BYTES of stage scratch (held until the process
+ * ends). Stage scratch needed: MLP_BF16 512 * round_up(max dims[l], 32) bytes
+ * (so every MLP the library accepts, widths <= 16384), CONV_POOL 32768 * ceil(H * W / 64) bytes (maps up to
+ * 16384 pixels), other kinds none; a stage needing more is refused with
+ * CAMELOT_EINVAL before anything runs.
+ *   stage, in, out, rows, reps   as camelot_stage_run (same layouts, same results,
+ *        bit for bit: the same kernel and grid)
+ *   n_cus  compute workgroups, one per CU of the caller's share: a multiple of 8 in
+ *        8..256, at most the device's CUs; the stream must give the kernel room for
+ *        all of them at once (an unmasked stream, or one masked to >= n_cus / 2 CUs)
+ *   stream the caller's HIP stream (NULL: the null stream); the run is enqueued on
+ *        it and the call returns without waiting (except once per device, the first
+ *        LOGMEL call outside capture, which writes the tables and waits for them).
+ * Writes to the device only through kernels (no memset or copy nodes), so it may be
+ * captured into a HIP graph. Every call on a GPU shares that GPU's array, which keeps
+ * the last call's contents; calls whose work overlaps on one GPU race and give
+ * undefined results. In-kernel waits are bounded (2 s); a run that times out
+ * leaves `out` undefined. Returns CAMELOT_EINVAL on a bad argument, CAMELOT_EDEVICE
+ * on a HIP error. */
+#define CAMELOT_NOALLOC_SCRATCH_BYTES (8 << 20)
+int32_t camelot_stage_run_noalloc(const camelot_stage_desc* stage, const void* in, void* out,
+                                  int32_t rows, int32_t n_cus, int32_t reps, void* stream);
+
 /* ------------------------------------------------------------------ pipelines
  * The query flow of Section V-B (queries wait in a queue, are batched, and pass
  * through the microservice stages in order, each stage on its own share of the

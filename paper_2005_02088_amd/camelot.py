@@ -22,6 +22,7 @@ _lib = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
 # ------------------------------------------------------------------ constants
 OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EINFEASIBLE, EDEVICE, ESTOPPED = 0, -1, -2, -3, -4, -5, -6, -7
 MAX_STAGES, MAX_LAYERS, MAX_K, MAX_BATCH = 8, 8, 128, 128
+NOALLOC_SCRATCH_BYTES = 8 << 20          # CAMELOT_NOALLOC_SCRATCH_BYTES
 (STAGE_GEMM_RELU, STAGE_GEMM_ARGMAX, STAGE_LOGMEL, STAGE_MLP_BF16, STAGE_TOPK, STAGE_GATHER, STAGE_CONV_POOL,
  STAGE_GATHER_SCORE) = 1, 2, 3, 4, 5, 6, 7, 8
 HANDOFF_DEVICE, HANDOFF_HOST = 0, 1
@@ -129,6 +130,8 @@ _SIGS = {
     "camelot_stage_row_bytes_out": (C.c_int64, [C.POINTER(StageDesc)]),
     "camelot_stage_run": (C.c_int32, [C.POINTER(StageDesc), _P, _P, C.c_int32, C.c_int32, C.c_int32,
                                       C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "camelot_stage_run_noalloc": (C.c_int32, [C.POINTER(StageDesc), _P, _P, C.c_int32, C.c_int32, C.c_int32,
+                                              _P]),
     "camelot_pipeline_create": (C.c_int32, [C.POINTER(PipelineConfig), C.POINTER(_P)]),
     "camelot_pipeline_footprint": (C.c_int64, [_P]),
     "camelot_pipeline_epoch_ns": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
@@ -290,6 +293,13 @@ def camelot_stage_run(desc: StageDesc, in_ptr: int, out_ptr: int, rows: int, n_c
     _check(_lib.camelot_stage_run(C.byref(desc), in_ptr, out_ptr, rows, n_cus, cu_offset, reps, C.byref(ns),
                                   C.byref(dns)))
     return dns.value if device else ns.value
+
+
+def camelot_stage_run_noalloc(desc: StageDesc, in_ptr: int, out_ptr: int, rows: int, n_cus: int, reps: int = 1,
+                              stream: int = 0) -> None:
+    """Enqueues the stage's one-shot kernel on `stream` using only the library's
+    static device array (no allocation); returns without waiting."""
+    _check(_lib.camelot_stage_run_noalloc(C.byref(desc), in_ptr, out_ptr, rows, n_cus, reps, stream or None))
 
 
 # ------------------------------------------------------------------ pipelines

@@ -46,8 +46,21 @@ int32_t cached_stream(int offset, int n, hipStream_t* s);
 // A new CU-masked stream the caller owns (and destroys).
 int32_t new_masked_stream(int offset, int n, hipStream_t* s);
 int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp);
+// The allocation-free part of fill_params: checks the descriptor and fills sp except
+// its device buffers; *scratch_bytes = the stage scratch the kernel needs (0: none).
+int32_t stage_params(const camelot_stage_desc* d, StageParams* sp, int64_t* scratch_bytes);
+// Points sp at its scratch buffer (MLP hidden state, conv partial sums) and, for
+// LOGMEL, at the device copy of the log-mel tables.
+void stage_params_bind(StageParams* sp, void* scratch, const float* logmel_tab);
+// Window, FFT twiddles and HTK mel filterbank of the LOGMEL stage, computed in double
+// and stored as float into t[kLogmelTableFloats]; false if they do not fit.
+constexpr int kLogmelTableFloats = 2304;
+bool logmel_tables(float* t);
+
 int32_t check_share(int n_cus, int offset, int total);
 int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s);
 bool is_result_stage(int kind);
+// Side bytes following each input row in a one-shot run (GATHER_SCORE: its ids).
+int64_t stage_side_bytes(const camelot_stage_desc* d);
 
 }  // namespace camelot

@@ -186,9 +186,9 @@ int32_t cached_stream(int offset, int n, hipStream_t* s) {
 // Window, FFT twiddles and the HTK mel filterbank (40 triangles on 42 points equally
 // spaced in mel over 0..8 kHz, evaluated at the bin frequencies k * 16000 / 512),
 // computed in double and stored as float.
-static std::vector<float> logmel_tables() {
+bool logmel_tables(float* t) {
   const double PI = 3.14159265358979323846;
-  std::vector<float> t(1546, 0.f);
+  std::fill(t, t + kLogmelTableFloats, 0.f);
   for (int n = 0; n < 400; ++n) t[n] = (float)(0.54 - 0.46 * std::cos(2 * PI * n / 399.0));
   for (int q = 0; q < 256; ++q) {
     t[400 + 2 * q] = (float)std::cos(-2 * PI * q / 256.0);
@@ -203,11 +203,12 @@ static std::vector<float> logmel_tables() {
   double pts[42];
   const double top = mel(8000.0);
   for (int i = 0; i < 42; ++i) pts[i] = hz(top * i / 41.0);
-  std::vector<float> w;
+  // per band: first bin, bin count, offset of its weights; the weights follow at 1546
+  int nw = 0;
   for (int m = 0; m < 40; ++m) {
     const double lo = pts[m], c = pts[m + 1], hi = pts[m + 2];
     int first = -1, last = -1;
-    std::vector<double> wk(257, 0.0);
+    double wk[257];
     for (int k = 0; k <= 256; ++k) {
       const double f = k * 16000.0 / 512.0;
       double v = 0.0;
@@ -219,21 +220,22 @@ static std::vector<float> logmel_tables() {
     if (first < 0) { first = 0; last = -1; }
     t[1426 + 3 * m] = (float)first;
     t[1426 + 3 * m + 1] = (float)(last - first + 1);
-    t[1426 + 3 * m + 2] = (float)w.size();
-    for (int k = first; k <= last; ++k) w.push_back((float)wk[k]);
+    t[1426 + 3 * m + 2] = (float)nw;
+    for (int k = first; k <= last; ++k) {
+      // cannot overflow for 40 bands over 257 bins; the caller reports it if it did
+      if (1546 + nw >= kLogmelTableFloats) return false;
+      t[1546 + nw++] = (float)wk[k];
+    }
   }
-  t.insert(t.end(), w.begin(), w.end());
-  if (t.size() > 2304) t.clear();   // cannot happen for 40 bands over 257 bins; caught by the caller
-  else t.resize(2304, 0.f);         // the kernel stages a fixed-size table in LDS
-  return t;
+  return true;
 }
 
 static float* g_logmel_dev = nullptr;
 static int32_t logmel_device_tables(const float** out) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_logmel_dev) {
-    std::vector<float> t = logmel_tables();
-    if (t.empty()) return fail(CAMELOT_EINVAL, "log-mel tables exceed the kernel's LDS table");
+    std::vector<float> t(kLogmelTableFloats);
+    if (!logmel_tables(t.data())) return fail(CAMELOT_EINVAL, "log-mel tables exceed the kernel's LDS table");
     float* d = nullptr;
     int32_t rc = dmalloc(&d, t.size() * sizeof(float));
     if (!rc) rc = h2d(d, t.data(), t.size() * sizeof(float));
@@ -322,7 +324,7 @@ static int32_t check_stage(const camelot_stage_desc* d, int64_t* in_b, int64_t* 
 }
 
 // side bytes a stage needs in a one-shot run (ids following each input row)
-static int64_t stage_side_bytes(const camelot_stage_desc* d) {
+int64_t stage_side_bytes(const camelot_stage_desc* d) {
   return d->kind == CAMELOT_STAGE_GATHER_SCORE ? 4LL * d->dims[2] : 0;
 }
 
@@ -346,7 +348,7 @@ static int64_t stage_scratch_bytes(const camelot_stage_desc* d, int* stride) {
 
 StageRes::~StageRes() { dfree(scratch); }
 
-int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp) {
+int32_t stage_params(const camelot_stage_desc* d, StageParams* sp, int64_t* scratch_bytes) {
   int64_t in_b = 0, out_b = 0;
   int32_t rc = check_stage(d, &in_b, &out_b);
   if (rc) return rc;
@@ -359,19 +361,29 @@ int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp)
   sp->out_row_bytes = (int32_t)out_b;
   for (int l = 0; l < CAMELOT_MAX_LAYERS; ++l) sp->w[l] = d->weights[l];
   int stride = 0;
-  const int64_t sb = stage_scratch_bytes(d, &stride);
+  *scratch_bytes = stage_scratch_bytes(d, &stride);
+  sp->scratch_stride = stride;
+  return CAMELOT_OK;
+}
+
+void stage_params_bind(StageParams* sp, void* scratch, const float* logmel_tab) {
+  sp->scratch = (uint16_t*)scratch;
+  if (sp->kind == CAMELOT_STAGE_CONV_POOL) sp->partial = (float*)scratch;
+  if (sp->kind == CAMELOT_STAGE_LOGMEL) sp->tables = logmel_tab;
+}
+
+int32_t fill_params(const camelot_stage_desc* d, StageRes* res, StageParams* sp) {
+  int64_t sb = 0;
+  int32_t rc = stage_params(d, sp, &sb);
+  if (rc) return rc;
   if (sb > 0 && !res->scratch) {
-    int32_t rc2 = dmalloc(&res->scratch, sb);
-    if (rc2) return rc2;
+    rc = dmalloc(&res->scratch, sb);
+    if (rc) return rc;
     res->scratch_bytes = sb;
   }
-  sp->scratch = res->scratch;
-  sp->scratch_stride = stride;
-  if (d->kind == CAMELOT_STAGE_CONV_POOL) sp->partial = (float*)res->scratch;
-  if (d->kind == CAMELOT_STAGE_LOGMEL) {
-    rc = logmel_device_tables(&sp->tables);
-    if (rc) return rc;
-  }
+  const float* tab = nullptr;
+  if (d->kind == CAMELOT_STAGE_LOGMEL && (rc = logmel_device_tables(&tab))) return rc;
+  stage_params_bind(sp, res->scratch, tab);
   return CAMELOT_OK;
 }
 

@@ -83,3 +83,24 @@ def _brute_handoff(slot_bytes, n_slots):
 @pytest.mark.parametrize("slot_bytes,n_slots", [(16, 1), (48, 3), (4096, 7), (65536 + 16, 5)])
 def test_handoff_expected_checksum(slot_bytes, n_slots):
     assert cm.camelot_handoff_expected(slot_bytes, n_slots) == _brute_handoff(slot_bytes, n_slots)
+
+
+def test_noalloc_run_refuses_what_its_array_cannot_hold():
+    """The allocation-free stage run checks every argument on the host first: a stage
+    whose scratch exceeds the static array, or a bad share, is refused before any
+    device call (so this runs without a GPU)."""
+    cap = cm.NOALLOC_SCRATCH_BYTES
+    # conv scratch = 128 rows x 64 channels x 4 bytes per 64-pixel tile: 256 tiles fit
+    assert 32768 * 256 == cap
+    big_map = cm.stage_desc(cm.STAGE_CONV_POOL, dims=(129, 128, 64, 64), weights=(1,), n_layers=0)
+    with pytest.raises(cm.CamelotError) as e:                 # 258 tiles
+        cm.camelot_stage_run_noalloc(big_map, 1, 1, 1, 8)
+    assert e.value.code == cm.EINVAL and "scratch" in str(e.value)
+    relu = cm.stage_desc(cm.STAGE_GEMM_RELU, dims=(512, 512), weights=(1,))
+    for n_cus in (0, 12, 264):
+        with pytest.raises(cm.CamelotError) as e:
+            cm.camelot_stage_run_noalloc(relu, 1, 1, 1, n_cus)
+        assert e.value.code == cm.EINVAL
+    with pytest.raises(cm.CamelotError) as e:
+        cm.camelot_stage_run_noalloc(relu, 1, 1, cm.MAX_BATCH + 1, 8)
+    assert e.value.code == cm.EINVAL
