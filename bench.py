@@ -67,13 +67,13 @@ def log(msg):
 
 
 # ---------------------------------------------------------------- CPU baseline
-def cpu_baseline(n: int) -> dict:
+def cpu_baseline(n: int, seed: int = 7) -> dict:
     """The oracle (FP64 NumPy) on `n` queries of the same workload, one thread."""
     import numpy as np  # noqa: F401
     import workload_gen as G
     from oracle import stages as O
     ws = G.c1_mlp_weights(0)
-    audio = G.c1_audio(n, seed=7)
+    audio = G.c1_audio(n, seed=seed)
     t0 = time.perf_counter()
     for i in range(0, n, 16):
         x = audio[i:i + 16]
@@ -85,12 +85,28 @@ def cpu_baseline(n: int) -> dict:
 
 
 def run_cpu_baseline(n: int) -> dict:
+    """The oracle on this host: one process, one thread, on n queries; then one
+    single-threaded process per available core (at most 16, the host share a GPU
+    gets), each on n // 2 queries of its own, timed together."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", str(n)],
-                       capture_output=True, text=True, env=env, timeout=600)
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only"]
+    r = subprocess.run(cmd + [str(n)], capture_output=True, text=True, env=env, timeout=600)
     if r.returncode != 0:
         raise RuntimeError(r.stderr)
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    one = json.loads(r.stdout.strip().splitlines()[-1])
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    m = max(8, n // 2)
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen(cmd + [str(m), "--cpu-seed", str(100 + i)], stdout=subprocess.PIPE,
+                              stderr=subprocess.PIPE, text=True, env=env) for i in range(cores)]
+    outs = [pr.communicate(timeout=900) for pr in procs]
+    dt = time.perf_counter() - t0
+    if any(pr.returncode != 0 for pr in procs):
+        raise RuntimeError("; ".join(o[1][-300:] for o in outs))
+    return {"value": cores * m / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} single-threaded processes x {m} queries of the speech pipeline (log-mel, "
+                      f"BF16-rounded MLP, top-10) in FP64 NumPy, {dt:.1f} s wall including start-up",
+            "single_thread": one}
 
 
 # ---------------------------------------------------------------- GPU parts
@@ -103,7 +119,8 @@ class Speech:
         self.stages = (cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0),
                        cm.stage_desc(cm.STAGE_MLP_BF16, dims=G.C1_MLP_DIMS, weights=[t.data_ptr() for t in self.d_ws]),
                        cm.stage_desc(cm.STAGE_TOPK, dims=(4096,), k=10, n_layers=0))
-        base = torch.from_numpy(G.c1_audio_fast(pool_base, seed=0)).cuda()
+        self.host_pool = G.c1_audio_fast(pool_base, seed=0)
+        base = torch.from_numpy(self.host_pool).cuda()
         # tiled copies at distinct addresses: the pool (1 GiB) does not fit the 256 MB MALL
         self.pool = torch.empty((pool_base * tiles, 2000), dtype=torch.float32, device="cuda")
         for t in range(tiles):
@@ -159,19 +176,24 @@ class Speech:
         mem = np.array([[self.stage_footprint(s, b) for b in BATCHES] for s in range(S)], np.int64)
         return lat, bw, mem
 
-    def trial(self, cu, rate, duration_s, handoff, batch, batch_timeout_ns, seed=0, cu_offset=0, n_inst=(1, 1, 1)):
+    def trial(self, cu, rate, duration_s, handoff, batch, batch_timeout_ns, seed=0, cu_offset=0, n_inst=(1, 1, 1),
+              host_ingest=False):
         """One Poisson replay; returns dict(p50, p99, n, wall_s, achieved_qps). n_inst[i]
-        instances of stage i run side by side, each on its own share of cu[i] CUs."""
+        instances of stage i run side by side, each on its own share of cu[i] CUs.
+        host_ingest: the queries are submitted from host memory by the library's paced
+        host submitter (through the pinned ingest ring) instead of the device replay."""
         import numpy as np
         import workload_gen as G
         cm = self.cm
         n = int(min(max(rate * duration_s, 2000), 6_000_000))
         arr = G.poisson_arrivals_ns(n, rate, seed=seed, sub=int(rate) % 100000)
         ids = np.arange(1, n + 1, dtype=np.uint64)
-        prow = np.arange(n, dtype=np.int64) % self.pool.shape[0]
+        pool_rows = self.host_pool.shape[0] if host_ingest else self.pool.shape[0]
+        prow = np.arange(n, dtype=np.int64) % pool_rows
         cfg = cm.pipeline_config(self.stages, cu, cu_offset=cu_offset, max_batch=batch, batch_target=batch,
                                  batch_timeout_ns=batch_timeout_ns, ring_depth=max(4, 2 * max(n_inst)),
-                                 handoff=handoff, ingest=cm.INGEST_REPLAY, egress_capacity=1 << 20,
+                                 handoff=handoff, ingest=cm.INGEST_HOST if host_ingest else cm.INGEST_REPLAY,
+                                 ingest_capacity=1 << 15, egress_capacity=1 << 20,
                                  idle_timeout_ns=5_000_000_000, n_inst=n_inst)
         p = cm.camelot_pipeline_create(cfg)
         lat = np.empty(n, np.int64)
@@ -181,8 +203,11 @@ class Speech:
         chunk_lat = np.empty(1 << 16, np.int64)
         t0 = time.perf_counter()
         try:
-            cm.camelot_pipeline_replay(p, ids, np.ones(n, np.int32), arr, prow, self.pool.data_ptr(),
-                                       self.pool.shape[0])
+            if host_ingest:
+                cm.camelot_pipeline_submit_replay(p, ids, np.ones(n, np.int32), arr, prow, self.host_pool)
+            else:
+                cm.camelot_pipeline_replay(p, ids, np.ones(n, np.int32), arr, prow, self.pool.data_ptr(),
+                                           self.pool.shape[0])
             deadline = t0 + duration_s * 3 + 2
             late = 0
             while done < n and time.perf_counter() < deadline:
@@ -209,7 +234,11 @@ class Speech:
                 f"worker status {list(st.worker_status[:S])}, per batch {stage}")
             return {"n": n, "done": done, "p50": math.inf, "p99": math.inf, "wall_s": wall, "ok": False,
                     "stage": stage}
-        assert np.array_equal(got_ids, ids), "delivery out of order"
+        if not np.array_equal(got_ids, ids):
+            bad = int(np.nonzero(got_ids != ids)[0][0])
+            self.failures.append(f"delivery out of order at {rate:.0f} q/s: position {bad} got id {int(got_ids[bad])}")
+            return {"n": n, "done": done, "p50": math.inf, "p99": math.inf, "wall_s": wall, "ok": False,
+                    "stage": stage}
         warm = n // 10                       # discard the warm-up tenth
         srt = np.sort(lat[warm:])
         p99 = int(srt[math.ceil(0.99 * len(srt)) - 1])
@@ -217,13 +246,14 @@ class Speech:
         return {"n": n, "done": done, "p50": p50, "p99": p99, "wall_s": wall, "ok": p99 <= QOS_NS,
                 "span_s": float(arr[-1]) / 1e9, "stage": stage}
 
-    def peak_search(self, cu, handoff, batch, guess_qps, duration_s, iters, tag, n_inst=(1, 1, 1)):
+    def peak_search(self, cu, handoff, batch, guess_qps, duration_s, iters, tag, n_inst=(1, 1, 1), host_ingest=False):
         lo, hi = 0.0, guess_qps * 2.0
         best = None
         timeout = QOS_NS // 4
         for it in range(iters):
             rate = (lo + hi) / 2 if it else guess_qps
-            r = self.trial(cu, rate, duration_s, handoff, batch, timeout, seed=it, n_inst=n_inst)
+            r = self.trial(cu, rate, duration_s, handoff, batch, timeout, seed=it, n_inst=n_inst,
+                           host_ingest=host_ingest)
             log(f"  [{tag}] rate {rate / 1e6:.3f} Mq/s -> p50 {r['p50'] / 1e3:.0f} us p99 {r['p99'] / 1e3:.0f} us "
                 f"ok={r['ok']} per batch {r['stage']}")
             if r["ok"]:
@@ -236,7 +266,7 @@ class Speech:
         return best
 
 
-def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1200, epochs=150):
+def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=4600, epochs=60):
     """The contention-aware allocator: co-location profiles of the three stages at
     random shares and batches, the 16-64-64-1 predictor trained on them with the
     library's kernels (target: log slowdown over the solo profile), then Eq. 1 over
@@ -281,6 +311,16 @@ def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1200, epochs=150):
     torch.cuda.synchronize()
     cm.camelot_predictor_forward(dp.data_ptr(), dxe.data_ptr(), len(te), yh.data_ptr())
     pred = solo[te] * np.exp(yh.cpu().numpy().astype(np.float64))
+    # one prediction as the allocator makes it: the features of one candidate's three
+    # stages through the network (launch, kernel and result back to the host)
+    one = torch.from_numpy(Z[te[:3]]).cuda()
+    yo = torch.empty(3, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(200):
+        cm.camelot_predictor_forward(dp.data_ptr(), one.data_ptr(), 3, yo.data_ptr())
+        torch.cuda.synchronize()
+    t_pred_call = (time.perf_counter() - t0) / 200
     meas = solo[te] * np.exp(y[te].astype(np.float64))
     co = multi[te]
     mape_l = float(np.mean(np.abs(pred[co] - meas[co]) / meas[co]))
@@ -304,12 +344,178 @@ def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=1200, epochs=150):
         dt_alloc = {"allocation_cus": dd["cu"], "allocation_instances": dd["n"], "batch": dd["batch"],
                     "predicted_qps": dd["thr_num"] / dd["thr_den"], "predicted_stage_ns": [int(v) for v in ldt[:3]]}
     info = {"samples": int(len(y)), "profile_s": t_prof, "train_s": t_train, "epochs": epochs,
+            "train_s_per_epoch": t_train / max(epochs, 1), "predict_call_us": t_pred_call * 1e6,
             "loss_first_last": [float(losses[0]), float(losses[-1])], "mape_colocated_learned": mape_l,
             "mape_colocated_solo_table": mape_s, "alloc_ms": t_alloc * 1e3,
             "decision_tree": {"mape_colocated": mape_dt, "max_depth": DT_MAX_DEPTH, "min_leaf": DT_MIN_LEAF,
                               "nodes": dt_nodes, "fit_ms": t_dt * 1e3, "allocation": dt_alloc}}
     log(f"learned predictor: {info}")
     return (a.as_dict() if a is not None else None), [int(v) for v in lp[:3]], info
+
+
+# ---------------------------------------------------------------- serving sweep
+SWEEP_SHARES = list(range(8, 65, 8))          # each pipeline's quarter of the GPU
+SWEEP_TABLE_ROWS = 1 << 20
+
+
+def serving_sweep(cm, G, torch, sp, trial_s):
+    """Four co-located pipelines (the two-stage FP32 one; the speech one; gather ->
+    GEMM 128x512 -> top-10; log-mel -> MLP 440-1024-1024-1024 -> top-10) serving
+    requests of U{1..128} rows, admitted by HBM footprint. Each pipeline's peak is
+    measured on a quarter of the GPU (64 CUs, Eq. 1 over its solo table); then at 10%,
+    20%, ..., 100% of those peaks all four run together, each on the fewest CUs Eq. 3
+    finds for its load, and every step reports p50/p99 request latency, the
+    requests served per second and the CUs in use."""
+    import numpy as np
+    np_rng = G.rng("requests", 77)
+    (w1, w2) = G.c0_weights(0)
+    keep = []
+
+    def dev(a):
+        t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        keep.append(t)
+        return t
+
+    dw1, dw2 = dev(w1), dev(w2)
+    table = G.fp16_table(SWEEP_TABLE_ROWS, 128, seed=1)
+    wg = (G.rng("c4", 7, 3).standard_normal((128, 512)) / np.sqrt(128)).astype(np.float32)
+    dt, dwg = dev(table.view(np.int16)), dev(wg)
+    ws3 = G.c1_mlp_weights(3, dims=(440, 1024, 1024, 1024))
+    d3 = [dev(x.view(np.int16)) for x in ws3]
+    pipes = [
+        ("fp32 gemm -> argmax",
+         (cm.stage_desc(cm.STAGE_GEMM_RELU, dims=(512, 512), weights=(dw1.data_ptr(),)),
+          cm.stage_desc(cm.STAGE_GEMM_ARGMAX, dims=(512, 10), weights=(dw2.data_ptr(),))),
+         G.c0_queries_fast(8192, seed=4)),
+        ("speech", sp.stages, sp.host_pool[:8192]),
+        ("gather -> gemm -> top-10",
+         (cm.stage_desc(cm.STAGE_GATHER, dims=(32, 128), weights=(dt.data_ptr(),), k=SWEEP_TABLE_ROWS),
+          cm.stage_desc(cm.STAGE_GEMM_RELU, dims=(128, 512), weights=(dwg.data_ptr(),)),
+          cm.stage_desc(cm.STAGE_TOPK, dims=(512,), k=10, n_layers=0)),
+         G.zipf_ids(8192, 32, SWEEP_TABLE_ROWS, seed=4)),
+        ("log-mel -> mlp 1024 -> top-10",
+         (cm.stage_desc(cm.STAGE_LOGMEL, n_layers=0),
+          cm.stage_desc(cm.STAGE_MLP_BF16, dims=(440, 1024, 1024, 1024), weights=[t.data_ptr() for t in d3]),
+          cm.stage_desc(cm.STAGE_TOPK, dims=(1024,), k=10, n_layers=0)),
+         G.c1_audio_fast(8192, seed=5)),
+    ]
+    pools = [dev(p[2]) for p in pipes]
+    torch.cuda.synchronize()
+    mean_rows = 64.5                               # E[U{1..128}]
+    K = len(SWEEP_SHARES)
+    info = {"pipelines": [p[0] for p in pipes], "request_rows": "U{1..128}", "qos_ns": QOS_NS, "steps": []}
+    t_start = time.perf_counter()
+    # solo tables of every stage (one-shot stage kernel, device time per batch)
+    probs, peaks = [], []
+    for pi, (name, stages, _) in enumerate(pipes):
+        S = len(stages)
+        lat = np.zeros((S, K, len(BATCHES)), np.int64)
+        for s, st in enumerate(stages):
+            ib, ob = cm.camelot_stage_row_bytes_in(st), cm.camelot_stage_row_bytes_out(st)
+            if s == 0:
+                src = pools[pi]
+            else:
+                src = dev(np.random.default_rng(s).standard_normal((128, ib // 4)).astype(np.float32))
+            dst = torch.empty(128 * max(ob, 8) * 2 // 4 + 64, dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            for k, share in enumerate(SWEEP_SHARES):
+                for j, b in enumerate(BATCHES):
+                    ns = cm.camelot_stage_run(st, src.data_ptr(), dst.data_ptr(), b, share, 0, 4, device=True)
+                    lat[s, k, j] = max(1, int(math.ceil(ns)))
+        mem = np.zeros((S, len(BATCHES)), np.int64)
+        probs.append(lambda total, lat=lat, mem=mem, S=S: cm.ProblemArrays(
+            cu_total=total, cu_step=8, max_instances=S, max_inst_per_stage=1, batches=BATCHES, qos_ns=QOS_NS,
+            hbm_bytes_budget=1 << 40, hbm_bw_budget=1 << 62, lat_ns=lat, bw_bps=np.zeros_like(lat), mem_bytes=mem))
+    info["profile_s"] = time.perf_counter() - t_start
+
+    def run_mix(allocs, rates, seed):
+        """All pipelines together, pipeline i on allocs[i] at offset 64 i, Poisson
+        requests at rates[i] requests/s; per pipeline p50/p99 request latency and
+        requests served per second."""
+        server = cm.camelot_server_create(1 << 40)
+        out = []
+        try:
+            hs, plans = [], []
+            for i, (a, r) in enumerate(zip(allocs, rates)):
+                name, stages, _ = pipes[i]
+                cfg = cm.pipeline_config(stages, a["cu"], cu_offset=64 * i, max_batch=128, batch_target=a["batch"],
+                                         batch_timeout_ns=QOS_NS // 4, ring_depth=4, ingest=cm.INGEST_REPLAY,
+                                         max_rows_per_request=128, egress_capacity=1 << 21,
+                                         idle_timeout_ns=5_000_000_000)
+                hs.append(cm.camelot_server_admit(server, cfg))
+                n = int(max(200, r * trial_s))
+                rows = np_rng.integers(1, 129, n).astype(np.int32)
+                arr = G.poisson_arrivals_ns(n, r, seed=seed, sub=i)
+                prow = np_rng.integers(0, pools[i].shape[0] - 128, n)
+                plans.append((n, rows, arr))
+                cm.camelot_pipeline_replay(hs[-1], np.arange(1, n + 1), rows, arr, prow, pools[i].data_ptr(),
+                                           pools[i].shape[0])
+            want = [int(pl[1].sum()) for pl in plans]
+            lat = [np.zeros(w, np.int64) for w in want]
+            rid = [np.zeros(w, np.uint64) for w in want]
+            got = [0] * 4
+            ci, cl = np.empty(1 << 16, np.uint64), np.empty(1 << 16, np.int64)
+            deadline = time.perf_counter() + 3 * trial_s + 5
+            while any(g < w for g, w in zip(got, want)) and time.perf_counter() < deadline:
+                for i in range(4):
+                    if got[i] < want[i]:
+                        k = cm.camelot_pipeline_drain_latency(hs[i], ci, cl, 1_000_000)
+                        lat[i][got[i]:got[i] + k] = cl[:k]
+                        rid[i][got[i]:got[i] + k] = ci[:k]
+                        got[i] += k
+            for i in range(4):
+                n, rows, arr = plans[i]
+                if got[i] < want[i]:
+                    out.append({"done": False, "rows": got[i], "of": want[i]})
+                    continue
+                # a request's latency is its last row's
+                req_lat = np.zeros(n, np.int64)
+                np.maximum.at(req_lat, rid[i].astype(np.int64) - 1, lat[i])
+                srt = np.sort(req_lat)
+                p50, p99 = int(srt[math.ceil(0.5 * n) - 1]), int(srt[math.ceil(0.99 * n) - 1])
+                out.append({"done": True, "p50_ns": p50, "p99_ns": p99, "qps": n / (arr[-1] * 1e-9),
+                            "qos_met": p99 <= QOS_NS})
+        finally:
+            cm.camelot_server_destroy(server)
+        return out
+
+    # each pipeline's peak on its quarter: Eq. 1, then a binary search on the rate
+    # with the whole mix running at the same fraction
+    peak_allocs = []
+    for pi in range(4):
+        a = cm.camelot_alloc_peak(probs[pi](64)).as_dict()
+        peak_allocs.append(a)
+        peaks.append(a["thr_num"] / a["thr_den"] / mean_rows)      # requests/s predicted
+    lo, hi, best = 0.0, 1.5, None
+    for it in range(6):
+        f = 1.0 if it == 0 else (lo + hi) / 2
+        r = run_mix(peak_allocs, [f * p for p in peaks], seed=it)
+        ok = all(x["done"] and x["qos_met"] for x in r)
+        log(f"  [serving mix peak] {f:.3f} x predicted -> ok={ok} {[round(x.get('p99_ns', 0) / 1e6, 2) for x in r]} ms")
+        if ok:
+            lo, best = f, f
+        else:
+            hi = f
+    scale = best if best else lo
+    measured = [scale * p for p in peaks]
+    info["peak_allocations"] = [{"cu": a["cu"], "batch": a["batch"]} for a in peak_allocs]
+    info["peak_qps"] = measured
+    for step in range(1, 11):
+        f = step / 10
+        allocs = []
+        for pi in range(4):
+            load_rows = f * measured[pi] * mean_rows
+            m = cm.camelot_alloc_min(probs[pi](64), int(load_rows * 1000), 1000)
+            allocs.append(m.as_dict() if m is not None else peak_allocs[pi])
+        r = run_mix(allocs, [f * q for q in measured], seed=100 + step)
+        cus = int(sum(sum(a["cu"]) for a in allocs))
+        info["steps"].append({"load_frac": f, "cus_used": cus, "cus": [a["cu"] for a in allocs],
+                              "batches": [a["batch"] for a in allocs], "pipelines": r})
+        log(f"  [serving sweep] {int(f * 100)}% load: {cus} CUs, p99 ms "
+            f"{[round(x.get('p99_ns', 0) / 1e6, 2) for x in r]}, qps {[round(x.get('qps', 0)) for x in r]}")
+    info["sweep_s"] = time.perf_counter() - t_start
+    del keep
+    return info
 
 
 ROOF_LAUNCHES, ROOF_REPS = 10, 50
@@ -338,7 +544,7 @@ def profiled_traffic(mlp_cus):
     return int(m_t.group(1))
 
 
-def mlp_roofline(mlp_cus):
+def mlp_roofline(cm, mlp_cus):
     """The dominant kernel: the BF16 MLP stage's one-shot kernel at batch 128 on the
     MLP's CU share, ROOF_LAUNCHES launches of ROOF_REPS batches each, timed with HIP
     events on the stream the kernel runs on, by the library's standalone driver (a
@@ -354,6 +560,10 @@ def mlp_roofline(mlp_cus):
     achieved = mlp_bytes / (ns * 1e-9)
     log(f"MLP @128 on {mlp_cus} CUs: {ns / 1e3:.1f} us/batch -> {achieved / 1e9:.0f} GB/s, "
         f"{mlp_flops / (ns * 1e-9) / 1e12:.0f} TFLOP/s")
+    # the share's own bandwidth: a plain reduction over 1 GiB (HBM) and over 32 MiB
+    # (resident in the 256 MB MALL, where the MLP's 35 MB of weights can stay)
+    part_hbm = cm.camelot_stream_bench(cm.STREAM_READ, 1 << 30, mlp_cus, 0, 2)["gbs"]
+    part_mall = cm.camelot_stream_bench(cm.STREAM_READ, 32 << 20, mlp_cus, 0, 32)["gbs"]
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": profiled_traffic(mlp_cus),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
@@ -361,6 +571,8 @@ def mlp_roofline(mlp_cus):
             "batches_per_launch": ROOF_REPS, "launches": ROOF_LAUNCHES,
             "avg_launch_us": sum(out["launch_us"]) / len(out["launch_us"]), "ns_per_batch": ns,
             "bytes_per_batch": mlp_bytes, "bytes_per_launch": mlp_bytes * ROOF_REPS,
+            "partition_read_gbs_hbm": part_hbm, "partition_read_gbs_mall": part_mall,
+            "frac_of_partition_hbm": achieved / 1e9 / part_hbm,
             "mfma_tflops": mlp_flops / (ns * 1e-9) / 1e12,
             "mfma_frac": mlp_flops / (ns * 1e-9) / MFMA_BF16_PEAK,
             "command": " ".join(["paper_2005_02088_amd/camelot_mlp_roofline"] + cmd[1:])}
@@ -373,15 +585,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trial-s", type=float, default=0.5, help="seconds of arrivals per replay trial")
     ap.add_argument("--search-iters", type=int, default=8)
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--cpu-baseline-only", type=int, default=0)
+    ap.add_argument("--cpu-seed", type=int, default=7)
+    ap.add_argument("--skip-serving", action="store_true", help="skip the four-pipeline serving sweep")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-learned", action="store_true", help="skip the learned-allocator comparison")
     ap.add_argument("--dump", default="", help="write the profile table and trials to this JSON file")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline(args.cpu_baseline_only)))
+        print(json.dumps(cpu_baseline(args.cpu_baseline_only, args.cpu_seed)))
         return 0
     if args.gpus != 1:
         print("bench.py measures one MI355X: the pipelines run on a single GPU (use --gpus 1); sharding over GPUs is not implemented.",
@@ -467,6 +681,10 @@ def main():
         table = sp.peak_search(a["cu"], cm.HANDOFF_DEVICE, a["batch"], pred, args.trial_s, args.search_iters,
                                "solo table", n_inst=tuple(a["n"]))
     base = sp.peak_search(even, cm.HANDOFF_HOST, a["batch"], pred_even, args.trial_s, args.search_iters, "baseline")
+    # the same even split with device-global handoff: separates what the allocation
+    # gains from what the handoff gains
+    base_dev = sp.peak_search(even, cm.HANDOFF_DEVICE, a["batch"], pred_even, args.trial_s, args.search_iters,
+                              "even split, device handoff")
     peak = cam[0] if cam else 0.0
     peak_table = (table[0] if table else 0.0) if la is not None else peak
     peak_base = base[0] if base else 0.0
@@ -560,6 +778,17 @@ def main():
     if steps is None:
         raise SystemExit("every allocation proposal failed in the timed steps")
 
+    # 4b: the host-submit ingest peak of the deployed allocation: queries submitted
+    # from host memory at their Poisson times by the library's paced submitter, through
+    # the pinned ingest ring (PCIe on the path), the same QoS
+    host_peak = None
+    try:
+        hp = sp.peak_search(use["cu"], cm.HANDOFF_DEVICE, batch, peak, args.trial_s, args.search_iters,
+                            "host submit", n_inst=ninst, host_ingest=True)
+        host_peak = hp[0] if hp else 0.0
+    except cm.CamelotError as e:
+        sp.failures.append(f"host-submit search: {e}")
+
     # 5: CUs at 20% load
     lam20 = 0.2 * peak_base
     num, den = int(lam20 * 1000), 1000
@@ -587,16 +816,27 @@ def main():
         log(f"learned allocation {la['cu']} x {la['n']}: measured peak {(peak_learned or 0) / 1e6:.3f} "
             f"Mq/s; solo-table allocation {a['cu']} x {a['n']}: {peak_table / 1e6:.3f} Mq/s")
 
+    # 5b: the serving loop: four co-located pipelines, load swept 10% -> 100%
+    serving = None
+    if not args.skip_serving:
+        serving = serving_sweep(cm, G, torch, sp, args.trial_s)
+
     # 6: handoff GB/s
     slot = 64 << 20
     h = cm.camelot_handoff_bench(cm.HANDOFF_DEVICE, slot, 16, 128, 128, 128)
     hs, hx = cm.camelot_handoff_expected(slot, 128)
     handoff_ok = (h["sum"], h["xor"]) == (hs, hx)
     hh = cm.camelot_handoff_bench(cm.HANDOFF_HOST, slot, 2, 8, 8, 8)
+    # its ceiling: a plain writer on the producer's 128 CUs while a plain reader runs
+    # on the consumer's 128 (other buffers, no doorbells), and the shares' bandwidth
+    split = cm.camelot_stream_bench(cm.STREAM_SPLIT, 1 << 30, 128, 0, 4)
+    share_bw = {str(c): round(cm.camelot_stream_bench(cm.STREAM_READ, 1 << 30, c, 0, 2)["gbs"], 1)
+                for c in (8, 16, 32, 64, 128, 256)}
+    log(f"stream: split 128+128 {split['gbs']:.0f} GB/s; read by share {share_bw}")
     log(f"handoff device {h['gbs']:.0f} GB/s (checksum ok={handoff_ok}), host-staged {hh['gbs']:.1f} GB/s")
 
     # 7: roofline of the dominant kernel (MLP stage, batch 128, on its share)
-    roof = mlp_roofline(use["cu"][1])
+    roof = mlp_roofline(cm, use["cu"][1])
 
     # 8: CPU baseline
     cpu = None if args.skip_cpu else run_cpu_baseline(args.cpu_sample)
@@ -613,14 +853,23 @@ def main():
                    "handoff": "device-global ring + doorbells", "qos_ns": QOS_NS},
         "timed_steps_p99_ns": p99s, "timed_steps_qos_met": all(s["ok"] for s in steps),
         "timed_step_per_batch": steps[0].get("stage"),
-        "predicted_qps": upred, "alloc_ms": alloc_ms, "profile_failures": sp.failures,
+        "busy_minus_kernel_us": [round(steps[0]["stage"]["busy_us"][i]
+                                       - lat[i, use["cu"][i] // SHARES[0] - 1, BATCHES.index(batch)] / 1e3, 1)
+                                 for i in range(3)],
+        "worker_failures": sp.failures,
+        "predicted_qps": upred, "alloc_ms": alloc_ms,
         "baseline": {"kind": "even split 88/88/80 CUs, host-staged handoff", "peak_qps": peak_base,
-                     "predicted_qps": pred_even},
+                     "predicted_qps": pred_even,
+                     "even_split_device_handoff_peak_qps": (base_dev[0] if base_dev else 0.0)},
+        "host_submit_peak_qps": host_peak,
         "gain_vs_even_split_host_staged": (peak / peak_base) if peak_base else None,
         "cus_at_20pct_load": {"camelot": cus20, "baseline_even_split": 256, "load_qps": lam20,
                               "p99_ns": p99_20},
         "handoff": {"gbs": h["gbs"], "frac_of_hbm_peak": h["gbs"] * 1e9 / HBM_PEAK, "checksum_ok": handoff_ok,
-                    "ring_bytes": slot * 16, "host_staged_gbs": hh["gbs"]},
+                    "ring_bytes": slot * 16, "host_staged_gbs": hh["gbs"],
+                    "ceiling_split_128_128_gbs": split["gbs"], "frac_of_ceiling": h["gbs"] / split["gbs"]},
+        "share_read_gbs": share_bw,
+        "serving_sweep": serving,
         "learned_allocator": learned,
         "calibrated_table_allocation": calib,
         "no_bw_constraint_allocation": nc,

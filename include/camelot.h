@@ -327,6 +327,25 @@ int32_t camelot_pipeline_epoch_ns(const camelot_pipeline* p, int64_t* epoch_ns);
 int32_t camelot_pipeline_submit(camelot_pipeline* p, uint64_t query_id,
                                 const void* payload, int32_t rows);
 
+/* Host ingest paced by a library thread, the host-submit counterpart of
+ * camelot_pipeline_replay (Section V-B: queries enter the pipeline's wait queue from
+ * the host as they arrive): request r (ids[r], rows[r] rows of host payload starting
+ * at payload row payload_row[r], rows of row_bytes_in of stage 0 plus side_bytes)
+ * goes through camelot_pipeline_submit once arrival_ns[r] ns have passed since this
+ * call, waiting while the ingest queue is full; its arrival time (the zero of its
+ * latency) is the scheduled one, so a submitter that falls behind adds to the
+ * latencies instead of hiding. Returns at once; the arrays are
+ * copied, the payload (host memory, payload_rows rows) is borrowed until the last
+ * request is submitted. One paced submission per pipeline, and no other submit
+ * calls meanwhile; destroy stops it. EINVAL on bad arguments (as replay). */
+int32_t camelot_pipeline_submit_replay(camelot_pipeline* p, int32_t n_req, const uint64_t* ids,
+                                       const int32_t* rows, const int64_t* arrival_ns,
+                                       const int64_t* payload_row, const void* payload,
+                                       int64_t payload_rows);
+/* Requests the paced submission has submitted so far; returns its error, if it
+ * stopped on one (a worker failure or ESTOPPED), else CAMELOT_OK. */
+int32_t camelot_pipeline_submit_status(camelot_pipeline* p, int64_t* submitted);
+
 /* One result row. t_ns: [0] arrival, then per stage (start, end) of the batch,
  * then done; all in ns of the device clock since the pipeline's epoch. */
 typedef struct {
@@ -419,6 +438,25 @@ int64_t camelot_stage_weight_bytes(const camelot_stage_desc* stage);
  * (what launching a worker requires), else 0. EINVAL for an unknown kind. */
 int32_t camelot_stage_kernel_info(int32_t kind, int32_t one_shot, int32_t* regs, int64_t* lds_bytes,
                                   int32_t* fits);
+
+/* ------------------------------------------------------------------ share bandwidth
+ * The attainable HBM bandwidth of a CU share, the bandwidth roofline of a stage
+ * confined to it (the paper's stages get SM shares; only compute units are
+ * partitioned, memory bandwidth is shared, Section IV). Plain streaming kernels,
+ * two workgroups per CU, 8 independent 16-byte accesses in flight per thread,
+ * non-temporal, over `bytes` (a multiple of 16; >= 1 GiB exceeds the 256 MB MALL so
+ * the traffic reaches HBM), `reps` passes, timed on the device clock:
+ *   CAMELOT_STREAM_READ   a reduction of one buffer on n_cus CUs at cu_offset
+ *   CAMELOT_STREAM_WRITE  a fill of one buffer
+ *   CAMELOT_STREAM_COPY   dst = src (bytes read + bytes written)
+ *   CAMELOT_STREAM_SPLIT  a fill on [cu_offset, +n_cus) while a reduction of
+ *                         another buffer runs on the next n_cus CUs: the ceiling of
+ *                         the device-global handoff at that producer/consumer split
+ * out[0] = seconds, out[1] = bytes moved, out[2] = GB/s. The library allocates the
+ * buffers; synchronous. EINVAL on bad sizes or shares (multiples of 8 CUs). */
+enum { CAMELOT_STREAM_READ = 0, CAMELOT_STREAM_WRITE = 1, CAMELOT_STREAM_COPY = 2, CAMELOT_STREAM_SPLIT = 3 };
+int32_t camelot_stream_bench(int32_t mode, int64_t bytes, int32_t n_cus, int32_t cu_offset, int32_t reps,
+                             double* out);
 
 /* ------------------------------------------------------------------ handoff benchmark
  * Section VI-B's claim, measured: a producer worker on cu_producer CUs writes
@@ -544,9 +582,13 @@ int32_t camelot_predictor_standardize(float* x, int32_t n, const float* mean, co
  * kind i), but every stage's latency is its solo latency (lat_ns) times exp(y), y =
  * the learned predictor's output for one of its instances in the co-location the
  * candidate forms (all instances of every stage; the network predicts the log
- * slowdown over the solo profile), rounded up to ns. Candidates are taken in the
- * lexicographic order (batch index, N_1, share_1, N_2, share_2, ...) and the
- * objective, constraints and tie rules are those of camelot_alloc_peak. params:
+ * slowdown over the solo profile) clamped to [0, 10] (co-runners never make a stage
+ * faster than alone), rounded up to ns. Candidates are taken in the lexicographic
+ * order (batch index, N_1, share_1, N_2, share_2, ...) and the objective, constraints
+ * and tie rules are those of camelot_alloc_peak. The clamp makes the solo table an
+ * upper bound of every candidate's throughput: the search predicts candidates in
+ * decreasing order of that bound and stops once no candidate left can win, with the
+ * same result as predicting them all (the overhead budget of Section VIII-G). params:
  * device [CAMELOT_PRED_NPARAMS]; mean/std: host [16]. lat_pred_ns (host [n_stages],
  * may be NULL) receives the predicted latencies of the chosen point. */
 int32_t camelot_alloc_peak_learned(const camelot_problem* problem, const camelot_solo_tables* t,

@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["stages.hip", "handoff.hip", "predictor.hip", "noalloc.hip", "runtime.cpp", "learned.cpp", "server.cpp", "alloc.cpp",
+SOURCES = ["stages.hip", "handoff.hip", "predictor.hip", "noalloc.hip", "stream.hip", "runtime.cpp", "learned.cpp", "server.cpp", "alloc.cpp",
            "dtree.cpp"]
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -132,6 +132,10 @@ _SIGS = {
                                       C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "camelot_stage_run_noalloc": (C.c_int32, [C.POINTER(StageDesc), _P, _P, C.c_int32, C.c_int32, C.c_int32,
                                               _P]),
+    "camelot_stream_bench": (C.c_int32, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                         C.POINTER(C.c_double)]),
+    "camelot_pipeline_submit_replay": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, C.c_int64]),
+    "camelot_pipeline_submit_status": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
     "camelot_pipeline_create": (C.c_int32, [C.POINTER(PipelineConfig), C.POINTER(_P)]),
     "camelot_pipeline_footprint": (C.c_int64, [_P]),
     "camelot_pipeline_epoch_ns": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
@@ -385,6 +389,24 @@ def camelot_pipeline_replay(p: int, ids, rows, arrival_ns, payload_row, payload_
                                         prow.ctypes.data, payload_ptr, int(payload_rows)))
 
 
+def camelot_pipeline_submit_replay(p: int, ids, rows, arrival_ns, payload_row, payload: np.ndarray):
+    """Starts the library's paced host submitter; keep `payload` (host array) alive
+    until every request is submitted (camelot_pipeline_submit_status)."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+    prow = np.ascontiguousarray(payload_row, dtype=np.int64)
+    assert payload.flags["C_CONTIGUOUS"]
+    _check(_lib.camelot_pipeline_submit_replay(p, len(ids), ids.ctypes.data, rows.ctypes.data, arr.ctypes.data,
+                                               prow.ctypes.data, payload.ctypes.data, int(payload.shape[0])))
+
+
+def camelot_pipeline_submit_status(p: int) -> int:
+    n = C.c_int64(0)
+    _check(_lib.camelot_pipeline_submit_status(p, C.byref(n)))
+    return n.value
+
+
 def camelot_pipeline_stats_get(p: int) -> PipelineStats:
     s = PipelineStats()
     _check(_lib.camelot_pipeline_stats_get(p, C.byref(s)))
@@ -396,6 +418,16 @@ def camelot_pipeline_destroy(p: int) -> int:
     u = C.c_uint64(0)
     _check(_lib.camelot_pipeline_destroy(p, C.byref(u)))
     return u.value
+
+
+# ------------------------------------------------------------------ share bandwidth
+STREAM_READ, STREAM_WRITE, STREAM_COPY, STREAM_SPLIT = 0, 1, 2, 3
+
+
+def camelot_stream_bench(mode: int, nbytes: int, n_cus: int, cu_offset: int = 0, reps: int = 1) -> dict:
+    out = (C.c_double * 3)()
+    _check(_lib.camelot_stream_bench(mode, nbytes, n_cus, cu_offset, reps, out))
+    return {"seconds": out[0], "bytes": out[1], "gbs": out[2]}
 
 
 # ------------------------------------------------------------------ handoff

@@ -64,6 +64,11 @@ struct EgressRec {
   uint64_t t_arr;
   uint64_t t_done;
   uint64_t t_stage[2 * kMaxStages];
+  // egress position + 1, written by the wave that wrote the record once its other
+  // stores are acknowledged: the host takes a record only when this word matches
+  // (the published egress head alone does not order the stores of other CUs
+  // against it on their way to host memory)
+  uint64_t seq;
 };
 
 // Host-written, device-read control block (pinned).

@@ -349,90 +349,115 @@ int32_t alloc_peak_predicted(const camelot_problem* p, const camelot_solo_tables
     enumerate(p, S, K, nmax, total_inst, bi, 0, 0, 0, c, cands);
   }
   if (cands.empty()) return fail(CAMELOT_EINFEASIBLE, "no candidate allocation");
-  // predicted latencies, in chunks of candidates (one feature row per stage: its
-  // instances are alike)
-  constexpr int64_t kChunk = 16384;
-  std::vector<int64_t> L((size_t)cands.size() * S);
-  {
-    std::vector<float> x((size_t)kChunk * S * CAMELOT_PRED_FEATURES), yhat((size_t)kChunk * S);
-    for (int64_t c0 = 0; c0 < (int64_t)cands.size() && !rc; c0 += kChunk) {
-      const int64_t nc = std::min<int64_t>(kChunk, (int64_t)cands.size() - c0);
-      for (int64_t c = 0; c < nc; ++c) {
-        const Cand& cd = cands[c0 + c];
-        int32_t kinds[CAMELOT_MAX_CORUN], cu[CAMELOT_MAX_CORUN], bis[CAMELOT_MAX_CORUN], first[3];
-        int m = 0;
-        for (int s = 0; s < S; ++s) {
-          first[s] = m;
-          for (int q = 0; q < cd.n[s]; ++q) {
-            kinds[m] = s;
-            cu[m] = (cd.k[s] + 1) * p->cu_step;
-            bis[m] = cd.bi;
-            ++m;
-          }
-        }
-        for (int s = 0; s < S; ++s)
-          feature_row(t, m, kinds, cu, bis, first[s], x.data() + (c * S + s) * CAMELOT_PRED_FEATURES);
-      }
-      rc = pred.predict(x.data(), (int32_t)(nc * S), yhat.data());
-      for (int64_t c = 0; c < nc && !rc; ++c) {
-        const Cand& cd = cands[c0 + c];
-        for (int s = 0; s < S; ++s) {
-          // the predictor gives the log of the co-location slowdown over the solo latency
-          const double y = std::max(-10.0, std::min<double>(yhat[c * S + s], 10.0));
-          const double solo = (double)p->lat_ns[((int64_t)s * K + cd.k[s]) * p->n_batches + cd.bi];
-          L[(c0 + c) * S + s] = std::max<int64_t>(1, (int64_t)std::ceil(solo * std::exp(y)));
-        }
-      }
-    }
-    if (rc) return rc;
-  }
-  // exact selection with the predicted integer latencies (rules of camelot_alloc_peak)
-  bool have = false;
-  camelot_alloc best;
-  int64_t best_lat[3] = {0, 0, 0};
+  // The predictor gives the log of the co-location slowdown over the solo latency,
+  // clamped to [0, 10]: a co-runner never makes a stage faster than it runs alone.
+  // So a candidate's solo-table throughput bounds its predicted one from above and
+  // its solo latency sum bounds its predicted one from below. Candidates that break
+  // a constraint the prediction cannot change (CUs, instances, bandwidth, memory,
+  // the QoS already at solo latencies) are dropped; the rest are predicted in
+  // chunks in decreasing order of the bound, until the best predicted throughput
+  // exceeds the bound of every candidate left. The result is the one a search over
+  // every candidate gives: most throughput, then fewest CUs, then least latency,
+  // then the first candidate in enumeration order.
+  struct Live {
+    int64_t tn, td;    // solo-table throughput bound, queries/s = tn / td
+    int64_t idx;       // enumeration order
+  };
+  std::vector<Live> live;
+  live.reserve(cands.size());
   for (size_t c = 0; c < cands.size(); ++c) {
     const Cand& cd = cands[c];
     const int bi = cd.bi;
     const int64_t b = p->batches[bi];
     int64_t cu = 0, inst = 0, bw = 0, mem = 0, lat = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
     int64_t tn = 0, td = 1;
-    bool has = false;
     for (int s = 0; s < S; ++s) {
       const int kk = cd.k[s], nn = cd.n[s];
-      const int64_t Ls = L[c * S + s];
+      const int64_t Ls = p->lat_ns[((int64_t)s * K + kk) * p->n_batches + bi];
       cu += (int64_t)nn * (kk + 1) * p->cu_step;
       inst += nn;
       bw += nn * p->bw_bps[((int64_t)s * K + kk) * p->n_batches + bi];
       mem += nn * p->mem_bytes[(int64_t)s * p->n_batches + bi];
       lat += Ls;
       const int64_t n1 = (int64_t)nn * b * 1000000000LL;
-      if (!has || cmp_rat(n1, Ls, tn, td) < 0) { tn = n1; td = Ls; }
-      has = true;
+      if (s == 0 || cmp_rat(n1, Ls, tn, td) < 0) { tn = n1; td = Ls; }
     }
     if (cu > p->cu_total || inst > p->max_instances || bw > p->hbm_bw_budget || mem > p->hbm_bytes_budget ||
         lat > p->qos_ns)
       continue;
-    bool better = !have;
-    if (have) {
-      const int c1 = cmp_rat(tn, td, best.thr_num, best.thr_den);
-      better = c1 > 0 || (c1 == 0 && (cu < best.cu_used || (cu == best.cu_used && lat < best.lat_ns)));
+    live.push_back({tn, td, (int64_t)c});
+  }
+  if (live.empty()) return fail(CAMELOT_EINFEASIBLE, "no allocation satisfies the constraints");
+  std::stable_sort(live.begin(), live.end(),
+                   [](const Live& x, const Live& y) { return cmp_rat(x.tn, x.td, y.tn, y.td) > 0; });
+  constexpr int64_t kChunk = 4096;
+  std::vector<float> x((size_t)kChunk * S * CAMELOT_PRED_FEATURES), yhat((size_t)kChunk * S);
+  bool have = false;
+  camelot_alloc best;
+  int64_t best_idx = 0;
+  int64_t best_lat[3] = {0, 0, 0};
+  for (int64_t c0 = 0; c0 < (int64_t)live.size(); c0 += kChunk) {
+    // nothing left can reach the best predicted throughput
+    if (have && cmp_rat(live[c0].tn, live[c0].td, best.thr_num, best.thr_den) < 0) break;
+    const int64_t nc = std::min<int64_t>(kChunk, (int64_t)live.size() - c0);
+    for (int64_t c = 0; c < nc; ++c) {
+      const Cand& cd = cands[live[c0 + c].idx];
+      int32_t kinds[CAMELOT_MAX_CORUN], cu[CAMELOT_MAX_CORUN], bis[CAMELOT_MAX_CORUN], first[3];
+      int m = 0;
+      for (int s = 0; s < S; ++s) {
+        first[s] = m;
+        for (int q = 0; q < cd.n[s]; ++q) {
+          kinds[m] = s;
+          cu[m] = (cd.k[s] + 1) * p->cu_step;
+          bis[m] = cd.bi;
+          ++m;
+        }
+      }
+      for (int s = 0; s < S; ++s)
+        feature_row(t, m, kinds, cu, bis, first[s], x.data() + (c * S + s) * CAMELOT_PRED_FEATURES);
     }
-    if (!better) continue;
-    have = true;
-    std::memset(&best, 0, sizeof best);
-    best.n_stages = S;
-    best.batch = (int32_t)b;
-    best.batch_index = bi;
-    for (int s = 0; s < S; ++s) {
-      best.n[s] = cd.n[s];
-      best.cu[s] = (cd.k[s] + 1) * p->cu_step;
-      best_lat[s] = L[c * S + s];
+    if ((rc = pred.predict(x.data(), (int32_t)(nc * S), yhat.data()))) return rc;
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t idx = live[c0 + c].idx;
+      const Cand& cd = cands[idx];
+      const int bi = cd.bi;
+      const int64_t b = p->batches[bi];
+      int64_t L[3];
+      int64_t cu = 0, lat = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0, tn = 0, td = 1;
+      for (int s = 0; s < S; ++s) {
+        const double y = std::max(0.0, std::min<double>(yhat[c * S + s], 10.0));
+        const double solo = (double)p->lat_ns[((int64_t)s * K + cd.k[s]) * p->n_batches + bi];
+        L[s] = std::max<int64_t>(1, (int64_t)std::ceil(solo * std::exp(y)));
+        cu += (int64_t)cd.n[s] * (cd.k[s] + 1) * p->cu_step;
+        lat += L[s];
+        const int64_t n1 = (int64_t)cd.n[s] * b * 1000000000LL;
+        if (s == 0 || cmp_rat(n1, L[s], tn, td) < 0) { tn = n1; td = L[s]; }
+      }
+      if (lat > p->qos_ns) continue;
+      bool better = !have;
+      if (have) {
+        const int c1 = cmp_rat(tn, td, best.thr_num, best.thr_den);
+        better = c1 > 0 || (c1 == 0 && (cu < best.cu_used || (cu == best.cu_used && (lat < best.lat_ns ||
+                                                                                   (lat == best.lat_ns && idx < best_idx)))));
+      }
+      if (!better) continue;
+      have = true;
+      best_idx = idx;
+      std::memset(&best, 0, sizeof best);
+      best.n_stages = S;
+      best.batch = (int32_t)b;
+      best.batch_index = bi;
+      for (int s = 0; s < S; ++s) {
+        best.n[s] = cd.n[s];
+        best.cu[s] = (cd.k[s] + 1) * p->cu_step;
+        best_lat[s] = L[s];
+      }
+      const int64_t g = std::gcd(tn, td);
+      best.thr_num = tn / g;
+      best.thr_den = td / g;
+      best.lat_ns = lat;
+      best.cu_used = cu;
     }
-    const int64_t g = std::gcd(tn, td);
-    best.thr_num = tn / g;
-    best.thr_den = td / g;
-    best.lat_ns = lat;
-    best.cu_used = cu;
   }
   if (!have) return fail(CAMELOT_EINFEASIBLE, "no allocation satisfies the constraints");
   *out = best;

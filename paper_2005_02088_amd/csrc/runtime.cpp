@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -590,6 +591,11 @@ struct camelot_pipeline {
   bool stopped = false;
   int64_t footprint = 0;
   std::atomic<bool> relay_stop{false};
+  // paced host submission (camelot_pipeline_submit_replay)
+  std::thread submitter;
+  std::atomic<bool> submit_stop{false};
+  std::atomic<int32_t> submit_rc{0};
+  std::atomic<int64_t> submit_count{0};
 };
 
 static void* pinned(size_t bytes) {
@@ -973,9 +979,18 @@ static int32_t worker_error(camelot_pipeline* p) {
   return CAMELOT_OK;
 }
 
+static int32_t submit_at(camelot_pipeline* p, uint64_t query_id, const void* payload, int32_t rows,
+                         int64_t arrival_host_ns);
+
 extern "C" int32_t camelot_pipeline_submit(camelot_pipeline* p, uint64_t query_id, const void* payload,
                                            int32_t rows) {
   clear_error();
+  return submit_at(p, query_id, payload, rows, -1);
+}
+
+// arrival_host_ns < 0: the query arrives now
+static int32_t submit_at(camelot_pipeline* p, uint64_t query_id, const void* payload, int32_t rows,
+                         int64_t arrival_host_ns) {
   if (!p) return fail(CAMELOT_EINVAL, "pipeline is NULL");
   if (p->stopped) return fail(CAMELOT_ESTOPPED, "pipeline is stopped");
   if (p->cfg.ingest != CAMELOT_INGEST_HOST) return fail(CAMELOT_EINVAL, "pipeline uses replay ingest");
@@ -992,7 +1007,9 @@ extern "C" int32_t camelot_pipeline_submit(camelot_pipeline* p, uint64_t query_i
               (size_t)rows * (p->in_b[0] + p->cfg.side_bytes));
   IngestRec rec;
   rec.id = query_id;
-  rec.t_arr = (uint64_t)host_now_ticks(p);
+  rec.t_arr = (uint64_t)(arrival_host_ns < 0
+                             ? host_now_ticks(p)
+                             : p->calib_dev_ticks + ns_to_ticks(arrival_host_ns - p->calib_host_ns, p->dev.wclk_hz));
   rec.payload_off = slot * (uint64_t)p->ingest_slot_bytes;
   rec.rows = (uint32_t)rows;
   rec.valid = (uint32_t)(p->head / (uint64_t)p->cfg.ingest_capacity + 1);
@@ -1004,6 +1021,77 @@ extern "C" int32_t camelot_pipeline_submit(camelot_pipeline* p, uint64_t query_i
   p->submitted_rows += rows;
   p->submitted_req += 1;
   return CAMELOT_OK;
+}
+
+// The paced submitter: request r goes through the submit path once arrival_ns[r]
+// has passed since the call (busy-waiting on the host clock), retried while the
+// ingest queue is full, stamped with its scheduled arrival time.
+static void submit_loop(camelot_pipeline* p, std::vector<uint64_t> ids, std::vector<int32_t> rows,
+                        std::vector<int64_t> arr, std::vector<int64_t> prow, const uint8_t* payload,
+                        int64_t row_bytes, int64_t t0) {
+  for (size_t r = 0; r < ids.size(); ++r) {
+    const int64_t due = t0 + arr[r];
+    while (host_ns() < due)
+      if (p->submit_stop.load(std::memory_order_relaxed)) return;
+    for (;;) {
+      // the query's arrival is its scheduled time: a submitter that falls behind
+      // shows up in the latencies, not hidden by a later stamp
+      const int32_t rc = submit_at(p, ids[r], payload + prow[r] * row_bytes, rows[r], due);
+      if (rc == CAMELOT_OK) break;
+      if (rc != CAMELOT_EAGAIN || p->submit_stop.load(std::memory_order_relaxed)) {
+        p->submit_rc.store(rc);
+        return;
+      }
+      std::this_thread::yield();
+    }
+    p->submit_count.store((int64_t)r + 1, std::memory_order_relaxed);
+  }
+}
+
+static void stop_submitter(camelot_pipeline* p) {
+  if (p->submitter.joinable()) {
+    p->submit_stop.store(true);
+    p->submitter.join();
+  }
+}
+
+extern "C" int32_t camelot_pipeline_submit_replay(camelot_pipeline* p, int32_t n_req, const uint64_t* ids,
+                                                  const int32_t* rows, const int64_t* arrival_ns,
+                                                  const int64_t* payload_row, const void* payload,
+                                                  int64_t payload_rows) {
+  clear_error();
+  if (!p) return fail(CAMELOT_EINVAL, "pipeline is NULL");
+  if (p->cfg.ingest != CAMELOT_INGEST_HOST) return fail(CAMELOT_EINVAL, "pipeline uses replay ingest");
+  if (p->submitter.joinable()) return fail(CAMELOT_EINVAL, "a paced submission already ran on this pipeline");
+  if (n_req < 0 || (n_req > 0 && (!ids || !rows || !arrival_ns || !payload_row || !payload)))
+    return fail(CAMELOT_EINVAL, "replay arrays are NULL");
+  for (int r = 0; r < n_req; ++r) {
+    if (rows[r] < 1 || rows[r] > p->cfg.max_rows_per_request)
+      return fail(CAMELOT_EINVAL, "request %d: rows must be in 1..%d", r, p->cfg.max_rows_per_request);
+    if ((r > 0 && ids[r] <= ids[r - 1]) || (p->any_id && ids[r] <= p->last_id))
+      return fail(CAMELOT_EINVAL, "request ids must increase");
+    if (arrival_ns[r] < 0 || (r > 0 && arrival_ns[r] < arrival_ns[r - 1]))
+      return fail(CAMELOT_EINVAL, "arrival times must be non-decreasing and >= 0");
+    if (payload_row[r] < 0 || payload_row[r] + rows[r] > payload_rows)
+      return fail(CAMELOT_EINVAL, "request %d: payload rows outside the buffer", r);
+  }
+  p->submit_rc.store(0);
+  p->submit_count.store(0);
+  p->submit_stop.store(false);
+  p->submitter = std::thread(submit_loop, p, std::vector<uint64_t>(ids, ids + n_req),
+                             std::vector<int32_t>(rows, rows + n_req), std::vector<int64_t>(arrival_ns, arrival_ns + n_req),
+                             std::vector<int64_t>(payload_row, payload_row + n_req), (const uint8_t*)payload,
+                             p->in_b[0] + p->cfg.side_bytes, host_ns());
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_pipeline_submit_status(camelot_pipeline* p, int64_t* submitted) {
+  clear_error();
+  if (!p || !submitted) return fail(CAMELOT_EINVAL, "bad status arguments");
+  *submitted = p->submit_count.load();
+  const int32_t rc = p->submit_rc.load();
+  return rc ? fail(rc, "paced submission stopped with error %d after %lld requests", rc, (long long)*submitted)
+            : CAMELOT_OK;
 }
 
 extern "C" int32_t camelot_pipeline_replay(camelot_pipeline* p, int32_t n_req, const uint64_t* ids,
@@ -1049,6 +1137,20 @@ extern "C" int32_t camelot_pipeline_replay(camelot_pipeline* p, int32_t n_req, c
   return CAMELOT_OK;
 }
 
+// Waits (bounded) until the egress record at position pos carries its sequence word:
+// the device writes it after the record's other fields are acknowledged.
+static int32_t await_record(camelot_pipeline* p, uint64_t pos, const uint8_t* rec) {
+  const uint64_t* seq = (const uint64_t*)(rec + offsetof(EgressRec, seq));
+  if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == pos + 1) return CAMELOT_OK;
+  const int64_t t_end = host_ns() + 1000000000LL;
+  while (__atomic_load_n(seq, __ATOMIC_ACQUIRE) != pos + 1) {
+    if (host_ns() > t_end)
+      return fail(CAMELOT_EDEVICE, "egress record %llu published without its contents", (unsigned long long)pos);
+    std::this_thread::yield();
+  }
+  return CAMELOT_OK;
+}
+
 extern "C" int32_t camelot_pipeline_drain(camelot_pipeline* p, camelot_result* out, int32_t max,
                                           int32_t* n_out, int64_t timeout_ns) {
   clear_error();
@@ -1076,6 +1178,7 @@ extern "C" int32_t camelot_pipeline_drain(camelot_pipeline* p, camelot_result* o
   for (uint64_t j = 0; j < n; ++j) {
     const uint64_t slot = (p->egress_tail + j) % (uint64_t)p->cfg.egress_capacity;
     const uint8_t* rec = p->egress + slot * p->rec_bytes;
+    if (int32_t rc = await_record(p, p->egress_tail + j, rec)) return rc;
     EgressRec h;
     std::memcpy(&h, rec, sizeof h);
     camelot_result& r = out[j];
@@ -1122,6 +1225,7 @@ extern "C" int32_t camelot_pipeline_drain_latency(camelot_pipeline* p, uint64_t*
   for (uint64_t j = 0; j < n; ++j) {
     const uint64_t slot = (p->egress_tail + j) % (uint64_t)p->cfg.egress_capacity;
     const EgressRec* h = (const EgressRec*)(p->egress + slot * p->rec_bytes);
+    if (int32_t rc = await_record(p, p->egress_tail + j, (const uint8_t*)h)) return rc;
     ids[j] = h->id;
     lat_ns[j] = (int64_t)ticks_to_ns((int64_t)h->t_done - (int64_t)h->t_arr, hz);
   }
@@ -1157,6 +1261,7 @@ extern "C" int32_t camelot_pipeline_stats_get(camelot_pipeline* p, camelot_pipel
 extern "C" int32_t camelot_pipeline_destroy(camelot_pipeline* p, uint64_t* undelivered) {
   clear_error();
   if (!p) return fail(CAMELOT_EINVAL, "pipeline is NULL");
+  stop_submitter(p);
   p->stopped = true;
   __atomic_store_n(&p->hctl->stop, 1ull, __ATOMIC_RELEASE);
   int32_t rc = CAMELOT_OK;

@@ -96,6 +96,20 @@ __device__ __forceinline__ BatchRows batch_rows(const WorkerArgs& a, const Batch
 __device__ __forceinline__ int xwg(const WorkerArgs&) { return (int)blockIdx.x; }
 __device__ __forceinline__ int xnwg(const WorkerArgs& a) { return (int)gridDim.x - a.ctl_wg; }
 
+// After a wave has written its result rows (r0, r0 + stride, ... below rows) to the
+// egress ring: a system-scope release (waits until the wave's stores are
+// acknowledged), then each record's sequence word, one lane per row.
+__device__ __forceinline__ void seal_rows(const WorkerArgs& a, const BatchDesc* bd, int rows, int r0, int stride,
+                                          int lane) {
+  if (a.out_kind != kOutEgress || r0 >= rows) return;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  for (int r = r0 + lane * stride; r < rows; r += 64 * stride) {
+    const uint64_t pos = bd->egress_base + (uint64_t)r;
+    EgressRec* h = (EgressRec*)(a.egress + (pos % (uint64_t)a.egress_cap) * (uint64_t)a.rec_bytes);
+    __hip_atomic_store(&h->seq, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // ------------------------------------------------------------------ GEMM + ReLU (FP32)
 // Unit = (64 output columns, 8 rows) per workgroup; the 4 waves split K in
 // interleaved 64-wide chunks and their partial sums are added in a fixed order,
@@ -187,6 +201,7 @@ __device__ void exec_gemm_argmax(const WorkerArgs& a, WorkerCtl* ctl, const Batc
     emit_row(a, br.bd, rows, r, 1, s_idx[w], s_val[w], lane);
     wave_lds_sync();
   }
+  seal_rows(a, br.bd, rows, xwg(a) * kWaves + w, xnwg(a) * kWaves, lane);
 }
 
 // Raw buffer loads: a 32-bit per-lane offset (a scalar offset for the rest), and an
@@ -353,6 +368,7 @@ __device__ void exec_topk(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& 
     emit_row(a, br.bd, rows, r, k, s_idx[w], s_val[w], lane);
     wave_lds_sync();
   }
+  seal_rows(a, br.bd, rows, xwg(a) * kWaves + w, xnwg(a) * kWaves, lane);
 }
 
 // ------------------------------------------------------------------ log-mel front end
@@ -839,30 +855,50 @@ __device__ __forceinline__ void mlp_input_to_frag(const BatchRows& br, uint16_t*
   }
 }
 
-// One layer on the BF16 (fragment-order) input: the unit shape is the largest of
-// (8 row blocks x 4 strips), (8 x 2), (4 x 2), (4 x 1) that still gives every
-// workgroup a unit (larger units read the activations and weights fewer times).
+// One layer on the BF16 (fragment-order) input. The unit shape (row blocks x column
+// strips: 8 x 4, 8 x 2, 4 x 2 or 4 x 1) is the one with the least work on the
+// busiest workgroup: rounds of the grid (ceil(units / workgroups)) times a unit's
+// cost, the activation and weight bytes it streams ((row blocks + strips) per K
+// element) plus a fixed per-unit cost of about three stages (pipeline fill, stores).
+// A shape that fits in fewer rounds wins on a larger share only if it is cheaper,
+// so the layer's time never grows when CUs are added; ties go to the larger unit.
+// Every shape gives the same bits (one MFMA chain per output in K order).
+__device__ __forceinline__ int mlp_bf16_shape(int nrt, int N, int K, int P) {
+  constexpr int kRw[4] = {2, 2, 1, 1}, kCt[4] = {4, 2, 2, 1};
+  int best = 3;
+  int64_t best_cost = INT64_MAX;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rw = kRw[i], ct = kCt[i], rpu = 4 * rw;
+    if (N % (16 * ct) != 0 || (rw == 2 && nrt <= 4)) continue;
+    const int units = ((nrt + rpu - 1) / rpu) * (N / (16 * ct));
+    const int64_t rounds = (units + P - 1) / P;
+    const int64_t cost = rounds * (int64_t)(K + 3 * 128) * (rpu + ct);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = i;
+    }
+  }
+  return best;
+}
+
 __device__ __forceinline__ void mlp_bf16_layer(const BatchRows& rp, const uint16_t* hin, int stride, const uint16_t* W,
                                                int K, int N, int rows, bool last, uint16_t* hout, float* o,
                                                uint8_t* lds, int w, int lane, int tid, int wgi, int nwg) {
-  const int nrt = (rows + 15) >> 4, P = nwg;
-  const bool even = (N % 32) == 0;
-  const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
-  if (N % 64 == 0 && nrt > 4 && ((nrt + 7) / 8) * (N / 64) >= P)
-    mlp_row_layer<2, 4, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
-  else if (even && nrt > 4 && u22 >= P)
-    mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
-  else if (even && u12 >= P)
-    mlp_row_layer<1, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
-  else
-    mlp_row_layer<1, 1, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
+  switch (mlp_bf16_shape((rows + 15) >> 4, N, K, nwg)) {
+    case 0: mlp_row_layer<2, 4, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg); break;
+    case 1: mlp_row_layer<2, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg); break;
+    case 2: mlp_row_layer<1, 2, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg); break;
+    default: mlp_row_layer<1, 1, false>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg); break;
+  }
 }
 
 // All layers of a batch. The first layer reads the FP32 input rows: the units read
-// and round them themselves (unit shapes (8 x 2), (4 x 2), (4 x 1)), or, for batches
-// of more than 32 rows whose units would take two or more rounds of the grid, the
-// rows are first rounded into fragment order once for the whole grid (one more
-// grid barrier) and the layer runs like the others. Both give the same bits.
+// and round them themselves (unit shapes (8 x 2), (4 x 2), (4 x 1)) when one round of
+// the grid covers them, or, for batches of more than 32 rows whose units would take
+// two or more rounds, the rows are first rounded into fragment order once for the
+// whole grid (one more grid barrier) and the layer runs like the others. Both give
+// the same bits.
 __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& rp, int rows, uint8_t* out,
                                              uint8_t* lds, int w, int lane, int tid) {
   const int L = a.sp.n_layers, stride = a.sp.scratch_stride;
@@ -883,7 +919,7 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
       const int u22 = ((nrt + 7) / 8) * (N / 32), u12 = ((nrt + 3) / 4) * (N / 32);
       const int shape = (even && nrt > 4 && u22 >= P) ? 2 : (even && u12 >= P) ? 1 : 0;
       const int units = shape == 2 ? u22 : shape == 1 ? u12 : ((nrt + 3) / 4) * (N / 16);
-      if (nrt <= 2 || units < 2 * P) {
+      if (nrt <= 2 || units <= P) {
         if (shape == 2)
           mlp_row_layer<2, 2, true>(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
         else if (shape == 1)

@@ -199,7 +199,7 @@ def test_tree_allocator_matches_brute_force():
                         yp = OD.predict(otree, f[[0, n0]])
                         L = []
                         for s, k in ((0, k0), (1, k1)):
-                            y = max(-10.0, min(float(yp[s]), 10.0))
+                            y = max(0.0, min(float(yp[s]), 10.0))     # co-runners never speed up
                             L.append(max(1, math.ceil(float(lat[s, k, bi]) * math.exp(y))))
                         tot = sum(L)
                         if tot > 400_000:

@@ -190,6 +190,81 @@ def test_c1_multi_row_requests(torch, cm):
     assert O.normwise_err(gval, rval) <= 2e-2
 
 
+def test_c1_paced_host_submission(torch, cm):
+    """The library's paced host submitter: uneven requests from host memory at Poisson
+    times, through a small ingest ring (so it waits on back-pressure), every row
+    delivered once, in order, with the oracle's values."""
+    n_req = 300
+    rows = G.request_rows(n_req, seed=8, hi=16)
+    n_rows = int(rows.sum())
+    ws, d_ws, stages = c1_stages(torch)
+    audio = G.c1_audio_fast(n_rows, seed=9)
+    prow = np.concatenate([[0], np.cumsum(rows)[:-1]])
+    arr = G.poisson_arrivals_ns(n_req, 100_000, seed=8)
+    ids = np.arange(1, n_req + 1)
+    torch.cuda.synchronize()
+    log(f"c1 paced host submission: {n_req} requests, {n_rows} rows, ingest ring of 64")
+    cfg = cm.pipeline_config(stages, (32, 128, 32), max_batch=64, max_rows_per_request=16, ingest_capacity=64,
+                             idle_timeout_ns=5_000_000_000)
+    p = cm.camelot_pipeline_create(cfg)
+    try:
+        cm.camelot_pipeline_submit_replay(p, ids, rows, arr, prow, audio)
+        res = drain_all(cm, p, n_rows)
+        assert cm.camelot_pipeline_submit_status(p) == n_req
+        stats = cm.camelot_pipeline_stats_get(p)
+    finally:
+        und = cm.camelot_pipeline_destroy(p)
+    assert und == 0 and len(res) == n_rows
+    assert [(r.query_id, r.row) for r in res] == [(int(q), j) for q, rr in zip(ids, rows) for j in range(rr)]
+    assert OD.check_delivery([int(q) for q in ids], list(dict.fromkeys(r.query_id for r in res))) == []
+    assert all(stats.worker_status[i] in (0, 4) for i in range(3))
+    scores = O.mlp_bf16(O.log_mel(audio), ws)
+    _, rval = O.topk(scores, 10)
+    gval = np.array([list(r.val[:10]) for r in res])
+    assert O.normwise_err(gval, rval) <= 2e-2
+    with pytest.raises(cm.CamelotError):          # replay ingest has no host submitter
+        q = cm.camelot_pipeline_create(cm.pipeline_config(stages, (32, 128, 32), ingest=cm.INGEST_REPLAY,
+                                                          idle_timeout_ns=1_000_000_000))
+        try:
+            cm.camelot_pipeline_submit_replay(q, ids[:1], rows[:1], arr[:1], prow[:1], audio)
+        finally:
+            cm.camelot_pipeline_destroy(q)
+
+
+def test_host_ingest_delivery_at_a_million_queries(torch, cm):
+    """A million single-row queries submitted from host memory at 2.5 M/s into the
+    speech pipeline (PCIe busy with payload reads): every result record is whole
+    when the host takes it, in submit order. Without the per-record sequence word a
+    record could be taken before its fields landed in host memory (seen once in about
+    a million rows under this load)."""
+    n = 1_000_000
+    ws, d_ws, stages = c1_stages(torch)
+    pool = G.c1_audio_fast(4096, seed=12)
+    arr = G.poisson_arrivals_ns(n, 2_500_000, seed=12)
+    ids = np.arange(1, n + 1, dtype=np.uint64)
+    torch.cuda.synchronize()
+    log("host ingest: 1M queries at 2.5 M/s, CUs 64 / 160 / 16")
+    cfg = cm.pipeline_config(stages, (64, 160, 16), max_batch=128, batch_target=128,
+                             batch_timeout_ns=2_000_000, ring_depth=4, ingest_capacity=1 << 15,
+                             egress_capacity=1 << 20, idle_timeout_ns=5_000_000_000)
+    p = cm.camelot_pipeline_create(cfg)
+    got = np.empty(n, np.uint64)
+    done = 0
+    ci, cl = np.empty(1 << 16, np.uint64), np.empty(1 << 16, np.int64)
+    try:
+        cm.camelot_pipeline_submit_replay(p, ids, np.ones(n, np.int32), arr, np.arange(n) % 4096, pool)
+        t_end = time.monotonic() + 30
+        while done < n and time.monotonic() < t_end:
+            k = cm.camelot_pipeline_drain_latency(p, ci, cl, 100_000_000)
+            got[done:done + k] = ci[:k]
+            done += k
+    finally:
+        cm.camelot_pipeline_destroy(p)
+    assert done == n
+    bad = np.nonzero(got != ids)[0]
+    assert len(bad) == 0, f"{len(bad)} records out of place, first at {bad[0]}: {got[bad[0]]}"
+
+
 def test_backpressure_and_destroy_in_flight(torch, cm):
     (w1, w2), dws, stages = c0_stages(torch)
     x = G.c0_queries(64, seed=3)
