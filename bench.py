@@ -333,6 +333,18 @@ def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=4600, epochs=60):
     pred_dt = solo[te] * np.exp(dt.predict(X[te]).astype(np.float64))
     mape_dt = float(np.mean(np.abs(pred_dt[co] - meas[co]) / meas[co]))
     dt_nodes = int(len(dt.export()["feat"]))
+    # the paper's predictor also gives a stage's global-memory bandwidth and its
+    # throughput under co-location (Section VII-A): trees on log(HBM bytes/s) and
+    # log(batches/s) of the same runs, judged on the held-out co-located samples
+    bts = np.array([bytes_[r.kinds[j], r.bi[j]] for r in recs for j in range(r.m)], np.float64)
+    bsz = np.array([BATCHES[r.bi[j]] for r in recs for j in range(r.m)], np.float64)
+    ns_meas = solo * np.exp(y.astype(np.float64))
+    side = {}
+    for name, target in (("bandwidth", np.log(bts / (ns_meas * 1e-9))), ("throughput", np.log(bsz / (ns_meas * 1e-9)))):
+        tr_t = cm.camelot_dt_fit(X[tr], target[tr].astype(np.float32), DT_MAX_DEPTH, DT_MIN_LEAF)
+        pr = np.exp(tr_t.predict(X[te]).astype(np.float64))
+        ms = np.exp(target[te])
+        side[name] = float(np.mean(np.abs(pr[co] - ms[co]) / ms[co]))
     t0 = time.perf_counter()
     a, lp = cm.camelot_alloc_peak_learned(prob, tabs, dp.data_ptr(), mean, std)
     t_alloc = time.perf_counter() - t0
@@ -347,7 +359,9 @@ def learned_allocation(cm, G, torch, sp, lat, prob, n_runs=4600, epochs=60):
             "train_s_per_epoch": t_train / max(epochs, 1), "predict_call_us": t_pred_call * 1e6,
             "loss_first_last": [float(losses[0]), float(losses[-1])], "mape_colocated_learned": mape_l,
             "mape_colocated_solo_table": mape_s, "alloc_ms": t_alloc * 1e3,
-            "decision_tree": {"mape_colocated": mape_dt, "max_depth": DT_MAX_DEPTH, "min_leaf": DT_MIN_LEAF,
+            "decision_tree": {"mape_colocated": mape_dt, "mape_colocated_bandwidth": side["bandwidth"],
+                              "mape_colocated_throughput": side["throughput"],
+                              "max_depth": DT_MAX_DEPTH, "min_leaf": DT_MIN_LEAF,
                               "nodes": dt_nodes, "fit_ms": t_dt * 1e3, "allocation": dt_alloc}}
     log(f"learned predictor: {info}")
     return (a.as_dict() if a is not None else None), [int(v) for v in lp[:3]], info
@@ -406,7 +420,7 @@ def serving_sweep(cm, G, torch, sp, trial_s):
     info = {"pipelines": [p[0] for p in pipes], "request_rows": "U{1..128}", "qos_ns": QOS_NS, "steps": []}
     t_start = time.perf_counter()
     # solo tables of every stage (one-shot stage kernel, device time per batch)
-    probs, peaks = [], []
+    lats, peaks = [], []
     for pi, (name, stages, _) in enumerate(pipes):
         S = len(stages)
         lat = np.zeros((S, K, len(BATCHES)), np.int64)
@@ -415,18 +429,21 @@ def serving_sweep(cm, G, torch, sp, trial_s):
             if s == 0:
                 src = pools[pi]
             else:
-                src = dev(np.random.default_rng(s).standard_normal((128, ib // 4)).astype(np.float32))
+                src = dev(G.rng("tables", 50 + s).standard_normal((128, ib // 4)).astype(np.float32))
             dst = torch.empty(128 * max(ob, 8) * 2 // 4 + 64, dtype=torch.float32, device="cuda")
             torch.cuda.synchronize()
             for k, share in enumerate(SWEEP_SHARES):
                 for j, b in enumerate(BATCHES):
                     ns = cm.camelot_stage_run(st, src.data_ptr(), dst.data_ptr(), b, share, 0, 4, device=True)
                     lat[s, k, j] = max(1, int(math.ceil(ns)))
-        mem = np.zeros((S, len(BATCHES)), np.int64)
-        probs.append(lambda total, lat=lat, mem=mem, S=S: cm.ProblemArrays(
-            cu_total=total, cu_step=8, max_instances=S, max_inst_per_stage=1, batches=BATCHES, qos_ns=QOS_NS,
-            hbm_bytes_budget=1 << 40, hbm_bw_budget=1 << 62, lat_ns=lat, bw_bps=np.zeros_like(lat), mem_bytes=mem))
+        lats.append(lat)
     info["profile_s"] = time.perf_counter() - t_start
+
+    def problem(pi, lat):
+        S = lat.shape[0]
+        return cm.ProblemArrays(cu_total=64, cu_step=8, max_instances=S, max_inst_per_stage=1, batches=BATCHES,
+                                qos_ns=QOS_NS, hbm_bytes_budget=1 << 40, hbm_bw_budget=1 << 62, lat_ns=lat,
+                                bw_bps=np.zeros_like(lat), mem_bytes=np.zeros((S, len(BATCHES)), np.int64))
 
     def run_mix(allocs, rates, seed):
         """All pipelines together, pipeline i on allocs[i] at offset 64 i, Poisson
@@ -473,8 +490,13 @@ def serving_sweep(cm, G, torch, sp, trial_s):
                 np.maximum.at(req_lat, rid[i].astype(np.int64) - 1, lat[i])
                 srt = np.sort(req_lat)
                 p50, p99 = int(srt[math.ceil(0.5 * n) - 1]), int(srt[math.ceil(0.99 * n) - 1])
+                st = cm.camelot_pipeline_stats_get(hs[i])
+                S = len(pipes[i][1])
+                nb = [max(int(st.batches[q]), 1) for q in range(S)]
                 out.append({"done": True, "p50_ns": p50, "p99_ns": p99, "qps": n / (arr[-1] * 1e-9),
-                            "qos_met": p99 <= QOS_NS})
+                            "qos_met": p99 <= QOS_NS,
+                            "busy_us": [round(st.busy_ns[q] / nb[q] / 1e3, 2) for q in range(S)],
+                            "rows_per_batch": [round(st.rows[q] / nb[q], 1) for q in range(S)]})
         finally:
             cm.camelot_server_destroy(server)
         return out
@@ -483,21 +505,35 @@ def serving_sweep(cm, G, torch, sp, trial_s):
     # with the whole mix running at the same fraction
     peak_allocs = []
     for pi in range(4):
-        a = cm.camelot_alloc_peak(probs[pi](64)).as_dict()
+        a = cm.camelot_alloc_peak(problem(pi, lats[pi])).as_dict()
         peak_allocs.append(a)
         peaks.append(a["thr_num"] / a["thr_den"] / mean_rows)      # requests/s predicted
-    lo, hi, best = 0.0, 1.5, None
+    lo, hi, best, best_run = 0.0, 1.5, None, None
     for it in range(6):
         f = 1.0 if it == 0 else (lo + hi) / 2
         r = run_mix(peak_allocs, [f * p for p in peaks], seed=it)
         ok = all(x["done"] and x["qos_met"] for x in r)
         log(f"  [serving mix peak] {f:.3f} x predicted -> ok={ok} {[round(x.get('p99_ns', 0) / 1e6, 2) for x in r]} ms")
         if ok:
-            lo, best = f, f
+            lo, best, best_run = f, f, r
         else:
             hi = f
     scale = best if best else lo
     measured = [scale * p for p in peaks]
+    # Eq. 3 below runs on each pipeline's table plus the per-batch cost the solo
+    # kernels miss in the mix (busy time per batch at the peak run minus the table's
+    # latency at its share and batch): the co-located stages are slower than alone
+    cal = []
+    for pi in range(4):
+        lat = lats[pi].copy()
+        if best_run is not None:
+            a = peak_allocs[pi]
+            for q in range(lat.shape[0]):
+                rb = best_run[pi]["rows_per_batch"][q]
+                j = next((j for j, b in enumerate(BATCHES) if b >= rb), len(BATCHES) - 1)
+                extra = int(best_run[pi]["busy_us"][q] * 1e3) - int(lats[pi][q, a["cu"][q] // 8 - 1, j])
+                lat[q] = np.where(lat[q] > 0, lat[q] + max(0, extra), 0)
+        cal.append(lat)
     info["peak_allocations"] = [{"cu": a["cu"], "batch": a["batch"]} for a in peak_allocs]
     info["peak_qps"] = measured
     for step in range(1, 11):
@@ -505,17 +541,189 @@ def serving_sweep(cm, G, torch, sp, trial_s):
         allocs = []
         for pi in range(4):
             load_rows = f * measured[pi] * mean_rows
-            m = cm.camelot_alloc_min(probs[pi](64), int(load_rows * 1000), 1000)
+            m = cm.camelot_alloc_min(problem(pi, cal[pi]), int(load_rows * 1000), 1000)
             allocs.append(m.as_dict() if m is not None else peak_allocs[pi])
         r = run_mix(allocs, [f * q for q in measured], seed=100 + step)
         cus = int(sum(sum(a["cu"]) for a in allocs))
-        info["steps"].append({"load_frac": f, "cus_used": cus, "cus": [a["cu"] for a in allocs],
+        info["steps"].append({"load_frac": f, "cus_used": cus, "qos_met": all(x.get("qos_met") for x in r),
+                              "cus": [a["cu"] for a in allocs],
                               "batches": [a["batch"] for a in allocs], "pipelines": r})
         log(f"  [serving sweep] {int(f * 100)}% load: {cus} CUs, p99 ms "
             f"{[round(x.get('p99_ns', 0) / 1e6, 2) for x in r]}, qps {[round(x.get('qps', 0)) for x in r]}")
     info["sweep_s"] = time.perf_counter() - t_start
     del keep
     return info
+
+
+# ---------------------------------------------------------------- artifact suite
+ART_P_TABLE_WORDS = 1 << 24        # 64 MiB of pinned host memory (the PCIe stages' source)
+ART_M_TABLE_WORDS = 1 << 28        # 1 GiB of device memory (beyond the 256 MB MALL)
+
+
+def replay_trial(cm, G, stages, pool, cu, n_inst, batch, rate, duration_s, seed, failures):
+    """One Poisson replay of single-row queries through a pipeline; p99 and whether
+    it met the QoS (the speech bench's trial, for any pipeline)."""
+    import numpy as np
+    n = int(min(max(rate * duration_s, 2000), 4_000_000))
+    arr = G.poisson_arrivals_ns(n, rate, seed=seed, sub=int(rate) % 100000)
+    ids = np.arange(1, n + 1, dtype=np.uint64)
+    cfg = cm.pipeline_config(stages, cu, max_batch=batch, batch_target=batch, batch_timeout_ns=QOS_NS // 4,
+                             ring_depth=max(4, 2 * max(n_inst)), ingest=cm.INGEST_REPLAY, egress_capacity=1 << 20,
+                             idle_timeout_ns=5_000_000_000, n_inst=n_inst)
+    p = cm.camelot_pipeline_create(cfg)
+    lat = np.empty(n, np.int64)
+    done, late = 0, 0
+    ci, cl = np.empty(1 << 16, np.uint64), np.empty(1 << 16, np.int64)
+    try:
+        cm.camelot_pipeline_replay(p, ids, np.ones(n, np.int32), arr, np.arange(n) % pool.shape[0], pool.data_ptr(),
+                                   pool.shape[0])
+        deadline = time.perf_counter() + duration_s * 3 + 2
+        while done < n and time.perf_counter() < deadline:
+            k = cm.camelot_pipeline_drain_latency(p, ci, cl, 100_000_000)
+            m = min(k, n - done)
+            lat[done:done + m] = cl[:m]
+            late += int(np.count_nonzero(cl[:m] > QOS_NS))
+            done += m
+            if late > 0.011 * n:
+                break
+    except cm.CamelotError as e:
+        failures.append(f"artifact pipeline {cu} x {n_inst}: {e}")
+        return {"ok": False, "p99": math.inf}
+    finally:
+        cm.camelot_pipeline_destroy(p)
+    if done < n:
+        return {"ok": False, "p99": math.inf}
+    srt = np.sort(lat[n // 10:])
+    p99 = int(srt[math.ceil(0.99 * len(srt)) - 1])
+    return {"ok": p99 <= QOS_NS, "p99": p99}
+
+
+def artifact_suite(cm, G, torch, trial_s, iters, failures):
+    """The paper's artifact benchmarks (Section VIII-E): PCIe-, compute- and
+    memory-intensive stages at three intensities each, pipelined as p_i -> c_j ->
+    m_k -> top-10 (27 pipelines). Solo tables of the ten stages; Eq. 1 for all 27
+    with the HBM bandwidth constraint at the GPU's measured read bandwidth and
+    without it (Camelot-NC); measured peaks of both where the constraint changes the
+    allocation; and the host-link contention of several PCIe-intensive instances."""
+    import numpy as np
+    t0 = time.perf_counter()
+    D = G.ARTIFACT_D
+    hp = torch.empty(ART_P_TABLE_WORDS, dtype=torch.int32, pin_memory=True)
+    hp.numpy()[:] = G.artifact_words(ART_P_TABLE_WORDS, seed=1).view(np.int32)
+    dm = torch.empty(ART_M_TABLE_WORDS, dtype=torch.int32, device="cuda")
+    step = 1 << 24
+    for i in range(0, ART_M_TABLE_WORDS, step):
+        dm[i:i + step] = torch.from_numpy(G.artifact_words(step, seed=2, sub=i // step).view(np.int32))
+    pool = torch.from_numpy(G.artifact_words(8192 * D, seed=3).view(np.int32).reshape(8192, D)).cuda()
+    torch.cuda.synchronize()
+    P = [cm.stage_desc(cm.STAGE_ARTIFACT_P, dims=(D, w), weights=(hp.data_ptr(),), k=ART_P_TABLE_WORDS, n_layers=0)
+         for w in G.ARTIFACT_P_WORDS]
+    Cs = [cm.stage_desc(cm.STAGE_ARTIFACT_C, dims=(D, n), n_layers=0) for n in G.ARTIFACT_C_ITERS]
+    M = [cm.stage_desc(cm.STAGE_ARTIFACT_M, dims=(D, w), weights=(dm.data_ptr(),), k=ART_M_TABLE_WORDS, n_layers=0)
+         for w in G.ARTIFACT_M_WORDS]
+    top = cm.stage_desc(cm.STAGE_TOPK, dims=(D,), k=10, n_layers=0)
+    src = pool[:128].contiguous()
+    dst = torch.empty((128, D), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    K, nb = len(SHARES), len(BATCHES)
+
+    def table(desc):
+        lat = np.zeros((K, nb), np.int64)
+        for k, share in enumerate(SHARES):
+            for j, b in enumerate(BATCHES):
+                ns = cm.camelot_stage_run(desc, src.data_ptr(), dst.data_ptr(), b, share, 0, 2, device=True)
+                lat[k, j] = max(1, int(math.ceil(ns)))
+        return lat
+
+    tabs = {"p": [table(d) for d in P], "c": [table(d) for d in Cs], "m": [table(d) for d in M], "top": table(top)}
+    prof_s = time.perf_counter() - t0
+    # HBM bytes per batch of b rows (rows in and out; the memory stage's table reads;
+    # the PCIe stage's table is host memory and not counted)
+    row = 4 * D
+
+    def hbm_bytes(kind, lvl, b):
+        if kind == "m":
+            return b * (2 * row + 4 * G.ARTIFACT_M_WORDS[lvl])
+        if kind == "top":
+            return b * (row + 80)
+        return b * 2 * row
+
+    bw_peak = cm.camelot_stream_bench(cm.STREAM_READ, 1 << 30, 256, 0, 2)["gbs"] * 1e9
+    results = []
+    for i in range(3):
+        for j in range(3):
+            for kx in range(3):
+                parts = [("p", i), ("c", j), ("m", kx), ("top", 0)]
+                lat = np.stack([tabs[kd][lv] if kd != "top" else tabs["top"] for kd, lv in parts])
+                bw = np.stack([(np.array([hbm_bytes(kd, lv, b) for b in BATCHES], np.float64)[None, :]
+                                * 1e9 / lat[q]).astype(np.int64) for q, (kd, lv) in enumerate(parts)])
+
+                def prob(bw_budget):
+                    return cm.ProblemArrays(cu_total=256, cu_step=8, max_instances=8, max_inst_per_stage=5,
+                                            batches=BATCHES, qos_ns=QOS_NS, hbm_bytes_budget=1 << 40,
+                                            hbm_bw_budget=bw_budget, lat_ns=lat, bw_bps=bw,
+                                            mem_bytes=np.zeros((4, nb), np.int64), inst_max=[1, 5, 5, 1])
+                ta = time.perf_counter()
+                a = cm.camelot_alloc_peak(prob(int(bw_peak)))
+                t_exact = time.perf_counter() - ta
+                sa = cm.camelot_alloc_sa(prob(int(bw_peak)), cm.OBJ_PEAK, iters=20000, seed=7)
+                nc = cm.camelot_alloc_peak(prob(1 << 62))
+                ok_even, ea = cm.camelot_alloc_eval(prob(1 << 62), nb - 1, [1, 1, 1, 1], [64, 64, 64, 64])
+                d = a.as_dict() if a is not None else None
+                dn = nc.as_dict() if nc is not None else None
+                rec = {"pipeline": f"p{i + 1}+c{j + 1}+m{kx + 1}",
+                       "camelot": None if d is None else {"cu": d["cu"], "n": d["n"], "batch": d["batch"],
+                                                           "predicted_qps": d["thr_num"] / d["thr_den"]},
+                       "exact_ms": t_exact * 1e3,
+                       "sa_predicted_qps": None if sa is None else sa.thr_num / sa.thr_den,
+                       "nc": None if dn is None else {"cu": dn["cu"], "n": dn["n"], "batch": dn["batch"],
+                                                      "predicted_qps": dn["thr_num"] / dn["thr_den"]},
+                       "even_split_predicted_qps": ea.thr_num / ea.thr_den}
+                rec["bw_constraint_binds"] = (d is not None and dn is not None and
+                                              (d["cu"], d["n"], d["batch"]) != (dn["cu"], dn["n"], dn["batch"]))
+                results.append(rec)
+    # measured peaks where the bandwidth constraint changes the allocation: the three
+    # with the largest predicted NC/Camelot gap
+    bind = sorted([r for r in results if r["bw_constraint_binds"]],
+                  key=lambda r: -r["nc"]["predicted_qps"] / r["camelot"]["predicted_qps"])[:3]
+    for r in bind:
+        i, j, kx = (int(r["pipeline"][1]) - 1, int(r["pipeline"][4]) - 1, int(r["pipeline"][7]) - 1)
+        stages = (P[i], Cs[j], M[kx], top)
+        for key in ("camelot", "nc"):
+            al = r[key]
+            lo, hi, best = 0.0, 2 * al["predicted_qps"], 0.0
+            for it in range(iters):
+                rate = al["predicted_qps"] if it == 0 else (lo + hi) / 2
+                tr = replay_trial(cm, G, stages, pool, al["cu"], tuple(al["n"]), al["batch"], rate, trial_s, it,
+                                  failures)
+                log(f"  [artifact {r['pipeline']} {key}] {rate / 1e3:.1f} kq/s -> p99 {tr['p99'] / 1e6:.2f} ms "
+                    f"ok={tr['ok']}")
+                if tr["ok"]:
+                    lo, best = rate, rate
+                else:
+                    hi = rate
+            al["measured_peak_qps"] = best
+            # at its own predicted peak: does the allocation meet the QoS?
+            al["qos_met_at_predicted_peak"] = replay_trial(cm, G, stages, pool, al["cu"], tuple(al["n"]), al["batch"],
+                                                           al["predicted_qps"], trial_s, 99, failures)["ok"]
+    # host-link contention (Section IV-B's experiment): N PCIe-intensive instances of
+    # the heaviest kind, 16 CUs each, run together; time per batch of each
+    contention = []
+    for nk in range(1, 9):
+        ns = cm.camelot_stage_corun([P[2]] * nk, [src.data_ptr()] * nk, [dst.data_ptr()] * nk, [128] * nk,
+                                    [16] * nk, [16 * q for q in range(nk)], 2_000_000)
+        per = float(np.mean(ns))
+        gbs = nk * 128 * 4 * G.ARTIFACT_P_WORDS[2] / per
+        contention.append({"instances": nk, "us_per_batch": round(per / 1e3, 1), "aggregate_gbs": round(gbs, 1)})
+    sat = next((c["instances"] for c in contention[1:]
+                if c["aggregate_gbs"] < 1.1 * contention[c["instances"] - 2]["aggregate_gbs"]), None)
+    del dm, hp
+    torch.cuda.empty_cache()
+    return {"stage_levels": {"p_words_per_row": list(G.ARTIFACT_P_WORDS), "c_iters": list(G.ARTIFACT_C_ITERS),
+                             "m_words_per_row": list(G.ARTIFACT_M_WORDS)},
+            "hbm_bw_budget_gbs": bw_peak / 1e9, "profile_s": prof_s, "pipelines": results,
+            "measured_where_bw_binds": bind, "pcie_contention": contention,
+            "pcie_saturates_at_instances": sat, "suite_s": time.perf_counter() - t0}
 
 
 ROOF_LAUNCHES, ROOF_REPS = 10, 50
@@ -589,6 +797,7 @@ def main():
     ap.add_argument("--cpu-baseline-only", type=int, default=0)
     ap.add_argument("--cpu-seed", type=int, default=7)
     ap.add_argument("--skip-serving", action="store_true", help="skip the four-pipeline serving sweep")
+    ap.add_argument("--skip-artifacts", action="store_true", help="skip the artifact-suite leg")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-learned", action="store_true", help="skip the learned-allocator comparison")
     ap.add_argument("--dump", default="", help="write the profile table and trials to this JSON file")
@@ -821,6 +1030,11 @@ def main():
     if not args.skip_serving:
         serving = serving_sweep(cm, G, torch, sp, args.trial_s)
 
+    # 5c: the artifact suite (27 pipelines, Camelot vs Camelot-NC, host-link contention)
+    artifacts = None
+    if not args.skip_artifacts:
+        artifacts = artifact_suite(cm, G, torch, args.trial_s, 6, sp.failures)
+
     # 6: handoff GB/s
     slot = 64 << 20
     h = cm.camelot_handoff_bench(cm.HANDOFF_DEVICE, slot, 16, 128, 128, 128)
@@ -870,6 +1084,7 @@ def main():
                     "ceiling_split_128_128_gbs": split["gbs"], "frac_of_ceiling": h["gbs"] / split["gbs"]},
         "share_read_gbs": share_bw,
         "serving_sweep": serving,
+        "artifact_suite": artifacts,
         "learned_allocator": learned,
         "calibrated_table_allocation": calib,
         "no_bw_constraint_allocation": nc,

@@ -136,6 +136,27 @@ int32_t camelot_alloc_min(const camelot_problem* problem, int64_t load_num,
  * CAMELOT_EINFEASIBLE otherwise (fields still filled when the table has the point). */
 int32_t camelot_alloc_eval(const camelot_problem* problem, camelot_alloc* inout);
 
+/* Section VII-C's solver for both problems: simulated annealing over V = (batch
+ * index, N_1..N_S, share index k_1..k_S), for search spaces too large to enumerate
+ * (many stages and instances). Each of `iters` iterations moves one coordinate of
+ * V by +-1 (coordinate and direction uniform, a move off the grid is no move); a
+ * candidate that breaks a constraint is rejected (while the current state itself is
+ * invalid every move is taken); a better or equal valid one is taken, a worse one
+ * with probability exp(-d / temp), d the relative loss (CAMELOT_OBJ_PEAK: relative
+ * throughput drop; CAMELOT_OBJ_MIN: relative growth of the CUs in use, with
+ * throughput >= load_num / load_den as a constraint), temp = 0.3 * 0.95^(t / 100)
+ * (integer division). Start: the largest batch, N_i = 1, k_i = K / S - 1. The best
+ * valid state seen is returned, compared with camelot_alloc_peak's /
+ * camelot_alloc_min's tie rules. Randomness: one SplitMix64 stream seeded with
+ * `seed` (a draw for the coordinate, mod 2S + 1, one for the direction, its low
+ * bit, and one for u = (draw >> 11) / 2^53 only when a worse valid candidate is
+ * tested), so the result is a deterministic function of (problem, objective, load,
+ * iters, seed). It may miss the optimum camelot_alloc_peak/min finds; it never
+ * returns an invalid allocation. EINFEASIBLE if no valid state was visited. */
+enum { CAMELOT_OBJ_PEAK = 0, CAMELOT_OBJ_MIN = 1 };
+int32_t camelot_alloc_sa(const camelot_problem* problem, int32_t objective, int64_t load_num,
+                         int64_t load_den, int32_t iters, uint64_t seed, camelot_alloc* out);
+
 /* ------------------------------------------------------------------ stages
  * The synthetic microservice stages. Row = one query. All activations are
  * row-major [rows][dim].
@@ -165,6 +186,21 @@ int32_t camelot_alloc_eval(const camelot_problem* problem, camelot_alloc* inout)
  *                camelot_stage_run) hold int32 ids[dims[2]]; weights[0] = FP16 table
  *                [k][dims[1]]; out f32[heads * dims[2]], score[h * dims[2] + j] =
  *                sum_d q[h * dims[1] + d] * table[id_j][d]; ids outside [0, k) score 0.
+ *   ARTIFACT_P / ARTIFACT_M  the artifact suite's PCIe- and memory-intensive stages
+ *                (Section III-B, Section VIII-E): in and out u32[D], D = dims[0] (a
+ *                multiple of 1024, <= 16384); weights[0] = a table of k u32 words:
+ *                pinned host memory read over the host link (P; a device-accessible
+ *                host pointer) or device memory (M); dims[1] = words read per row (the
+ *                intensity; a multiple of D, <= k). Block b = in[0] mod (k / dims[1])
+ *                of the table (words b dims[1] .. + dims[1]) is folded into D words by
+ *                XOR (fold[j] = XOR over t of block[t D + j]); P outputs in[j] ^
+ *                fold[j]; M outputs f32: ((in[j] ^ fold[j]) >> 8) * 2^-24.
+ *   ARTIFACT_C   the compute-intensive stage: in and out u32[D], D = dims[0] (a
+ *                multiple of 1024, <= 16384); word w -> x = f32 with bits
+ *                (w >> 9) | 0x3F800000 (a value in [1, 2)), then dims[1] times (the
+ *                intensity, 0..2^20) x = (x * (1 - 2^-11)) + 2^-10, the product and
+ *                the sum each rounded to FP32 (no fused multiply-add); out = the bits of
+ *                x. No weights.
  * GEMM_ARGMAX and TOPK produce results and must be the last stage of a pipeline.
  */
 typedef enum {
@@ -175,7 +211,10 @@ typedef enum {
   CAMELOT_STAGE_TOPK = 5,
   CAMELOT_STAGE_GATHER = 6,
   CAMELOT_STAGE_CONV_POOL = 7,
-  CAMELOT_STAGE_GATHER_SCORE = 8
+  CAMELOT_STAGE_GATHER_SCORE = 8,
+  CAMELOT_STAGE_ARTIFACT_P = 9,
+  CAMELOT_STAGE_ARTIFACT_C = 10,
+  CAMELOT_STAGE_ARTIFACT_M = 11
 } camelot_stage_kind;
 
 #define CAMELOT_MAX_LAYERS 8
@@ -533,16 +572,22 @@ typedef struct {
   double ns[CAMELOT_MAX_CORUN];         /* measured time per batch of each               */
 } camelot_corun_record;
 
-/* Random co-location profiles: n_runs runs, each of m kernels, m uniform in
+/* Random co-location profiles: n_runs runs of a random walk over co-locations.
+ * Every 16th run (the first included) is a fresh draw: m kernels, m uniform in
  * 1..min(CAMELOT_MAX_CORUN, cu_total / cu_step); with probability 1/2 (when m >=
  * n_kinds) the first n_kinds kernels are one of each stage (a deployment's shape),
  * and every other kernel's kind is uniform over the n_kinds stages (independently,
  * so a kind can run as several instances, as in an allocation with N_i > 1);
- * shares drawn uniformly in cu_step steps with total <=
- * cu_total and placed side by side from bit 0, batch indices equal for all kernels
- * with probability 1/2 and independent otherwise; the draws come from a SplitMix64
- * stream seeded with `seed`. in[k]/out[k] are kind k's device buffers for
- * max(batches) rows (instances of one kind share them). */
+ * shares drawn uniformly in cu_step steps with total <= cu_total and placed side by
+ * side from bit 0, batch indices equal for all kernels with probability 1/2 and
+ * independent otherwise. Each other run makes one move from the previous one: a
+ * kernel's kind and batch re-drawn, its share re-drawn within the free CUs after it,
+ * a kernel added in a free range, or one removed (batches of changed kernels equal
+ * to another kernel's with probability 1/2). Kernels that keep their CUs keep their
+ * masked streams, which makes a run cost its ~1 ms of work rather than the ~5 ms a
+ * masked stream takes to create. The draws come from a SplitMix64 stream seeded
+ * with `seed`. in[k]/out[k] are kind k's device buffers for max(batches) rows
+ * (instances of one kind share them). */
 int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_desc* stages, const void* const* in,
                                void* const* out, int32_t cu_total, int32_t cu_step, int32_t n_batches,
                                const int32_t* batches, int32_t n_runs, uint64_t seed,

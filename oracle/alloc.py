@@ -174,3 +174,107 @@ def even_split(p: Problem, bi: int) -> Optional[Alloc]:
     per = [steps // S + (1 if s < steps % S else 0) for s in range(S)]
     choice = tuple((1, per[s] - 1) for s in range(S))
     return evaluate(p, bi, choice)
+
+
+# ---------------------------------------------------------------- simulated annealing
+# Section VII-C: Camelot solves both problems by simulated annealing over the vector
+# V = [N_1 .. N_S, p_1 .. p_S]; each iteration moves V one step in a random direction,
+# rejects a move that breaks a constraint, and otherwise takes it if it improves the
+# objective, or with a probability that shrinks as the iterations go on. The best
+# valid V seen is the answer. The paper gives neither the move set, the schedule nor
+# how the acceptance probability is computed; the readings here (in the design
+# notes) are:
+# * the state also holds the batch index (batch size is a decision variable); a move
+#   changes one coordinate (batch index, one N_i or one share index k_i) by +-1,
+#   coordinate and direction uniform; a move off the grid is no move;
+# * start: largest batch, N_i = 1, share index K // S - 1 (about an even split);
+# * while the current state is invalid, every move is taken (a walk towards the
+#   valid region); from a valid state an invalid candidate is rejected;
+# * Metropolis acceptance of a worse valid candidate with probability
+#   exp(-d / temp), d the relative loss (peak: (T - T') / T; min: (R' - R) / R with R
+#   the CUs in use), temp = 0.3 at the start and multiplied by 0.95 every 100
+#   iterations;
+# * the best state seen is compared with the exhaustive solvers' tie rules;
+# * random numbers come from one SplitMix64 stream (splitmix64_next, pinned to the
+#   generator's published outputs) seeded with `seed`: per iteration one draw for the
+#   coordinate (mod 2S + 1), one for the direction (low bit), and, only when a worse
+#   valid candidate is tested, one for u = (draw >> 11) / 2^53.
+SA_T0, SA_COOLING, SA_LEVEL = 0.3, 0.95, 100
+
+
+def simulated_annealing(p: Problem, iters: int, seed: int, load: Optional[Fraction] = None) -> Optional[Alloc]:
+    """Eq. 1 (load None) or Eq. 3 at `load` queries/s by simulated annealing; None
+    when no valid state was visited."""
+    import math
+    from oracle.delivery import splitmix64_next
+
+    S, K, nb = p.n_stages, p.n_shares, len(p.batches)
+    nmax = []
+    for s in range(S):
+        m = min(p.max_inst_per_stage, p.max_instances)
+        if p.inst_max is not None:
+            m = min(m, int(p.inst_max[s]))
+        nmax.append(m)
+    bi = nb - 1
+    n = [1] * S
+    k = [max(0, K // S - 1)] * S
+    rng = seed & ((1 << 64) - 1)
+
+    def draw():
+        nonlocal rng
+        rng, out = splitmix64_next(rng)
+        return out
+
+    def score(bi_, n_, k_):
+        a = evaluate(p, bi_, tuple(zip(n_, k_)))
+        if a is not None and load is not None and a.thr < load:
+            return None
+        return a
+
+    def key(a):
+        if load is None:
+            return (-a.thr, a.cu_used, a.lat_ns, a.key)
+        return (a.cu_used, -a.thr, a.lat_ns, a.key)
+
+    cur = score(bi, n, k)
+    best = cur
+    temp = SA_T0
+    for t in range(iters):
+        if t > 0 and t % SA_LEVEL == 0:
+            temp *= SA_COOLING
+        c = draw() % (2 * S + 1)
+        step = 1 if draw() & 1 else -1
+        bi2, n2, k2 = bi, list(n), list(k)
+        if c == 0:
+            bi2 += step
+            if not 0 <= bi2 < nb:
+                continue
+        elif c <= S:
+            n2[c - 1] += step
+            if not 1 <= n2[c - 1] <= nmax[c - 1]:
+                continue
+        else:
+            k2[c - S - 1] += step
+            if not 0 <= k2[c - S - 1] < K:
+                continue
+        cand = score(bi2, n2, k2)
+        if cur is None:
+            take = True
+        elif cand is None:
+            take = False
+        else:
+            if load is None:
+                tc, tn = float(cur.thr), float(cand.thr)
+                d = (tc - tn) / tc
+            else:
+                d = (cand.cu_used - cur.cu_used) / cur.cu_used
+            if d <= 0:
+                take = True
+            else:
+                u = (draw() >> 11) / float(1 << 53)
+                take = u < math.exp(-d / temp)
+        if take:
+            bi, n, k, cur = bi2, n2, k2, cand
+            if cur is not None and (best is None or key(cur) < key(best)):
+                best = cur
+    return best

@@ -253,3 +253,41 @@ def normwise_err(y, ref) -> float:
     if den == 0.0:
         return 0.0 if num == 0.0 else math.inf
     return num / den
+
+
+# ------------------------------------------------------------------ artifact stages
+# The paper's artifact suite (Section III-B, Section VIII-E) re-created from its
+# description: a PCIe-intensive, a compute-intensive and a memory-intensive
+# microservice with tunable intensity. The stage definitions (what a row becomes)
+# are the library's; here they are written out with plain integer and float32
+# NumPy operations, row by row.
+def artifact_fold(x_u32: np.ndarray, table_u32: np.ndarray, block_words: int, float_out: bool) -> np.ndarray:
+    """ARTIFACT_P (float_out False) / ARTIFACT_M (True). x [rows, D] uint32; the row
+    takes block b = x[r, 0] mod (len(table) // block_words) of the table, XORs its
+    words j, j + D, j + 2D, ... into word j, XORs that into the row; M then keeps the
+    top 24 bits of each word as a float in [0, 1)."""
+    x = np.asarray(x_u32, np.uint32)
+    rows, D = x.shape
+    nblocks = len(table_u32) // block_words
+    out = np.empty_like(x)
+    for r in range(rows):
+        b = int(x[r, 0]) % nblocks
+        block = table_u32[b * block_words:(b + 1) * block_words].reshape(block_words // D, D)
+        out[r] = x[r] ^ np.bitwise_xor.reduce(block, axis=0)
+    if float_out:
+        return (out >> np.uint32(8)).astype(np.float32) * np.float32(2.0 ** -24)
+    return out
+
+
+ARTIFACT_C_MUL = np.float32(1.0 - 2.0 ** -11)
+ARTIFACT_C_ADD = np.float32(2.0 ** -10)
+
+
+def artifact_compute(x_u32: np.ndarray, iters: int) -> np.ndarray:
+    """ARTIFACT_C: word w -> the float32 with bits (w >> 9) | 0x3F800000, then `iters`
+    times x = x * (1 - 2^-11) rounded, + 2^-10 rounded; returns the bits (uint32)."""
+    x = ((np.asarray(x_u32, np.uint32) >> np.uint32(9)) | np.uint32(0x3F800000)).view(np.float32)
+    for _ in range(iters):
+        x = (x * ARTIFACT_C_MUL).astype(np.float32)
+        x = (x + ARTIFACT_C_ADD).astype(np.float32)
+    return x.view(np.uint32)

@@ -24,7 +24,7 @@ OK, EINVAL, ENOMEM, EAGAIN, ETIMEDOUT, EINFEASIBLE, EDEVICE, ESTOPPED = 0, -1, -
 MAX_STAGES, MAX_LAYERS, MAX_K, MAX_BATCH = 8, 8, 128, 128
 NOALLOC_SCRATCH_BYTES = 8 << 20          # CAMELOT_NOALLOC_SCRATCH_BYTES
 (STAGE_GEMM_RELU, STAGE_GEMM_ARGMAX, STAGE_LOGMEL, STAGE_MLP_BF16, STAGE_TOPK, STAGE_GATHER, STAGE_CONV_POOL,
- STAGE_GATHER_SCORE) = 1, 2, 3, 4, 5, 6, 7, 8
+ STAGE_GATHER_SCORE, STAGE_ARTIFACT_P, STAGE_ARTIFACT_C, STAGE_ARTIFACT_M) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 HANDOFF_DEVICE, HANDOFF_HOST = 0, 1
 INGEST_HOST, INGEST_REPLAY = 0, 1
 PRED_NIN, PRED_NHID = 16, 64
@@ -136,6 +136,8 @@ _SIGS = {
                                          C.POINTER(C.c_double)]),
     "camelot_pipeline_submit_replay": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, C.c_int64]),
     "camelot_pipeline_submit_status": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
+    "camelot_alloc_sa": (C.c_int32, [C.POINTER(Problem), C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_uint64,
+                                     C.POINTER(Alloc)]),
     "camelot_pipeline_create": (C.c_int32, [C.POINTER(PipelineConfig), C.POINTER(_P)]),
     "camelot_pipeline_footprint": (C.c_int64, [_P]),
     "camelot_pipeline_epoch_ns": (C.c_int32, [_P, C.POINTER(C.c_int64)]),
@@ -231,6 +233,22 @@ class ProblemArrays:
             mem_bytes=_ptr(self.mem, C.c_int64),
             batch_wait_ns=_ptr(self.wait, C.c_int64) if self.wait is not None else None,
             inst_max=_ptr(self.inst_max, C.c_int32) if self.inst_max is not None else None)
+
+
+OBJ_PEAK, OBJ_MIN = 0, 1
+
+
+def camelot_alloc_sa(problem: ProblemArrays, objective: int, load_num: int = 0, load_den: int = 1,
+                     iters: int = 4000, seed: int = 0):
+    """Simulated annealing for Eq. 1 (OBJ_PEAK) or Eq. 3 (OBJ_MIN); None when no
+    valid state was visited."""
+    a = Alloc()
+    rc = _lib.camelot_alloc_sa(C.byref(problem.struct), objective, int(load_num), int(load_den), int(iters),
+                               int(seed) & ((1 << 64) - 1), C.byref(a))
+    if rc == EINFEASIBLE:
+        return None
+    _check(rc)
+    return a
 
 
 def camelot_alloc_peak(problem: ProblemArrays):

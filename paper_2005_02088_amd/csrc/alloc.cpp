@@ -11,6 +11,7 @@
 // candidates the lexicographically first one is kept. Throughputs are compared
 // as exact rationals with 128-bit cross products.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <numeric>
@@ -171,6 +172,175 @@ int solve(const camelot_problem* p, bool peak, int64_t load_num, int64_t load_de
   return CAMELOT_OK;
 }
 
+// ---------------------------------------------------------------- simulated annealing
+// Section VII-C's solver: a state V = (batch index, N_1..N_S, share index k_1..k_S)
+// moves one coordinate by +-1 per iteration (coordinate and direction uniform; a
+// move off the grid is no move). From a valid state an invalid candidate is
+// rejected; a better or equal candidate is taken; a worse one with probability
+// exp(-d / temp), d its relative loss (Eq. 1: (T - T') / T; Eq. 3: (R' - R) / R, R the
+// CUs in use); temp starts at 0.3 and is multiplied by 0.95 every 100 iterations.
+// While the state is invalid every move is taken. The best valid state seen is
+// kept with camelot_alloc_peak's / camelot_alloc_min's tie rules (lexicographic
+// order of (batch index, N_1, k_1, N_2, k_2, ...) last). Start: the largest batch,
+// N_i = 1, k_i = K / S - 1. Random draws: one SplitMix64 stream seeded with `seed`:
+// the coordinate (draw mod 2S + 1), the direction (low bit of the next draw), and,
+// only when a worse valid candidate is tested, u = (draw >> 11) / 2^53.
+constexpr double kSaT0 = 0.3, kSaCooling = 0.95;
+constexpr int kSaLevel = 100;
+
+struct SaState {
+  int bi;
+  int n[CAMELOT_MAX_STAGES], k[CAMELOT_MAX_STAGES];
+};
+
+struct SaEval {
+  bool ok = false;
+  Rat thr;
+  int64_t cu = 0, lat = 0;
+};
+
+uint64_t sa_next(uint64_t& st) {
+  st += 0x9E3779B97F4A7C15ull;
+  uint64_t z = st;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+SaEval sa_eval(const camelot_problem* p, int K, const SaState& v, bool peak, const Rat& load) {
+  SaEval e;
+  const int bi = v.bi;
+  const int64_t b = p->batches[bi];
+  int64_t inst = 0, bw = 0, mem = 0;
+  e.lat = p->batch_wait_ns ? p->batch_wait_ns[bi] : 0;
+  bool has = false;
+  for (int s = 0; s < p->n_stages; ++s) {
+    const int64_t L = p->lat_ns[((int64_t)s * K + v.k[s]) * p->n_batches + bi];
+    if (L <= 0) return e;
+    e.cu += (int64_t)v.n[s] * (v.k[s] + 1) * p->cu_step;
+    inst += v.n[s];
+    bw += v.n[s] * p->bw_bps[((int64_t)s * K + v.k[s]) * p->n_batches + bi];
+    mem += v.n[s] * p->mem_bytes[(int64_t)s * p->n_batches + bi];
+    e.lat += L;
+    const Rat t{(int64_t)v.n[s] * b * kNsPerS, L};
+    if (!has || cmp(t, e.thr) < 0) e.thr = t;
+    has = true;
+  }
+  if (e.cu > p->cu_total || inst > p->max_instances || bw > p->hbm_bw_budget || mem > p->hbm_bytes_budget ||
+      e.lat > p->qos_ns)
+    return e;
+  if (!peak && cmp(e.thr, load) < 0) return e;
+  e.ok = true;
+  return e;
+}
+
+// true when (a, va) beats (b, vb) under the exhaustive solvers' tie rules
+bool sa_better(const SaEval& a, const SaState& va, const SaEval& b, const SaState& vb, int S, bool peak) {
+  if (peak) {
+    const int c = cmp(a.thr, b.thr);
+    if (c != 0) return c > 0;
+    if (a.cu != b.cu) return a.cu < b.cu;
+  } else {
+    if (a.cu != b.cu) return a.cu < b.cu;
+    const int c = cmp(a.thr, b.thr);
+    if (c != 0) return c > 0;
+  }
+  if (a.lat != b.lat) return a.lat < b.lat;
+  if (va.bi != vb.bi) return va.bi < vb.bi;
+  for (int s = 0; s < S; ++s) {
+    if (va.n[s] != vb.n[s]) return va.n[s] < vb.n[s];
+    if (va.k[s] != vb.k[s]) return va.k[s] < vb.k[s];
+  }
+  return false;
+}
+
+int solve_sa(const camelot_problem* p, bool peak, int64_t load_num, int64_t load_den, int32_t iters, uint64_t seed,
+             camelot_alloc* out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return camelot::fail(CAMELOT_EINVAL, "out is NULL");
+  if (iters < 0) return camelot::fail(CAMELOT_EINVAL, "iters must be >= 0");
+  if (!peak && (load_num < 0 || load_den <= 0))
+    return camelot::fail(CAMELOT_EINVAL, "load must be a non-negative rational with den > 0");
+  const int S = p->n_stages, K = p->cu_total / p->cu_step, D = 2 * S + 1;
+  const Rat load{load_num, load_den};
+  int nmax[CAMELOT_MAX_STAGES];
+  for (int s = 0; s < S; ++s) {
+    nmax[s] = std::min(p->max_inst_per_stage, p->max_instances);
+    if (p->inst_max) nmax[s] = std::min(nmax[s], p->inst_max[s]);
+  }
+  SaState cur;
+  std::memset(&cur, 0, sizeof cur);
+  cur.bi = p->n_batches - 1;
+  for (int s = 0; s < S; ++s) {
+    cur.n[s] = 1;
+    cur.k[s] = std::max(0, K / S - 1);
+  }
+  SaEval ecur = sa_eval(p, K, cur, peak, load), ebest = ecur;
+  SaState best = cur;
+  uint64_t rng = seed;
+  double temp = kSaT0;
+  for (int32_t t = 0; t < iters; ++t) {
+    if (t > 0 && t % kSaLevel == 0) temp *= kSaCooling;
+    const int c = (int)(sa_next(rng) % (uint64_t)D);
+    const int step = (sa_next(rng) & 1u) ? 1 : -1;
+    SaState cand = cur;
+    if (c == 0) {
+      cand.bi += step;
+      if (cand.bi < 0 || cand.bi >= p->n_batches) continue;
+    } else if (c <= S) {
+      cand.n[c - 1] += step;
+      if (cand.n[c - 1] < 1 || cand.n[c - 1] > nmax[c - 1]) continue;
+    } else {
+      cand.k[c - S - 1] += step;
+      if (cand.k[c - S - 1] < 0 || cand.k[c - S - 1] >= K) continue;
+    }
+    const SaEval ec = sa_eval(p, K, cand, peak, load);
+    bool take;
+    if (!ecur.ok) {
+      take = true;
+    } else if (!ec.ok) {
+      take = false;
+    } else {
+      double d;
+      if (peak) {
+        const double tc = (double)ecur.thr.num / (double)ecur.thr.den, tn = (double)ec.thr.num / (double)ec.thr.den;
+        d = (tc - tn) / tc;
+      } else {
+        d = (double)(ec.cu - ecur.cu) / (double)ecur.cu;
+      }
+      if (d <= 0) {
+        take = true;
+      } else {
+        const double u = (double)(sa_next(rng) >> 11) / 9007199254740992.0;
+        take = u < std::exp(-d / temp);
+      }
+    }
+    if (!take) continue;
+    cur = cand;
+    ecur = ec;
+    if (ecur.ok && (!ebest.ok || sa_better(ecur, cur, ebest, best, S, peak))) {
+      ebest = ecur;
+      best = cur;
+    }
+  }
+  if (!ebest.ok) return camelot::fail(CAMELOT_EINFEASIBLE, "annealing visited no valid allocation");
+  std::memset(out, 0, sizeof *out);
+  out->n_stages = S;
+  out->batch_index = best.bi;
+  out->batch = p->batches[best.bi];
+  for (int s = 0; s < S; ++s) {
+    out->n[s] = best.n[s];
+    out->cu[s] = (best.k[s] + 1) * p->cu_step;
+  }
+  const int64_t g = std::gcd(ebest.thr.num, ebest.thr.den);
+  out->thr_num = ebest.thr.num / g;
+  out->thr_den = ebest.thr.den / g;
+  out->lat_ns = ebest.lat;
+  out->cu_used = ebest.cu;
+  return CAMELOT_OK;
+}
+
 }  // namespace
 
 extern "C" int32_t camelot_alloc_peak(const camelot_problem* problem, camelot_alloc* out) {
@@ -224,4 +394,12 @@ extern "C" int32_t camelot_alloc_eval(const camelot_problem* p, camelot_alloc* a
       mem > p->hbm_bytes_budget || lat > p->qos_ns)
     return camelot::fail(CAMELOT_EINFEASIBLE, "allocation violates a constraint");
   return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_alloc_sa(const camelot_problem* problem, int32_t objective, int64_t load_num,
+                                    int64_t load_den, int32_t iters, uint64_t seed, camelot_alloc* out) {
+  camelot::clear_error();
+  if (objective != CAMELOT_OBJ_PEAK && objective != CAMELOT_OBJ_MIN)
+    return camelot::fail(CAMELOT_EINVAL, "objective must be CAMELOT_OBJ_PEAK or CAMELOT_OBJ_MIN");
+  return solve_sa(problem, objective == CAMELOT_OBJ_PEAK, load_num, load_den, iters, seed, out);
 }

@@ -37,45 +37,28 @@ uint64_t splitmix_next(uint64_t& s) {
 // uniform integer in [0, n)
 int uniform(uint64_t& s, int n) { return (int)(splitmix_next(s) % (uint64_t)n); }
 
+// runs of the co-location walk between two fresh draws
+constexpr int kWalkRestart = 16;
+
 }  // namespace
 
-extern "C" int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stages, const void* const* in,
-                                       void* const* out, const int32_t* rows, const int32_t* n_cus,
-                                       const int32_t* cu_offset, int64_t duration_ns, double* ns_per_batch) {
-  clear_error();
-  if (n < 1 || n > kMaxStages || !stages || !in || !out || !rows || !n_cus || !cu_offset || !ns_per_batch)
-    return fail(CAMELOT_EINVAL, "bad co-run arguments");
-  if (duration_ns <= 0 || duration_ns > 10LL * 1000000000LL)
-    return fail(CAMELOT_EINVAL, "duration_ns must be in (0, 10 s]");
+namespace {
+// The co-location run on caller-provided CU-masked streams (streams[j] masked to
+// n_cus[j] CUs at cu_offset[j]).
+int32_t corun_on(int32_t n, const camelot_stage_desc* stages, const void* const* in, void* const* out,
+                 const int32_t* rows, const int32_t* n_cus, int64_t duration_ns, double* ns_per_batch,
+                 const hipStream_t* streams) {
   DevInfo dev;
   int32_t rc = dev_info(&dev);
   if (rc) return rc;
-  for (int j = 0; j < n; ++j) {
-    if ((rc = check_share(n_cus[j], cu_offset[j], dev.n_cus))) return rc;
-    if (rows[j] < 0 || rows[j] > kMaxBatch) return fail(CAMELOT_EINVAL, "rows must be in 0..%d", kMaxBatch);
-    for (int q = 0; q < j; ++q)
-      if (overlaps(cu_offset[j], n_cus[j], cu_offset[q], n_cus[q]))
-        return fail(CAMELOT_EINVAL, "co-run shares %d and %d overlap", q, j);
-  }
   std::vector<StageRes> res(n);
   std::vector<CtlBuf> ctl(n);
   std::vector<WorkerArgs> args(n);
-  // own streams (a co-run can hold more kernels than the cache keeps streams)
-  struct Streams {
-    std::vector<hipStream_t> s;
-    ~Streams() {
-      for (hipStream_t x : s)
-        if (x) (void)hipStreamDestroy(x);
-    }
-  } own;
-  own.s.assign(n, nullptr);
-  std::vector<hipStream_t>& streams = own.s;
   for (int j = 0; j < n; ++j) {
     WorkerArgs& a = args[j];
     std::memset(&a, 0, sizeof a);
     if ((rc = fill_params(&stages[j], &res[j], &a.sp))) return rc;
     if ((rc = dmalloc(&ctl[j].p, sizeof(WorkerCtl))) || (rc = dzero(ctl[j].p, sizeof(WorkerCtl)))) return rc;
-    if ((rc = new_masked_stream(cu_offset[j], n_cus[j], &streams[j]))) return rc;
     a.n_stages = 1;
     a.max_batch = kMaxBatch;
     a.spin_ticks = 2 * dev.wclk_hz;
@@ -105,6 +88,65 @@ extern "C" int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stag
   return CAMELOT_OK;
 }
 
+struct OwnStreams {
+  std::vector<hipStream_t> s;
+  ~OwnStreams() {
+    for (hipStream_t x : s)
+      if (x) (void)hipStreamDestroy(x);
+  }
+};
+}  // namespace
+
+extern "C" int32_t camelot_stage_corun(int32_t n, const camelot_stage_desc* stages, const void* const* in,
+                                       void* const* out, const int32_t* rows, const int32_t* n_cus,
+                                       const int32_t* cu_offset, int64_t duration_ns, double* ns_per_batch) {
+  clear_error();
+  if (n < 1 || n > kMaxStages || !stages || !in || !out || !rows || !n_cus || !cu_offset || !ns_per_batch)
+    return fail(CAMELOT_EINVAL, "bad co-run arguments");
+  if (duration_ns <= 0 || duration_ns > 10LL * 1000000000LL)
+    return fail(CAMELOT_EINVAL, "duration_ns must be in (0, 10 s]");
+  DevInfo dev;
+  int32_t rc = dev_info(&dev);
+  if (rc) return rc;
+  for (int j = 0; j < n; ++j) {
+    if ((rc = check_share(n_cus[j], cu_offset[j], dev.n_cus))) return rc;
+    if (rows[j] < 0 || rows[j] > kMaxBatch) return fail(CAMELOT_EINVAL, "rows must be in 0..%d", kMaxBatch);
+    for (int q = 0; q < j; ++q)
+      if (overlaps(cu_offset[j], n_cus[j], cu_offset[q], n_cus[q]))
+        return fail(CAMELOT_EINVAL, "co-run shares %d and %d overlap", q, j);
+  }
+  // own streams (a co-run can hold more kernels than the cache keeps streams)
+  OwnStreams own;
+  own.s.assign(n, nullptr);
+  for (int j = 0; j < n; ++j)
+    if ((rc = new_masked_stream(cu_offset[j], n_cus[j], &own.s[j]))) return rc;
+  return corun_on(n, stages, in, out, rows, n_cus, duration_ns, ns_per_batch, own.s.data());
+}
+
+namespace {
+// One kernel of the co-location walk: its kind, share and offset (in CU steps),
+// batch index, and the stream masked to its share.
+struct WalkKernel {
+  int kind, sh, off, bi;
+  hipStream_t s;
+};
+
+// Free gaps (offset, length in steps) of [0, steps) around the kernels.
+std::vector<std::pair<int, int>> free_gaps(const std::vector<WalkKernel>& ks, int steps) {
+  std::vector<std::pair<int, int>> used;
+  for (const auto& k : ks) used.push_back({k.off, k.sh});
+  std::sort(used.begin(), used.end());
+  std::vector<std::pair<int, int>> gaps;
+  int at = 0;
+  for (const auto& u : used) {
+    if (u.first > at) gaps.push_back({at, u.first - at});
+    at = u.first + u.second;
+  }
+  if (at < steps) gaps.push_back({at, steps - at});
+  return gaps;
+}
+}  // namespace
+
 extern "C" int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_desc* stages, const void* const* in,
                                           void* const* out, int32_t cu_total, int32_t cu_step, int32_t n_batches,
                                           const int32_t* batches, int32_t n_runs, uint64_t seed,
@@ -113,45 +155,101 @@ extern "C" int32_t camelot_profile_coruns(int32_t n_kinds, const camelot_stage_d
   if (n_kinds < 1 || n_kinds > 3 || !stages || !in || !out || !batches || n_batches < 1 || n_runs < 0 ||
       !records || cu_step < 8 || cu_step % 8 != 0 || cu_total < cu_step * n_kinds)
     return fail(CAMELOT_EINVAL, "bad co-run profiling arguments");
+  DevInfo dev;
+  int32_t rc = dev_info(&dev);
+  if (rc) return rc;
+  if ((rc = check_share(cu_total, 0, dev.n_cus))) return rc;
   uint64_t st = seed;
   const int steps = cu_total / cu_step;
   const int mmax = std::min(CAMELOT_MAX_CORUN, steps);
+  std::vector<WalkKernel> ks;
+  struct Release {
+    std::vector<WalkKernel>* ks;
+    ~Release() {
+      for (auto& k : *ks)
+        if (k.s) (void)hipStreamDestroy(k.s);
+    }
+  } release{&ks};
+  auto drop = [&](size_t i) {
+    if (ks[i].s) (void)hipStreamDestroy(ks[i].s);
+    ks.erase(ks.begin() + (long)i);
+  };
+  auto batch_for = [&](bool same) {
+    return (same && !ks.empty()) ? ks[uniform(st, (int)ks.size())].bi : uniform(st, n_batches);
+  };
   for (int r = 0; r < n_runs; ++r) {
+    if (r % kWalkRestart == 0) {
+      // a fresh draw: m kernels, shares uniform with total <= the GPU, side by side
+      while (!ks.empty()) drop(ks.size() - 1);
+      const int m = 1 + uniform(st, mmax);
+      int sh[CAMELOT_MAX_CORUN];
+      for (;;) {
+        int tot = 0;
+        for (int i = 0; i < m; ++i) { sh[i] = 1 + uniform(st, steps - (m - 1)); tot += sh[i]; }
+        if (tot <= steps) break;
+      }
+      const bool same = uniform(st, 2) == 0;
+      const int b0 = uniform(st, n_batches);
+      const bool shaped = m >= n_kinds && uniform(st, 2) == 0;
+      int off = 0;
+      for (int i = 0; i < m; ++i) {
+        const int k = (shaped && i < n_kinds) ? i : uniform(st, n_kinds);
+        ks.push_back({k, sh[i], off, same ? b0 : uniform(st, n_batches), nullptr});
+        off += sh[i];
+      }
+    } else {
+      // one move of the walk: re-draw a kernel's kind and batch (its share kept),
+      // re-draw its share inside the gap it sits in, add a kernel in a free gap, or
+      // remove one
+      const auto gaps = free_gaps(ks, steps);
+      const int move = uniform(st, 4);
+      if (move == 0 || (move == 2 && (gaps.empty() || (int)ks.size() >= mmax)) || (move == 3 && ks.size() < 2)) {
+        WalkKernel& k = ks[uniform(st, (int)ks.size())];
+        k.kind = uniform(st, n_kinds);
+        k.bi = batch_for(uniform(st, 2) == 0);
+      } else if (move == 1) {
+        const size_t i = (size_t)uniform(st, (int)ks.size());
+        // the span the kernel may take: its own steps plus the free gap right after it
+        int room = ks[i].sh;
+        for (const auto& g : gaps)
+          if (g.first == ks[i].off + ks[i].sh) room += g.second;
+        const int sh = 1 + uniform(st, room);
+        if (sh != ks[i].sh) {
+          if (ks[i].s) (void)hipStreamDestroy(ks[i].s);
+          ks[i].s = nullptr;
+          ks[i].sh = sh;
+        }
+      } else if (move == 2) {
+        const auto& g = gaps[(size_t)uniform(st, (int)gaps.size())];
+        const int bi = batch_for(uniform(st, 2) == 0);
+        ks.push_back({uniform(st, n_kinds), 1 + uniform(st, g.second), g.first, bi, nullptr});
+      } else {
+        drop((size_t)uniform(st, (int)ks.size()));
+      }
+    }
+    const int m = (int)ks.size();
     camelot_corun_record& rec = records[r];
     std::memset(&rec, 0, sizeof rec);
-    const int m = 1 + uniform(st, mmax);
-    int sh[CAMELOT_MAX_CORUN];
-    for (;;) {
-      int tot = 0;
-      for (int i = 0; i < m; ++i) { sh[i] = 1 + uniform(st, steps - (m - 1)); tot += sh[i]; }
-      if (tot <= steps) break;
-    }
-    const bool same = uniform(st, 2) == 0;
-    const int b0 = uniform(st, n_batches);
+    rec.m = m;
     camelot_stage_desc d[CAMELOT_MAX_CORUN];
     const void* ins[CAMELOT_MAX_CORUN];
     void* outs[CAMELOT_MAX_CORUN];
-    int32_t rows[CAMELOT_MAX_CORUN], cus[CAMELOT_MAX_CORUN], offs[CAMELOT_MAX_CORUN];
-    int off = 0;
-    rec.m = m;
-    // half the runs are shaped like a deployment: every stage present, extra
-    // kernels repeating stages (instances); the rest draw kinds independently
-    const bool shaped = m >= n_kinds && uniform(st, 2) == 0;
+    int32_t rows[CAMELOT_MAX_CORUN], cus[CAMELOT_MAX_CORUN];
+    hipStream_t ss[CAMELOT_MAX_CORUN];
     for (int i = 0; i < m; ++i) {
-      const int k = (shaped && i < n_kinds) ? i : uniform(st, n_kinds);
-      rec.kinds[i] = k;
-      rec.cu[i] = sh[i] * cu_step;
-      rec.bi[i] = same ? b0 : uniform(st, n_batches);
-      d[i] = stages[k];
-      ins[i] = in[k];
-      outs[i] = out[k];
-      rows[i] = batches[rec.bi[i]];
+      WalkKernel& k = ks[(size_t)i];
+      if (!k.s && (rc = new_masked_stream(k.off * cu_step, k.sh * cu_step, &k.s))) return rc;
+      rec.kinds[i] = k.kind;
+      rec.cu[i] = k.sh * cu_step;
+      rec.bi[i] = k.bi;
+      d[i] = stages[k.kind];
+      ins[i] = in[k.kind];
+      outs[i] = out[k.kind];
+      rows[i] = batches[k.bi];
       cus[i] = rec.cu[i];
-      offs[i] = off;
-      off += rec.cu[i];
+      ss[i] = k.s;
     }
-    int32_t rc = camelot_stage_corun(m, d, ins, outs, rows, cus, offs, duration_ns, rec.ns);
-    if (rc) return rc;
+    if ((rc = corun_on(m, d, ins, outs, rows, cus, duration_ns, rec.ns, ss))) return rc;
   }
   return CAMELOT_OK;
 }

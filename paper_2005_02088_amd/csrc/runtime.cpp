@@ -319,6 +319,23 @@ static int32_t check_stage(const camelot_stage_desc* d, int64_t* in_b, int64_t* 
       *in_b = 4LL * d->dims[0];
       *out_b = 4LL * (d->dims[0] / d->dims[1]) * d->dims[2];
       return CAMELOT_OK;
+    case CAMELOT_STAGE_ARTIFACT_P:
+    case CAMELOT_STAGE_ARTIFACT_M:
+      if (d->dims[0] < 1024 || d->dims[0] > 16384 || d->dims[0] % 1024 != 0)
+        return fail(CAMELOT_EINVAL, "artifact stages need D = dims[0], a multiple of 1024 up to 16384");
+      if (d->dims[1] < d->dims[0] || d->dims[1] % d->dims[0] != 0 || d->k < d->dims[1])
+        return fail(CAMELOT_EINVAL, "ARTIFACT_P/M need dims[1] a multiple of D and a table of k >= dims[1] words");
+      if (!d->weights[0]) return fail(CAMELOT_EINVAL, "ARTIFACT_P/M need the table in weights[0]");
+      *in_b = 4LL * d->dims[0];
+      *out_b = 4LL * d->dims[0];
+      return CAMELOT_OK;
+    case CAMELOT_STAGE_ARTIFACT_C:
+      if (d->dims[0] < 1024 || d->dims[0] > 16384 || d->dims[0] % 1024 != 0)
+        return fail(CAMELOT_EINVAL, "artifact stages need D = dims[0], a multiple of 1024 up to 16384");
+      if (d->dims[1] < 0 || d->dims[1] > (1 << 20)) return fail(CAMELOT_EINVAL, "ARTIFACT_C needs 0..2^20 iterations");
+      *in_b = 4LL * d->dims[0];
+      *out_b = 4LL * d->dims[0];
+      return CAMELOT_OK;
     default:
       return fail(CAMELOT_EINVAL, "unknown stage kind %d", d->kind);
   }
@@ -1144,8 +1161,16 @@ static int32_t await_record(camelot_pipeline* p, uint64_t pos, const uint8_t* re
   if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == pos + 1) return CAMELOT_OK;
   const int64_t t_end = host_ns() + 1000000000LL;
   while (__atomic_load_n(seq, __ATOMIC_ACQUIRE) != pos + 1) {
-    if (host_ns() > t_end)
-      return fail(CAMELOT_EDEVICE, "egress record %llu published without its contents", (unsigned long long)pos);
+    if (host_ns() > t_end) {
+      const EgressRec* h = (const EgressRec*)rec;
+      return fail(CAMELOT_EDEVICE,
+                  "egress record %llu published without its contents (sequence word %llu, id %llu, row %u, "
+                  "egress head %llu, tail %llu)",
+                  (unsigned long long)pos, (unsigned long long)__atomic_load_n(seq, __ATOMIC_ACQUIRE),
+                  (unsigned long long)h->id, h->row,
+                  (unsigned long long)__atomic_load_n(&p->pub->egress_head, __ATOMIC_ACQUIRE),
+                  (unsigned long long)p->egress_tail);
+    }
     std::this_thread::yield();
   }
   return CAMELOT_OK;

@@ -45,6 +45,8 @@ int64_t weight_bytes(const camelot_stage_desc* d, std::vector<std::pair<const vo
       return add(d->weights[0], 2LL * d->k * d->dims[1]);
     case CAMELOT_STAGE_CONV_POOL:
       return add(d->weights[0], 2LL * d->dims[3] * 9 * d->dims[2]);
+    case CAMELOT_STAGE_ARTIFACT_M:            // the device table (P's lives in host memory)
+      return add(d->weights[0], 4LL * d->k);
     default:
       return 0;
   }

@@ -1090,6 +1090,85 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const Bat
   }
 }
 
+// ------------------------------------------------------------------ artifact stages
+// The synthetic microservices of the paper's artifact suite (Section III-B, Section
+// VIII-E): a PCIe-intensive, a compute-intensive and a memory-intensive stage, each
+// with a tunable intensity. Rows are D = dims[0] 32-bit words (a multiple of 1024).
+//
+// PCIe / memory: the row's block (dims[1] words, a multiple of D, block number
+// in[0] mod (k / dims[1])) of a k-word table - pinned host memory read over the
+// host link (ARTIFACT_P) or device memory (ARTIFACT_M) - folded into D words by XOR
+// (word j of the fold = XOR of block words j, j + D, ...), XORed into the row.
+// ARTIFACT_P keeps the words; ARTIFACT_M turns each into a float in [0, 1), its
+// top 24 bits times 2^-24. One workgroup per row: its 256 threads read 16 bytes each,
+// 4 KiB contiguous per step, 8 steps in flight; XOR needs no fixed order.
+//
+// Compute: each word w becomes x = 1 + (w >> 9) 2^-23 (a float in [1, 2)), then
+// dims[1] times x = x (1 - 2^-11) + 2^-10, a multiply and an add each rounded to
+// FP32 (no fused multiply-add), and the row is the floats' bits. One workgroup per
+// row, 4 independent chains per thread.
+constexpr int kArtWordsPerStep = kThreads * 4;       // 1024 words: one D slice per step
+
+template <bool FLOAT_OUT>
+__device__ void exec_artifact_fold(const WorkerArgs& a, const BatchRows& br, int rows, uint8_t* out) {
+  const int D = a.sp.dims[0];
+  const int64_t bw = a.sp.dims[1], nblocks = (int64_t)a.sp.k / bw;
+  const uint32_t* T = (const uint32_t*)a.sp.w[0];
+  const int tid = threadIdx.x;
+  for (int r = xwg(a); r < rows; r += xnwg(a)) {
+    const uint32_t* in = (const uint32_t*)br.row(r);
+    const uint32_t* blk = T + (int64_t)(in[0] % (uint64_t)nblocks) * bw;
+    for (int j0 = 0; j0 < D; j0 += kArtWordsPerStep) {
+      u32x4_t acc = {0u, 0u, 0u, 0u};
+      const int64_t steps = bw / D;
+      int64_t t = 0;
+      for (; t + 8 <= steps; t += 8) {
+        u32x4_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = *(const u32x4_t*)(blk + (t + u) * D + j0 + 4 * tid);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc ^= v[u];
+      }
+      for (; t < steps; ++t) acc ^= *(const u32x4_t*)(blk + t * D + j0 + 4 * tid);
+      const u32x4_t x = *(const u32x4_t*)(in + j0 + 4 * tid) ^ acc;
+      if constexpr (FLOAT_OUT) {
+        float4 f;
+        f.x = (float)(x.x >> 8) * 0x1p-24f;
+        f.y = (float)(x.y >> 8) * 0x1p-24f;
+        f.z = (float)(x.z >> 8) * 0x1p-24f;
+        f.w = (float)(x.w >> 8) * 0x1p-24f;
+        *(float4*)(out + ((int64_t)r * D + j0 + 4 * tid) * 4) = f;
+      } else {
+        *(u32x4_t*)(out + ((int64_t)r * D + j0 + 4 * tid) * 4) = x;
+      }
+    }
+  }
+}
+
+__device__ void exec_artifact_compute(const WorkerArgs& a, const BatchRows& br, int rows, uint8_t* out) {
+  // two roundings per iteration, as defined: the product and the sum are not fused
+#pragma clang fp contract(off)
+  const int D = a.sp.dims[0], n = a.sp.dims[1];
+  const float mul = 1.0f - 0x1p-11f, add = 0x1p-10f;
+  const int tid = threadIdx.x;
+  for (int r = xwg(a); r < rows; r += xnwg(a)) {
+    const uint32_t* in = (const uint32_t*)br.row(r);
+    for (int j0 = 0; j0 < D; j0 += kArtWordsPerStep) {
+      const u32x4_t w = *(const u32x4_t*)(in + j0 + 4 * tid);
+      float x0 = __uint_as_float((w.x >> 9) | 0x3F800000u), x1 = __uint_as_float((w.y >> 9) | 0x3F800000u);
+      float x2 = __uint_as_float((w.z >> 9) | 0x3F800000u), x3 = __uint_as_float((w.w >> 9) | 0x3F800000u);
+      for (int i = 0; i < n; ++i) {
+        x0 = x0 * mul + add;
+        x1 = x1 * mul + add;
+        x2 = x2 * mul + add;
+        x3 = x3 * mul + add;
+      }
+      *(u32x4_t*)(out + ((int64_t)r * D + j0 + 4 * tid) * 4) =
+          (u32x4_t){__float_as_uint(x0), __float_as_uint(x1), __float_as_uint(x2), __float_as_uint(x3)};
+    }
+  }
+}
+
 // ------------------------------------------------------------------ side bytes
 // Copies every row's side bytes from the input to the output slot's side plane.
 __device__ __forceinline__ void copy_side(const WorkerArgs& a, const BatchDesc* bd, int rows) {
@@ -1114,6 +1193,9 @@ __device__ __forceinline__ bool exec_stage(const WorkerArgs& a, WorkerCtl* ctl, 
   if constexpr (KIND == CAMELOT_STAGE_GATHER) { exec_gather(a, ctl, br, rows, out); return true; }
   if constexpr (KIND == CAMELOT_STAGE_CONV_POOL) { return exec_conv_pool(a, ctl, br, rows, out); }
   if constexpr (KIND == CAMELOT_STAGE_GATHER_SCORE) { exec_gather_score(a, ctl, br, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_ARTIFACT_P) { exec_artifact_fold<false>(a, br, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_ARTIFACT_C) { exec_artifact_compute(a, br, rows, out); return true; }
+  if constexpr (KIND == CAMELOT_STAGE_ARTIFACT_M) { exec_artifact_fold<true>(a, br, rows, out); return true; }
   return false;
 }
 
@@ -1805,6 +1887,12 @@ template __global__ void stage_bench<CAMELOT_STAGE_GEMM_ARGMAX>(WorkerArgs);
 template __global__ void stage_bench<CAMELOT_STAGE_LOGMEL>(WorkerArgs);
 template __global__ void stage_bench<CAMELOT_STAGE_MLP_BF16>(WorkerArgs);
 template __global__ void stage_bench<CAMELOT_STAGE_TOPK>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_ARTIFACT_P>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_ARTIFACT_P>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_ARTIFACT_C>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_ARTIFACT_C>(WorkerArgs);
+template __global__ void stage_worker<CAMELOT_STAGE_ARTIFACT_M>(WorkerArgs);
+template __global__ void stage_bench<CAMELOT_STAGE_ARTIFACT_M>(WorkerArgs);
 
 // Host-side accessor of the kernel entry for a stage kind (bench: one-shot kernel).
 const void* worker_kernel(int kind, bool bench) {
@@ -1818,6 +1906,9 @@ const void* worker_kernel(int kind, bool bench) {
       case CAMELOT_STAGE_GATHER: return (const void*)&stage_bench<CAMELOT_STAGE_GATHER>;
       case CAMELOT_STAGE_GATHER_SCORE: return (const void*)&stage_bench<CAMELOT_STAGE_GATHER_SCORE>;
       case CAMELOT_STAGE_CONV_POOL: return (const void*)&stage_bench<CAMELOT_STAGE_CONV_POOL>;
+      case CAMELOT_STAGE_ARTIFACT_P: return (const void*)&stage_bench<CAMELOT_STAGE_ARTIFACT_P>;
+      case CAMELOT_STAGE_ARTIFACT_C: return (const void*)&stage_bench<CAMELOT_STAGE_ARTIFACT_C>;
+      case CAMELOT_STAGE_ARTIFACT_M: return (const void*)&stage_bench<CAMELOT_STAGE_ARTIFACT_M>;
       default: return nullptr;
     }
   }
@@ -1830,6 +1921,9 @@ const void* worker_kernel(int kind, bool bench) {
     case CAMELOT_STAGE_GATHER: return (const void*)&stage_worker<CAMELOT_STAGE_GATHER>;
     case CAMELOT_STAGE_GATHER_SCORE: return (const void*)&stage_worker<CAMELOT_STAGE_GATHER_SCORE>;
     case CAMELOT_STAGE_CONV_POOL: return (const void*)&stage_worker<CAMELOT_STAGE_CONV_POOL>;
+    case CAMELOT_STAGE_ARTIFACT_P: return (const void*)&stage_worker<CAMELOT_STAGE_ARTIFACT_P>;
+    case CAMELOT_STAGE_ARTIFACT_C: return (const void*)&stage_worker<CAMELOT_STAGE_ARTIFACT_C>;
+    case CAMELOT_STAGE_ARTIFACT_M: return (const void*)&stage_worker<CAMELOT_STAGE_ARTIFACT_M>;
     default: return nullptr;
   }
 }

@@ -126,3 +126,46 @@ def test_per_stage_instance_bounds_match_brute_force(sub):
         assert all(n <= m for n, m in zip(o.n, inst_max))
         lam = o.thr_num // (2 * o.thr_den) + 1
         _same(OA.alloc_min(po, lam, 1), cm.camelot_alloc_min(pc, lam, 1))
+
+
+def _sa_case(sub):
+    """A random problem of up to 5 stages (beyond what a test enumerates quickly for
+    the larger ones), with bandwidth, memory and QoS constraints that bind."""
+    g = G.rng("tables", 123, sub)
+    S = int(g.integers(2, 6))
+    K = int(g.integers(4, 17))
+    batches = [1, 4, 16, 64][: int(g.integers(2, 5))]
+    lat, bw, mem = G.random_problem_tables(S, K, batches, seed=11, sub=sub)
+    lat[g.random(lat.shape) < 0.05] = 0
+    nmax = int(g.integers(1, 5))
+    tot = int(np.sum(np.max(lat, axis=(1, 2))))
+    kw = dict(nmax=nmax, I=int(g.integers(S, S * nmax + 1)), qos=int(tot * g.uniform(0.4, 1.2)),
+              bw_budget=int(np.sum(np.max(bw, axis=(1, 2))) * g.uniform(0.5, 2.0)),
+              mem_budget=int(np.sum(mem) * g.uniform(0.5, 2.0)))
+    return _both(lat, bw, mem, batches, 8 * K, 8, **kw)
+
+
+@pytest.mark.parametrize("sub", range(10))
+def test_annealing_matches_the_oracle(sub):
+    """Same problem, objective, iterations and seed: the library's annealing and the
+    oracle's visit the same states (one SplitMix64 stream) and return the same bits."""
+    po, pc = _sa_case(sub)
+    for seed in (0, 1 + sub):
+        o = OA.simulated_annealing(po, 3000, seed)
+        c = cm.camelot_alloc_sa(pc, cm.OBJ_PEAK, iters=3000, seed=seed)
+        _same(o, c)
+        if o is not None:
+            lam = o.thr / 2
+            o2 = OA.simulated_annealing(po, 3000, seed, load=lam)
+            c2 = cm.camelot_alloc_sa(pc, cm.OBJ_MIN, lam.numerator, lam.denominator, iters=3000, seed=seed)
+            _same(o2, c2)
+
+
+def test_annealing_arguments():
+    po, pc = _sa_case(0)
+    with pytest.raises(cm.CamelotError):
+        cm.camelot_alloc_sa(pc, 7)
+    with pytest.raises(cm.CamelotError):
+        cm.camelot_alloc_sa(pc, cm.OBJ_MIN, 1, 0)
+    with pytest.raises(cm.CamelotError):
+        cm.camelot_alloc_sa(pc, cm.OBJ_PEAK, iters=-1)

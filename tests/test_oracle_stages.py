@@ -207,3 +207,54 @@ def test_gather_score_hand_case():
     q = np.array([[1.0, 1.0, 2.0, -1.0]])           # two heads of dim 2
     got = O.gather_score(q, np.array([[0, 2, 7]]), t, 2)
     assert np.array_equal(got, [[1.0, 2.0, 0.0, 2.0, 1.0, 0.0]])
+
+
+# ------------------------------------------------------------------ artifact stages
+def test_artifact_fold_by_hand():
+    D = 4
+    table = np.arange(48, dtype=np.uint32)               # 3 blocks of 16 words
+    x = np.array([[7, 0, 0, 0], [3, 1, 2, 3], [2, 0, 0, 0xFFFFFFFF]], np.uint32)
+    got = O.artifact_fold(x, table, 16, False)
+    # block index = x[r, 0] mod 3; fold word j = XOR of block words j, j+4, j+8, j+12
+    for r in range(3):
+        b = int(x[r, 0]) % 3
+        blk = [int(v) for v in table[16 * b:16 * b + 16]]
+        for j in range(D):
+            f = blk[j] ^ blk[j + 4] ^ blk[j + 8] ^ blk[j + 12]
+            assert int(got[r, j]) == (int(x[r, j]) ^ f)
+    # a zero table leaves the row; a table of one repeated slice folds to that slice
+    # (an even number of copies cancels)
+    assert np.array_equal(O.artifact_fold(x, np.zeros(48, np.uint32), 16, False), x)
+    rep = np.tile(np.array([5, 6, 7, 8], np.uint32), 8)            # blocks of 2 slices
+    assert np.array_equal(O.artifact_fold(x, rep, 8, False), x)
+    rep3 = np.tile(np.array([5, 6, 7, 8], np.uint32), 9)           # blocks of 3 slices
+    assert np.array_equal(O.artifact_fold(x, rep3, 12, False), x ^ np.array([5, 6, 7, 8], np.uint32))
+
+
+def test_artifact_memory_output_is_the_top_24_bits():
+    x = np.array([[0, 0xFFFFFFFF, 0x00000100, 0x80000000]], np.uint32)
+    got = O.artifact_fold(x, np.zeros(4, np.uint32), 4, True)
+    assert got.dtype == np.float32
+    assert list(got[0]) == [0.0, (2 ** 24 - 1) / 2 ** 24, 2.0 ** -24, 0.5]
+
+
+def test_artifact_compute_steps():
+    # zero iterations: the word's top 23 bits as the mantissa of a float in [1, 2)
+    w = np.array([0, 0xFFFFFFFF, 1 << 31, 511], np.uint32)
+    x0 = O.artifact_compute(w, 0).view(np.float32)
+    assert list(x0) == [1.0, 2.0 - 2.0 ** -23, 1.5, 1.0]
+    # one iteration from 1: 1 - 2^-11 + 2^-10 = 1 + 2^-11, exact in FP32
+    assert int(O.artifact_compute(np.array([0], np.uint32), 1)[0]) == 0x3F801000
+    # two roundings, not one fused operation: for this word (one of 1,022 of the 2^23
+    # mantissas where the two differ) a single rounding of x a + b gives another float
+    w = np.array([0x40200], np.uint32)
+    x = ((w >> np.uint32(9)) | np.uint32(0x3F800000)).view(np.float32)[0]
+    two = np.float32(np.float32(x * O.ARTIFACT_C_MUL) + O.ARTIFACT_C_ADD)
+    fused = np.float32(np.float64(x) * np.float64(O.ARTIFACT_C_MUL) + np.float64(O.ARTIFACT_C_ADD))
+    step = O.artifact_compute(w, 1).view(np.float32)[0]
+    assert step == two and step != fused
+    # the iteration contracts towards its fixed point 2 (= 2^-10 / 2^-11); in FP32 it
+    # settles below, at 2 - 2^-13 (bits 0x3FFFFC00), where a step no longer moves it
+    far = O.artifact_compute(np.array([0, 1 << 31], np.uint32), 40000)
+    assert list(far) == [0x3FFFFC00, 0x3FFFFC00]
+    assert list(O.artifact_compute(np.array([0], np.uint32), 40001)) == [0x3FFFFC00]

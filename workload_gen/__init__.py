@@ -24,7 +24,7 @@ import numpy as np
 _STREAMS = {
     "c0_weights": 1, "c0_queries": 2, "c1_audio": 3, "c1_weights": 4,
     "arrivals": 5, "requests": 6, "tables": 7, "predictor": 8, "c4": 9,
-    "handoff": 10, "dtree": 11,
+    "handoff": 10, "dtree": 11, "artifact": 12,
 }
 
 
@@ -217,3 +217,15 @@ def predictor_batch(m: int, seed: int = 0, sub: int = 0, n_in: int = 16):
     x = g.uniform(0.0, 1.0, (m, n_in)).astype(np.float32)
     y = g.normal(10.0, 1.0, m).astype(np.float32)
     return x, y
+
+
+# ---------------------------------------------------------------- artifact stages
+ARTIFACT_D = 1024                   # words per row
+ARTIFACT_P_WORDS = (4096, 16384, 65536)        # p1, p2, p3: 16 / 64 / 256 KiB per row over the host link
+ARTIFACT_C_ITERS = (256, 1024, 4096)           # c1, c2, c3: 0.5 / 2 / 8 MFLOP per row
+ARTIFACT_M_WORDS = (16384, 65536, 262144)      # m1, m2, m3: 64 KiB / 256 KiB / 1 MiB per row from HBM
+
+
+def artifact_words(n: int, seed: int = 0, sub: int = 0) -> np.ndarray:
+    """n uniform random uint32 words (artifact queries, tables)."""
+    return rng("artifact", seed, sub).integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
