@@ -715,6 +715,10 @@ def artifact_suite(cm, G, torch, trial_s, iters, failures):
         per = float(np.mean(ns))
         gbs = nk * 128 * 4 * G.ARTIFACT_P_WORDS[2] / per
         contention.append({"instances": nk, "us_per_batch": round(per / 1e3, 1), "aggregate_gbs": round(gbs, 1)})
+    # contention: an instance's time per batch grows by more than a quarter over one
+    # instance alone (the host link is shared); saturation: the aggregate stops growing
+    cont = next((c["instances"] for c in contention[1:] if c["us_per_batch"] > 1.25 * contention[0]["us_per_batch"]),
+                None)
     sat = next((c["instances"] for c in contention[1:]
                 if c["aggregate_gbs"] < 1.1 * contention[c["instances"] - 2]["aggregate_gbs"]), None)
     del dm, hp
@@ -723,7 +727,113 @@ def artifact_suite(cm, G, torch, trial_s, iters, failures):
                              "m_words_per_row": list(G.ARTIFACT_M_WORDS)},
             "hbm_bw_budget_gbs": bw_peak / 1e9, "profile_s": prof_s, "pipelines": results,
             "measured_where_bw_binds": bind, "pcie_contention": contention,
-            "pcie_saturates_at_instances": sat, "suite_s": time.perf_counter() - t0}
+            "pcie_contention_from_instances": cont, "pcie_aggregate_stops_growing_at_instances": sat,
+            "suite_s": time.perf_counter() - t0}
+
+
+# ---------------------------------------------------------------- image retrieval
+C4_TABLE_ROWS = 10_000_000        # 10M x 128 FP16 = 2.56 GB
+C4_IDS, C4_HEADS, C4_DIM = 32, 8, 128
+
+
+def c4_retrieval(cm, G, torch, trial_s, iters, failures):
+    """The five-step image-retrieval pipeline as configured: conv3x3 on 56x56x64 BF16
+    maps + global pool -> MLP 64-1024-1024 (BF16) -> gather of 32 Zipf(1.1) ids per
+    query from a 10M x 128 FP16 table and scores against 8 query heads -> top-100.
+    Solo table, Eq. 1 exactly and by simulated annealing (middle stages up to 5
+    instances), and the measured peak at p99 <= QoS of the exact allocation."""
+    import numpy as np
+    t0 = time.perf_counter()
+    table = torch.empty((C4_TABLE_ROWS, C4_DIM), dtype=torch.float16, device="cuda")
+    for r0, chunk in G.fp16_table_chunks(C4_TABLE_ROWS, C4_DIM, seed=4):
+        table[r0:r0 + chunk.shape[0]] = torch.from_numpy(chunk).cuda()
+    wc = torch.from_numpy(G.c4_conv_weights(0).view(np.int16)).cuda()
+    wm = [torch.from_numpy(w.view(np.int16)).cuda() for w in G.c1_mlp_weights(4, dims=G.C4_MLP_DIMS)]
+    n = 1024
+    x = G.c4_feature_maps(n, seed=9)
+    ids = G.zipf_ids(n, C4_IDS, C4_TABLE_ROWS, seed=9)
+    pool = torch.from_numpy(np.concatenate([x.reshape(n, -1).view(np.uint8), ids.view(np.uint8)], axis=1)).cuda()
+    stages = (cm.stage_desc(cm.STAGE_CONV_POOL, dims=(G.C4_H, G.C4_W, 64, 64), weights=(wc.data_ptr(),), n_layers=0),
+              cm.stage_desc(cm.STAGE_MLP_BF16, dims=G.C4_MLP_DIMS, weights=[t.data_ptr() for t in wm]),
+              cm.stage_desc(cm.STAGE_GATHER_SCORE, dims=(C4_HEADS * C4_DIM, C4_DIM, C4_IDS),
+                            weights=(table.data_ptr(),), k=C4_TABLE_ROWS),
+              cm.stage_desc(cm.STAGE_TOPK, dims=(C4_HEADS * C4_IDS,), k=100, n_layers=0))
+    gs_in = np.concatenate([G.rng("c4", 5).standard_normal((128, C4_HEADS * C4_DIM)).astype(np.float32).view(np.uint8),
+                            ids[:128].view(np.uint8)], axis=1)
+    ins = [pool[:128].contiguous(), torch.from_numpy(G.rng("c4", 6).standard_normal((128, 64)).astype(np.float32)).cuda(),
+           torch.from_numpy(gs_in).cuda(),
+           torch.from_numpy(G.rng("c4", 7).standard_normal((128, C4_HEADS * C4_IDS)).astype(np.float32)).cuda()]
+    out = torch.empty(128 * 1024, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    K, nb = len(SHARES), len(BATCHES)
+    lat = np.zeros((4, K, nb), np.int64)
+    for s_, st in enumerate(stages):
+        for k, share in enumerate(SHARES):
+            for j, b in enumerate(BATCHES):
+                ns = cm.camelot_stage_run(st, ins[s_].data_ptr(), out.data_ptr(), b, share, 0, 2, device=True)
+                lat[s_, k, j] = max(1, int(math.ceil(ns)))
+    prof_s = time.perf_counter() - t0 - setup_s
+    prob = cm.ProblemArrays(cu_total=256, cu_step=8, max_instances=8, max_inst_per_stage=5, batches=BATCHES,
+                            qos_ns=QOS_NS, hbm_bytes_budget=1 << 40, hbm_bw_budget=1 << 62, lat_ns=lat,
+                            bw_bps=np.zeros_like(lat), mem_bytes=np.zeros((4, nb), np.int64), inst_max=[1, 5, 5, 1])
+    ta = time.perf_counter()
+    a = cm.camelot_alloc_peak(prob).as_dict()
+    t_exact = time.perf_counter() - ta
+    ta = time.perf_counter()
+    sa = cm.camelot_alloc_sa(prob, cm.OBJ_PEAK, iters=20000, seed=11)
+    t_sa = time.perf_counter() - ta
+    pred = a["thr_num"] / a["thr_den"]
+    lo, hi, best = 0.0, 2 * pred, 0.0
+    best_p99 = None
+    for it in range(iters):
+        rate = pred if it == 0 else (lo + hi) / 2
+        n_req = int(min(max(rate * trial_s, 2000), 2_000_000))
+        arr = G.poisson_arrivals_ns(n_req, rate, seed=it, sub=7)
+        cfg = cm.pipeline_config(stages, a["cu"], max_batch=a["batch"], batch_target=a["batch"],
+                                 batch_timeout_ns=QOS_NS // 4, ring_depth=max(4, 2 * max(a["n"])),
+                                 ingest=cm.INGEST_REPLAY, side_bytes=4 * C4_IDS, egress_capacity=1 << 18,
+                                 idle_timeout_ns=5_000_000_000, n_inst=a["n"])
+        p = cm.camelot_pipeline_create(cfg)
+        lats = np.empty(n_req, np.int64)
+        done, late, ok = 0, 0, False
+        ci, cl = np.empty(1 << 16, np.uint64), np.empty(1 << 16, np.int64)
+        try:
+            cm.camelot_pipeline_replay(p, np.arange(1, n_req + 1), np.ones(n_req, np.int32), arr,
+                                       np.arange(n_req) % n, pool.data_ptr(), n)
+            deadline = time.perf_counter() + trial_s * 3 + 2
+            while done < n_req and time.perf_counter() < deadline:
+                k = cm.camelot_pipeline_drain_latency(p, ci, cl, 100_000_000)
+                mm = min(k, n_req - done)
+                lats[done:done + mm] = cl[:mm]
+                late += int(np.count_nonzero(cl[:mm] > QOS_NS))
+                done += mm
+                if late > 0.011 * n_req:
+                    break
+            if done == n_req:
+                srt = np.sort(lats[n_req // 10:])
+                p99 = int(srt[math.ceil(0.99 * len(srt)) - 1])
+                ok = p99 <= QOS_NS
+        except cm.CamelotError as e:
+            failures.append(f"retrieval pipeline: {e}")
+        finally:
+            cm.camelot_pipeline_destroy(p)
+        log(f"  [retrieval] {rate / 1e3:.1f} kq/s -> ok={ok}")
+        if ok:
+            lo, best, best_p99 = rate, rate, p99
+        else:
+            hi = rate
+    del table, pool
+    torch.cuda.empty_cache()
+    return {"workload": "conv3x3 56x56x64 BF16 + pool -> MLP 64-1024-1024 BF16 -> gather+score (32 Zipf(1.1) ids "
+                        "of a 10M x 128 FP16 table, 8 heads) -> top-100",
+            "table_rows": C4_TABLE_ROWS, "allocation": {"cu": a["cu"], "n": a["n"], "batch": a["batch"]},
+            "predicted_qps": pred, "measured_peak_qps": best, "p99_ns_at_peak": best_p99,
+            "exact_alloc_ms": t_exact * 1e3, "sa_alloc_ms": t_sa * 1e3,
+            "sa_predicted_qps": None if sa is None else sa.thr_num / sa.thr_den,
+            "sa_allocation": None if sa is None else {"cu": sa.as_dict()["cu"], "n": sa.as_dict()["n"],
+                                                      "batch": sa.batch},
+            "setup_s": setup_s, "profile_s": prof_s}
 
 
 ROOF_LAUNCHES, ROOF_REPS = 10, 50
@@ -798,6 +908,7 @@ def main():
     ap.add_argument("--cpu-seed", type=int, default=7)
     ap.add_argument("--skip-serving", action="store_true", help="skip the four-pipeline serving sweep")
     ap.add_argument("--skip-artifacts", action="store_true", help="skip the artifact-suite leg")
+    ap.add_argument("--skip-retrieval", action="store_true", help="skip the image-retrieval leg")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-learned", action="store_true", help="skip the learned-allocator comparison")
     ap.add_argument("--dump", default="", help="write the profile table and trials to this JSON file")
@@ -990,10 +1101,15 @@ def main():
     # 4b: the host-submit ingest peak of the deployed allocation: queries submitted
     # from host memory at their Poisson times by the library's paced submitter, through
     # the pinned ingest ring (PCIe on the path), the same QoS
-    host_peak = None
+    # (on Eq. 1's allocation with one MLP instance: with five MLP instances, a
+    # host-submit trial that followed an overloaded one has twice stalled or lost a
+    # record, which is under investigation)
+    host_peak, host_alloc = None, None
     try:
-        hp = sp.peak_search(use["cu"], cm.HANDOFF_DEVICE, batch, peak, args.trial_s, args.search_iters,
-                            "host submit", n_inst=ninst, host_ingest=True)
+        a1 = cm.camelot_alloc_peak(prob1).as_dict()
+        host_alloc = {"cu": a1["cu"], "n": a1["n"], "batch": a1["batch"]}
+        hp = sp.peak_search(a1["cu"], cm.HANDOFF_DEVICE, a1["batch"], a1["thr_num"] / a1["thr_den"], args.trial_s,
+                            args.search_iters, "host submit", n_inst=tuple(a1["n"]), host_ingest=True)
         host_peak = hp[0] if hp else 0.0
     except cm.CamelotError as e:
         sp.failures.append(f"host-submit search: {e}")
@@ -1035,6 +1151,11 @@ def main():
     if not args.skip_artifacts:
         artifacts = artifact_suite(cm, G, torch, args.trial_s, 6, sp.failures)
 
+    # 5d: the image-retrieval pipeline at its configured size
+    retrieval = None
+    if not args.skip_retrieval:
+        retrieval = c4_retrieval(cm, G, torch, args.trial_s, 6, sp.failures)
+
     # 6: handoff GB/s
     slot = 64 << 20
     h = cm.camelot_handoff_bench(cm.HANDOFF_DEVICE, slot, 16, 128, 128, 128)
@@ -1075,7 +1196,7 @@ def main():
         "baseline": {"kind": "even split 88/88/80 CUs, host-staged handoff", "peak_qps": peak_base,
                      "predicted_qps": pred_even,
                      "even_split_device_handoff_peak_qps": (base_dev[0] if base_dev else 0.0)},
-        "host_submit_peak_qps": host_peak,
+        "host_submit_peak_qps": host_peak, "host_submit_allocation": host_alloc,
         "gain_vs_even_split_host_staged": (peak / peak_base) if peak_base else None,
         "cus_at_20pct_load": {"camelot": cus20, "baseline_even_split": 256, "load_qps": lam20,
                               "p99_ns": p99_20},
@@ -1085,6 +1206,7 @@ def main():
         "share_read_gbs": share_bw,
         "serving_sweep": serving,
         "artifact_suite": artifacts,
+        "image_retrieval": retrieval,
         "learned_allocator": learned,
         "calibrated_table_allocation": calib,
         "no_bw_constraint_allocation": nc,

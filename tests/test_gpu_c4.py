@@ -175,3 +175,41 @@ def test_c4_pipeline_replay(torch, cm, c4, handoff):
     err = O.normwise_err(gv, rval)
     log(f"  top-100 values err={err:.3e}; rows with identical index lists {exact_idx}/{n}")
     assert err <= 2e-2
+
+
+def test_gather_score_on_the_configured_10m_table(torch, cm):
+    """Gather + score against the 10M x 128 FP16 table of the configured pipeline
+    (2.56 GB on the device) with Zipf(1.1) ids; the oracle scores the same rows."""
+    rows_t = 10_000_000
+    dt = torch.empty((rows_t, DIM), dtype=torch.float16, device="cuda")
+    for r0, chunk in G.fp16_table_chunks(rows_t, DIM, seed=4):
+        dt[r0:r0 + chunk.shape[0]] = torch.from_numpy(chunk).cuda()
+    rows = 16
+    ids = G.zipf_ids(rows, N_IDS, rows_t, seed=21)
+    q = G.rng("c4", 21, 3).standard_normal((rows, HEADS * DIM), dtype=np.float32)
+    buf = np.concatenate([q.view(np.uint8).reshape(rows, -1), ids.view(np.uint8).reshape(rows, -1)], axis=1)
+    desc = cm.stage_desc(cm.STAGE_GATHER_SCORE, dims=(HEADS * DIM, DIM, N_IDS), weights=(dt.data_ptr(),), k=rows_t)
+    din = to_dev(torch, buf)
+    dy = torch.full((rows, HEADS * N_IDS), float("nan"), device="cuda")
+    torch.cuda.synchronize()
+    log(f"gather_score over a 10M-row table, {rows} rows, ids {int(ids.min())}..{int(ids.max())}")
+    cm.camelot_stage_run(desc, din.data_ptr(), dy.data_ptr(), rows, 32, 0)
+    y = dy.cpu().numpy()
+    # the oracle's table: only the referenced rows, regenerated chunk by chunk
+    need = sorted(set(int(v) // (1 << 20) for v in ids.reshape(-1)))
+    base = G.fp16_table(1 << 20, DIM, seed=4)
+    rowmap = {}
+    for c in need:
+        ch = G.fp16_table_row_chunk(rows_t, DIM, 4, c, base=base)
+        for v in ids.reshape(-1):
+            if int(v) // (1 << 20) == c:
+                rowmap[int(v)] = ch[int(v) - c * (1 << 20)]
+    uniq = sorted(rowmap)
+    small = np.stack([rowmap[v] for v in uniq])
+    remap = np.vectorize({v: i for i, v in enumerate(uniq)}.get)(ids).astype(np.int32)
+    ref = O.gather_score(q, remap, small, DIM)
+    err = O.normwise_err(y, ref)
+    log(f"  err={err:.3e} over {len(uniq)} distinct rows")
+    assert err <= 1e-5
+    del dt
+    torch.cuda.empty_cache()

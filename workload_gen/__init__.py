@@ -141,6 +141,33 @@ def fp16_table(rows: int, dim: int, seed: int = 0) -> np.ndarray:
     return out
 
 
+def fp16_table_chunks(rows: int, dim: int, seed: int = 0, base_rows: int = 1 << 20):
+    """A large N(0,1) FP16 table, chunk by chunk (yields (first_row, chunk)): one
+    seeded block of base_rows N(0,1) rows, and each chunk its rows in a seeded order
+    with seeded sign flips (a sign flip keeps N(0,1)), so 10M rows cost one block's
+    draws. fp16_table_row_chunk(..) regenerates any one chunk."""
+    base = fp16_table(min(rows, base_rows), dim, seed=seed)
+    for c0 in range(0, rows, base_rows):
+        yield c0, _tiled_chunk(base, rows, dim, seed, c0 // base_rows)
+
+
+def _tiled_chunk(base, rows, dim, seed, c):
+    n = min(base.shape[0], rows - c * base.shape[0])
+    if c == 0:
+        return base[:n]
+    g = rng("c4", seed, 100 + c)
+    perm = g.permutation(base.shape[0])[:n]
+    flip = (g.integers(0, 2, (n, dim), dtype=np.uint8).astype(np.uint16) << np.uint16(15))
+    return (base[perm].view(np.uint16) ^ flip).view(np.float16)
+
+
+def fp16_table_row_chunk(rows: int, dim: int, seed: int, c: int, base=None, base_rows: int = 1 << 20):
+    """Chunk c of fp16_table_chunks (pass `base`, the seeded block, to avoid redrawing it)."""
+    if base is None:
+        base = fp16_table(min(rows, base_rows), dim, seed=seed)
+    return _tiled_chunk(base, rows, dim, seed, c)
+
+
 def zipf_ids(n: int, per_row: int, n_items: int, s: float = 1.1, seed: int = 0) -> np.ndarray:
     """[n, per_row] int32 ids with Zipf(s) popularity over n_items: ranks drawn by
     inverse CDF of p(r) ~ r^-s on 1..n_items, mapped to rows by a seeded
@@ -221,9 +248,9 @@ def predictor_batch(m: int, seed: int = 0, sub: int = 0, n_in: int = 16):
 
 # ---------------------------------------------------------------- artifact stages
 ARTIFACT_D = 1024                   # words per row
-ARTIFACT_P_WORDS = (4096, 16384, 65536)        # p1, p2, p3: 16 / 64 / 256 KiB per row over the host link
+ARTIFACT_P_WORDS = (1024, 4096, 16384)         # p1, p2, p3: 4 / 16 / 64 KiB per row over the host link
 ARTIFACT_C_ITERS = (256, 1024, 4096)           # c1, c2, c3: 0.5 / 2 / 8 MFLOP per row
-ARTIFACT_M_WORDS = (16384, 65536, 262144)      # m1, m2, m3: 64 KiB / 256 KiB / 1 MiB per row from HBM
+ARTIFACT_M_WORDS = (65536, 262144, 1048576)    # m1, m2, m3: 256 KiB / 1 MiB / 4 MiB per row from HBM
 
 
 def artifact_words(n: int, seed: int = 0, sub: int = 0) -> np.ndarray:
