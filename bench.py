@@ -731,6 +731,80 @@ def artifact_suite(cm, G, torch, trial_s, iters, failures):
             "suite_s": time.perf_counter() - t0}
 
 
+# ---------------------------------------------------------------- cross-process handoff
+IPC_SIZES = (64, 1024, 16 << 10, 256 << 10, 4 << 20, 64 << 20)
+
+
+def ipc_suite(cm):
+    """Section VI-B across processes: the handoff between a producer in this process and
+    a consumer in a peer process on the same GPU, through a region the peer opens by
+    IPC handle, at slot sizes from 64 B to 64 MiB, beside the host-staged path (a
+    device->pinned and a pinned->device copy per slot, in one process: a lower bound
+    for the host-staged path between two processes). Setup: the export (allocation,
+    clearing, handle) here and the open (mapping, header read) in the peer."""
+    import select
+    peer = subprocess.Popen([sys.executable, "-u", "-m", "paper_2005_02088_amd.ipc_peer", "consumers"],
+                            stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                            cwd=ROOT)
+
+    def next_line(timeout_s):
+        t_end = time.monotonic() + timeout_s
+        while time.monotonic() < t_end:
+            r, _, _ = select.select([peer.stdout], [], [], 0.2)
+            if r:
+                ln = peer.stdout.readline()
+                if not ln:
+                    break
+                if ln.strip().startswith("{"):
+                    return json.loads(ln)
+            elif peer.poll() is not None:
+                break
+        raise SystemExit(f"IPC peer gave no result within {timeout_s} s: {peer.stderr.read()[-1000:]}")
+
+    rows = []
+    try:
+        for size in IPC_SIZES:
+            n = int(min(8192, max(32, (1 << 30) // size)))
+            r, handle = cm.camelot_ipc_region_create(size, 4, 128)
+            info = cm.camelot_ipc_region_info(r)
+            try:
+                peer.stdin.write(f"{handle.hex()} {n} 128 20000\n")
+                peer.stdin.flush()
+                ready = next_line(60)
+                cm.camelot_ipc_handoff_run(r, cm.IPC_PRODUCER, n, 0, 20000)
+                res = next_line(60)
+            finally:
+                cm.camelot_ipc_region_destroy(r)
+            s, x = cm.camelot_handoff_expected(size, n)
+            nh = int(min(2048, max(8, (256 << 20) // size)))
+            hh = cm.camelot_handoff_bench(cm.HANDOFF_HOST, size, 2, nh, 8, 8)
+            row = {"slot_bytes": size, "slots": n, "channels": info["channels"],
+                   "device_us_per_slot": res["seconds"] * 1e6 / n, "device_gbs": res["gbs"],
+                   "checksum_ok": (res["sum"], res["xor"]) == (s, x),
+                   "host_staged_us_per_slot": hh["seconds"] * 1e6 / nh, "host_staged_gbs": hh["gbs"],
+                   "export_us": info["setup_ns"] / 1e3, "open_us": ready["setup_ns"] / 1e3}
+            rows.append(row)
+            log(f"  [ipc] {size} B: device {row['device_us_per_slot']:.2f} us/slot ({row['device_gbs']:.1f} GB/s), "
+                f"host-staged {row['host_staged_us_per_slot']:.2f} us/slot; export {row['export_us']:.0f} us, "
+                f"open {row['open_us']:.0f} us, checksum ok={row['checksum_ok']}")
+    finally:
+        try:
+            peer.stdin.close()
+            peer.wait(timeout=30)
+        except Exception:
+            peer.kill()
+    # the smallest size from which the device path is faster at every larger size
+    faster_from = None
+    for i in range(len(rows) - 1, -1, -1):
+        if rows[i]["device_us_per_slot"] < rows[i]["host_staged_us_per_slot"]:
+            faster_from = rows[i]["slot_bytes"]
+        else:
+            break
+    return {"sizes": rows, "device_faster_from_bytes": faster_from,
+            "max_export_us": max(r["export_us"] for r in rows), "max_open_us": max(r["open_us"] for r in rows),
+            "setup_budget_us": 1000}
+
+
 # ---------------------------------------------------------------- image retrieval
 C4_TABLE_ROWS = 10_000_000        # 10M x 128 FP16 = 2.56 GB
 C4_IDS, C4_HEADS, C4_DIM = 32, 8, 128
@@ -909,6 +983,7 @@ def main():
     ap.add_argument("--skip-serving", action="store_true", help="skip the four-pipeline serving sweep")
     ap.add_argument("--skip-artifacts", action="store_true", help="skip the artifact-suite leg")
     ap.add_argument("--skip-retrieval", action="store_true", help="skip the image-retrieval leg")
+    ap.add_argument("--skip-ipc", action="store_true", help="skip the cross-process handoff leg")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-learned", action="store_true", help="skip the learned-allocator comparison")
     ap.add_argument("--dump", default="", help="write the profile table and trials to this JSON file")
@@ -1156,6 +1231,9 @@ def main():
     if not args.skip_retrieval:
         retrieval = c4_retrieval(cm, G, torch, args.trial_s, 6, sp.failures)
 
+    # 5e: the handoff between processes
+    ipc = None if args.skip_ipc else ipc_suite(cm)
+
     # 6: handoff GB/s
     slot = 64 << 20
     h = cm.camelot_handoff_bench(cm.HANDOFF_DEVICE, slot, 16, 128, 128, 128)
@@ -1207,6 +1285,7 @@ def main():
         "serving_sweep": serving,
         "artifact_suite": artifacts,
         "image_retrieval": retrieval,
+        "ipc_handoff": ipc,
         "learned_allocator": learned,
         "calibrated_table_allocation": calib,
         "no_bw_constraint_allocation": nc,

@@ -308,9 +308,13 @@ int32_t camelot_stage_run_noalloc(const camelot_stage_desc* stage, const void* i
  *                          are resident in device memory before the run starts
  *                          (camelot_pipeline_replay); stage 0 admits request r
  *                          once the device clock passes its arrival time.
+ *   CAMELOT_INGEST_IPC     stage 0 reads the batches another process's pipeline
+ *                          exports (out_ipc there), from the ring behind
+ *                          ipc_handle (see "Pipelines across processes" below).
  */
 typedef enum { CAMELOT_HANDOFF_DEVICE = 0, CAMELOT_HANDOFF_HOST = 1 } camelot_handoff;
-typedef enum { CAMELOT_INGEST_HOST = 0, CAMELOT_INGEST_REPLAY = 1 } camelot_ingest;
+typedef enum { CAMELOT_INGEST_HOST = 0, CAMELOT_INGEST_REPLAY = 1, CAMELOT_INGEST_IPC = 2 } camelot_ingest;
+#define CAMELOT_IPC_HANDLE_BYTES 64
 
 typedef struct {
   int32_t n_stages;
@@ -340,7 +344,11 @@ typedef struct {
                                   payload row through every stage (0..4096, multiple of
                                   16): e.g. a query's item ids for a GATHER_SCORE stage.
                                   Payload rows are row_bytes_in(stage 0) + side_bytes. */
-  int32_t pad_;
+  int32_t out_ipc;             /* 1: the last stage is not a result stage; its batches go
+                                  to a ring exported to another process (no results,
+                                  no drain here)                                      */
+  uint8_t ipc_handle[CAMELOT_IPC_HANDLE_BYTES]; /* ingest == CAMELOT_INGEST_IPC: the
+                                  exporting pipeline's handle (camelot_pipeline_ipc_info) */
 } camelot_pipeline_config;
 
 typedef struct camelot_pipeline camelot_pipeline;
@@ -349,6 +357,27 @@ typedef struct camelot_pipeline camelot_pipeline;
  * prepares them (REPLAY ingest; workers start in camelot_pipeline_replay).
  * *out receives the handle. ENOMEM when the footprint exceeds hbm_budget_bytes. */
 int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, camelot_pipeline** out);
+
+/* Pipelines across processes (Section VI-B: microservices in separate processes
+ * exchange batches through GPU global memory, not through the host). A pipeline
+ * created with out_ipc = 1 allocates its last stage's output ring (header with the
+ * ring's geometry, slot state words, ring_depth slots; under 2 GiB, else EINVAL) in
+ * one device allocation and exports it; a pipeline in another process, created with
+ * ingest = CAMELOT_INGEST_IPC and that handle, opens it and its stage 0 consumes the
+ * batches with the same slot protocol as between two stages of one pipeline (the
+ * batch, its requests' ids and arrival times and the stage times travel in the
+ * slot). The importer checks the geometry (EINVAL if its stage 0 consumes another
+ * row size, another side_bytes, or a smaller max_batch than the exporter's); its
+ * stages follow the exporter's in the result timestamps, which are then absolute
+ * device-clock ns (epoch 0). Both pipelines must run on the same GPU. The importer
+ * launches its workers at create; destroy the importer before the exporter's memory
+ * is needed back (the exporter frees its allocation at destroy, the importer closes
+ * its mapping at destroy).
+ * camelot_pipeline_ipc_info: the exported handle (zeros for an importer that does not
+ * export) and the host time the export and/or the open took (allocation, clearing,
+ * header, handle; open, header read and checks). EINVAL for a pipeline that neither
+ * exports nor imports. */
+int32_t camelot_pipeline_ipc_info(const camelot_pipeline* p, uint8_t* handle, int64_t* setup_ns);
 
 /* HBM bytes the pipeline holds (rings, scratch, control; weights are borrowed and
  * not counted). */
@@ -474,7 +503,8 @@ int64_t camelot_stage_weight_bytes(const camelot_stage_desc* stage);
 /* Resources of the kernel that runs a stage kind: one_shot != 0 for the kernel of
  * camelot_stage_run, else the pipeline worker. *regs: registers per lane;
  * *lds_bytes: static LDS per workgroup; *fits: 1 when two workgroups fit on a CU
- * (what launching a worker requires), else 0. EINVAL for an unknown kind. */
+ * and the kernel needs no scratch (what launching a worker requires), else 0.
+ * EINVAL for an unknown kind. */
 int32_t camelot_stage_kernel_info(int32_t kind, int32_t one_shot, int32_t* regs, int64_t* lds_bytes,
                                   int32_t* fits);
 
@@ -514,6 +544,35 @@ int32_t camelot_handoff_bench(int32_t mode, int64_t slot_bytes, int32_t depth,
 /* Expected (sum, xor) checksum of the handoff pattern (host computation). */
 int32_t camelot_handoff_expected(int64_t slot_bytes, int64_t n_slots_total,
                                  uint64_t* sum, uint64_t* xr);
+
+/* The same handoff between two processes on one GPU (Section VI-B: the microservices
+ * of a pipeline are separate processes; the slot goes through global memory the two
+ * share, not through the host). One process creates a region (its ring of depth slots
+ * of slot_bytes, the per-(slot, channel) doorbells and the results; under 2 GiB, else
+ * EINVAL) and exports it (*handle: CAMELOT_IPC_HANDLE_BYTES); the other opens it.
+ * Every channel is a producer/consumer workgroup pair owning a chunk of each slot:
+ * min(channels, slot_bytes / 16) of them, at least 16 bytes each.
+ * camelot_ipc_handoff_run runs one side in the calling process on the CUs from
+ * cu_offset (as many as the region's channels, rounded up to a multiple of 8) and
+ * returns when it has finished: role CAMELOT_IPC_PRODUCER writes n_slots slots (the
+ * pattern of camelot_handoff_expected), CAMELOT_IPC_CONSUMER reads them; each region
+ * carries one producer run and one consumer run, started in either order (each waits
+ * at most timeout_ms for the other, ETIMEDOUT after). The side that ends last (the
+ * consumer) returns out as camelot_handoff_bench does: [0] seconds from the
+ * producer's first store to the consumer's last read, [1] bytes written + read,
+ * [2], [3] the checksum bits, [4] GB/s.
+ * camelot_ipc_region_info: host time the create (allocation, clearing, handle) or
+ * the open (mapping, header read) took, and the channel count.
+ * camelot_ipc_region_destroy: the creator frees the region, an opener unmaps it. */
+typedef struct camelot_ipc_region camelot_ipc_region;
+enum { CAMELOT_IPC_PRODUCER = 0, CAMELOT_IPC_CONSUMER = 1 };
+int32_t camelot_ipc_region_create(int64_t slot_bytes, int32_t depth, int32_t channels, uint8_t* handle,
+                                  camelot_ipc_region** out);
+int32_t camelot_ipc_region_open(const uint8_t* handle, camelot_ipc_region** out);
+int32_t camelot_ipc_region_info(const camelot_ipc_region* r, int64_t* setup_ns, int32_t* channels);
+int32_t camelot_ipc_handoff_run(camelot_ipc_region* r, int32_t role, int64_t n_slots, int32_t cu_offset,
+                                int32_t timeout_ms, double* out);
+int32_t camelot_ipc_region_destroy(camelot_ipc_region* r);
 
 /* ------------------------------------------------------------------ predictor
  * Learned contention predictor (replaces Section VII-A's per-microservice model):

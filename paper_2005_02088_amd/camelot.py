@@ -26,7 +26,9 @@ NOALLOC_SCRATCH_BYTES = 8 << 20          # CAMELOT_NOALLOC_SCRATCH_BYTES
 (STAGE_GEMM_RELU, STAGE_GEMM_ARGMAX, STAGE_LOGMEL, STAGE_MLP_BF16, STAGE_TOPK, STAGE_GATHER, STAGE_CONV_POOL,
  STAGE_GATHER_SCORE, STAGE_ARTIFACT_P, STAGE_ARTIFACT_C, STAGE_ARTIFACT_M) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 HANDOFF_DEVICE, HANDOFF_HOST = 0, 1
-INGEST_HOST, INGEST_REPLAY = 0, 1
+INGEST_HOST, INGEST_REPLAY, INGEST_IPC = 0, 1, 2
+IPC_HANDLE_BYTES = 64
+IPC_PRODUCER, IPC_CONSUMER = 0, 1
 PRED_NIN, PRED_NHID = 16, 64
 PRED_NPARAMS = 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -80,7 +82,8 @@ class PipelineConfig(C.Structure):
                 ("batch_timeout_ns", C.c_int64), ("ring_depth", C.c_int32), ("handoff", C.c_int32),
                 ("ingest", C.c_int32), ("max_rows_per_request", C.c_int32), ("ingest_capacity", C.c_int32),
                 ("egress_capacity", C.c_int32), ("idle_timeout_ns", C.c_int64),
-                ("hbm_budget_bytes", C.c_int64), ("side_bytes", C.c_int32), ("pad_", C.c_int32)]
+                ("hbm_budget_bytes", C.c_int64), ("side_bytes", C.c_int32), ("out_ipc", C.c_int32),
+                ("ipc_handle", C.c_uint8 * IPC_HANDLE_BYTES)]
 
 
 class Result(C.Structure):
@@ -178,6 +181,13 @@ _SIGS = {
     "camelot_dt_predict": (C.c_int32, [_P, _P, C.c_int32, _P]),
     "camelot_dt_export": (C.c_int32, [_P, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, _P, _P]),
     "camelot_dt_destroy": (None, [_P]),
+    "camelot_pipeline_ipc_info": (C.c_int32, [_P, _P, C.POINTER(C.c_int64)]),
+    "camelot_ipc_region_create": (C.c_int32, [C.c_int64, C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
+    "camelot_ipc_region_open": (C.c_int32, [_P, C.POINTER(_P)]),
+    "camelot_ipc_region_info": (C.c_int32, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "camelot_ipc_handoff_run": (C.c_int32, [_P, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                            C.POINTER(C.c_double)]),
+    "camelot_ipc_region_destroy": (C.c_int32, [_P]),
     "camelot_alloc_peak_dt": (C.c_int32, [C.POINTER(Problem), C.POINTER(SoloTables), _P, C.POINTER(Alloc), _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -328,7 +338,8 @@ def camelot_stage_run_noalloc(desc: StageDesc, in_ptr: int, out_ptr: int, rows: 
 def pipeline_config(stages, cu, *, cu_offset=0, max_batch=32, batch_target=1, batch_timeout_ns=0,
                     ring_depth=4, handoff=HANDOFF_DEVICE, ingest=INGEST_HOST, max_rows_per_request=1,
                     ingest_capacity=4096, egress_capacity=65536, idle_timeout_ns=20_000_000_000,
-                    hbm_budget_bytes=0, side_bytes=0, n_inst=None) -> PipelineConfig:
+                    hbm_budget_bytes=0, side_bytes=0, n_inst=None, out_ipc=False,
+                    ipc_handle=None) -> PipelineConfig:
     c = PipelineConfig()
     c.n_stages = len(stages)
     for i, s in enumerate(stages):
@@ -348,6 +359,11 @@ def pipeline_config(stages, cu, *, cu_offset=0, max_batch=32, batch_target=1, ba
     c.idle_timeout_ns = idle_timeout_ns
     c.hbm_budget_bytes = hbm_budget_bytes
     c.side_bytes = side_bytes
+    c.out_ipc = 1 if out_ipc else 0
+    if ipc_handle is not None:
+        h = bytes(ipc_handle)
+        assert len(h) == IPC_HANDLE_BYTES
+        C.memmove(c.ipc_handle, h, IPC_HANDLE_BYTES)
     return c
 
 
@@ -355,6 +371,49 @@ def camelot_pipeline_create(cfg: PipelineConfig) -> int:
     h = C.c_void_p()
     _check(_lib.camelot_pipeline_create(C.byref(cfg), C.byref(h)))
     return h.value
+
+
+def camelot_pipeline_ipc_info(p: int) -> tuple:
+    """(exported handle as bytes, setup ns of the export and/or open)."""
+    h = (C.c_uint8 * IPC_HANDLE_BYTES)()
+    ns = C.c_int64(0)
+    _check(_lib.camelot_pipeline_ipc_info(p, C.addressof(h), C.byref(ns)))
+    return bytes(h), ns.value
+
+
+# ------------------------------------------------------------------ cross-process handoff
+def camelot_ipc_region_create(slot_bytes: int, depth: int, channels: int) -> tuple:
+    """(region handle, exported IPC handle bytes)."""
+    h = (C.c_uint8 * IPC_HANDLE_BYTES)()
+    r = C.c_void_p()
+    _check(_lib.camelot_ipc_region_create(slot_bytes, depth, channels, C.addressof(h), C.byref(r)))
+    return r.value, bytes(h)
+
+
+def camelot_ipc_region_open(handle: bytes) -> int:
+    h = (C.c_uint8 * IPC_HANDLE_BYTES).from_buffer_copy(bytes(handle))
+    r = C.c_void_p()
+    _check(_lib.camelot_ipc_region_open(C.addressof(h), C.byref(r)))
+    return r.value
+
+
+def camelot_ipc_region_info(r: int) -> dict:
+    ns = C.c_int64(0)
+    ch = C.c_int32(0)
+    _check(_lib.camelot_ipc_region_info(r, C.byref(ns), C.byref(ch)))
+    return {"setup_ns": ns.value, "channels": ch.value}
+
+
+def camelot_ipc_handoff_run(r: int, role: int, n_slots: int, cu_offset: int, timeout_ms: int = 10000) -> dict:
+    out = (C.c_double * 5)()
+    _check(_lib.camelot_ipc_handoff_run(r, role, n_slots, cu_offset, timeout_ms, out))
+    raw = bytes(out)
+    return {"seconds": out[0], "bytes": out[1], "sum": int.from_bytes(raw[16:24], "little"),
+            "xor": int.from_bytes(raw[24:32], "little"), "gbs": out[4]}
+
+
+def camelot_ipc_region_destroy(r: int) -> None:
+    _check(_lib.camelot_ipc_region_destroy(r))
 
 
 def camelot_pipeline_footprint(p: int) -> int:

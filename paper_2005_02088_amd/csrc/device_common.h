@@ -267,9 +267,13 @@ __device__ __host__ __forceinline__ uint64_t id_hash(uint64_t x) {
 // polling uses relaxed loads. Counter resets are waited on (s_waitcnt) before the
 // next arrival can depend on them. The wait is bounded: on expiry, or when another
 // workgroup aborted, returns false (and sets ctl->abort).
-// Workgroup barrier after which every wave's global stores have completed (reached
-// the L2), so that one agent-scope write-back by thread 0 publishes all of them.
+// Workgroup barrier before one thread publishes the workgroup's stores with a flag.
+// Every wave releases its own stores at agent scope first (an L2 write-back per wave):
+// thread 0's write-back alone after the barrier did not always cover the other
+// waves' stores on gfx950 (a reader on another XCD then saw old data behind a new
+// flag).
 __device__ __forceinline__ void wg_barrier_stores_done() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 }
@@ -282,6 +286,13 @@ __device__ __forceinline__ void poll_backoff(uint32_t polls) {
   else if (polls < 1024) __builtin_amdgcn_s_sleep(4);
   else __builtin_amdgcn_s_sleep(32);
 }
+
+// Acquire at agent scope in every wave of the workgroup, after the barrier that
+// follows one thread's observation of a flag (the once-per-batch hand-offs use it
+// besides that thread's own acquire: a cheap extra guard; the per-wave release in
+// wg_barrier_stores_done is what the stale reads seen on gfx950 needed).
+__device__ __forceinline__ void wave_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void wave_acquire_system() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, ""); }
 
 // The barrier in two halves: arrive publishes this workgroup's writes and counts
 // it in; wait returns once every workgroup has arrived. Work that reads nothing

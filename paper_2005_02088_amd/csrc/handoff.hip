@@ -4,7 +4,8 @@
 // waits on each doorbell, folds every 32-bit word of the chunk into a checksum and
 // frees the slot. Producer workgroup j and consumer workgroup j own the same chunk
 // of every slot, so the channels are independent (no grid barrier). All waits are
-// bounded by spin_ticks.
+// bounded by spin_ticks. Every producer wave releases its own stores before the
+// workgroup barrier after which one thread rings the doorbell.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -421,11 +421,16 @@ int32_t launch_worker(int kind, const WorkerArgs& a, int n_cus, hipStream_t s) {
   // its grid barriers could never complete. Refuse such a kernel instead: two
   // workgroups of 4 wave64s fit on a CU when each wave needs at most 256 of the
   // SIMD's 512 registers per lane and each workgroup at most half of the LDS.
+  // Nor may it need scratch: the runtime may start fewer waves than the grid when it
+  // cannot back every wave's scratch at once, which leaves workgroups unplaced too.
   hipFuncAttributes fa;
   HIP_TRY(hipFuncGetAttributes(&fa, fn));
   if (fa.numRegs > kMaxRegsResident || fa.sharedSizeBytes > kMaxLdsResident)
     return fail(CAMELOT_EDEVICE, "stage kind %d: %d registers and %zu LDS bytes per workgroup leave fewer than %d "
                 "workgroups per CU", kind, fa.numRegs, (size_t)fa.sharedSizeBytes, kMinWgPerCuResident);
+  if (fa.localSizeBytes > 0)
+    return fail(CAMELOT_EDEVICE, "stage kind %d needs %zu bytes of scratch per lane; a worker grid must not",
+                kind, (size_t)fa.localSizeBytes);
   void* args[] = {(void*)&a};
   // a persistent worker adds its control workgroup last: it shares a CU with one of
   // the compute workgroups, which are placed first, one per CU
@@ -447,7 +452,7 @@ extern "C" int32_t camelot_stage_kernel_info(int32_t kind, int32_t one_shot, int
   HIP_TRY(hipFuncGetAttributes(&fa, fn));
   *regs = fa.numRegs;
   *lds_bytes = (int64_t)fa.sharedSizeBytes;
-  *fits = (fa.numRegs <= kMaxRegsResident && fa.sharedSizeBytes <= kMaxLdsResident) ? 1 : 0;
+  *fits = (fa.numRegs <= kMaxRegsResident && fa.sharedSizeBytes <= kMaxLdsResident && fa.localSizeBytes == 0) ? 1 : 0;
   return CAMELOT_OK;
 }
 
@@ -561,6 +566,25 @@ struct Ring {
   int64_t stride = 0;
 };
 
+// Header at the start of an exported ring's allocation (written by the exporting
+// process, read and checked by the importing one): the geometry both sides must
+// agree on. The state words follow it, then the slots.
+struct IpcRingHeader {
+  uint64_t magic;
+  int32_t version, depth;
+  int64_t stride, side_off, row_bytes;
+  int32_t side_bytes, max_batch, stamp_next, pad;
+};
+constexpr uint64_t kIpcMagic = 0x474e495254454d43ull;      // "CMETRING"
+constexpr int32_t kIpcVersion = 1;
+constexpr int64_t kIpcHeaderBytes = 256;
+constexpr int64_t kIpcMaxBytes = 2LL << 30;                 // an opened allocation stays under 2 GiB
+// Exported allocations are whole multiples of 2 MiB: a smaller one may be carved out
+// of a larger block the runtime holds, which another process cannot open.
+constexpr int64_t kIpcGranule = 2LL << 20;
+static_assert(sizeof(IpcRingHeader) <= kIpcHeaderBytes, "ring header");
+static_assert(sizeof(hipIpcMemHandle_t) == CAMELOT_IPC_HANDLE_BYTES, "IPC handle size");
+
 struct camelot_pipeline {
   camelot_pipeline_config cfg;
   DevInfo dev;
@@ -613,7 +637,16 @@ struct camelot_pipeline {
   std::atomic<bool> submit_stop{false};
   std::atomic<int32_t> submit_rc{0};
   std::atomic<int64_t> submit_count{0};
+  // cross-process rings: the last stage's exported output ring (out_ipc) and the
+  // first stage's input ring opened from another process (CAMELOT_INGEST_IPC)
+  uint8_t* ipc_out_base = nullptr;         // this process's allocation, exported
+  uint8_t* ipc_in_base = nullptr;          // another process's allocation, opened
+  uint8_t ipc_handle[CAMELOT_IPC_HANDLE_BYTES] = {0};
+  int64_t ipc_setup_ns = 0;
+  IpcRingHeader ipc_in_hdr = {};           // geometry of the opened ring
+  int stamp_base = 0;                      // index of stage 0 in the timestamps
 };
+
 
 static void* pinned(size_t bytes) {
   void* p = nullptr;
@@ -716,6 +749,8 @@ static void free_pipeline(camelot_pipeline* p) {
       p->in_ring[i + 1].state = nullptr;
     }
   }
+  if (p->ipc_out_base) (void)hipFree(p->ipc_out_base);
+  if (p->ipc_in_base) (void)hipIpcCloseMemHandle(p->ipc_in_base);
   if (p->hctl) (void)hipHostFree(p->hctl);
   if (p->pub) (void)hipHostFree(p->pub);
   if (p->ingest) (void)hipHostFree(p->ingest);
@@ -732,8 +767,13 @@ static int32_t validate_config(const camelot_pipeline_config* c, const DevInfo& 
   int off = c->cu_offset;
   for (int i = 0; i < c->n_stages; ++i) {
     if ((rc = check_stage(&c->stages[i], &p->in_b[i], &p->out_b[i]))) return rc;
-    if (is_result_stage(c->stages[i].kind) != (i == c->n_stages - 1))
-      return fail(CAMELOT_EINVAL, "stage %d: result stages (GEMM_ARGMAX, TOPK) must be last and the last stage must be one", i);
+    // an exporting pipeline ends in a ring another process reads, not in results
+    const bool result_here = i == c->n_stages - 1 && !c->out_ipc;
+    if (is_result_stage(c->stages[i].kind) != result_here)
+      return fail(CAMELOT_EINVAL,
+                  c->out_ipc ? "stage %d: an exporting pipeline (out_ipc) has no result stage (GEMM_ARGMAX, TOPK)"
+                             : "stage %d: result stages (GEMM_ARGMAX, TOPK) must be last and the last stage must be one",
+                  i);
     if (i > 0 && p->out_b[i - 1] != p->in_b[i])
       return fail(CAMELOT_EINVAL, "stage %d consumes %lld-byte rows but stage %d produces %lld", i,
                   (long long)p->in_b[i], i - 1, (long long)p->out_b[i - 1]);
@@ -758,8 +798,9 @@ static int32_t validate_config(const camelot_pipeline_config* c, const DevInfo& 
   if (c->ring_depth < 2 || c->ring_depth > 1024) return fail(CAMELOT_EINVAL, "ring_depth must be in 2..1024");
   if (c->handoff != CAMELOT_HANDOFF_DEVICE && c->handoff != CAMELOT_HANDOFF_HOST)
     return fail(CAMELOT_EINVAL, "unknown handoff mode");
-  if (c->ingest != CAMELOT_INGEST_HOST && c->ingest != CAMELOT_INGEST_REPLAY)
+  if (c->ingest != CAMELOT_INGEST_HOST && c->ingest != CAMELOT_INGEST_REPLAY && c->ingest != CAMELOT_INGEST_IPC)
     return fail(CAMELOT_EINVAL, "unknown ingest mode");
+  if (c->out_ipc != 0 && c->out_ipc != 1) return fail(CAMELOT_EINVAL, "out_ipc must be 0 or 1");
   if (c->max_rows_per_request < 1 || c->max_rows_per_request > c->max_batch)
     return fail(CAMELOT_EINVAL, "max_rows_per_request must be in 1..max_batch");
   if (c->ingest == CAMELOT_INGEST_HOST && (c->ingest_capacity < 1 || c->ingest_capacity > (1 << 22)))
@@ -804,6 +845,19 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
   for (int w = 0; w < p->NW; ++w) {
     int st = 0;
     fp += stage_scratch_bytes(&cfg->stages[p->w_stage[w]], &st) + round_up(sizeof(WorkerCtl), 256);
+  }
+  // the last stage's exported ring (out_ipc): [header | state words | slots]
+  int64_t ipc_side_off = 0, ipc_stride = 0, ipc_bytes = 0;
+  if (cfg->out_ipc) {
+    ipc_side_off = kSlotHeaderBytes + round_up((int64_t)cfg->max_batch * p->out_b[S - 1], 256);
+    ipc_stride = ipc_side_off + round_up((int64_t)cfg->max_batch * side, 256);
+    ipc_bytes = kIpcHeaderBytes + round_up(8LL * D, 256) + D * ipc_stride;
+    if (round_up(ipc_bytes, kIpcGranule) >= kIpcMaxBytes) {
+      delete p;
+      return fail(CAMELOT_EINVAL, "the exported ring takes %lld bytes; it must stay under 2 GiB (fewer slots)",
+                  (long long)ipc_bytes);
+    }
+    fp += round_up(ipc_bytes, kIpcGranule);
   }
   p->footprint = fp;
   if (cfg->hbm_budget_bytes > 0 && fp > cfg->hbm_budget_bytes) {
@@ -873,6 +927,52 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     }
   }
 
+  // ---- cross-process rings: open the input ring first (it fixes where this
+  // pipeline's stages sit in the timestamps), then export the output ring
+  if (cfg->ingest == CAMELOT_INGEST_IPC) {
+    const int64_t t0 = host_ns();
+    hipIpcMemHandle_t h;
+    std::memcpy(&h, cfg->ipc_handle, sizeof h);
+    P_TRY(hipIpcOpenMemHandle((void**)&p->ipc_in_base, h, hipIpcMemLazyEnablePeerAccess));
+    IpcRingHeader& hd = p->ipc_in_hdr;
+    rc = d2h(&hd, p->ipc_in_base, sizeof hd);
+    if (rc) { free_pipeline(p); return rc; }
+    const char* bad = hd.magic != kIpcMagic || hd.version != kIpcVersion ? "is not a ring exported by this library"
+                      : hd.row_bytes != p->in_b[0] ? "carries rows of another size than stage 0 consumes"
+                      : hd.side_bytes != cfg->side_bytes ? "carries another number of side bytes"
+                      : hd.max_batch > cfg->max_batch ? "carries batches larger than max_batch"
+                      : hd.stamp_next + S > kMaxStages ? "leaves too few stage timestamps for this pipeline"
+                                                       : nullptr;
+    if (bad) {
+      rc = fail(CAMELOT_EINVAL, "the opened ring %s", bad);
+      free_pipeline(p);
+      return rc;
+    }
+    p->stamp_base = hd.stamp_next;
+    p->ipc_setup_ns += host_ns() - t0;
+  }
+  if (cfg->out_ipc) {
+    const int64_t t0 = host_ns();
+    P_TRY(hipMalloc((void**)&p->ipc_out_base, round_up(ipc_bytes, kIpcGranule)));
+    P_TRY(hipMemset(p->ipc_out_base, 0, ipc_bytes));
+    IpcRingHeader hd = {};
+    hd.magic = kIpcMagic;
+    hd.version = kIpcVersion;
+    hd.depth = D;
+    hd.stride = ipc_stride;
+    hd.side_off = ipc_side_off;
+    hd.row_bytes = p->out_b[S - 1];
+    hd.side_bytes = cfg->side_bytes;
+    hd.max_batch = cfg->max_batch;
+    hd.stamp_next = p->stamp_base + S;
+    rc = h2d(p->ipc_out_base, &hd, sizeof hd);
+    if (rc) { free_pipeline(p); return rc; }
+    hipIpcMemHandle_t h;
+    P_TRY(hipIpcGetMemHandle(&h, p->ipc_out_base));
+    std::memcpy(p->ipc_handle, &h, sizeof h);
+    p->ipc_setup_ns += host_ns() - t0;
+  }
+
   release_cached_streams();
   // ---- stage instance (worker) resources, control, streams
   int off = cfg->cu_offset;
@@ -893,7 +993,7 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     if (rc) { free_pipeline(p); return rc; }
     p->w_off[w] = off;
     off += cfg->cu[i];
-    a.stage_index = i;
+    a.stage_index = p->stamp_base + i;
     a.n_stages = S;
     a.worker_index = w;
     a.n_inst = p->n_inst[i];
@@ -907,7 +1007,16 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
     a.batch_timeout_ticks = ns_to_ticks(cfg->batch_timeout_ns, p->dev.wclk_hz);
     a.idle_ticks = ns_to_ticks(cfg->idle_timeout_ns, p->dev.wclk_hz);
     a.spin_ticks = 2 * p->dev.wclk_hz;
-    if (i == 0) {
+    if (i == 0 && cfg->ingest == CAMELOT_INGEST_IPC) {
+      const IpcRingHeader& hd = p->ipc_in_hdr;
+      a.in_kind = kInRing;
+      a.in_depth = hd.depth;
+      a.in_state = (uint64_t*)(p->ipc_in_base + kIpcHeaderBytes);
+      a.in_ring = p->ipc_in_base + kIpcHeaderBytes + round_up(8LL * hd.depth, 256);
+      a.in_state_sys = 0;
+      a.in_stride = hd.stride;
+      a.in_side_off = hd.side_off;
+    } else if (i == 0) {
       a.in_kind = cfg->ingest == CAMELOT_INGEST_HOST ? kInHost : kInReplay;
       if (cfg->ingest == CAMELOT_INGEST_HOST) {
         a.ingest = p->ingest;
@@ -931,6 +1040,14 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
       a.out_state = r.state;
       a.out_state_sys = r.state_host ? 1 : 0;
       a.out_stride = r.stride;
+    } else if (cfg->out_ipc) {
+      a.out_kind = kOutRing;
+      a.out_depth = D;
+      a.out_state = (uint64_t*)(p->ipc_out_base + kIpcHeaderBytes);
+      a.out_ring = p->ipc_out_base + kIpcHeaderBytes + round_up(8LL * D, 256);
+      a.out_state_sys = 0;
+      a.out_stride = ipc_stride;
+      a.out_side_off = ipc_side_off;
     } else {
       a.out_kind = kOutEgress;
       a.egress = p->egress;
@@ -943,12 +1060,14 @@ extern "C" int32_t camelot_pipeline_create(const camelot_pipeline_config* cfg, c
   }
   rc = calibrate_clock(p);
   if (rc) { free_pipeline(p); return rc; }
-  p->epoch_ticks = host_now_ticks(p);
+  // a pipeline fed by another process keeps the device clock's zero as its epoch, so
+  // its results' timestamps (arrivals stamped upstream included) are absolute
+  p->epoch_ticks = cfg->ingest == CAMELOT_INGEST_IPC ? 0 : host_now_ticks(p);
 
   if (host_handoff)
     for (int i = 0; i + 1 < S; ++i) p->relays.emplace_back(relay_loop, p, i);
 
-  if (cfg->ingest == CAMELOT_INGEST_HOST) {
+  if (cfg->ingest == CAMELOT_INGEST_HOST || cfg->ingest == CAMELOT_INGEST_IPC) {
     for (int w = p->NW - 1; w >= 0; --w) {
       const int i = p->w_stage[w];
       rc = launch_worker(cfg->stages[i].kind, p->args[w], cfg->cu[i], p->streams[w]);
@@ -973,6 +1092,16 @@ extern "C" int32_t camelot_pipeline_epoch_ns(const camelot_pipeline* p, int64_t*
     if (!p->launched || ticks == 0) return fail(CAMELOT_EAGAIN, "the replay has not started");
   }
   *epoch_ns = (int64_t)ticks_to_ns(ticks, p->dev.wclk_hz);
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_pipeline_ipc_info(const camelot_pipeline* p, uint8_t* handle, int64_t* setup_ns) {
+  clear_error();
+  if (!p || !handle || !setup_ns) return fail(CAMELOT_EINVAL, "bad ipc_info arguments");
+  std::memcpy(handle, p->ipc_handle, CAMELOT_IPC_HANDLE_BYTES);
+  *setup_ns = p->ipc_setup_ns;
+  if (!p->cfg.out_ipc && p->cfg.ingest != CAMELOT_INGEST_IPC)
+    return fail(CAMELOT_EINVAL, "the pipeline neither exports nor imports a ring");
   return CAMELOT_OK;
 }
 
@@ -1180,6 +1309,7 @@ extern "C" int32_t camelot_pipeline_drain(camelot_pipeline* p, camelot_result* o
                                           int32_t* n_out, int64_t timeout_ns) {
   clear_error();
   if (!p || !out || !n_out || max < 0) return fail(CAMELOT_EINVAL, "bad drain arguments");
+  if (p->cfg.out_ipc) return fail(CAMELOT_EINVAL, "the pipeline exports its batches; results come out of the importing one");
   *n_out = 0;
   const int64_t t_end = host_ns() + std::max<int64_t>(timeout_ns, 0);
   uint64_t head;
@@ -1195,7 +1325,8 @@ extern "C" int32_t camelot_pipeline_drain(camelot_pipeline* p, camelot_result* o
     std::this_thread::yield();
   }
   const uint64_t n = std::min<uint64_t>(head - p->egress_tail, (uint64_t)max);
-  const int S = p->S;
+  // the stages of upstream processes come first in the timestamps
+  const int S = p->stamp_base + p->S;
   const int64_t epoch = p->cfg.ingest == CAMELOT_INGEST_REPLAY
                             ? (int64_t)__atomic_load_n(&p->pub->t0, __ATOMIC_ACQUIRE)
                             : p->epoch_ticks;
@@ -1231,6 +1362,7 @@ extern "C" int32_t camelot_pipeline_drain_latency(camelot_pipeline* p, uint64_t*
                                                   int32_t max, int32_t* n_out, int64_t timeout_ns) {
   clear_error();
   if (!p || !ids || !lat_ns || !n_out || max < 0) return fail(CAMELOT_EINVAL, "bad drain arguments");
+  if (p->cfg.out_ipc) return fail(CAMELOT_EINVAL, "the pipeline exports its batches; results come out of the importing one");
   *n_out = 0;
   const int64_t t_end = host_ns() + std::max<int64_t>(timeout_ns, 0);
   uint64_t head;
@@ -1426,6 +1558,158 @@ extern "C" int32_t camelot_handoff_bench(int32_t mode, int64_t slot_bytes, int32
   // exact checksums are returned bit-for-bit through the double slots' bytes
   std::memcpy(&out[2], &r[0], 8);
   std::memcpy(&out[3], &r[1], 8);
+  return CAMELOT_OK;
+}
+
+// ==================================================================== cross-process handoff benchmark
+// The handoff kernels above with their ring, doorbells and results in one device
+// allocation that a second process opens: the producer runs in one process, the
+// consumer in the other, on the same GPU.
+struct IpcRegionHeader {
+  uint64_t magic;
+  int32_t version, depth, nwg, pad;
+  int64_t slot_bytes, chunk_bytes;
+};
+constexpr uint64_t kIpcRegionMagic = 0x4e4f494745524d43ull;   // "CMREGION"
+
+struct camelot_ipc_region {
+  uint8_t* base = nullptr;
+  bool owner = false;
+  IpcRegionHeader h = {};
+  int64_t setup_ns = 0;
+};
+
+// [header 256 | results 64 | full: depth x nwg words | freed: same | ring: depth slots]
+static int64_t region_full_off() { return 256 + 64; }
+static int64_t region_freed_off(const IpcRegionHeader& h) { return region_full_off() + round_up(4LL * h.depth * h.nwg, 256); }
+static int64_t region_ring_off(const IpcRegionHeader& h) { return region_freed_off(h) + round_up(4LL * h.depth * h.nwg, 256); }
+
+extern "C" int32_t camelot_ipc_region_create(int64_t slot_bytes, int32_t depth, int32_t channels, uint8_t* handle,
+                                             camelot_ipc_region** out) {
+  clear_error();
+  if (!handle || !out) return fail(CAMELOT_EINVAL, "handle/out is NULL");
+  *out = nullptr;
+  if (slot_bytes < 16 || slot_bytes % 16 != 0 || depth < 1 || channels < 1 || channels > 256)
+    return fail(CAMELOT_EINVAL, "slot_bytes must be a positive multiple of 16, depth >= 1, channels in 1..256");
+  IpcRegionHeader h = {};
+  h.magic = kIpcRegionMagic;
+  h.version = kIpcVersion;
+  h.depth = depth;
+  h.slot_bytes = slot_bytes;
+  // every channel (workgroup pair) owns a chunk of each slot, at least 16 bytes
+  const int64_t want = std::min<int64_t>(channels, slot_bytes / 16);
+  h.chunk_bytes = round_up((slot_bytes + want - 1) / want, 16);
+  h.nwg = (int32_t)((slot_bytes + h.chunk_bytes - 1) / h.chunk_bytes);
+  const int64_t bytes = region_ring_off(h) + (int64_t)depth * slot_bytes;
+  if (round_up(bytes, kIpcGranule) >= kIpcMaxBytes) return fail(CAMELOT_EINVAL, "the region takes %lld bytes; it must stay under 2 GiB",
+                                         (long long)bytes);
+  DevInfo dev;                                    // the runtime is up before the clock starts
+  if (int32_t rc = dev_info(&dev)) return rc;
+  const int64_t t0 = host_ns();
+  auto* r = new camelot_ipc_region();
+  r->owner = true;
+  r->h = h;
+  hipError_t e = hipMalloc((void**)&r->base, round_up(bytes, kIpcGranule));
+  if (e == hipSuccess) e = hipMemset(r->base, 0, bytes);
+  uint64_t init[8] = {0, 0, ~0ull, 0, 0, 0, 0, 0};      // sum, xor, first start (min), last end (max), error
+  if (e == hipSuccess) e = hipMemcpy(r->base, &h, sizeof h, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(r->base + 256, init, sizeof init, hipMemcpyHostToDevice);
+  hipIpcMemHandle_t ih;
+  if (e == hipSuccess) e = hipIpcGetMemHandle(&ih, r->base);
+  if (e != hipSuccess) {
+    if (r->base) (void)hipFree(r->base);
+    delete r;
+    return fail(CAMELOT_EDEVICE, "IPC region: %s", hipGetErrorString(e));
+  }
+  std::memcpy(handle, &ih, sizeof ih);
+  r->setup_ns = host_ns() - t0;
+  *out = r;
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_ipc_region_open(const uint8_t* handle, camelot_ipc_region** out) {
+  clear_error();
+  if (!handle || !out) return fail(CAMELOT_EINVAL, "handle/out is NULL");
+  *out = nullptr;
+  DevInfo dev;                                    // the runtime is up before the clock starts
+  if (int32_t rc = dev_info(&dev)) return rc;
+  const int64_t t0 = host_ns();
+  hipIpcMemHandle_t ih;
+  std::memcpy(&ih, handle, sizeof ih);
+  auto* r = new camelot_ipc_region();
+  hipError_t e = hipIpcOpenMemHandle((void**)&r->base, ih, hipIpcMemLazyEnablePeerAccess);
+  if (e == hipSuccess) e = hipMemcpy(&r->h, r->base, sizeof r->h, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    if (r->base) (void)hipIpcCloseMemHandle(r->base);
+    delete r;
+    return fail(CAMELOT_EDEVICE, "IPC region open: %s", hipGetErrorString(e));
+  }
+  if (r->h.magic != kIpcRegionMagic || r->h.version != kIpcVersion) {
+    (void)hipIpcCloseMemHandle(r->base);
+    delete r;
+    return fail(CAMELOT_EINVAL, "the opened allocation is not a handoff region of this library");
+  }
+  r->setup_ns = host_ns() - t0;
+  *out = r;
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_ipc_region_info(const camelot_ipc_region* r, int64_t* setup_ns, int32_t* channels) {
+  clear_error();
+  if (!r || !setup_ns || !channels) return fail(CAMELOT_EINVAL, "bad region_info arguments");
+  *setup_ns = r->setup_ns;
+  *channels = r->h.nwg;
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_ipc_handoff_run(camelot_ipc_region* r, int32_t role, int64_t n_slots, int32_t cu_offset,
+                                           int32_t timeout_ms, double* out) {
+  clear_error();
+  if (!r || !out) return fail(CAMELOT_EINVAL, "region/out is NULL");
+  if (role != CAMELOT_IPC_PRODUCER && role != CAMELOT_IPC_CONSUMER) return fail(CAMELOT_EINVAL, "unknown role");
+  if (n_slots < 1 || timeout_ms < 1 || timeout_ms > 600000)
+    return fail(CAMELOT_EINVAL, "n_slots >= 1; timeout_ms in 1..600000");
+  DevInfo dev;
+  int32_t rc = dev_info(&dev);
+  if (rc) return rc;
+  const int n_cus = (int)round_up(r->h.nwg, 8);
+  if ((rc = check_share(n_cus, cu_offset, dev.n_cus))) return rc;
+  std::memset(out, 0, 5 * sizeof(double));
+  hipStream_t s;
+  if ((rc = cached_stream(cu_offset, n_cus, &s))) return rc;
+  HandoffArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.result = (uint64_t*)(r->base + 256);
+  a.full = (uint32_t*)(r->base + region_full_off());
+  a.freed = (uint32_t*)(r->base + region_freed_off(r->h));
+  a.ring = r->base + region_ring_off(r->h);
+  a.slot_bytes = r->h.slot_bytes;
+  a.depth = r->h.depth;
+  a.n_slots = n_slots;
+  a.chunk_bytes = r->h.chunk_bytes;
+  a.spin_ticks = (int64_t)timeout_ms * (dev.wclk_hz / 1000);
+  void* args[] = {(void*)&a};
+  const void* fn = role == CAMELOT_IPC_PRODUCER ? (const void*)camelot_handoff_producer
+                                                : (const void*)camelot_handoff_consumer;
+  HIP_TRY(hipLaunchKernel(fn, dim3(r->h.nwg), dim3(kThreads), args, 0, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  uint64_t res[8];
+  if ((rc = d2h(res, a.result, 64))) return rc;
+  if (res[4]) return fail(CAMELOT_ETIMEDOUT, "handoff channel wait timed out (the other side did not keep up)");
+  out[0] = res[3] > res[2] ? (double)(res[3] - res[2]) / (double)dev.wclk_hz : 0.0;
+  out[1] = 2.0 * (double)r->h.slot_bytes * (double)n_slots;
+  std::memcpy(&out[2], &res[0], 8);
+  std::memcpy(&out[3], &res[1], 8);
+  out[4] = out[0] > 0 ? out[1] / out[0] / 1e9 : 0.0;
+  return CAMELOT_OK;
+}
+
+extern "C" int32_t camelot_ipc_region_destroy(camelot_ipc_region* r) {
+  clear_error();
+  if (!r) return fail(CAMELOT_EINVAL, "region is NULL");
+  hipError_t e = r->owner ? hipFree(r->base) : hipIpcCloseMemHandle(r->base);
+  delete r;
+  if (e != hipSuccess) return fail(CAMELOT_EDEVICE, "IPC region release: %s", hipGetErrorString(e));
   return CAMELOT_OK;
 }
 

@@ -732,9 +732,17 @@ __device__ __forceinline__ void mlp_row_mfma(f32x4 (&acc)[RW][CT], const MlpRowS
   }
 }
 
-// load groups in flight per unit shape: as many as the registers hold without spills
+// Load groups in flight per unit shape. All shapes are compiled into one kernel, whose
+// registers are those of its hungriest path, so the depths are chosen together: as
+// deep as the whole kernel stays within 256 registers per lane with no spills. A
+// worker kernel must not need scratch (the launch refuses one that does): the
+// runtime may start fewer waves of a kernel than its grid when it cannot back the
+// scratch of all of them at once, and a persistent grid whose workgroups are not all
+// resident never completes a grid barrier. (Eight groups for the narrow BF16 units
+// would spill.) At least two: the B stage of the next group is written while the
+// MFMAs read the current one, so there are always two B buffers.
 #ifndef MLP_PA
-#define MLP_PA(RW, CT, F32) ((F32) ? ((RW) == 2 ? 2 : 4) : (RW) == 2 ? ((CT) == 4 ? 2 : 4) : 8)
+#define MLP_PA(RW, CT, F32) ((F32) ? ((RW) == 2 ? 2 : 4) : (RW) == 2 ? 2 : 4)
 #endif
 // LDS of the row path: the waves' A regions (FP32 rows), then the B stage buffers
 constexpr int kMlpRowLds = 8 * 32 * kRowPitch;
@@ -748,7 +756,7 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
                                              int tid) {
   constexpr int PA = MLP_PA(RW, CT, F32);                       // load groups in flight
   constexpr int NB = (PA % 2 == 0) ? 2 : PA;                    // B stage buffers
-  static_assert(PA % NB == 0, "buffer of a stage must be known at compile time");
+  static_assert(PA >= 2 && PA % NB == 0, "two B buffers at least; buffer of a stage known at compile time");
   constexpr int SB = 16 * CT * kRowPitch;                       // bytes of one B stage buffer
   constexpr int SA = F32 ? 16 * RW * kRowPitch : 0;             // a wave's A region (FP32 rows only)
   static_assert(4 * SA + NB * SB <= kMlpRowLds, "row path LDS");
@@ -1426,6 +1434,7 @@ __device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t s
     s_go = ok;
   }
   __syncthreads();
+  wave_acquire_agent();          // every wave: the descriptor and the rows it points at
   return s_go != 0;
 }
 
@@ -1455,9 +1464,9 @@ struct BatchLds {
 __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, uint64_t seq, uint64_t t0, bool try_only,
                           BatchLds& s) {
   const int tid = threadIdx.x;
-  const int si = a.stage_index;
+  const bool first = a.in_kind != kInRing;     // takes requests from the ingest
   int nreq;
-  if (si == 0) {
+  if (first) {
     if (tid < 64) {
       Acq q = acquire_ingest(a, s.cursor, t0, try_only, s.id, s.tarr, s.rows, s.ptr);
       if (q.status == 0 && tid == 0)
@@ -1472,6 +1481,9 @@ __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, u
     if (tid == 0) s.acq[0] = acquire_ring_slots(a, seq, try_only);
     __syncthreads();
     if (s.acq[0] != 0) return s.acq[0];
+    // every wave reads the slot header: every wave acquires
+    if (a.in_state_sys || (a.out_kind == kOutRing && a.out_state_sys)) wave_acquire_system();
+    else wave_acquire_agent();
     // the whole header in one round of loads: the counts, the stage times and every
     // request entry (those past n_req are not used)
     const SlotHeader* ih = (const SlotHeader*)(a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride);
@@ -1511,7 +1523,7 @@ __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, u
     }
     if (tid == 0) {
       s.rbase[nreq] = carry;
-      if (si == 0) s.cursor += (uint64_t)nreq;
+      if (first) s.cursor += (uint64_t)nreq;
       if (a.out_kind == kOutEgress) {
         s.egress_base = s.egress_head;
         s.egress_head += (uint64_t)s.acq[2];
@@ -1556,7 +1568,10 @@ struct BatchPub {
 __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_ptrs) {
   WorkerCtl* ctl = a.ctl;
   const int tid = threadIdx.x;
+  // the stage's place in the timestamps (after the stages of upstream processes);
+  // the first stage of this pipeline takes requests from the ingest, the others a ring
   const int si = a.stage_index;
+  const bool first = a.in_kind != kInRing;
   const int nx = (int)gridDim.x - 1;              // compute workgroups
   const int ng = nx < 8 ? nx : 8;                 // their groups (index mod 8)
 
@@ -1609,7 +1624,7 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
     } else {
       st_relaxed_sys(&a.pub->egress_head, pb.egress_end);
     }
-    if (si == 0) {
+    if (first) {
       st_relaxed_sys(&a.pub->ingest_tail, pb.ingest_end);
     } else {
       uint64_t* p = &a.in_state[q % (uint64_t)a.in_depth];
@@ -1633,7 +1648,7 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
     s_dur = 0;
     // the compute workgroups count a batch only after its broadcast
     for (int g = 0; g < 8; ++g) done_base[g] = __hip_atomic_load(&ctl->done[g][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (si == 0) st_relaxed_sys(&a.pub->t0, s_t0);
+    if (first) st_relaxed_sys(&a.pub->t0, s_t0);
     st_relaxed_sys(&a.pub->started[a.worker_index], 1);
   }
   __syncthreads();
@@ -1651,18 +1666,18 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
       const int nreq = s.acq[1], rows = s.acq[2];
       // per-row descriptors: input row pointers (ingest), side bytes, and the
       // request of each row (egress records)
-      const uint8_t* in_payload = si > 0 ? a.in_ring + (q % (uint64_t)a.in_depth) * (uint64_t)a.in_stride +
+      const uint8_t* in_payload = !first ? a.in_ring + (q % (uint64_t)a.in_depth) * (uint64_t)a.in_stride +
                                                kSlotHeaderBytes
                                          : nullptr;
-      const uint8_t* in_hdr = si > 0 ? in_payload - kSlotHeaderBytes : nullptr;
+      const uint8_t* in_hdr = !first ? in_payload - kSlotHeaderBytes : nullptr;
       for (int r = tid; r < nreq; r += kThreads) {
         for (uint32_t j = 0; j < s.rows[r]; ++j) {
           const uint32_t row = s.rbase[r] + j;
-          const uint8_t* rp = si > 0 ? in_payload + (int64_t)row * a.sp.in_row_bytes
+          const uint8_t* rp = !first ? in_payload + (int64_t)row * a.sp.in_row_bytes
                                      : s.ptr[r] + (int64_t)j * a.in_row_stride;
-          if (si == 0) d.rowptr[row] = rp;
+          if (first) d.rowptr[row] = rp;
           if (side_ptrs)
-            d.rowside[row] = si > 0 ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
+            d.rowside[row] = !first ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
                                     : rp + a.sp.in_row_bytes;
           if (a.out_kind == kOutEgress) {
             d.row_id[row] = s.id[r];

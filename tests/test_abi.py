@@ -104,3 +104,16 @@ def test_noalloc_run_refuses_what_its_array_cannot_hold():
     with pytest.raises(cm.CamelotError) as e:
         cm.camelot_stage_run_noalloc(relu, 1, 1, cm.MAX_BATCH + 1, 8)
     assert e.value.code == cm.EINVAL
+
+
+def test_ipc_region_refuses_bad_geometry_before_any_device_call():
+    """A cross-process handoff region is checked on the host first: slot sizes that are
+    not multiples of 16, no channels, and regions of 2 GiB or more (an opened
+    allocation must stay under 2 GiB) are refused without touching a GPU."""
+    for slot, depth, ch in ((8, 4, 8), (24, 4, 8), (1 << 20, 0, 8), (1 << 20, 4, 0), (1 << 20, 4, 257)):
+        with pytest.raises(cm.CamelotError) as e:
+            cm.camelot_ipc_region_create(slot, depth, ch)
+        assert e.value.code == cm.EINVAL
+    with pytest.raises(cm.CamelotError) as e:
+        cm.camelot_ipc_region_create(1 << 29, 4, 128)          # 2 GiB of slots
+    assert e.value.code == cm.EINVAL and "2 GiB" in str(e.value)
