@@ -529,7 +529,8 @@ int32_t camelot_stream_bench(int32_t mode, int64_t bytes, int32_t n_cus, int32_t
 
 /* ------------------------------------------------------------------ handoff benchmark
  * Section VI-B's claim, measured: a producer worker on cu_producer CUs writes
- * n_slots_total slots of slot_bytes into a device ring of depth slots; a consumer
+ * n_slots_total slots of slot_bytes (a multiple of 16, at most 2^30) into a device
+ * ring of depth slots; a consumer
  * worker on the next cu_consumer CUs waits on each slot's doorbell, reads every
  * word into a checksum and frees the slot. Both run concurrently.
  * out: [0] seconds of the run (device clock), [1] bytes moved (written + read),

@@ -305,10 +305,17 @@ struct BarTicket {
 };
 
 // wgi: this workgroup's index among the nwg that take part (default: blockIdx.x).
+// wave_release = false: the caller's cross-workgroup stores were written through
+// (cache policy sc1), so thread 0's release alone publishes them.
 __device__ __forceinline__ BarTicket grid_arrive(WorkerCtl* ctl, uint32_t nwg, bool sys_release = false,
-                                                 int wgi = -1) {
+                                                 int wgi = -1, bool wave_release = true) {
   BarTicket t{0u, false};
-  wg_barrier_stores_done();
+  if (wave_release) {
+    wg_barrier_stores_done();
+  } else {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     const uint32_t g = (wgi < 0 ? blockIdx.x : (uint32_t)wgi) & 7u;
     const uint32_t ngroups = nwg < 8u ? nwg : 8u;
@@ -373,8 +380,8 @@ __device__ __forceinline__ bool grid_wait(WorkerCtl* ctl, uint32_t nwg, BarTicke
 }
 
 __device__ __forceinline__ bool grid_barrier(WorkerCtl* ctl, uint32_t nwg, int64_t spin_ticks,
-                                             bool sys_release = false, int wgi = -1) {
-  return grid_wait(ctl, nwg, grid_arrive(ctl, nwg, sys_release, wgi), spin_ticks, wgi);
+                                             bool sys_release = false, int wgi = -1, bool wave_release = true) {
+  return grid_wait(ctl, nwg, grid_arrive(ctl, nwg, sys_release, wgi, wave_release), spin_ticks, wgi);
 }
 
 // Intra-wave LDS hand-off: orders this wave's LDS writes before its later reads

@@ -4,8 +4,10 @@
 // waits on each doorbell, folds every 32-bit word of the chunk into a checksum and
 // frees the slot. Producer workgroup j and consumer workgroup j own the same chunk
 // of every slot, so the channels are independent (no grid barrier). All waits are
-// bounded by spin_ticks. Every producer wave releases its own stores before the
-// workgroup barrier after which one thread rings the doorbell.
+// bounded by spin_ticks. The producer writes its chunk through to the device's point
+// of coherence (cache policy nt sc1), so one release by thread 0 after the workgroup
+// barrier publishes it (with plain stores and that one release, a reader on another
+// XCD sometimes saw old data behind the new doorbell).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -20,6 +22,7 @@ __device__ __forceinline__ uint32_t pattern(uint64_t s, uint32_t w) {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kUnroll = 8;
+constexpr int kStreamThrough = 18;     // cache policy nt sc1
 constexpr int64_t kStep = (int64_t)kThreads * 16;
 
 __device__ __forceinline__ u32x4 pattern4(uint64_t s, uint32_t w) {
@@ -52,18 +55,22 @@ extern "C" __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void came
     if (tid == 0) s_ok = wait_eq(&a.freed[(int64_t)d * nwg + j], lap, a.spin_ticks, &a.result[4]);
     __syncthreads();
     if (!s_ok) return;
-    u32x4* base = (u32x4*)(a.ring + (int64_t)d * a.slot_bytes);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(a.ring + (int64_t)d * a.slot_bytes, (short)0, (int)a.slot_bytes, 0x00020000);
     int64_t o = lo + (int64_t)tid * 16;
-    // kUnroll independent 16-byte stores per thread per step (streaming, non-temporal)
+    // kUnroll independent 16-byte stores per thread per step, streaming and written
+    // through (nt sc1): no dirty L2 line is left behind, so thread 0's release after
+    // the barrier publishes the chunk
     for (; o + (kUnroll - 1) * kStep < hi; o += kUnroll * kStep) {
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int64_t ou = o + u * kStep;
-        __builtin_nontemporal_store(pattern4(s, (uint32_t)(ou >> 2)), base + (ou >> 4));
+        __builtin_amdgcn_raw_buffer_store_b128(pattern4(s, (uint32_t)(ou >> 2)), rs, (int)ou, 0, kStreamThrough);
       }
     }
-    for (; o < hi; o += kStep) __builtin_nontemporal_store(pattern4(s, (uint32_t)(o >> 2)), base + (o >> 4));
-    wg_barrier_stores_done();
+    for (; o < hi; o += kStep) __builtin_amdgcn_raw_buffer_store_b128(pattern4(s, (uint32_t)(o >> 2)), rs, (int)o, 0, kStreamThrough);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     if (tid == 0) st_release_agent(&a.full[(int64_t)d * nwg + j], lap + 1);
   }
   if (tid == 0) atomicMax((unsigned long long*)&a.result[3], (unsigned long long)now_ticks());

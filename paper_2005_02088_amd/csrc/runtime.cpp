@@ -1482,8 +1482,8 @@ extern "C" int32_t camelot_handoff_bench(int32_t mode, int64_t slot_bytes, int32
                                          int32_t cu_producer, int32_t cu_consumer, double* out) {
   clear_error();
   if (!out) return fail(CAMELOT_EINVAL, "out is NULL");
-  if (slot_bytes < 16 || slot_bytes % 16 != 0 || depth < 1 || n_slots < 1)
-    return fail(CAMELOT_EINVAL, "slot_bytes must be a positive multiple of 16; depth, n_slots >= 1");
+  if (slot_bytes < 16 || slot_bytes % 16 != 0 || slot_bytes > (1LL << 30) || depth < 1 || n_slots < 1)
+    return fail(CAMELOT_EINVAL, "slot_bytes must be a multiple of 16 in 16..2^30; depth, n_slots >= 1");
   DevInfo dev;
   int32_t rc = dev_info(&dev);
   if (rc) return rc;

@@ -217,6 +217,18 @@ __device__ __forceinline__ uint4 bld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
   __builtin_memcpy(&q, &v, 16);
   return q;
 }
+// Stores written through to the point of coherence of the whole device (cache
+// policy sc1): data another XCD reads after a grid barrier leaves no dirty L2 line
+// behind, so the barrier's one release per workgroup publishes it.
+constexpr int kWriteThrough = 16;      // sc1
+__device__ __forceinline__ void wt_store16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint4 v) {
+  i32x4_t q;
+  __builtin_memcpy(&q, &v, 16);
+  __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)voff, 0, kWriteThrough);
+}
+__device__ __forceinline__ void wt_store2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, 0, kWriteThrough);
+}
 __device__ __forceinline__ float4 u4_as_f4(uint4 u) {
   float4 f;
   __builtin_memcpy(&f, &u, 16);
@@ -806,6 +818,7 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
     }
   }
   const int nckn = (N + 31) >> 5;
+  const __amdgpu_buffer_rsrc_t rh = mlp_rsrc(hout, (int64_t)kMaxBatch * nckn * 32 * 2);
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
 #pragma unroll
@@ -823,7 +836,7 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
             // 32-wide chunk, lane = row % 16 + 16 ((col % 32) / 8), element col % 8)
             const int64_t e = ((int64_t)((row >> 4) * nckn + (col >> 5)) * 64 + (row & 15) + 16 * ((col & 31) >> 3)) * 8 +
                               (col & 7);
-            hout[e] = f32_to_bf16_rne(fmaxf(v, 0.f));
+            wt_store2(rh, (uint32_t)(e * 2), f32_to_bf16_rne(fmaxf(v, 0.f)));
           }
         }
       }
@@ -851,6 +864,7 @@ __device__ __forceinline__ void mlp_row_layer(const BatchRows& br, const uint16_
 __device__ __forceinline__ void mlp_input_to_frag(const BatchRows& br, uint16_t* h, int K, int rows, int wgi, int nwg) {
   const int nck = (K + 31) >> 5, ngr = nck * 4;             // 8-element groups per padded row
   const int total = rows * ngr;
+  const __amdgpu_buffer_rsrc_t rh = mlp_rsrc(h, (int64_t)kMaxBatch * nck * 32 * 2);
   for (int i = wgi * kThreads + threadIdx.x; i < total; i += nwg * kThreads) {
     const int row = i / ngr, g = i - row * ngr, k0 = g * 8;
     uint4 v = {0u, 0u, 0u, 0u};
@@ -859,7 +873,7 @@ __device__ __forceinline__ void mlp_input_to_frag(const BatchRows& br, uint16_t*
       v = f32x8_to_bf16x8_bits(u4_as_f4(gld16(x)), u4_as_f4(gld16(x + 4)));
     }
     const int c = g >> 2, lane = (row & 15) + 16 * (g & 3);
-    *(uint4*)(h + ((int64_t)((row >> 4) * nck + c) * 64 + lane) * 8) = v;
+    wt_store16(rh, (uint32_t)((((row >> 4) * nck + c) * 64 + lane) * 16), v);
   }
 }
 
@@ -913,7 +927,8 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
   const int wgi = xwg(a), nwg = xnwg(a);
   const int nrt = (rows + 15) >> 4, P = nwg;
   for (int l = 0; l < L; ++l) {
-    if (l > 0 && !grid_barrier(ctl, nwg, a.spin_ticks, false, wgi)) return false;
+    // the hidden state is written through: one release per workgroup publishes it
+    if (l > 0 && !grid_barrier(ctl, nwg, a.spin_ticks, false, wgi, false)) return false;
     const int K = a.sp.dims[l], N = a.sp.dims[l + 1];
     uint16_t* hout = a.sp.scratch + (int64_t)(l & 1) * kMaxBatch * stride;
     uint16_t* hin = a.sp.scratch + (int64_t)((l + 1) & 1) * kMaxBatch * stride;
@@ -937,7 +952,7 @@ __device__ __forceinline__ bool mlp_rows_all(const WorkerArgs& a, WorkerCtl* ctl
         continue;
       }
       mlp_input_to_frag(rp, hin, K, rows, wgi, nwg);
-      if (!grid_barrier(ctl, nwg, a.spin_ticks, false, wgi)) return false;
+      if (!grid_barrier(ctl, nwg, a.spin_ticks, false, wgi, false)) return false;
     }
     mlp_bf16_layer(rp, hin, stride, W, K, N, rows, last, hout, o, lds, w, lane, tid, wgi, nwg);
   }
