@@ -287,12 +287,6 @@ __device__ __forceinline__ void poll_backoff(uint32_t polls) {
   else __builtin_amdgcn_s_sleep(32);
 }
 
-// Acquire at agent scope in every wave of the workgroup, after the barrier that
-// follows one thread's observation of a flag (the once-per-batch hand-offs use it
-// besides that thread's own acquire: a cheap extra guard; the per-wave release in
-// wg_barrier_stores_done is what the stale reads seen on gfx950 needed).
-__device__ __forceinline__ void wave_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-__device__ __forceinline__ void wave_acquire_system() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, ""); }
 
 // The barrier in two halves: arrive publishes this workgroup's writes and counts
 // it in; wait returns once every workgroup has arrived. Work that reads nothing

@@ -17,6 +17,20 @@
 
 namespace camelot {
 
+// A stage's output rows go to a ring slot that other workgroups (the next stage, on
+// other XCDs) read once the batch is counted done. They are written through to the
+// device's point of coherence (relaxed agent-scope atomic stores: cache policy sc1),
+// so no dirty L2 line is left behind and the one release of the done count publishes
+// them; with plain stores a write-back in every wave was needed, which cost the MLP
+// instance ~40 us per batch when co-located.
+__device__ __forceinline__ void out_f32(float* p, float v) {
+  __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void out_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -152,7 +166,7 @@ __device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
       const int r = i >> 6, c = i & 63, row = rb * 8 + r, cc = cb * 64 + c;
       if (row < rows && cc < N) {
         const float s = ((part[0][r][c] + part[1][r][c]) + part[2][r][c]) + part[3][r][c];
-        Y[(int64_t)row * N + cc] = fmaxf(s, 0.f);
+        out_f32(&Y[(int64_t)row * N + cc], fmaxf(s, 0.f));
       }
     }
     __syncthreads();
@@ -217,6 +231,16 @@ __device__ __forceinline__ uint4 bld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
   __builtin_memcpy(&q, &v, 16);
   return q;
 }
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+// 16 bytes of a stage's output at byte offset off of its (wave-uniform) output
+// base, written through like out_f32.
+__device__ __forceinline__ void out_u32x4(uint8_t* base, uint32_t off, u32x4_t v) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7fffffff, 0x00020000);
+  i32x4_t q;
+  __builtin_memcpy(&q, &v, 16);
+  __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)off, 0, 16);
+}
+
 // Stores written through to the point of coherence of the whole device (cache
 // policy sc1): data another XCD reads after a grid barrier leaves no dirty L2 line
 // behind, so the barrier's one release per workgroup publishes it.
@@ -506,10 +530,10 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows
         e1 = fmaf(wt, pbuf[w][1][lo + t], e1);
       }
       const int r0 = u / 11, f0 = u - r0 * 11;
-      Y[(int64_t)r0 * 440 + f0 * 40 + lane] = logf(fmaxf(e0, 1e-10f));
+      out_f32(&Y[(int64_t)r0 * 440 + f0 * 40 + lane], logf(fmaxf(e0, 1e-10f)));
       if (second) {
         const int r1 = u1 / 11, f1 = u1 - r1 * 11;
-        Y[(int64_t)r1 * 440 + f1 * 40 + lane] = logf(fmaxf(e1, 1e-10f));
+        out_f32(&Y[(int64_t)r1 * 440 + f1 * 40 + lane], logf(fmaxf(e1, 1e-10f)));
       }
     }
     wave_lds_sync();
@@ -520,7 +544,6 @@ __device__ void exec_logmel(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows
 // 16-byte load from global memory (explicitly in the global address space, so it
 // is a global load counted by vmcnt only, never a flat load that also holds up
 // every LDS wait).
-typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 typedef const u32x4_t __attribute__((address_space(1)))* gptr_u32x4;
 __device__ __forceinline__ uint4 gld16(const void* p) {
   const u32x4_t v = *(gptr_u32x4)p;
@@ -830,7 +853,7 @@ __device__ __forceinline__ void mlp_row_unit(const BatchRows& br, const uint16_t
         if (row < rows) {
           const float v = acc[j][t][i];
           if (last) {
-            out[(int64_t)row * N + col] = v;
+            out_f32(&out[(int64_t)row * N + col], v);
           } else {
             // the next layer reads the hidden state in fragment order (row block,
             // 32-wide chunk, lane = row % 16 + 16 ((col % 32) / 8), element col % 8)
@@ -1000,7 +1023,7 @@ __device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows
     const float inv = 1.f / (float)n_ids;
 #pragma unroll
     for (int c = 0; c < kGatherMaxDim / 64; ++c)
-      if (c < per) Y[(int64_t)r * dim + c * 64 + lane] = acc[c] * inv;
+      if (c < per) out_f32(&Y[(int64_t)r * dim + c * 64 + lane], acc[c] * inv);
   }
 }
 
@@ -1074,7 +1097,7 @@ __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
     const float* pp = a.sp.partial + (int64_t)r * ntiles * kConvCout + c;
     float t = 0.f;
     for (int q = 0; q < ntiles; ++q) t += pp[(int64_t)q * kConvCout];
-    ((float*)out)[(int64_t)r * kConvCout + c] = t * inv;
+    out_f32(&((float*)out)[(int64_t)r * kConvCout + c], t * inv);
   }
   return true;
 }
@@ -1107,7 +1130,7 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const Bat
         const float* qh = q_s[w] + h * dim;
         for (int d = 0; d < dim; ++d) acc = fmaf(qh[d], __half2float(tr[d]), acc);
       }
-      Y[(int64_t)r * heads * n_ids + o] = acc;
+      out_f32(&Y[(int64_t)r * heads * n_ids + o], acc);
     }
     wave_lds_sync();
   }
@@ -1160,9 +1183,11 @@ __device__ void exec_artifact_fold(const WorkerArgs& a, const BatchRows& br, int
         f.y = (float)(x.y >> 8) * 0x1p-24f;
         f.z = (float)(x.z >> 8) * 0x1p-24f;
         f.w = (float)(x.w >> 8) * 0x1p-24f;
-        *(float4*)(out + ((int64_t)r * D + j0 + 4 * tid) * 4) = f;
+        u32x4_t q;
+        __builtin_memcpy(&q, &f, 16);
+        out_u32x4(out, (uint32_t)(((int64_t)r * D + j0 + 4 * tid) * 4), q);
       } else {
-        *(u32x4_t*)(out + ((int64_t)r * D + j0 + 4 * tid) * 4) = x;
+        out_u32x4(out, (uint32_t)(((int64_t)r * D + j0 + 4 * tid) * 4), x);
       }
     }
   }
@@ -1186,8 +1211,8 @@ __device__ void exec_artifact_compute(const WorkerArgs& a, const BatchRows& br, 
         x2 = x2 * mul + add;
         x3 = x3 * mul + add;
       }
-      *(u32x4_t*)(out + ((int64_t)r * D + j0 + 4 * tid) * 4) =
-          (u32x4_t){__float_as_uint(x0), __float_as_uint(x1), __float_as_uint(x2), __float_as_uint(x3)};
+      out_u32x4(out, (uint32_t)(((int64_t)r * D + j0 + 4 * tid) * 4),
+                (u32x4_t){__float_as_uint(x0), __float_as_uint(x1), __float_as_uint(x2), __float_as_uint(x3)});
     }
   }
 }
@@ -1200,7 +1225,7 @@ __device__ __forceinline__ void copy_side(const WorkerArgs& a, const BatchDesc* 
   const int words = a.side_bytes >> 2;
   for (int i = xwg(a) * kThreads + threadIdx.x; i < rows * words; i += xnwg(a) * kThreads) {
     const int r = i / words, wd = i - r * words;
-    ((uint32_t*)(dst + (int64_t)r * a.side_bytes))[wd] = ((const uint32_t*)bd->rowside[r])[wd];
+    out_u32(&((uint32_t*)(dst + (int64_t)r * a.side_bytes))[wd], ((const uint32_t*)bd->rowside[r])[wd]);
   }
 }
 
@@ -1449,7 +1474,6 @@ __device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t s
     s_go = ok;
   }
   __syncthreads();
-  wave_acquire_agent();          // every wave: the descriptor and the rows it points at
   return s_go != 0;
 }
 
@@ -1496,9 +1520,7 @@ __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, u
     if (tid == 0) s.acq[0] = acquire_ring_slots(a, seq, try_only);
     __syncthreads();
     if (s.acq[0] != 0) return s.acq[0];
-    // every wave reads the slot header: every wave acquires
-    if (a.in_state_sys || (a.out_kind == kOutRing && a.out_state_sys)) wave_acquire_system();
-    else wave_acquire_agent();
+
     // the whole header in one round of loads: the counts, the stage times and every
     // request entry (those past n_req are not used)
     const SlotHeader* ih = (const SlotHeader*)(a.in_ring + (seq % (uint64_t)a.in_depth) * (uint64_t)a.in_stride);
@@ -1884,7 +1906,9 @@ __device__ __forceinline__ void worker_compute(const WorkerArgs& a) {
                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)outp));
     if (!exec_stage<KIND>(a, ctl, batch_rows(a, bd, seq), rows, out)) break;
     copy_side(a, bd, rows);
-    wg_barrier_stores_done();
+    // the rows and side bytes were written through: thread 0's release publishes them
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     if (tid == 0) {
       if (sys) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
       else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
