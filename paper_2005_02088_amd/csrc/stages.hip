@@ -1034,39 +1034,62 @@ __device__ void exec_gather(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows
 // all 64 channels, applies ReLU and sums its pixels per channel in a fixed order
 // (within a wave: rows, then the 4 lane groups; then the 4 waves); phase 2, after a
 // grid barrier, adds the tiles of each query in tile order and divides by H*W.
+// The weights (64 x 576 BF16, 72 KiB) are staged in LDS once per batch and the B
+// fragments read from there: 16-byte granule g of output channel n sits at
+// n * 72 + (g ^ ((n >> 1) & 7)), so the 16 channels a fragment read touches fall on
+// 16 distinct groups of 4 banks (a row is 1,152 bytes: without the swizzle, rows two
+// apart share banks). A wave's 18 A fragments of a tile (9 positions x 2 chunks) are
+// loaded before its first MFMA.
 constexpr int kConvC = 64, kConvCout = 64, kConvTile = 64;
+constexpr int kConvRowGran = 9 * kConvC / 8;           // 16-byte granules per output channel
 
 __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
   __shared__ float wsum[kWaves][kConvCout];
+  __shared__ __attribute__((aligned(16))) uint4 wl[kConvCout * kConvRowGran];
   const int H = a.sp.dims[0], Wd = a.sp.dims[1];
   const int npix = H * Wd, ntiles = (npix + kConvTile - 1) / kConvTile;
   const uint16_t* Wc = (const uint16_t*)a.sp.w[0];          // [64][9][64]
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int cin0 = (lane >> 4) * 8;                          // this lane's 8 channels in a chunk
   const int units = rows * ntiles;
+  if (xwg(a) < units) {
+    for (int i = tid; i < kConvCout * kConvRowGran; i += kThreads) {
+      const int n = i / kConvRowGran, g = i - n * kConvRowGran;
+      wl[n * kConvRowGran + (g ^ ((n >> 1) & 7))] = gld16(Wc + (int64_t)n * (9 * kConvC) + g * 8);
+    }
+    __syncthreads();
+  }
+  const int bn = lane & 15;                                  // this lane's output channel within a block of 16
   for (int u = xwg(a); u < units; u += xnwg(a)) {
     const int r = u / ntiles, tile = u - r * ntiles;
     const uint16_t* X = (const uint16_t*)br.row(r);
     const int p = tile * kConvTile + w * 16 + (lane & 15);   // A-operand pixel of this lane
     const int py = p / Wd, px = p - py * Wd;
     const bool pin = p < npix;
-    f32x4 acc[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    bf16x8 af[9][2];
 #pragma unroll
     for (int pos = 0; pos < 9; ++pos) {
       const int ky = pos / 3, kx = pos - ky * 3;
       const int yy = py + ky - 1, xx = px + kx - 1;
       const bool in = pin && yy >= 0 && yy < H && xx >= 0 && xx < Wd;
-      const uint16_t* xs = X + ((int64_t)yy * Wd + xx) * kConvC;
+      const uint16_t* xs = X + ((int64_t)yy * Wd + xx) * kConvC + (lane >> 4) * 8;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) af[pos][h] = in ? ld_bf16x8(xs + h * 32) : (bf16x8){};
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int pos = 0; pos < 9; ++pos) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bf16x8 af = in ? ld_bf16x8(xs + h * 32 + cin0) : (bf16x8){};
-        const int kb = pos * kConvC + h * 32 + cin0;
+        const int g = pos * 8 + h * 4 + (lane >> 4);         // this lane's 8 input channels at (ky, kx)
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
-          const bf16x8 bf = ld_bf16x8(Wc + (int64_t)(nb * 16 + (lane & 15)) * (9 * kConvC) + kb);
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[nb], 0, 0, 0);
+          const int n = nb * 16 + bn;
+          bf16x8 bf;
+          const uint4 q = wl[n * kConvRowGran + (g ^ ((n >> 1) & 7))];
+          __builtin_memcpy(&bf, &q, 16);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[pos][h], bf, acc[nb], 0, 0, 0);
         }
       }
     }
