@@ -29,9 +29,6 @@ __device__ __forceinline__ void out_f32(float* p, float v) {
 __device__ __forceinline__ void out_u32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void out_u64(void* p, uint64_t v) {
-  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -1738,27 +1735,27 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
           const uint32_t row = s.rbase[r] + j;
           const uint8_t* rp = !first ? in_payload + (int64_t)row * a.sp.in_row_bytes
                                      : s.ptr[r] + (int64_t)j * a.in_row_stride;
-          if (first) out_u64(&d.rowptr[row], (uint64_t)rp);
+          if (first) d.rowptr[row] = rp;
           if (side_ptrs)
-            out_u64(&d.rowside[row], (uint64_t)(!first ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
-                                                       : rp + a.sp.in_row_bytes));
+            d.rowside[row] = !first ? in_hdr + a.in_side_off + (int64_t)row * a.side_bytes
+                                    : rp + a.sp.in_row_bytes;
           if (a.out_kind == kOutEgress) {
-            out_u64(&d.row_id[row], s.id[r]);
-            out_u32(&d.row_idx[row], j);
-            out_u64(&d.row_tarr[row], s.tarr[r]);
+            d.row_id[row] = s.id[r];
+            d.row_idx[row] = j;
+            d.row_tarr[row] = s.tarr[r];
           }
         }
       }
       // this stage's start time is filled in at the broadcast
-      if (tid < 2 * kMaxStages && tid != 2 * si) out_u64(&d.t_stage[tid], s.t_stage[tid]);
+      if (tid < 2 * kMaxStages && tid != 2 * si) d.t_stage[tid] = s.t_stage[tid];
       if (a.out_kind == kOutRing) {
         SlotHeader* oh = (SlotHeader*)(a.out_ring + (q % (uint64_t)a.out_depth) * (uint64_t)a.out_stride);
         for (int r = tid; r < nreq; r += kThreads) {
-          out_u64(&oh->req_id[r], s.id[r]);
-          out_u64(&oh->req_tarr[r], s.tarr[r]);
-          out_u32(&oh->req_rows[r], s.rows[r]);
+          oh->req_id[r] = s.id[r];
+          oh->req_tarr[r] = s.tarr[r];
+          oh->req_rows[r] = s.rows[r];
         }
-        if (tid < 2 * kMaxStages && tid != 2 * si) out_u64(&oh->t_stage[tid], s.t_stage[tid]);
+        if (tid < 2 * kMaxStages && tid != 2 * si) oh->t_stage[tid] = s.t_stage[tid];
         if (tid == 0) {
           oh->seq = q;
           oh->n_req = (uint32_t)nreq;
@@ -1803,10 +1800,8 @@ __device__ __forceinline__ void worker_control(const WorkerArgs& a, bool side_pt
               t_start;
       }
     }
-    // broadcast: the batch descriptor (or the stop) is in place; the threads other
-    // than thread 0 wrote theirs through, so thread 0's release publishes them
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    // broadcast: the batch descriptor (or the stop) is in place
+    wg_barrier_stores_done();
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       for (int g = 0; g < 8; ++g)
