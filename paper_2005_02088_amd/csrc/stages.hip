@@ -1497,6 +1497,9 @@ __device__ __forceinline__ bool wait_go(WorkerCtl* ctl, uint32_t want, int64_t s
     s_go = ok;
   }
   __syncthreads();
+  // every wave acquires too: the descriptor slot is small and re-read every second
+  // batch, so stale copies of it can survive in a reader's caches
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return s_go != 0;
 }
 
@@ -1543,6 +1546,9 @@ __device__ __forceinline__ int form_batch(const WorkerArgs& a, WorkerCtl* ctl, u
     if (tid == 0) s.acq[0] = acquire_ring_slots(a, seq, try_only);
     __syncthreads();
     if (s.acq[0] != 0) return s.acq[0];
+    // every wave reads the slot header: every wave acquires
+    if (a.in_state_sys || (a.out_kind == kOutRing && a.out_state_sys)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
     // the whole header in one round of loads: the counts, the stage times and every
     // request entry (those past n_req are not used)
