@@ -116,3 +116,42 @@ def test_artifact_pipeline(torch, cm, tables, handoff):
     gval = np.array([list(r.val[:10]) for r in res], np.float64)
     assert np.array_equal(gidx, ridx) and np.array_equal(gval, rval)
     log(f"  p -> c -> m -> top-10 ({handoff} handoff): {n} queries bit-identical to the oracle")
+
+
+def test_artifact_pipeline_many_instances_delivers_every_record(torch, cm, tables):
+    """Regression for stale batch descriptors: five memory-stage instances side by side
+    (the allocation under which a compute workgroup once wrote a batch's egress records
+    from a descriptor two batches old, leaving records unwritten), 200,000 single-row
+    queries offered faster than the pipeline serves them. Every record arrives whole,
+    once, in submit order, and the last stage's id checksums cover every query."""
+    p, c, m = _descs(cm, tables, 1024, 256, 65536)
+    top = cm.stage_desc(cm.STAGE_TOPK, dims=(D,), k=10, n_layers=0)
+    pool_n = 2048
+    x = G.artifact_words(pool_n * D, seed=21).reshape(pool_n, D)
+    dx = to_dev(torch, x.view(np.int32))
+    torch.cuda.synchronize()
+    n = 200_000
+    cfg = cm.pipeline_config((p, c, m, top), (8, 24, 32, 8), max_batch=128, batch_target=128,
+                             batch_timeout_ns=2_000_000, ring_depth=10, ingest=cm.INGEST_REPLAY,
+                             egress_capacity=1 << 20, idle_timeout_ns=5_000_000_000, n_inst=(1, 1, 5, 1))
+    log(f"artifact pipeline 8 / 24 / 5 x 32 / 8 CUs, {n} queries")
+    pl = cm.camelot_pipeline_create(cfg)
+    ids = np.empty(n, np.uint64)
+    ci, cl = np.empty(1 << 16, np.uint64), np.empty(1 << 16, np.int64)
+    done = 0
+    try:
+        cm.camelot_pipeline_replay(pl, np.arange(1, n + 1), np.ones(n), G.poisson_arrivals_ns(n, 4_000_000, seed=21),
+                                   np.arange(n) % pool_n, dx.data_ptr(), pool_n)
+        t_end = time.monotonic() + 30
+        while done < n and time.monotonic() < t_end:
+            k = cm.camelot_pipeline_drain_latency(pl, ci, cl, 100_000_000)
+            ids[done:done + k] = ci[:k]
+            done += k
+        stats = cm.camelot_pipeline_stats_get(pl)
+    finally:
+        cm.camelot_pipeline_destroy(pl)
+    assert done == n
+    assert np.array_equal(ids, np.arange(1, n + 1, dtype=np.uint64))
+    s_, x_ = OD.checksums(list(range(1, n + 1)))
+    assert stats.id_sum[3] == s_ and stats.id_xor[3] == x_
+    log(f"  {n} records whole and in order, batches per stage {list(stats.batches[:4])}")
