@@ -338,7 +338,9 @@ typedef struct {
   int32_t max_rows_per_request;/* 1..max_batch                                       */
   int32_t ingest_capacity;     /* requests the ingest queue holds (host mode)        */
   int32_t egress_capacity;     /* result rows buffered for drain                     */
-  int64_t idle_timeout_ns;     /* workers exit after this long with nothing to do   */
+  int64_t idle_timeout_ns;     /* workers exit after this long with nothing to do;
+                                  with host ingest the next submit starts them again
+                                  where they left off                               */
   int64_t hbm_budget_bytes;    /* admission: ENOMEM if the footprint exceeds it (0 = no limit) */
   int32_t side_bytes;          /* per-row bytes carried unchanged from the end of each
                                   payload row through every stage (0..4096, multiple of

@@ -1134,6 +1134,27 @@ extern "C" int32_t camelot_pipeline_submit(camelot_pipeline* p, uint64_t query_i
   return submit_at(p, query_id, payload, rows, -1);
 }
 
+// Workers that left after the idle timeout start again, from the state they saved at
+// exit (batch sequence, ingest cursor, egress head, counters), when new work is
+// submitted. Their go words still hold the value of the stop broadcast, which is the
+// one the next batch would use, so they are cleared first, on the worker's own
+// stream, ahead of the launch.
+static int32_t relaunch_idle(camelot_pipeline* p) {
+  if (!p->launched || p->stopped) return CAMELOT_OK;
+  for (int w = 0; w < p->NW; ++w) {
+    if (__atomic_load_n(&p->pub->status[w], __ATOMIC_ACQUIRE) != kStatusIdleExit) continue;
+    // the control workgroup publishes the status last; the compute workgroups leave
+    // on its stop broadcast
+    HIP_TRY(hipStreamSynchronize(p->streams[w]));
+    HIP_TRY(hipMemsetAsync(&p->ctl[w]->go, 0, sizeof(p->ctl[w]->go), p->streams[w]));
+    __atomic_store_n(&p->pub->started[w], 0, __ATOMIC_RELEASE);
+    __atomic_store_n(&p->pub->status[w], (int32_t)kStatusOk, __ATOMIC_RELEASE);
+    const int i = p->w_stage[w];
+    if (int32_t rc = launch_worker(p->cfg.stages[i].kind, p->args[w], p->cfg.cu[i], p->streams[w])) return rc;
+  }
+  return CAMELOT_OK;
+}
+
 // arrival_host_ns < 0: the query arrives now
 static int32_t submit_at(camelot_pipeline* p, uint64_t query_id, const void* payload, int32_t rows,
                          int64_t arrival_host_ns) {
@@ -1144,7 +1165,9 @@ static int32_t submit_at(camelot_pipeline* p, uint64_t query_id, const void* pay
     return fail(CAMELOT_EINVAL, "rows must be in 1..%d", p->cfg.max_rows_per_request);
   if (!payload) return fail(CAMELOT_EINVAL, "payload is NULL");
   if (p->any_id && query_id <= p->last_id) return fail(CAMELOT_EINVAL, "query ids must increase");
-  int32_t rc = worker_error(p);
+  int32_t rc = relaunch_idle(p);
+  if (rc) return rc;
+  rc = worker_error(p);
   if (rc) return rc;
   const uint64_t tail = __atomic_load_n(&p->pub->ingest_tail, __ATOMIC_ACQUIRE);
   if (p->head - tail >= (uint64_t)p->cfg.ingest_capacity) return fail(CAMELOT_EAGAIN, "ingest queue full");

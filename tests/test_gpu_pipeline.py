@@ -291,18 +291,30 @@ def test_backpressure_and_destroy_in_flight(torch, cm):
     assert 0 <= und <= sent
 
 
-def test_idle_timeout_stops_workers(torch, cm):
-    _, dws, stages = c0_stages(torch)             # dws: keeps the device weights alive
+def test_idle_workers_leave_and_restart_on_submit(torch, cm):
+    """Workers leave after the idle timeout (status 1) and the next submit starts them
+    again where they left off: the later queries come out after the earlier ones,
+    once each, with the oracle's results, and the stages' batch counts continue."""
+    (w1, w2), dws, stages = c0_stages(torch)      # dws: keeps the device weights alive
+    x = G.c0_queries(24, seed=17)
     torch.cuda.synchronize()
-    cfg = cm.pipeline_config(stages, (8, 8), idle_timeout_ns=200_000_000)
+    cfg = cm.pipeline_config(stages, (8, 8), max_batch=8, idle_timeout_ns=200_000_000)
     p = cm.camelot_pipeline_create(cfg)
+    res = []
     try:
-        time.sleep(1.0)
-        with pytest.raises(cm.CamelotError) as e:
-            cm.camelot_pipeline_submit(p, 1, np.zeros(512, np.float32), 1)
-        assert e.value.code == cm.ESTOPPED
+        for rnd in range(3):
+            for i in range(8 * rnd, 8 * rnd + 8):
+                assert cm.camelot_pipeline_submit(p, i + 1, x[i], 1) == cm.OK
+            res += drain_all(cm, p, 8)
+            assert len(res) == 8 * (rnd + 1)
+            time.sleep(1.0)                       # five idle timeouts: both workers leave
+            st = cm.camelot_pipeline_stats_get(p)
+            assert list(st.worker_status[:2]) == [1, 1], list(st.worker_status[:2])
+        assert st.batches[0] >= 3 and st.batches[1] >= 3
     finally:
         cm.camelot_pipeline_destroy(p)
+    assert [r.query_id for r in res] == list(range(1, 25))
+    check_c0_outputs(res, x, w1, w2)
 
 
 def test_create_rejects_bad_configs(torch, cm):
