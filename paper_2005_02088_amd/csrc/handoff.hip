@@ -5,9 +5,10 @@
 // frees the slot. Producer workgroup j and consumer workgroup j own the same chunk
 // of every slot, so the channels are independent (no grid barrier). All waits are
 // bounded by spin_ticks. The producer writes its chunk through to the device's point
-// of coherence (cache policy nt sc1), so one release by thread 0 after the workgroup
-// barrier publishes it (with plain stores and that one release, a reader on another
-// XCD sometimes saw old data behind the new doorbell).
+// of coherence (cache policy nt sc1) and every wave waits for its stores before the
+// workgroup barrier, so thread 0 rings the doorbell right after it (with plain stores
+// and one release by thread 0, a reader on another XCD sometimes saw old data behind
+// the new doorbell).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -69,9 +70,12 @@ extern "C" __global__ __launch_bounds__(kThreads, kMinWgPerCuResident) void came
       }
     }
     for (; o < hi; o += kStep) __builtin_amdgcn_raw_buffer_store_b128(pattern4(s, (uint32_t)(o >> 2)), rs, (int)o, 0, kStreamThrough);
+    // every wave's written-through stores are acknowledged (performed at the
+    // device's point of coherence) before the barrier, so the doorbell needs no L2
+    // write-back: a relaxed store after the barrier
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) st_release_agent(&a.full[(int64_t)d * nwg + j], lap + 1);
+    if (tid == 0) __hip_atomic_store(&a.full[(int64_t)d * nwg + j], lap + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (tid == 0) atomicMax((unsigned long long*)&a.result[3], (unsigned long long)now_ticks());
 }
