@@ -1126,9 +1126,11 @@ __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
 }
 
 // ------------------------------------------------------------------ gather + score
-// One wave per row: the row's query vectors are staged in LDS; each lane computes
-// whole dot products (fixed order over d) for the (head, id) outputs lane, lane + 64,
-// ...; lanes of the same id read the same table row, which stays in L1.
+// One wave per row: the row's query vectors are staged in LDS. When the table width
+// is a multiple of 8 (its rows are then 16-byte aligned), each quarter wave takes one
+// id: its 16 lanes read the table row in contiguous 16-byte pieces once and score it
+// against every head. Other widths: each lane computes whole dot products (in order
+// over d) for the (head, id) outputs lane, lane + 64, ...
 constexpr int kScoreMaxQ = 1024;
 
 __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
@@ -1144,16 +1146,94 @@ __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const Bat
     const int32_t* ids = (const int32_t*)br.bd->rowside[r];
     for (int i = lane; i < qdim; i += 64) q_s[w][i] = q[i];
     wave_lds_sync();
-    for (int o = lane; o < heads * n_ids; o += 64) {
-      const int h = o / n_ids, j = o - h * n_ids;
-      const int id = ids[j];
-      float acc = 0.f;
-      if (id >= 0 && id < trows) {
-        const __half* tr = T + (int64_t)id * dim;
-        const float* qh = q_s[w] + h * dim;
-        for (int d = 0; d < dim; ++d) acc = fmaf(qh[d], __half2float(tr[d]), acc);
+    const int g = lane >> 4, sl = lane & 15;
+    if (dim % 8 == 0 && dim <= 128) {
+      // rows of at most 128 values: a quarter wave per id, lane s holding piece s (8
+      // values) of the row; the rows of 8 ids per quarter wave (32 per wave) are loaded
+      // before any is scored. Per head, the lane adds its 8 products in order and the 16
+      // lanes' sums are added by a fixed butterfly: one summation order per score, the
+      // same as the wider rows' path below
+      for (int j0 = 0; j0 < n_ids; j0 += 32) {
+        int idv[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int j = j0 + 4 * b + g;
+          idv[b] = j < n_ids ? ids[j] : -1;
+        }
+        uint4 tv[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          tv[b] = (idv[b] >= 0 && idv[b] < trows && sl * 8 < dim) ? gld16(T + (int64_t)idv[b] * dim + sl * 8)
+                                                               : make_uint4(0u, 0u, 0u, 0u);
+        for (int h = 0; h < heads; ++h) {
+          float qv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          if (sl * 8 < dim) {
+            const float4 qa = *(const float4*)(q_s[w] + h * dim + sl * 8), qb = *(const float4*)(q_s[w] + h * dim + sl * 8 + 4);
+            qv[0] = qa.x; qv[1] = qa.y; qv[2] = qa.z; qv[3] = qa.w; qv[4] = qb.x; qv[5] = qb.y; qv[6] = qb.z; qv[7] = qb.w;
+          }
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const uint32_t u[4] = {tv[b].x, tv[b].y, tv[b].z, tv[b].w};
+            float acc = 0.f;
+            if (sl * 8 < dim) {
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                acc = fmaf(qv[e], __half2float(__ushort_as_half((unsigned short)(u[e >> 1] >> (16 * (e & 1))))), acc);
+            }
+#pragma unroll
+            for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+            const int j = j0 + 4 * b + g;
+            if (sl == 0 && j < n_ids)
+              out_f32(&Y[((int64_t)r * heads + h) * n_ids + j], (idv[b] >= 0 && idv[b] < trows) ? acc : 0.f);
+          }
+        }
       }
-      out_f32(&Y[(int64_t)r * heads * n_ids + o], acc);
+    } else if (dim % 8 == 0) {
+      // wider rows: lane s holds pieces s, s + 16, ... of one id's row for all heads,
+      // adds them in order, then the same butterfly
+      for (int j0 = 0; j0 < n_ids; j0 += 4) {
+        const int j = j0 + g;
+        const int id = j < n_ids ? ids[j] : -1;
+        const bool in = id >= 0 && id < trows;
+        uint4 tv[kScoreMaxQ / 128];
+#pragma unroll
+        for (int p = 0; p < kScoreMaxQ / 128; ++p) {
+          const int d0 = p * 128 + sl * 8;
+          tv[p] = (in && d0 < dim) ? gld16(T + (int64_t)id * dim + d0) : make_uint4(0u, 0u, 0u, 0u);
+        }
+        for (int h = 0; h < heads; ++h) {
+          const float* qh = q_s[w] + h * dim;
+          float acc = 0.f;
+#pragma unroll
+          for (int p = 0; p < kScoreMaxQ / 128; ++p) {
+            const int d0 = p * 128 + sl * 8;
+            if (d0 < dim) {
+              const float4 qa = *(const float4*)(qh + d0), qb = *(const float4*)(qh + d0 + 4);
+              const uint32_t u[4] = {tv[p].x, tv[p].y, tv[p].z, tv[p].w};
+              const float qv[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                acc = fmaf(qv[e], __half2float(__ushort_as_half((unsigned short)(u[e >> 1] >> (16 * (e & 1))))), acc);
+            }
+          }
+#pragma unroll
+          for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+          if (sl == 0 && j < n_ids) out_f32(&Y[((int64_t)r * heads + h) * n_ids + j], in ? acc : 0.f);
+        }
+      }
+    } else {
+      // other widths: one (head, id) per lane, the row walked in order
+      for (int o = lane; o < heads * n_ids; o += 64) {
+        const int h = o / n_ids, j = o - h * n_ids;
+        const int id = ids[j];
+        float acc = 0.f;
+        if (id >= 0 && id < trows) {
+          const __half* tr = T + (int64_t)id * dim;
+          const float* qh = q_s[w] + h * dim;
+          for (int d = 0; d < dim; ++d) acc = fmaf(qh[d], __half2float(tr[d]), acc);
+        }
+        out_f32(&Y[(int64_t)r * heads * n_ids + o], acc);
+      }
     }
     wave_lds_sync();
   }

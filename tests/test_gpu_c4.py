@@ -82,28 +82,35 @@ def test_conv_pool_grid_and_batch_invariant(torch, cm):
     assert np.array_equal(a[2], c[0])
 
 
-def test_gather_score_parity_and_out_of_range_ids(torch, cm):
+@pytest.mark.parametrize("heads,dim,n_ids", [(HEADS, DIM, N_IDS), (4, 256, 20), (16, 64, 7), (2, 512, 5),
+                                             (1, 1024, 3), (5, 36, 9)])
+def test_gather_score_parity_and_out_of_range_ids(torch, cm, heads, dim, n_ids):
+    """Widths that are multiples of 8 (16-byte table pieces, one, several or part of
+    a 128-wide pass per lane; id counts not a multiple of 4) and one that is not (the
+    per-lane path)."""
     rows, trows = 7, 4096
-    table = G.fp16_table(trows, DIM, seed=3)
+    table = G.fp16_table(trows, dim, seed=3)
     g = G.rng("c4", 3, 20)
-    q = g.standard_normal((rows, HEADS * DIM), dtype=np.float32)
-    ids = g.integers(0, trows, (rows, N_IDS)).astype(np.int32)
-    ids[0, 0], ids[1, 5], ids[2, 31] = -1, trows, 2 ** 31 - 1       # outside the table: score 0
+    q = g.standard_normal((rows, heads * dim), dtype=np.float32)
+    ids = g.integers(0, trows, (rows, n_ids)).astype(np.int32)
+    last = n_ids - 1
+    ids[0, 0], ids[1, min(5, last)], ids[2, last] = -1, trows, 2 ** 31 - 1       # outside the table: score 0
     buf = np.concatenate([q.view(np.uint8).reshape(rows, -1), ids.view(np.uint8).reshape(rows, -1)], axis=1)
     dt = to_dev(torch, table.view(np.int16))
-    desc = cm.stage_desc(cm.STAGE_GATHER_SCORE, dims=(HEADS * DIM, DIM, N_IDS), weights=(dt.data_ptr(),), k=trows)
+    desc = cm.stage_desc(cm.STAGE_GATHER_SCORE, dims=(heads * dim, dim, n_ids), weights=(dt.data_ptr(),), k=trows)
     din = to_dev(torch, buf)
-    dy = torch.full((rows, HEADS * N_IDS), float("nan"), device="cuda")
+    dy = torch.full((rows, heads * n_ids), float("nan"), device="cuda")
     torch.cuda.synchronize()
-    log("gather_score rows=7 heads=8 dim=128 ids=32")
+    log(f"gather_score rows=7 heads={heads} dim={dim} ids={n_ids}")
     cm.camelot_stage_run(desc, din.data_ptr(), dy.data_ptr(), rows, 16, 0)
     y = dy.cpu().numpy()
-    ref = O.gather_score(q, ids, table, DIM)
+    ref = O.gather_score(q, ids, table, dim)
     err = O.normwise_err(y, ref)
     log(f"  err={err:.3e}")
     assert err <= 1e-5
-    assert y[0, 0] == 0 and y[1, 5] == 0 and y[2, 31] == 0
-    assert y[0, N_IDS] == 0                                            # same id, head 1
+    assert y[0, 0] == 0 and y[1, min(5, last)] == 0 and y[2, last] == 0
+    if heads > 1:
+        assert y[0, n_ids] == 0                                        # same id, head 1
 
 
 @pytest.fixture(scope="module")
