@@ -1134,7 +1134,7 @@ __device__ bool exec_conv_pool(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
 constexpr int kScoreMaxQ = 1024;
 
 __device__ void exec_gather_score(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
-  __shared__ float q_s[kWaves][kScoreMaxQ];
+  __shared__ __attribute__((aligned(16))) float q_s[kWaves][kScoreMaxQ];   // read as float4
   const int qdim = a.sp.dims[0], dim = a.sp.dims[1], n_ids = a.sp.dims[2];
   const int heads = qdim / dim;
   const int64_t trows = a.sp.k;
