@@ -127,7 +127,8 @@ __device__ __forceinline__ void seal_rows(const WorkerArgs& a, const BatchDesc* 
 // ------------------------------------------------------------------ GEMM + ReLU (FP32)
 // Unit = (64 output columns, 8 rows) per workgroup; the 4 waves split K in
 // interleaved 64-wide chunks and their partial sums are added in a fixed order,
-// so every output's arithmetic is independent of the batch and of the grid.
+// so every output's arithmetic is independent of the batch and of the grid. A lane
+// owns one column: its weight loads are 256 contiguous bytes per wave and k.
 constexpr int kGemmMaxK = 1024;
 
 __device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, const BatchRows& br, int rows, uint8_t* out) {
@@ -152,7 +153,18 @@ __device__ void exec_gemm_relu(const WorkerArgs& a, WorkerCtl* ctl, const BatchR
     if (col < N) {
       for (int kc = w * 64; kc < K; kc += kWaves * 64) {
         const int kend = min(kc + 64, K);
-        for (int kk = kc; kk < kend; ++kk) {
+        int kk = kc;
+        // 16 weight loads in flight before their FMAs (the FMAs keep increasing k)
+        for (; kk + 16 <= kend; kk += 16) {
+          float wv[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) wv[q] = W[(int64_t)(kk + q) * N + col];
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc[r] = fmaf(xs[r][kk + q], wv[q], acc[r]);
+        }
+        for (; kk < kend; ++kk) {
           const float wv = W[(int64_t)kk * N + col];
 #pragma unroll
           for (int r = 0; r < 8; ++r) acc[r] = fmaf(xs[r][kk], wv, acc[r]);
