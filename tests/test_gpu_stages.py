@@ -71,6 +71,24 @@ def test_gemm_relu_grid_and_batch_invariant(torch, cm):
     assert np.array_equal(outs[3][0], outs[0][0])
 
 
+@pytest.mark.parametrize("k,n", [(100, 200), (1024, 64), (16, 17), (7, 130)])
+def test_gemm_relu_ragged_shapes(torch, cm, k, n):
+    """Input widths that leave a short K chunk per wave (not a multiple of 16 or of
+    64) and output widths that leave a partial 64-column block."""
+    g = G.rng("c0_weights", 77, k)
+    w = (g.standard_normal((k, n)) / np.sqrt(k)).astype(np.float32)
+    x = g.standard_normal((13, k)).astype(np.float32)
+    dw, dx = to_dev(torch, w), to_dev(torch, x)
+    dy = torch.empty((13, n), dtype=torch.float32, device="cuda")
+    desc = cm.stage_desc(cm.STAGE_GEMM_RELU, dims=(k, n), weights=(dw.data_ptr(),))
+    torch.cuda.synchronize()
+    log(f"gemm_relu ragged k={k} n={n}")
+    cm.camelot_stage_run(desc, dx.data_ptr(), dy.data_ptr(), 13, 16, 0)
+    err = O.normwise_err(dy.cpu().numpy(), O.gemm_relu(x, w))
+    log(f"  err={err:.3e}")
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("rows", [1, 9, 64])
 def test_gemm_argmax_parity(torch, cm, rows):
     (w1, w2), dws, (sa, sb) = c0_stages(torch)    # dws: keeps the device weights alive
