@@ -715,7 +715,7 @@ def artifact_suite(cm, G, torch, trial_s, iters, failures):
             # at its own predicted peak: does the allocation meet the QoS?
             al["qos_met_at_predicted_peak"] = replay_trial(cm, G, stages, pool, al["cu"], tuple(al["n"]), al["batch"],
                                                            al["predicted_qps"], trial_s, 99, failures)["ok"]
-    # host-link contention (Section IV-B's experiment): N PCIe-intensive instances of
+    # host-link contention (Section VI-A's experiment): N PCIe-intensive instances of
     # the heaviest kind, 16 CUs each, run together; time per batch of each
     contention = []
     for nk in range(1, 9):
